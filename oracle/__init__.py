@@ -1,0 +1,219 @@
+"""FP64 CPU oracle of the adaptive-relaxation LBM (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It wraps ``libarlbm_oracle.so`` (plain C, built by
+``oracle/build.py``) with ctypes and numpy; it imports nothing from the GPU
+library.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+ADVECTION, EULER, SWE = 0, 1, 2
+PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
+
+
+class OraCfg(C.Structure):
+    _fields_ = [
+        ("system", C.c_int32), ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+        ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+        ("bc", C.c_int32 * 4),
+        ("cfl", C.c_double), ("eps", C.c_double), ("gamma", C.c_double), ("g", C.c_double),
+        ("adv", C.c_double * 2), ("h_dry", C.c_double), ("rho_floor", C.c_double),
+        ("p_floor", C.c_double), ("has_bed", C.c_int32), ("omega_fixed_on", C.c_int32),
+        ("omega_fixed", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load the oracle library, building it first only if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+        vp = C.c_void_p
+        L.ora_num_fields.argtypes = [C.c_int, C.c_int]
+        L.ora_num_fields.restype = C.c_int
+        L.ora_create.argtypes = [C.POINTER(OraCfg)]
+        L.ora_create.restype = vp
+        L.ora_destroy.argtypes = [vp]
+        L.ora_init.argtypes = [vp, dp, vp, C.c_double]
+        L.ora_init.restype = C.c_int
+        L.ora_run.argtypes = [vp, C.c_int64, C.c_double]
+        L.ora_run.restype = C.c_int64
+        for name in ("ora_moments", "ora_get_f", "ora_last_omega", "ora_omega_field",
+                     "ora_nu_field"):
+            getattr(L, name).argtypes = [vp, dp]
+        L.ora_set_f.argtypes = [vp, dp]
+        L.ora_alpha_bar.argtypes = [vp, dp]
+        L.ora_time.argtypes = [vp]
+        L.ora_time.restype = C.c_double
+        L.ora_steps.argtypes = [vp]
+        L.ora_steps.restype = C.c_int64
+        L.ora_flags.argtypes = [vp]
+        L.ora_flags.restype = C.c_int32
+        L.ora_last_scalars.argtypes = [vp, dp, C.POINTER(C.c_double)]
+        L.ora_flux.argtypes = [C.POINTER(OraCfg), C.c_int, dp, dp]
+        L.ora_max_speed.argtypes = [C.POINTER(OraCfg), C.c_int, dp]
+        L.ora_max_speed.restype = C.c_double
+        L.ora_left_eigvecs.argtypes = [C.POINTER(OraCfg), C.c_int, dp, dp]
+        L.ora_lf_coeffs.argtypes = [C.c_int, dp, C.c_double, dp, dp]
+        L.ora_equilibrium.argtypes = [C.POINTER(OraCfg), dp, dp, C.c_double, dp]
+        _lib = L
+    return _lib
+
+
+def num_fields(system, dim):
+    return lib().ora_num_fields(system, dim)
+
+
+def make_cfg(system, dim, nx, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=(PERIODIC,) * 4,
+             cfl=0.5, eps=1e-10, gamma=1.4, g=9.81, adv=(1.0, 0.0), h_dry=1e-6,
+             rho_floor=1e-12, p_floor=1e-12, has_bed=False, omega_fixed=None):
+    c = OraCfg()
+    c.system, c.dim, c.nx, c.ny = system, dim, nx, (ny if dim == 2 else 1)
+    c.x0, c.x1, c.y0, c.y1 = x0, x1, y0, y1
+    for i in range(4):
+        c.bc[i] = bc[i]
+    c.cfl, c.eps, c.gamma, c.g = cfl, eps, gamma, g
+    c.adv[0], c.adv[1] = adv
+    c.h_dry, c.rho_floor, c.p_floor = h_dry, rho_floor, p_floor
+    c.has_bed = int(bool(has_bed))
+    c.omega_fixed_on = int(omega_fixed is not None)
+    c.omega_fixed = float(omega_fixed) if omega_fixed is not None else 0.0
+    return c
+
+
+class Lattice:
+    """One oracle lattice: ``U0`` is an array of shape (m, ny, nx) or (m, nx)."""
+
+    def __init__(self, cfg: OraCfg):
+        self.cfg = cfg
+        self.d = cfg.dim
+        self.m = num_fields(cfg.system, cfg.dim)
+        self.Q = 2 * self.d + 1
+        self.nx, self.ny = cfg.nx, cfg.ny
+        self._h = lib().ora_create(C.byref(cfg))
+        if not self._h:
+            raise ValueError("oracle rejected the configuration")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().ora_destroy(h)
+            self._h = None
+
+    def _shape(self, lead):
+        return (lead, self.ny, self.nx) if self.d == 2 else (lead, self.nx)
+
+    def init(self, U0, bed=None, t0=0.0):
+        U0 = np.ascontiguousarray(U0, dtype=np.float64).reshape(self._shape(self.m))
+        bp = None
+        if bed is not None:
+            bed = np.ascontiguousarray(bed, dtype=np.float64)
+            self._bed = bed
+            bp = bed.ctypes.data_as(C.c_void_p)
+        rc = lib().ora_init(self._h, U0, bp, float(t0))
+        if rc != 0:
+            raise RuntimeError(f"ora_init failed: {rc}")
+        return self
+
+    def run(self, nsteps, t_final=0.0):
+        n = lib().ora_run(self._h, int(nsteps), float(t_final))
+        if n < 0:
+            raise RuntimeError(f"ora_run failed: {n}")
+        return n
+
+    def moments(self):
+        out = np.empty(self._shape(self.m))
+        lib().ora_moments(self._h, out)
+        return out
+
+    def f(self):
+        out = np.empty((self.Q,) + self._shape(self.m))
+        lib().ora_get_f(self._h, out)
+        return out
+
+    def set_f(self, f):
+        lib().ora_set_f(self._h, np.ascontiguousarray(f, dtype=np.float64))
+
+    def last_omega(self):
+        out = np.empty(self._shape(1)[1:])
+        lib().ora_last_omega(self._h, out)
+        return out
+
+    def omega_field(self):
+        out = np.empty(self._shape(1)[1:])
+        lib().ora_omega_field(self._h, out)
+        return out
+
+    def nu_field(self):
+        out = np.empty(self._shape(1)[1:])
+        lib().ora_nu_field(self._h, out)
+        return out
+
+    def alpha_bar(self):
+        out = np.zeros(2)
+        lib().ora_alpha_bar(self._h, out)
+        return out[: self.d]
+
+    @property
+    def t(self):
+        return lib().ora_time(self._h)
+
+    @property
+    def steps(self):
+        return lib().ora_steps(self._h)
+
+    @property
+    def flags(self):
+        return lib().ora_flags(self._h)
+
+    def last_scalars(self):
+        ab = np.zeros(2)
+        dt = C.c_double()
+        lib().ora_last_scalars(self._h, ab, C.byref(dt))
+        return ab[: self.d], dt.value
+
+
+def flux(cfg, direction, U):
+    m = num_fields(cfg.system, cfg.dim)
+    out = np.zeros(m)
+    lib().ora_flux(C.byref(cfg), direction, np.ascontiguousarray(U, dtype=np.float64), out)
+    return out
+
+
+def max_speed(cfg, direction, U):
+    return lib().ora_max_speed(C.byref(cfg), direction, np.ascontiguousarray(U, dtype=np.float64))
+
+
+def left_eigvecs(cfg, direction, U):
+    m = num_fields(cfg.system, cfg.dim)
+    out = np.zeros(m * m)
+    lib().ora_left_eigvecs(C.byref(cfg), direction, np.ascontiguousarray(U, dtype=np.float64), out)
+    return out.reshape(m, m)
+
+
+def lf_coeffs(dim, alpha, lam):
+    Q = 2 * dim + 1
+    a = np.zeros(Q)
+    b = np.zeros(Q * dim)
+    lib().ora_lf_coeffs(dim, np.ascontiguousarray(alpha, dtype=np.float64), float(lam), a, b)
+    return a, b.reshape(Q, dim)
+
+
+def equilibrium(cfg, U, alpha, lam):
+    m = num_fields(cfg.system, cfg.dim)
+    Q = 2 * cfg.dim + 1
+    out = np.zeros(Q * m)
+    lib().ora_equilibrium(C.byref(cfg), np.ascontiguousarray(U, dtype=np.float64),
+                          np.ascontiguousarray(alpha, dtype=np.float64), float(lam), out)
+    return out.reshape(Q, m)

@@ -1,0 +1,308 @@
+"""Seeded synthetic workloads: initial states and problem settings.
+
+This module only draws inputs.  It holds none of the lattice Boltzmann
+arithmetic and is shared by the CPU oracle's tests, the GPU parity tests and
+the benchmark.  Every generator is deterministic in its seed (numpy PCG64).
+
+Conserved variables, one plane per field, cell-centred points
+``x_i = x0 + (i + 1/2) dx``:
+
+* scalar advection: ``u``;
+* Euler (gamma-law gas): ``(rho, rho u[, rho v], E)`` with
+  ``E = p/(gamma-1) + rho |u|^2 / 2``;
+* shallow water: ``(h, h u[, h v])``.
+
+Workloads follow the structure of the paper's experiments (Section 5): smooth
+periodic sine waves, piecewise-constant Riemann data, four-quadrant 2D Riemann
+data, dry-bed and circular dam breaks.  The shallow-water bed of Gaussian
+bumps is a synthetic stand-in (the paper's examples use a flat bed).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+ADVECTION, EULER, SWE = 0, 1, 2
+PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
+GAMMA = 1.4
+GRAVITY = 9.81
+
+
+@dataclasses.dataclass
+class Problem:
+    """A lattice problem: settings plus conserved initial data."""
+    name: str
+    system: int
+    dim: int
+    nx: int
+    ny: int
+    x0: float
+    x1: float
+    y0: float
+    y1: float
+    bc: tuple
+    cfl: float
+    steps: int
+    U0: np.ndarray                 # (m, nx) in 1D, (m, ny, nx) in 2D, float64
+    bed: Optional[np.ndarray] = None
+    t_final: float = 0.0           # > 0: time-targeted run
+    gamma: float = GAMMA
+    g: float = GRAVITY
+    adv: tuple = (1.0, 0.0)
+    eps: float = 1e-10
+
+    @property
+    def cells(self) -> int:
+        return self.nx * (self.ny if self.dim == 2 else 1)
+
+
+def centres(n: int, a: float, b: float) -> np.ndarray:
+    dx = (b - a) / n
+    return a + (np.arange(n) + 0.5) * dx
+
+
+def euler_conserved(rho, u, v, p, gamma=GAMMA, dim=2):
+    rho, u, v, p = (np.asarray(a, dtype=np.float64) for a in (rho, u, v, p))
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    if dim == 1:
+        return np.stack([rho, rho * u, E])
+    return np.stack([rho, rho * u, rho * v, E])
+
+
+def swe_conserved(h, u, v, dim=2):
+    h, u, v = (np.asarray(a, dtype=np.float64) for a in (h, u, v))
+    if dim == 1:
+        return np.stack([h, h * u])
+    return np.stack([h, h * u, h * v])
+
+
+# --------------------------------------------------------------------------
+# Configuration 1: smooth periodic advection
+# --------------------------------------------------------------------------
+
+def advection_sine(n=256, cfl=0.5, steps=512, t_final=0.0) -> Problem:
+    x = centres(n, 0.0, 1.0)
+    U0 = np.sin(2.0 * np.pi * x)[None, :]
+    return Problem("advection_sine", ADVECTION, 1, n, 1, 0.0, 1.0, 0.0, 1.0,
+                   (PERIODIC,) * 4, cfl, steps, U0, t_final=t_final)
+
+
+def advection_square(n=400, cfl=0.9, t_final=1.0) -> Problem:
+    x = centres(n, 0.0, 1.0)
+    U0 = ((x >= 0.25) & (x <= 0.75)).astype(np.float64)[None, :]
+    return Problem("advection_square", ADVECTION, 1, n, 1, 0.0, 1.0, 0.0, 1.0,
+                   (PERIODIC,) * 4, cfl, 10 ** 9, U0, t_final=t_final)
+
+
+def advection_sine_2d(n=64, ax=1.0, ay=0.5, cfl=0.5, steps=64, seed=0) -> Problem:
+    x = centres(n, 0.0, 1.0)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * np.pi)
+    U0 = np.sin(2 * np.pi * (X + Y) + ph)[None]
+    return Problem("advection_sine_2d", ADVECTION, 2, n, n, 0.0, 1.0, 0.0, 1.0,
+                   (PERIODIC,) * 4, cfl, steps, U0, adv=(ax, ay))
+
+
+# --------------------------------------------------------------------------
+# Configuration 2: 1D Euler Riemann problems
+# --------------------------------------------------------------------------
+
+def riemann_states_1d(seed: int):
+    rng = np.random.default_rng(seed)
+    L = (rng.uniform(0.125, 1.0), rng.uniform(-1.0, 1.0), rng.uniform(0.1, 1.0))
+    R = (rng.uniform(0.125, 1.0), rng.uniform(-1.0, 1.0), rng.uniform(0.1, 1.0))
+    return L, R
+
+
+def euler_riemann_1d(left, right, n=4096, x0=0.0, x1=1.0, xs=0.5, cfl=0.5, steps=2000,
+                     t_final=0.0, gamma=GAMMA, name="euler_riemann_1d") -> Problem:
+    x = centres(n, x0, x1)
+    L = x < xs
+    rho = np.where(L, left[0], right[0])
+    u = np.where(L, left[1], right[1])
+    p = np.where(L, left[2], right[2])
+    U0 = euler_conserved(rho, u, 0 * u, p, gamma, dim=1)
+    return Problem(name, EULER, 1, n, 1, x0, x1, 0.0, 1.0,
+                   (TRANSMISSIVE,) * 4, cfl, steps, U0, t_final=t_final, gamma=gamma)
+
+
+def euler_seeded_1d(seed=0, n=4096, cfl=0.5, steps=2000) -> Problem:
+    L, R = riemann_states_1d(seed)
+    return euler_riemann_1d(L, R, n=n, cfl=cfl, steps=steps, name=f"euler1d_seed{seed}")
+
+
+SOD = ((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+LAX = ((0.445, 0.698, 3.528), (0.5, 0.0, 0.571))
+
+
+def euler_entropy_wave_1d(n=400, cfl=0.6, t_final=1.0) -> Problem:
+    x = centres(n, 0.0, 1.0)
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * x)
+    U0 = euler_conserved(rho, np.ones(n), np.zeros(n), np.ones(n), dim=1)
+    return Problem("euler_entropy_1d", EULER, 1, n, 1, 0.0, 1.0, 0.0, 1.0,
+                   (PERIODIC,) * 4, cfl, 10 ** 9, U0, t_final=t_final)
+
+
+# --------------------------------------------------------------------------
+# Configuration 3: 2D Euler four-quadrant Riemann problems
+# --------------------------------------------------------------------------
+
+def _vacuum(uL, cL, uR, cR, gamma):
+    return (uR - uL) >= 2.0 * (cL + cR) / (gamma - 1.0)
+
+
+def quadrant_states(seed: int, gamma=GAMMA):
+    """Per-quadrant (rho, u, v, p), redrawn while any interface would create
+    vacuum (Toro's pressure-positivity condition).  Order: quadrants
+    1 (x>.5,y>.5), 2 (x<.5,y>.5), 3 (x<.5,y<.5), 4 (x>.5,y<.5)."""
+    rng = np.random.default_rng(seed)
+    while True:
+        q = [(rng.uniform(0.1, 1.5), rng.uniform(-1, 1), rng.uniform(-1, 1),
+              rng.uniform(0.03, 1.5)) for _ in range(4)]
+        c = [math.sqrt(gamma * s[3] / s[0]) for s in q]
+        bad = (_vacuum(q[1][1], c[1], q[0][1], c[0], gamma) or   # 2 | 1 along x
+               _vacuum(q[2][1], c[2], q[3][1], c[3], gamma) or   # 3 | 4 along x
+               _vacuum(q[2][2], c[2], q[1][2], c[1], gamma) or   # 3 / 2 along y
+               _vacuum(q[3][2], c[3], q[0][2], c[0], gamma))     # 4 / 1 along y
+        if not bad:
+            return q
+
+
+def euler_quadrants_2d(states, n=2048, cfl=0.5, steps=1000, bc=(TRANSMISSIVE,) * 4,
+                       gamma=GAMMA, name="euler2d_quadrants") -> Problem:
+    x = centres(n, 0.0, 1.0)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    quad = np.where(X > 0.5, np.where(Y > 0.5, 0, 3), np.where(Y > 0.5, 1, 2))
+    arr = np.array(states, dtype=np.float64)        # (4, 4)
+    prim = arr[quad]                                # (n, n, 4)
+    U0 = euler_conserved(prim[..., 0], prim[..., 1], prim[..., 2], prim[..., 3], gamma, dim=2)
+    return Problem(name, EULER, 2, n, n, 0.0, 1.0, 0.0, 1.0, tuple(bc), cfl, steps, U0,
+                   gamma=gamma)
+
+
+def euler_seeded_2d(seed=0, n=2048, cfl=0.5, steps=1000) -> Problem:
+    return euler_quadrants_2d(quadrant_states(seed), n=n, cfl=cfl, steps=steps,
+                              name=f"euler2d_seed{seed}")
+
+
+def euler_entropy_wave_2d(n=40, cfl=0.3, t_final=0.3) -> Problem:
+    x = centres(n, 0.0, 1.0)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * (X + Y))
+    one = np.ones_like(rho)
+    U0 = euler_conserved(rho, one, one, one, dim=2)
+    return Problem("euler_entropy_2d", EULER, 2, n, n, 0.0, 1.0, 0.0, 1.0,
+                   (PERIODIC,) * 4, cfl, 10 ** 9, U0, t_final=t_final)
+
+
+# --------------------------------------------------------------------------
+# Configuration 4: 2D shallow water over a seeded bed of Gaussian bumps
+# --------------------------------------------------------------------------
+
+def swe_bed_params(seed: int, bumps: int = 32):
+    rng = np.random.default_rng(seed)
+    H = rng.uniform(0.0, 0.8, bumps)
+    w = rng.uniform(0.02, 0.1, bumps)
+    c = rng.uniform(0.0, 1.0, (bumps, 2))
+    disc_c = rng.uniform(0.3, 0.7, 2)
+    disc_r = rng.uniform(0.15, 0.3)
+    return H, w, c, disc_c, disc_r
+
+
+def swe_bed_2d(seed=0, n=4096, cfl=0.5, steps=2000, level=1.0) -> Problem:
+    H, w, cen, dc, dr = swe_bed_params(seed)
+    x = centres(n, 0.0, 1.0)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    bed = np.zeros((n, n))
+    for Hm, wm, cm in zip(H, w, cen):
+        bed += Hm * np.exp(-((X - cm[0]) ** 2 + (Y - cm[1]) ** 2) / (wm * wm))
+    inside = (X - dc[0]) ** 2 + (Y - dc[1]) ** 2 <= dr * dr
+    h = np.where(inside, np.maximum(0.0, level - bed), 0.0)
+    U0 = swe_conserved(h, 0 * h, 0 * h, dim=2)
+    return Problem(f"swe2d_bed_seed{seed}", SWE, 2, n, n, 0.0, 1.0, 0.0, 1.0,
+                   (REFLECTIVE,) * 4, cfl, steps, U0, bed=bed)
+
+
+def swe_dam_break_1d(n=600, cfl=0.9, t_final=0.15) -> Problem:
+    x = centres(n, -1.0, 1.0)
+    h = np.where(x <= 0.0, 2.0, 0.0)
+    U0 = swe_conserved(h, 0 * h, 0 * h, dim=1)
+    return Problem("swe_dry_dam_break", SWE, 1, n, 1, -1.0, 1.0, 0.0, 1.0,
+                   (TRANSMISSIVE,) * 4, cfl, 10 ** 9, U0, t_final=t_final)
+
+
+def swe_circular_dam_2d(n=64, cfl=0.4, t_final=0.07) -> Problem:
+    x = centres(n, -1.0, 1.0)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    h = np.where(np.sqrt(X * X + Y * Y) <= 0.5, 2.0, 1.0)
+    U0 = swe_conserved(h, 0 * h, 0 * h, dim=2)
+    return Problem("swe_circular_dam", SWE, 2, n, n, -1.0, 1.0, -1.0, 1.0,
+                   (TRANSMISSIVE,) * 4, cfl, 10 ** 9, U0, t_final=t_final)
+
+
+def swe_lake_at_rest_2d(n=64, seed=0, steps=50, cfl=0.5) -> Problem:
+    """Flat free surface over a smooth bed, closed basin: the lake at rest."""
+    rng = np.random.default_rng(seed)
+    x = centres(n, 0.0, 1.0)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    bed = np.zeros((n, n))
+    for _ in range(4):
+        c = rng.uniform(0.3, 0.7, 2)
+        bed += rng.uniform(0.1, 0.3) * np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2) / 0.02)
+    h = 1.0 - bed
+    U0 = swe_conserved(h, 0 * h, 0 * h, dim=2)
+    return Problem("swe_lake_at_rest", SWE, 2, n, n, 0.0, 1.0, 0.0, 1.0,
+                   (REFLECTIVE,) * 4, cfl, steps, U0, bed=bed)
+
+
+def swe_bed_1d(n=512, seed=0, steps=200, cfl=0.5) -> Problem:
+    rng = np.random.default_rng(seed)
+    x = centres(n, 0.0, 1.0)
+    bed = np.zeros(n)
+    for _ in range(4):
+        bed += rng.uniform(0.1, 0.5) * np.exp(-((x - rng.uniform(0.2, 0.8)) ** 2) / 0.003)
+    h = np.where(np.abs(x - 0.5) < 0.3, np.maximum(0.0, 1.0 - bed), 0.0)
+    U0 = swe_conserved(h, 0 * h, 0 * h, dim=1)
+    return Problem(f"swe1d_bed_seed{seed}", SWE, 1, n, 1, 0.0, 1.0, 0.0, 1.0,
+                   (REFLECTIVE,) * 4, cfl, steps, U0, bed=bed)
+
+
+# --------------------------------------------------------------------------
+# Configuration 5: serving mix
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival_s: float
+    kind: str          # "euler1d" | "euler2d" | "swe2d"
+    size: int          # cells (1D) or side (2D)
+    steps: int
+    seed: int
+
+    def problem(self) -> Problem:
+        if self.kind == "euler1d":
+            return euler_seeded_1d(self.seed, n=self.size, steps=self.steps)
+        if self.kind == "euler2d":
+            return euler_seeded_2d(self.seed, n=self.size, steps=self.steps)
+        return swe_bed_2d(self.seed, n=self.size, steps=self.steps)
+
+
+def serving_requests(count=512, rate_hz=200.0, seed=0, n1d=(1024, 65536),
+                     side2d=(128, 1024), steps=(500, 5000)) -> List[Request]:
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    kinds = ("euler1d", "euler2d", "swe2d")
+    for i in range(count):
+        t += rng.exponential(1.0 / rate_hz)
+        kind = kinds[int(rng.integers(0, 3))]
+        size = int(rng.integers(n1d[0], n1d[1] + 1)) if kind == "euler1d" else \
+            int(rng.integers(side2d[0], side2d[1] + 1))
+        out.append(Request(i, t, kind, size, int(rng.integers(steps[0], steps[1] + 1)),
+                           int(rng.integers(0, 2 ** 31))))
+    return out

