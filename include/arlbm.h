@@ -1,0 +1,243 @@
+/*
+ * arlbm.h - C ABI of the MI355X adaptive-relaxation lattice Boltzmann library.
+ *
+ * One time step of the method of Zhang, Lin, Zhao and Zhao ("A Lattice
+ * Boltzmann Method with Adaptive Relaxation Parameter and Lax-Friedrichs-Type
+ * Equilibrium for Hyperbolic Systems") runs as a single fused HIP kernel on a
+ * gfx950 GPU:
+ *   moments U = sum_k f_k (eq. 2.3) -> characteristic projections and
+ *   smoothness indicator (eqs. 2.9-2.10, 2.13-2.14) -> box sum (2.11, 2.15)
+ *   -> relaxation parameter omega = 1 + 1/(1 + nu~) (2.12, 2.16) ->
+ *   Lax-Friedrichs-type equilibrium with the global wave-speed bound
+ *   (2.17-2.20) and time step (2.21) -> source split (2.6) -> collision at
+ *   the source node and pull streaming (the implementation form of 2.2) ->
+ *   implicit moment update (2.8) and second half source.
+ *
+ * Systems (Section 5): scalar advection, compressible Euler (gamma law) and
+ * shallow water, in 1D (D1Q3) and 2D (D2Q5), with an optional shallow-water
+ * bed-slope source S = (0, -g h db/dx, -g h db/dy) (not in the paper).
+ *
+ * Conventions
+ *  - Every function returns 0 (ARLBM_OK) or a negative ARLBM_E* code.  No
+ *    exception crosses the ABI.  arlbm_last_error() describes the last failure.
+ *  - Host arrays are FP64, structure of arrays: plane c of a field with m
+ *    components starts at c*nx*ny, x is fastest, then y.  Host pointers are
+ *    borrowed for the duration of the call only.
+ *  - Device pointers are HIP device addresses on the current device.
+ *  - A handle is not thread-safe; all its work runs in order on the HIP stream
+ *    given at creation (NULL = the default stream).
+ *  - Cells are cell-centred: x_i = x0 + (i + 1/2) dx, dx = (x1 - x0)/nx, and
+ *    in 2D the same dx must hold along y (the paper's uniform grid).
+ */
+#ifndef ARLBM_H
+#define ARLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ARLBM_ABI_VERSION 1
+
+/* Systems, boundary conditions, precisions, relaxation modes. */
+enum { ARLBM_ADVECTION = 0, ARLBM_EULER = 1, ARLBM_SWE = 2 };
+enum { ARLBM_PERIODIC = 0, ARLBM_TRANSMISSIVE = 1, ARLBM_REFLECTIVE = 2 };
+enum { ARLBM_F32 = 0, ARLBM_F64 = 1 };
+enum { ARLBM_OMEGA_ADAPTIVE = 0, ARLBM_OMEGA_FIXED = 1 };
+
+/* Error codes. */
+#define ARLBM_OK 0
+#define ARLBM_EINVAL (-1)      /* bad configuration or argument               */
+#define ARLBM_ENOMEM (-2)      /* device allocation failed                    */
+#define ARLBM_EDEVICE (-3)     /* a HIP call failed (message kept)            */
+#define ARLBM_ENONFINITE (-4)  /* a moment became NaN/Inf                     */
+#define ARLBM_EPOSITIVITY (-5) /* rho or p at/below floor, or h < -h_dry seen  */
+#define ARLBM_EDEGENERATE (-6) /* sum of wave-speed bounds is 0: dt undefined */
+#define ARLBM_EBUSY (-7)       /* handle is owned by a server                 */
+#define ARLBM_EBUDGET (-8)     /* request can never fit the server budget     */
+
+/* Status flag bits (arlbm_status.flags). */
+#define ARLBM_FLAG_NONFINITE 1u
+#define ARLBM_FLAG_POSITIVITY 2u
+#define ARLBM_FLAG_DEGENERATE 4u
+
+typedef struct arlbm_config {
+    int32_t abi_version;  /* ARLBM_ABI_VERSION                                  */
+    int32_t system;       /* ARLBM_ADVECTION / ARLBM_EULER / ARLBM_SWE          */
+    int32_t dim;          /* 1 or 2                                             */
+    int32_t precision;    /* ARLBM_F32 or ARLBM_F64: storage and arithmetic     */
+    int64_t nx, ny;       /* cells; ny = 1 in 1D; nx, ny >= 4                   */
+    double x0, x1, y0, y1;/* domain; in 2D (x1-x0)/nx must equal (y1-y0)/ny     */
+    int32_t bc[4];        /* x-lo, x-hi, y-lo, y-hi; periodic must be paired;
+                             reflective is rejected for advection              */
+    double cfl;           /* in (0, 1): delta t = CFL dx / sum_j alpha_bar_j    */
+    double eps;           /* alpha_j = alpha_bar_j + eps, eps > 0 (paper: 1e-10)*/
+    double gamma;         /* Euler ratio of specific heats (> 1)                */
+    double g;             /* shallow-water gravity (> 0)                        */
+    double adv_speed[2];  /* advection velocity per direction                   */
+    double h_dry;         /* shallow-water dry threshold (FP64 compare)         */
+    double rho_floor, p_floor; /* Euler floors used in the sound speed          */
+    int32_t has_bed;      /* shallow water: bed-slope source on                 */
+    int32_t omega_mode;   /* ARLBM_OMEGA_ADAPTIVE (eq. 2.16) or _FIXED          */
+    double omega_fixed;   /* omega when fixed, in (0, 2]                        */
+} arlbm_config;
+
+/* Byte sizes of the device buffers of one lattice (each 256-byte aligned). */
+typedef struct arlbm_sizes {
+    size_t f_bytes;       /* one distribution buffer: Q*m planes                */
+    size_t u_bytes;       /* one moment buffer: m planes                        */
+    size_t bed_bytes;     /* bed plane (0 without a bed)                        */
+    size_t scalar_bytes;  /* per-lattice device scalars                         */
+    size_t omega_bytes;   /* omega export plane                                 */
+    size_t total_bytes;   /* 2 f + 2 u + bed + scalars (omega export excluded)  */
+    size_t alignment;     /* required alignment of caller buffers               */
+    int32_t m, q;         /* fields per cell, velocities per cell (2d+1)        */
+} arlbm_sizes;
+
+/* Caller-owned device buffers (e.g. torch tensors).  They must outlive the
+ * handle.  omega may be NULL (export disabled). */
+typedef struct arlbm_buffers {
+    void *f[2];
+    void *u[2];
+    void *bed;
+    void *scalars;
+    void *omega;
+} arlbm_buffers;
+
+typedef struct arlbm_status {
+    double t;             /* simulated time                                     */
+    double last_dt;       /* delta t of the last step                           */
+    double abar[2];       /* wave-speed bounds of the current state (eq. 2.19)  */
+    int64_t step;         /* steps taken since set_state                        */
+    int64_t first_bad_step; /* first step whose result set a flag, or -1        */
+    uint32_t flags;       /* ARLBM_FLAG_* bits seen so far                      */
+    uint32_t reserved;
+} arlbm_status;
+
+typedef struct arlbm_lattice arlbm_lattice;
+
+/* Fill *cfg with defaults: ABI version, EULER, 1D, F32, nx = 64, ny = 1,
+ * unit domain, transmissive, CFL 0.5, eps 1e-10, gamma 1.4, g 9.81,
+ * advection speed (1, 0), h_dry 1e-6, floors 1e-12, adaptive omega. */
+int arlbm_config_init(arlbm_config *cfg);
+
+/* Validate cfg and report buffer sizes.  EINVAL on a bad configuration. */
+int arlbm_query_sizes(const arlbm_config *cfg, arlbm_sizes *out);
+
+/* Create a lattice.  bufs == NULL: the library allocates (and frees in
+ * destroy) every buffer; otherwise the caller's buffers are bound (each at
+ * least the queried size and aligned).  stream is a hipStream_t or NULL.
+ * Validates CFL in (0,1), eps > 0 and the sizes; the eps bound of
+ * Theorem 4.3, eps < (1/d)(1/CFL - 1) sum_j alpha_bar_j, needs the state and
+ * is checked by arlbm_set_state. */
+int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, void *stream,
+                 arlbm_lattice **out);
+
+/* Set the initial state from host FP64 planes U0 (m planes) and, with a bed,
+ * bed (one plane); t0 is the starting time.  Rejects non-finite values,
+ * rho <= 0 or p <= 0 (Euler), h < 0 (shallow water) with EPOSITIVITY, a zero
+ * wave-speed bound with EDEGENERATE and an eps above the Theorem 4.3 bound
+ * with EINVAL.  Initialises f = f^eq(U0) with the step-0 coefficients and
+ * synchronises the stream. */
+int arlbm_set_state(arlbm_lattice *h, const double *U0, const double *bed, double t0);
+
+/* Same, with U0 (and bed) already on the device as FP64 planes. */
+int arlbm_set_state_device(arlbm_lattice *h, const double *U0_dev, const double *bed_dev,
+                           double t0);
+
+/* Enqueue n time steps (asynchronous: one kernel launch per step on the
+ * handle's stream, no host round trip).  Device-side problems are latched in
+ * the status flags and reported by arlbm_sync. */
+int arlbm_step(arlbm_lattice *h, int64_t n);
+
+/* Wait for the stream and report the status.  Returns ENONFINITE,
+ * EPOSITIVITY or EDEGENERATE when the matching flag is set (status still
+ * filled), else 0. */
+int arlbm_sync(arlbm_lattice *h, arlbm_status *st);
+
+/* Copy the current moments U = sum_k f_k to host FP64 planes (synchronises). */
+int arlbm_read_moments(arlbm_lattice *h, double *U_out);
+
+/* Enable (1) or disable (0) writing the relaxation parameter of each step to
+ * the omega plane (2.16); library-owned handles allocate the plane. */
+int arlbm_set_omega_export(arlbm_lattice *h, int on);
+
+/* Copy the omega plane of the last exported step to host FP64 (synchronises). */
+int arlbm_read_omega(arlbm_lattice *h, double *omega_out);
+
+/* Sums over all cells of each conserved field, FP64 with compensated
+ * (Neumaier) summation in a fixed order, so repeated calls agree bitwise. */
+int arlbm_conservation(arlbm_lattice *h, double *sums_out);
+
+/* Checkpoint: the state is the f planes, the moment planes, the device
+ * scalars and the step count.  state_bytes gives the size of the blob. */
+int arlbm_state_bytes(arlbm_lattice *h, size_t *bytes);
+int arlbm_save_state(arlbm_lattice *h, void *host_blob, size_t bytes);
+int arlbm_load_state(arlbm_lattice *h, const void *host_blob, size_t bytes);
+
+/* Release the handle and any library-owned buffers. */
+int arlbm_destroy(arlbm_lattice *h);
+
+/* Message of the last failure on h (or of the calling thread when h is NULL).
+ * The string stays valid until the next call on the same handle/thread. */
+const char *arlbm_last_error(const arlbm_lattice *h);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: many FP32 lattices resident at once, one batched launch per      */
+/* iteration advances every resident lattice by one step.                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct arlbm_server arlbm_server;
+
+typedef struct arlbm_completion {
+    uint64_t id;          /* id returned by submit                              */
+    int32_t status;       /* 0 or an ARLBM_E* code                              */
+    int32_t reserved;
+    int64_t steps;        /* steps taken                                        */
+    double t;             /* simulated time reached                             */
+    double submit_s;      /* host clock (seconds) at submit                     */
+    double admit_s;       /* host clock when its lattice became resident        */
+    double done_s;        /* host clock when its result was read back           */
+    double *U;            /* m planes FP64, owned by the server until the next
+                             poll; NULL if status != 0                         */
+    int64_t u_count;      /* number of doubles in U                             */
+} arlbm_completion;
+
+/* Create a server whose resident lattices never exceed hbm_budget bytes of
+ * device memory.  precision must be ARLBM_F32 or ARLBM_F64. */
+int arlbm_server_create(size_t hbm_budget, int32_t precision, void *stream,
+                        arlbm_server **out);
+
+/* Queue a request: a configuration, host FP64 initial planes (and bed) copied
+ * at submit time, and a step count.  EBUDGET if it can never fit the budget. */
+int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, const double *U0,
+                        const double *bed, int64_t nsteps, uint64_t *id);
+
+/* One serving iteration: admit queued requests while the budget allows, run
+ * one batched step for every resident lattice, and retire finished ones
+ * (their moments are read back).  *resident and *queued report the counts
+ * after the iteration (either may be NULL). */
+int arlbm_server_iterate(arlbm_server *s, int32_t *resident, int32_t *queued);
+
+/* Pop up to max finished requests into out; *n receives the count. */
+int arlbm_server_poll(arlbm_server *s, arlbm_completion *out, int32_t max, int32_t *n);
+
+/* Bytes of device memory held by resident lattices. */
+int arlbm_server_memory(arlbm_server *s, size_t *bytes_in_use);
+
+int arlbm_server_destroy(arlbm_server *s);
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Vector registers per lane of the fused step kernel for a precision, system
+ * and dimension (from the code object), or -1. */
+int arlbm_step_kernel_vgprs(int32_t precision, int32_t system, int32_t dim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ARLBM_H */

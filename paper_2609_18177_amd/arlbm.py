@@ -1,0 +1,331 @@
+"""Thin ctypes binding of libarlbm (the C ABI in include/arlbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch provides device memory (caller-owned buffers) and the HIP stream.
+The library must be built (``__graft_entry__.build()``); loading fails loudly
+otherwise, and there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libarlbm.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "arlbm.h")
+
+ADVECTION, EULER, SWE = 0, 1, 2
+PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
+F32, F64 = 0, 1
+OMEGA_ADAPTIVE, OMEGA_FIXED = 0, 1
+ABI_VERSION = 1
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EPOSITIVITY, EDEGENERATE, EBUSY, EBUDGET = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+FLAG_NONFINITE, FLAG_POSITIVITY, FLAG_DEGENERATE = 1, 2, 4
+
+
+class ArlbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"arlbm error {code}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32), ("system", C.c_int32), ("dim", C.c_int32), ("precision", C.c_int32),
+        ("nx", C.c_int64), ("ny", C.c_int64),
+        ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+        ("bc", C.c_int32 * 4),
+        ("cfl", C.c_double), ("eps", C.c_double), ("gamma", C.c_double), ("g", C.c_double),
+        ("adv_speed", C.c_double * 2), ("h_dry", C.c_double), ("rho_floor", C.c_double),
+        ("p_floor", C.c_double), ("has_bed", C.c_int32), ("omega_mode", C.c_int32),
+        ("omega_fixed", C.c_double),
+    ]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("f_bytes", C.c_size_t), ("u_bytes", C.c_size_t), ("bed_bytes", C.c_size_t),
+                ("scalar_bytes", C.c_size_t), ("omega_bytes", C.c_size_t), ("total_bytes", C.c_size_t),
+                ("alignment", C.c_size_t), ("m", C.c_int32), ("q", C.c_int32)]
+
+
+class Buffers(C.Structure):
+    _fields_ = [("f", C.c_void_p * 2), ("u", C.c_void_p * 2), ("bed", C.c_void_p),
+                ("scalars", C.c_void_p), ("omega", C.c_void_p)]
+
+
+class Status(C.Structure):
+    _fields_ = [("t", C.c_double), ("last_dt", C.c_double), ("abar", C.c_double * 2),
+                ("step", C.c_int64), ("first_bad_step", C.c_int64), ("flags", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int32), ("reserved", C.c_int32), ("steps", C.c_int64),
+                ("t", C.c_double), ("submit_s", C.c_double), ("admit_s", C.c_double), ("done_s", C.c_double),
+                ("U", C.POINTER(C.c_double)), ("u_count", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libarlbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        sig = {
+            "arlbm_config_init": ([C.POINTER(Config)], C.c_int),
+            "arlbm_query_sizes": ([C.POINTER(Config), C.POINTER(Sizes)], C.c_int),
+            "arlbm_create": ([C.POINTER(Config), C.POINTER(Buffers), vp, C.POINTER(vp)], C.c_int),
+            "arlbm_set_state": ([vp, dp, dp, C.c_double], C.c_int),
+            "arlbm_set_state_device": ([vp, vp, vp, C.c_double], C.c_int),
+            "arlbm_step": ([vp, C.c_int64], C.c_int),
+            "arlbm_sync": ([vp, C.POINTER(Status)], C.c_int),
+            "arlbm_read_moments": ([vp, dp], C.c_int),
+            "arlbm_set_omega_export": ([vp, C.c_int], C.c_int),
+            "arlbm_read_omega": ([vp, dp], C.c_int),
+            "arlbm_conservation": ([vp, dp], C.c_int),
+            "arlbm_state_bytes": ([vp, C.POINTER(C.c_size_t)], C.c_int),
+            "arlbm_save_state": ([vp, vp, C.c_size_t], C.c_int),
+            "arlbm_load_state": ([vp, vp, C.c_size_t], C.c_int),
+            "arlbm_destroy": ([vp], C.c_int),
+            "arlbm_last_error": ([vp], C.c_char_p),
+            "arlbm_server_create": ([C.c_size_t, C.c_int32, vp, C.POINTER(vp)], C.c_int),
+            "arlbm_server_submit": ([vp, C.POINTER(Config), dp, dp, C.c_int64, C.POINTER(C.c_uint64)], C.c_int),
+            "arlbm_server_iterate": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+            "arlbm_server_poll": ([vp, C.POINTER(Completion), C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+            "arlbm_server_memory": ([vp, C.POINTER(C.c_size_t)], C.c_int),
+            "arlbm_server_destroy": ([vp], C.c_int),
+            "arlbm_step_kernel_vgprs": ([C.c_int32, C.c_int32, C.c_int32], C.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def last_error(handle=None) -> str:
+    s = lib().arlbm_last_error(handle)
+    return s.decode() if s else ""
+
+
+def _check(rc, handle=None):
+    if rc != OK:
+        raise ArlbmError(rc, last_error(handle))
+    return rc
+
+
+def _dptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def config_from(problem=None, precision=F32, omega_fixed=None, **over) -> Config:
+    """Build an arlbm_config from a workloads.Problem (or keywords)."""
+    c = Config()
+    _check(lib().arlbm_config_init(C.byref(c)))
+    if problem is not None:
+        c.system, c.dim = problem.system, problem.dim
+        c.nx, c.ny = problem.nx, (problem.ny if problem.dim == 2 else 1)
+        c.x0, c.x1, c.y0, c.y1 = problem.x0, problem.x1, problem.y0, problem.y1
+        for i in range(4):
+            c.bc[i] = problem.bc[i]
+        c.cfl, c.eps, c.gamma, c.g = problem.cfl, problem.eps, problem.gamma, problem.g
+        c.adv_speed[0], c.adv_speed[1] = problem.adv
+        c.has_bed = int(problem.bed is not None)
+    c.precision = precision
+    if omega_fixed is not None:
+        c.omega_mode, c.omega_fixed = OMEGA_FIXED, float(omega_fixed)
+    for k, v in over.items():
+        if k == "bc":
+            for i in range(4):
+                c.bc[i] = v[i]
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def query_sizes(cfg: Config) -> Sizes:
+    s = Sizes()
+    _check(lib().arlbm_query_sizes(C.byref(cfg), C.byref(s)))
+    return s
+
+
+class Lattice:
+    """One lattice on the GPU.
+
+    owner="torch": the device buffers are torch tensors (caller-owned, kept
+    alive here); owner="library": libarlbm allocates them.  The HIP stream is
+    torch's current stream unless one is given.
+    """
+
+    def __init__(self, cfg: Config, owner: str = "torch", stream=None):
+        import torch  # device memory and streams only
+
+        self.cfg = cfg
+        self.sizes = query_sizes(cfg)
+        self.m, self.q = self.sizes.m, self.sizes.q
+        self.dim, self.nx, self.ny = cfg.dim, cfg.nx, cfg.ny
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        raw_stream = C.c_void_p(stream.cuda_stream)
+        self._tensors = []
+        bufs = None
+        if owner == "torch":
+            def alloc(nbytes):
+                t = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device="cuda")
+                p = t.data_ptr()
+                off = (-p) % 256
+                self._tensors.append(t)
+                return p + off
+            b = Buffers()
+            for i in range(2):
+                b.f[i] = alloc(self.sizes.f_bytes)
+                b.u[i] = alloc(self.sizes.u_bytes)
+            b.bed = alloc(self.sizes.bed_bytes) if cfg.has_bed else None
+            b.scalars = alloc(self.sizes.scalar_bytes)
+            b.omega = None
+            bufs = C.byref(b)
+        h = C.c_void_p()
+        _check(lib().arlbm_create(C.byref(cfg), bufs, raw_stream, C.byref(h)))
+        self._h = h
+
+    # ------------------------------------------------------------------
+    def _shape(self, lead):
+        return (lead, self.ny, self.nx) if self.dim == 2 else (lead, self.nx)
+
+    def set_state(self, U0: np.ndarray, bed: Optional[np.ndarray] = None, t0: float = 0.0):
+        U0 = np.ascontiguousarray(U0, dtype=np.float64).reshape(self._shape(self.m))
+        bed = None if bed is None else np.ascontiguousarray(bed, dtype=np.float64)
+        _check(lib().arlbm_set_state(self._h, _dptr(U0), _dptr(bed), float(t0)), self._h)
+        return self
+
+    def set_state_device(self, U0_dev, bed_dev=None, t0: float = 0.0):
+        """U0_dev / bed_dev: float64 CUDA tensors (m planes / one plane)."""
+        _check(lib().arlbm_set_state_device(self._h, C.c_void_p(U0_dev.data_ptr()),
+                                            C.c_void_p(bed_dev.data_ptr()) if bed_dev is not None else None,
+                                            float(t0)), self._h)
+        return self
+
+    def step(self, n: int = 1):
+        _check(lib().arlbm_step(self._h, int(n)), self._h)
+
+    def sync(self, check: bool = True) -> dict:
+        st = Status()
+        rc = lib().arlbm_sync(self._h, C.byref(st))
+        if check:
+            _check(rc, self._h)
+        return {"rc": rc, "t": st.t, "last_dt": st.last_dt, "abar": [st.abar[0], st.abar[1]][: self.dim],
+                "step": st.step, "flags": st.flags, "first_bad_step": st.first_bad_step}
+
+    def moments(self) -> np.ndarray:
+        out = np.empty(self._shape(self.m))
+        _check(lib().arlbm_read_moments(self._h, _dptr(out)), self._h)
+        return out
+
+    def set_omega_export(self, on: bool = True):
+        _check(lib().arlbm_set_omega_export(self._h, int(bool(on))), self._h)
+
+    def omega(self) -> np.ndarray:
+        out = np.empty(self._shape(1)[1:])
+        _check(lib().arlbm_read_omega(self._h, _dptr(out)), self._h)
+        return out
+
+    def conservation(self) -> np.ndarray:
+        out = np.empty(self.m)
+        _check(lib().arlbm_conservation(self._h, _dptr(out)), self._h)
+        return out
+
+    def save_state(self) -> bytes:
+        n = C.c_size_t()
+        _check(lib().arlbm_state_bytes(self._h, C.byref(n)), self._h)
+        buf = C.create_string_buffer(n.value)
+        _check(lib().arlbm_save_state(self._h, buf, n.value), self._h)
+        return buf.raw
+
+    def load_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(lib().arlbm_load_state(self._h, buf, len(blob)), self._h)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().arlbm_destroy(h)
+            self._h = None
+        self._tensors = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server: resident lattices advance together, one
+    batched launch per iteration; admission is bounded by an HBM budget."""
+
+    def __init__(self, hbm_budget: int, precision: int = F32, stream=None):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib().arlbm_server_create(int(hbm_budget), precision, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def submit(self, cfg: Config, U0: np.ndarray, bed: Optional[np.ndarray], nsteps: int) -> int:
+        U0 = np.ascontiguousarray(U0, dtype=np.float64)
+        bed = None if bed is None else np.ascontiguousarray(bed, dtype=np.float64)
+        rid = C.c_uint64()
+        _check(lib().arlbm_server_submit(self._h, C.byref(cfg), _dptr(U0), _dptr(bed), int(nsteps), C.byref(rid)))
+        return rid.value
+
+    def iterate(self):
+        r, q = C.c_int32(), C.c_int32()
+        _check(lib().arlbm_server_iterate(self._h, C.byref(r), C.byref(q)))
+        return r.value, q.value
+
+    def poll(self, max_items: int = 64):
+        arr = (Completion * max_items)()
+        n = C.c_int32()
+        _check(lib().arlbm_server_poll(self._h, arr, max_items, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            c = arr[i]
+            U = np.ctypeslib.as_array(c.U, shape=(c.u_count,)).copy() if c.status == OK and c.u_count else None
+            out.append({"id": c.id, "status": c.status, "steps": c.steps, "t": c.t, "submit_s": c.submit_s,
+                        "admit_s": c.admit_s, "done_s": c.done_s, "U": U})
+        return out
+
+    def memory(self) -> int:
+        b = C.c_size_t()
+        _check(lib().arlbm_server_memory(self._h, C.byref(b)))
+        return b.value
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().arlbm_server_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def step_kernel_vgprs(precision: int, system: int, dim: int) -> int:
+    return lib().arlbm_step_kernel_vgprs(precision, system, dim)

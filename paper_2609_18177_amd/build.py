@@ -1,0 +1,48 @@
+"""Build libarlbm.so in-tree for gfx950 with hipcc.
+
+The kernel source is compiled twice: FP32 (contraction allowed) and FP64
+(-ffp-contract=off, so every rounding follows the written expression order).
+All device code is built with packed-FP32 instructions disabled.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "csrc")
+OUT = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libarlbm.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+DEVICE_FLAGS = ["-std=c++17", "-O3", f"--offload-arch={ARCH}", "-fPIC",
+                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source and link the shared library (always rebuilds)."""
+    os.makedirs(OUT, exist_ok=True)
+    k32 = os.path.join(OUT, "kernels_f32.o")
+    k64 = os.path.join(OUT, "kernels_f64.o")
+    rt = os.path.join(OUT, "runtime.o")
+    kern = os.path.join(SRC, "kernels.hip")
+    _run([HIPCC, *DEVICE_FLAGS, "-DARLBM_F64=0", "-c", kern, "-o", k32], verbose)
+    _run([HIPCC, *DEVICE_FLAGS, "-DARLBM_F64=1", "-ffp-contract=off", "-c", kern, "-o", k64], verbose)
+    _run([HIPCC, "-std=c++17", "-O2", "-fPIC", "-Wall", "-x", "c++", "-D__HIP_PLATFORM_AMD__",
+          "-I/opt/rocm/include", "-c", os.path.join(SRC, "runtime.cpp"), "-o", rt], verbose)
+    tmp = LIB + ".tmp"
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, k32, k64, rt], verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

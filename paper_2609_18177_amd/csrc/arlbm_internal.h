@@ -1,0 +1,87 @@
+// Internal types shared by the HIP kernels and the host runtime of libarlbm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace arlbm {
+
+// Cells produced per wave along x: a wave of 64 lanes covers x0-3 .. x0+60,
+// the 3-cell halo on each side feeds the radius-2 indicator stencil and the
+// radius-1 pull (omega is needed one cell beyond the outputs).
+constexpr int kWave = 64;
+constexpr int kHalo = 3;
+constexpr int kOutW = kWave - 2 * kHalo;  // 58
+constexpr int kBlock = 256;               // 4 independent waves per block
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+enum Variant : int32_t { V_ADV1 = 0, V_EUL1 = 1, V_SWE1 = 2, V_ADV2 = 3, V_EUL2 = 4, V_SWE2 = 5 };
+
+__host__ __device__ constexpr int variant_of(int system, int dim) { return (dim == 2 ? 3 : 0) + system; }
+__host__ __device__ constexpr int num_fields(int system, int dim) {
+    return system == 0 ? 1 : (system == 1 ? dim + 2 : dim + 1);
+}
+
+// Per-lattice device scalars (FP64), kept resident between launches.
+struct DevScalars {
+    // alpha_bar bit patterns (non-negative doubles order like unsigned
+    // integers, so the grid-wide max is an integer atomic max).  Three slots:
+    // step n reads slot n%3, maxes into (n+1)%3 and clears (n+2)%3.
+    unsigned long long abar[3][2];
+    double t;
+    double last_dt;
+    unsigned long long first_bad_step;  // min over flagged steps (~0 = none)
+    unsigned int flags;
+    unsigned int pad;
+    double reserved[6];
+};
+static_assert(sizeof(DevScalars) == 128, "DevScalars layout");
+
+// Everything a kernel needs to know about one lattice.  Uploaded once at
+// creation (and at admission in the server); the step index is derived from
+// the launch's iteration counter: n = iter - iter0.
+struct LatticeDesc {
+    void *f[2];
+    void *u[2];
+    const void *bed;
+    void *omega;
+    DevScalars *sc;
+    int32_t variant, nx, ny, bc[4];
+    int32_t omega_fixed_on;
+    int32_t band_h;       // rows per strip (2D)
+    int32_t ncols;        // strips along x
+    int64_t iter0;
+    int64_t plane;        // nx * ny
+    double dx, cfl, eps, gamma, g, adv[2], h_dry, rho_floor, p_floor, omega_fixed;
+};
+
+// One wave's work item in a batched launch.
+struct WorkItem {
+    int32_t lattice;
+    int32_t col;
+    int32_t band;
+    int32_t first;  // 1 for the item that updates the lattice's scalars
+};
+
+}  // namespace arlbm
+
+// Host-side launchers, implemented once per precision (kernels.hip is
+// compiled twice: FP32 with contraction, FP64 without).
+#define ARLBM_DECLARE_LAUNCHERS(NS)                                                                    \
+    namespace arlbm {                                                                                  \
+    namespace NS {                                                                                     \
+    hipError_t reduce_abar(const LatticeDesc &h, const double *U0, int slot, hipStream_t s);          \
+    hipError_t init(const LatticeDesc &h, const double *U0, const double *bed64, int slot_in,         \
+                    hipStream_t s);                                                                    \
+    hipError_t step_single(const LatticeDesc &h, int64_t iter, hipStream_t s);                        \
+    hipError_t step_batched(const LatticeDesc *d_descs, const WorkItem *d_items, int32_t nitems,      \
+                            int64_t iter, hipStream_t s);                                              \
+    hipError_t conservation(const void *u, int64_t plane, int m, double *partial, int nblocks,        \
+                            hipStream_t s);                                                            \
+    hipError_t to_double(const void *src, double *dst, int64_t n, hipStream_t s);                     \
+    int step_kernel_vgprs(int variant);                                                                \
+    }                                                                                                  \
+    }
+
+ARLBM_DECLARE_LAUNCHERS(f32)
+ARLBM_DECLARE_LAUNCHERS(f64)

@@ -1,0 +1,129 @@
+// Kernel instantiations and launchers for one storage precision.  Built twice
+// by the package's build step: -DARLBM_F64=0 (float, contraction allowed) and
+// -DARLBM_F64=1 (double, -ffp-contract=off so every rounding matches the
+// written expression order).
+#include "arlbm_internal.h"
+#include "step.hpp"
+
+#if ARLBM_F64
+#define ARLBM_NS f64
+typedef double real;
+#else
+#define ARLBM_NS f32
+typedef float real;
+#endif
+
+namespace arlbm {
+namespace ARLBM_NS {
+
+static int grid_for(int64_t items, int per_block)
+{
+    int64_t b = (items + per_block - 1) / per_block;
+    b = (b + 7) / 8 * 8;  // multiple of 8: the XCD-aware remap is a bijection
+    return (int)(b < 8 ? 8 : b);
+}
+
+static int cell_grid(int64_t cells)
+{
+    int64_t b = (cells + kBlock - 1) / kBlock;
+    return (int)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
+}
+
+template <int SYS, int D>
+static hipError_t reduce_impl(const LatticeDesc &h, const double *U0, int slot, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_reduce_abar<SYS, D, real>), dim3(cell_grid(h.plane)), dim3(kBlock), 0, s, h, U0, slot);
+    return hipGetLastError();
+}
+
+template <int SYS, int D>
+static hipError_t init_impl(const LatticeDesc &h, const double *U0, const double *bed64, int slot_in,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL((k_init<SYS, D, real>), dim3(cell_grid(h.plane)), dim3(kBlock), 0, s, h, U0, bed64,
+                       slot_in);
+    return hipGetLastError();
+}
+
+template <int SYS, int D>
+static hipError_t step_impl(const LatticeDesc &h, int64_t iter, hipStream_t s)
+{
+    const int64_t nbands = D == 2 ? (h.ny + h.band_h - 1) / h.band_h : 1;
+    const int64_t nwork = (int64_t)h.ncols * nbands;
+    hipLaunchKernelGGL((k_step_single<SYS, D, real>), dim3(grid_for(nwork, kWavesPerBlock)), dim3(kBlock), 0, s,
+                       h, iter, (int32_t)nwork);
+    return hipGetLastError();
+}
+
+#define ARLBM_DISPATCH(v, CALL)                  \
+    switch (v) {                                 \
+    case V_ADV1: return CALL(0, 1);              \
+    case V_EUL1: return CALL(1, 1);              \
+    case V_SWE1: return CALL(2, 1);              \
+    case V_ADV2: return CALL(0, 2);              \
+    case V_EUL2: return CALL(1, 2);              \
+    case V_SWE2: return CALL(2, 2);              \
+    default: return hipErrorInvalidValue;        \
+    }
+
+hipError_t reduce_abar(const LatticeDesc &h, const double *U0, int slot, hipStream_t s)
+{
+#define C_(S, D) reduce_impl<S, D>(h, U0, slot, s)
+    ARLBM_DISPATCH(h.variant, C_)
+#undef C_
+}
+
+hipError_t init(const LatticeDesc &h, const double *U0, const double *bed64, int slot_in, hipStream_t s)
+{
+#define C_(S, D) init_impl<S, D>(h, U0, bed64, slot_in, s)
+    ARLBM_DISPATCH(h.variant, C_)
+#undef C_
+}
+
+hipError_t step_single(const LatticeDesc &h, int64_t iter, hipStream_t s)
+{
+#define C_(S, D) step_impl<S, D>(h, iter, s)
+    ARLBM_DISPATCH(h.variant, C_)
+#undef C_
+}
+
+hipError_t step_batched(const LatticeDesc *d_descs, const WorkItem *d_items, int32_t nitems, int64_t iter,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL((k_step_batched<real>), dim3(grid_for(nitems, kWavesPerBlock)), dim3(kBlock), 0, s,
+                       d_descs, d_items, nitems, iter);
+    return hipGetLastError();
+}
+
+hipError_t conservation(const void *u, int64_t plane, int m, double *partial, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_conservation<real>), dim3(nblocks), dim3(kBlock), 0, s, (const real *)u, plane, m,
+                       partial);
+    return hipGetLastError();
+}
+
+hipError_t to_double(const void *src, double *dst, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_to_double<real>), dim3(cell_grid(n)), dim3(kBlock), 0, s, (const real *)src, dst, n);
+    return hipGetLastError();
+}
+
+int step_kernel_vgprs(int variant)
+{
+    hipFuncAttributes a;
+    const void *fn = nullptr;
+    switch (variant) {
+    case V_ADV1: fn = (const void *)&k_step_single<0, 1, real>; break;
+    case V_EUL1: fn = (const void *)&k_step_single<1, 1, real>; break;
+    case V_SWE1: fn = (const void *)&k_step_single<2, 1, real>; break;
+    case V_ADV2: fn = (const void *)&k_step_single<0, 2, real>; break;
+    case V_EUL2: fn = (const void *)&k_step_single<1, 2, real>; break;
+    case V_SWE2: fn = (const void *)&k_step_single<2, 2, real>; break;
+    default: return -1;
+    }
+    if (hipFuncGetAttributes(&a, fn) != hipSuccess) return -1;
+    return a.numRegs;
+}
+
+}  // namespace ARLBM_NS
+}  // namespace arlbm

@@ -1,0 +1,231 @@
+// Per-cell physics of the three balance laws on the device: primitive
+// variables, physical fluxes F_j(U), the eigenvalue bound max_r |lambda_j^(r)|
+// and the characteristic projections L_j(U_i)(U_a - U_b) entering the
+// smoothness indicator (eqs. 2.13-2.14).
+//
+// Operation order.  In the FP64 build (compiled without contraction) every
+// expression keeps the association written here, which follows the textbook
+// forms: p = (gamma-1)(E - (rho/2)|u|^2), c = sqrt(gamma p / rho),
+// b1 = (gamma-1)/(c c), b2 = (|u|^2/2) b1, left eigenvectors L = R^{-1} for
+// right eigenvectors whose acoustic and entropy columns start with 1 and whose
+// shear column is the unit tangential momentum.  Matrix-vector products sum
+// their non-zero terms in column order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace arlbm {
+
+template <typename T>
+struct Phys {
+    T gamma, gm1, g, half_g, adv[2], dx, p_floor_t, rho_floor_t, h_dry_t;
+    double h_dry, rho_floor, p_floor;
+};
+
+template <typename T>
+__device__ __forceinline__ T dsqrt(T v);
+template <>
+__device__ __forceinline__ double dsqrt<double>(double v) { return __builtin_sqrt(v); }
+template <>
+__device__ __forceinline__ float dsqrt<float>(float v) { return __builtin_sqrtf(v); }
+
+template <typename T>
+__device__ __forceinline__ T dabs(T v) { return __builtin_fabs(v); }
+template <>
+__device__ __forceinline__ float dabs<float>(float v) { return __builtin_fabsf(v); }
+
+template <int SYS, int D>
+struct SysInfo {
+    static constexpr int M = SYS == 0 ? 1 : (SYS == 1 ? D + 2 : D + 1);
+    static constexpr int Q = 2 * D + 1;
+};
+
+template <typename T>
+struct Prim {
+    T rho, E, p, c, cL;
+    T vel[2], mom[2];
+    unsigned flags;
+};
+
+// Primitive variables.  Euler: floors enter only the sound speed (a state at
+// or below a floor raises the positivity flag).  Shallow water: a cell with
+// h <= h_dry (FP64 compare) has zero velocity and momentum flux and the
+// acoustic speed in L uses max(h, h_dry); depths within h_dry of zero are dry,
+// so only h < -h_dry raises the positivity flag.
+template <int SYS, int D, typename T>
+__device__ __forceinline__ void primitives(const T *U, const Phys<T> &P, Prim<T> &q)
+{
+    q.flags = 0;
+    q.vel[1] = T(0);
+    q.mom[1] = T(0);
+    if constexpr (SYS == 1) {
+        q.rho = U[0];
+        q.E = U[D + 1];
+        q.mom[0] = U[1];
+        q.vel[0] = U[1] / q.rho;
+        T q2;
+        if constexpr (D == 2) {
+            q.mom[1] = U[2];
+            q.vel[1] = U[2] / q.rho;
+            q2 = q.vel[0] * q.vel[0] + q.vel[1] * q.vel[1];
+        } else {
+            q2 = q.vel[0] * q.vel[0];
+        }
+        q.p = P.gm1 * (q.E - T(0.5) * q.rho * q2);
+        const bool pok = double(q.p) > P.p_floor, rok = double(q.rho) > P.rho_floor;
+        const T pf = pok ? q.p : P.p_floor_t;
+        const T rf = rok ? q.rho : P.rho_floor_t;
+        if (!(pok && rok)) q.flags |= 2u;
+        q.c = dsqrt<T>(P.gamma * pf / rf);
+        q.cL = q.c;
+    } else if constexpr (SYS == 2) {
+        const T h = U[0];
+        q.rho = h;
+        const bool wet = double(h) > P.h_dry;
+        q.mom[0] = wet ? U[1] : T(0);
+        q.vel[0] = wet ? U[1] / h : T(0);
+        if constexpr (D == 2) {
+            q.mom[1] = wet ? U[2] : T(0);
+            q.vel[1] = wet ? U[2] / h : T(0);
+        }
+        if (double(h) < -P.h_dry) q.flags |= 2u;
+        q.c = dsqrt<T>(P.g * (h > T(0) ? h : T(0)));
+        q.cL = dsqrt<T>(P.g * (wet ? h : P.h_dry_t));
+        q.E = q.p = T(0);
+    } else {
+        q.rho = U[0];
+        q.E = q.p = q.c = q.cL = T(0);
+        q.vel[0] = q.mom[0] = T(0);
+    }
+}
+
+// Physical flux F_dir(U) (Section 5 systems).
+template <int SYS, int D, typename T>
+__device__ __forceinline__ void flux(int dir, const T *U, const Prim<T> &q, const Phys<T> &P, T *F)
+{
+    if constexpr (SYS == 0) {
+        F[0] = P.adv[dir] * U[0];
+    } else if constexpr (SYS == 1) {
+        const T md = q.mom[dir], vd = q.vel[dir];
+        F[0] = md;
+#pragma unroll
+        for (int i = 0; i < D; ++i) F[1 + i] = (i == dir) ? md * q.vel[i] + q.p : md * q.vel[i];
+        F[D + 1] = vd * (q.E + q.p);
+    } else {
+        const T md = q.mom[dir];
+        const T ph = P.half_g * q.rho * q.rho;
+        F[0] = md;
+#pragma unroll
+        for (int i = 0; i < D; ++i) F[1 + i] = (i == dir) ? md * q.vel[i] + ph : md * q.vel[i];
+    }
+}
+
+// max_r |lambda_dir^(r)(U)| of eq. (2.19).
+template <int SYS, typename T>
+__device__ __forceinline__ T max_speed(int dir, const Prim<T> &q, const Phys<T> &P)
+{
+    if constexpr (SYS == 0) return dabs<T>(P.adv[dir]);
+    else return dabs<T>(q.vel[dir]) + q.c;
+}
+
+// Indicator of eq. (2.13) for one field: |dp - dm| / (|dm| + |dp| + dx) + |dm| + |dp|.
+template <typename T>
+__device__ __forceinline__ T theta(T dm, T dp, T dx)
+{
+    const T adm = dabs<T>(dm), adp = dabs<T>(dp);
+    return dabs<T>(dp - dm) / (adm + adp + dx) + adm + adp;
+}
+
+// Adds sum_r theta^(r,dir) to nu, with L_dir evaluated at the centre state
+// (primitives qc), backward difference dU- = Uc - Um and forward dU+ = Up - Uc.
+template <int SYS, int D, typename T>
+__device__ __forceinline__ void add_theta(int dir, const Prim<T> &qc, const T *Uc, const T *Um,
+                                          const T *Up, const Phys<T> &P, T &nu)
+{
+    constexpr int M = SysInfo<SYS, D>::M;
+    T a[M], b[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        a[c] = Uc[c] - Um[c];
+        b[c] = Up[c] - Uc[c];
+    }
+    const T dx = P.dx;
+    if constexpr (SYS == 0) {
+        nu = nu + theta<T>(a[0], b[0], dx);
+    } else if constexpr (SYS == 1) {
+        const T cs = qc.c;
+        T q2;
+        if constexpr (D == 2) q2 = qc.vel[0] * qc.vel[0] + qc.vel[1] * qc.vel[1];
+        else q2 = qc.vel[0] * qc.vel[0];
+        const T b1 = P.gm1 / (cs * cs);
+        const T b2 = T(0.5) * q2 * b1;
+        const T un = qc.vel[dir];
+        const T r0c0 = T(0.5) * (b2 + un / cs);
+        const T r0cn = T(-0.5) * (b1 * un + T(1) / cs);
+        const T r3c0 = T(0.5) * (b2 - un / cs);
+        const T r3cn = T(-0.5) * (b1 * un - T(1) / cs);
+        const T hb1 = T(0.5) * b1;
+        const T r1c0 = T(1) - b2;
+        if constexpr (D == 1) {
+            const T r1c1 = b1 * qc.vel[0];
+            // rows: u-c, u (entropy), u+c; columns: rho, rho u, E
+            const T dm0 = r0c0 * a[0] + r0cn * a[1] + hb1 * a[2];
+            const T dp0 = r0c0 * b[0] + r0cn * b[1] + hb1 * b[2];
+            const T dm1 = r1c0 * a[0] + r1c1 * a[1] + (-b1) * a[2];
+            const T dp1 = r1c0 * b[0] + r1c1 * b[1] + (-b1) * b[2];
+            const T dm2 = r3c0 * a[0] + r3cn * a[1] + hb1 * a[2];
+            const T dp2 = r3c0 * b[0] + r3cn * b[1] + hb1 * b[2];
+            nu = nu + theta<T>(dm0, dp0, dx);
+            nu = nu + theta<T>(dm1, dp1, dx);
+            nu = nu + theta<T>(dm2, dp2, dx);
+        } else {
+            const int t = 1 - dir;
+            const T vt = qc.vel[t];
+            const T r0ct = T(-0.5) * b1 * vt;  // tangential-momentum column of the acoustic rows
+            const T r1c1 = b1 * qc.vel[0], r1c2 = b1 * qc.vel[1];
+            // acoustic rows: column 1 is normal for dir 0, tangential for dir 1
+            const T r0c1 = dir == 0 ? r0cn : r0ct, r0c2 = dir == 0 ? r0ct : r0cn;
+            const T r3c1 = dir == 0 ? r3cn : r0ct, r3c2 = dir == 0 ? r0ct : r3cn;
+            const T dm0 = r0c0 * a[0] + r0c1 * a[1] + r0c2 * a[2] + hb1 * a[3];
+            const T dp0 = r0c0 * b[0] + r0c1 * b[1] + r0c2 * b[2] + hb1 * b[3];
+            const T dm1 = r1c0 * a[0] + r1c1 * a[1] + r1c2 * a[2] + (-b1) * a[3];
+            const T dp1 = r1c0 * b[0] + r1c1 * b[1] + r1c2 * b[2] + (-b1) * b[3];
+            // shear row: -v_t rho + (rho v_t)
+            const T at = dir == 0 ? a[2] : a[1], bt = dir == 0 ? b[2] : b[1];
+            const T dm2 = (-vt) * a[0] + at;
+            const T dp2 = (-vt) * b[0] + bt;
+            const T dm3 = r3c0 * a[0] + r3c1 * a[1] + r3c2 * a[2] + hb1 * a[3];
+            const T dp3 = r3c0 * b[0] + r3c1 * b[1] + r3c2 * b[2] + hb1 * b[3];
+            nu = nu + theta<T>(dm0, dp0, dx);
+            nu = nu + theta<T>(dm1, dp1, dx);
+            nu = nu + theta<T>(dm2, dp2, dx);
+            nu = nu + theta<T>(dm3, dp3, dx);
+        }
+    } else {
+        const T cs = qc.cL;
+        const T un = qc.vel[dir];
+        const T l00 = (un + cs) / (T(2) * cs);
+        const T l0n = T(-1) / (T(2) * cs);
+        const T l20 = (-(un - cs)) / (T(2) * cs);
+        const T l2n = T(1) / (T(2) * cs);
+        const T an = a[1 + dir], bn = b[1 + dir];
+        const T dm0 = l00 * a[0] + l0n * an;
+        const T dp0 = l00 * b[0] + l0n * bn;
+        const T dm2 = l20 * a[0] + l2n * an;
+        const T dp2 = l20 * b[0] + l2n * bn;
+        if constexpr (D == 1) {
+            nu = nu + theta<T>(dm0, dp0, dx);
+            nu = nu + theta<T>(dm2, dp2, dx);
+        } else {
+            const int t = 1 - dir;
+            const T vt = qc.vel[t];
+            const T dm1 = (-vt) * a[0] + a[1 + t];
+            const T dp1 = (-vt) * b[0] + b[1 + t];
+            nu = nu + theta<T>(dm0, dp0, dx);
+            nu = nu + theta<T>(dm1, dp1, dx);
+            nu = nu + theta<T>(dm2, dp2, dx);
+        }
+    }
+}
+
+}  // namespace arlbm

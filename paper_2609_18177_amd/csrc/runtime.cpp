@@ -1,0 +1,809 @@
+// Host runtime of libarlbm: the C ABI declared in include/arlbm.h.
+//
+// A lattice owns (or borrows) two population buffers and two moment buffers
+// (ping-pong), an optional bed plane, an optional omega plane and a 128-byte
+// block of device scalars.  Stepping enqueues one fused kernel per step on the
+// handle's stream; the host never reads the device between steps.  The server
+// keeps many lattices resident and advances all of them with one batched
+// launch per iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "../../include/arlbm.h"
+#include "arlbm_internal.h"
+
+using namespace arlbm;
+
+namespace {
+
+thread_local std::string g_thread_err;
+
+constexpr size_t kAlign = 256;
+constexpr int kConsBlocks = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+int q_of(int dim) { return 2 * dim + 1; }
+
+// Validation of a configuration; returns an empty string when valid.
+std::string check_config(const arlbm_config *c)
+{
+    if (!c) return "config is NULL";
+    if (c->abi_version != ARLBM_ABI_VERSION) return "abi_version mismatch";
+    if (c->system < 0 || c->system > 2) return "unknown system";
+    if (c->dim != 1 && c->dim != 2) return "dim must be 1 or 2";
+    if (c->precision != ARLBM_F32 && c->precision != ARLBM_F64) return "precision must be F32 or F64";
+    if (c->nx < 4) return "nx must be >= 4";
+    if (c->dim == 1 && c->ny != 1) return "ny must be 1 in 1D";
+    if (c->dim == 2 && c->ny < 4) return "ny must be >= 4";
+    if (c->nx > (1 << 26) || c->ny > (1 << 26) || c->nx * c->ny > ((int64_t)1 << 34)) return "lattice too large";
+    if (!(c->x1 > c->x0)) return "x1 must exceed x0";
+    if (c->dim == 2) {
+        if (!(c->y1 > c->y0)) return "y1 must exceed y0";
+        const double dx = (c->x1 - c->x0) / (double)c->nx, dy = (c->y1 - c->y0) / (double)c->ny;
+        if (std::fabs(dx - dy) > 1e-12 * dx) return "dx must equal dy (uniform lattice)";
+    }
+    for (int s = 0; s < 2 * c->dim; ++s)
+        if (c->bc[s] < 0 || c->bc[s] > 2) return "unknown boundary condition";
+    for (int a = 0; a < c->dim; ++a)
+        if ((c->bc[2 * a] == ARLBM_PERIODIC) != (c->bc[2 * a + 1] == ARLBM_PERIODIC))
+            return "periodic boundaries must be paired on an axis";
+    if (c->system == ARLBM_ADVECTION)
+        for (int s = 0; s < 2 * c->dim; ++s)
+            if (c->bc[s] == ARLBM_REFLECTIVE) return "reflective walls need a momentum field (not advection)";
+    if (!(c->cfl > 0.0 && c->cfl < 1.0)) return "CFL must lie in (0, 1)";
+    if (!(c->eps > 0.0)) return "eps must be > 0";
+    if (c->system == ARLBM_EULER && !(c->gamma > 1.0)) return "gamma must be > 1";
+    if (c->system == ARLBM_SWE && !(c->g > 0.0)) return "g must be > 0";
+    if (c->system == ARLBM_SWE && !(c->h_dry > 0.0)) return "h_dry must be > 0";
+    if (c->system == ARLBM_EULER && !(c->rho_floor > 0.0 && c->p_floor > 0.0)) return "floors must be > 0";
+    if (c->has_bed && c->system != ARLBM_SWE) return "a bed source needs shallow water";
+    if (c->system == ARLBM_ADVECTION) {
+        double s = std::fabs(c->adv_speed[0]) + (c->dim == 2 ? std::fabs(c->adv_speed[1]) : 0.0);
+        if (!(s > 0.0)) return "advection speed must be non-zero";
+    }
+    if (c->omega_mode != ARLBM_OMEGA_ADAPTIVE && c->omega_mode != ARLBM_OMEGA_FIXED) return "unknown omega mode";
+    if (c->omega_mode == ARLBM_OMEGA_FIXED && !(c->omega_fixed > 0.0 && c->omega_fixed <= 2.0))
+        return "omega_fixed must lie in (0, 2]";
+    return "";
+}
+
+void fill_sizes(const arlbm_config *c, arlbm_sizes *o)
+{
+    const int m = num_fields(c->system, c->dim), q = q_of(c->dim);
+    const size_t s = c->precision == ARLBM_F64 ? 8 : 4;
+    const size_t plane = (size_t)c->nx * (size_t)c->ny;
+    o->m = m;
+    o->q = q;
+    o->f_bytes = align_up((size_t)q * m * plane * s);
+    o->u_bytes = align_up((size_t)m * plane * s);
+    o->bed_bytes = c->has_bed ? align_up(plane * s) : 0;
+    o->scalar_bytes = align_up(sizeof(DevScalars));
+    o->omega_bytes = align_up(plane * s);
+    o->total_bytes = 2 * o->f_bytes + 2 * o->u_bytes + o->bed_bytes + o->scalar_bytes;
+    o->alignment = kAlign;
+}
+
+// Rows per strip: long strips amortise the 3-row warm-up; shorter ones give
+// enough waves to fill 256 CUs.
+int choose_band(int64_t ny, int ncols)
+{
+    int h = 64;
+    while (h > 16 && (int64_t)ncols * ((ny + h - 1) / h) < 4096) h /= 2;
+    return h;
+}
+
+}  // namespace
+
+struct arlbm_lattice {
+    arlbm_config cfg{};
+    arlbm_sizes sz{};
+    LatticeDesc desc{};
+    hipStream_t stream = nullptr;
+    bool owns = false;
+    bool owns_omega = false;
+    bool busy = false;
+    int64_t step = 0;
+    double *d_partial = nullptr;
+    std::string err;
+};
+
+namespace {
+
+int fail(arlbm_lattice *h, int code, const std::string &msg)
+{
+    if (h) h->err = msg;
+    g_thread_err = msg;
+    return code;
+}
+
+int hip_fail(arlbm_lattice *h, hipError_t e, const char *what)
+{
+    return fail(h, e == hipErrorOutOfMemory ? ARLBM_ENOMEM : ARLBM_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(h, call)                                    \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail(h, e_, #call); \
+    } while (0)
+
+bool is_f64(const arlbm_lattice *h) { return h->cfg.precision == ARLBM_F64; }
+
+hipError_t L_reduce(const arlbm_lattice *h, const double *U0, int slot)
+{
+    return is_f64(h) ? f64::reduce_abar(h->desc, U0, slot, h->stream) : f32::reduce_abar(h->desc, U0, slot, h->stream);
+}
+hipError_t L_init(const arlbm_lattice *h, const double *U0, const double *bed, int slot)
+{
+    return is_f64(h) ? f64::init(h->desc, U0, bed, slot, h->stream) : f32::init(h->desc, U0, bed, slot, h->stream);
+}
+hipError_t L_step(const arlbm_lattice *h, int64_t iter)
+{
+    return is_f64(h) ? f64::step_single(h->desc, iter, h->stream) : f32::step_single(h->desc, iter, h->stream);
+}
+
+void free_owned(arlbm_lattice *h)
+{
+    if (h->owns) {
+        for (int i = 0; i < 2; ++i) {
+            if (h->desc.f[i]) (void)hipFree(h->desc.f[i]);
+            if (h->desc.u[i]) (void)hipFree(h->desc.u[i]);
+        }
+        if (h->desc.bed) (void)hipFree((void *)h->desc.bed);
+        if (h->desc.sc) (void)hipFree(h->desc.sc);
+    }
+    if (h->owns_omega && h->desc.omega) (void)hipFree(h->desc.omega);
+    if (h->d_partial) (void)hipFree(h->d_partial);
+}
+
+// Host-side admissibility of an initial state (finite, rho > 0, p > 0, h >= 0).
+int check_state(arlbm_lattice *h, const double *U0, const double *bed)
+{
+    const arlbm_config &c = h->cfg;
+    const int64_t plane = h->desc.plane;
+    const int m = h->sz.m;
+    for (int64_t i = 0; i < (int64_t)m * plane; ++i)
+        if (!std::isfinite(U0[i])) return fail(h, ARLBM_EPOSITIVITY, "initial state is not finite");
+    if (bed)
+        for (int64_t i = 0; i < plane; ++i)
+            if (!std::isfinite(bed[i])) return fail(h, ARLBM_EPOSITIVITY, "bed is not finite");
+    if (c.system == ARLBM_EULER) {
+        for (int64_t i = 0; i < plane; ++i) {
+            const double rho = U0[i];
+            double ke = 0.0;
+            for (int d = 0; d < c.dim; ++d) {
+                const double mom = U0[(1 + d) * plane + i];
+                ke += 0.5 * mom * mom / rho;
+            }
+            const double p = (c.gamma - 1.0) * (U0[(m - 1) * plane + i] - ke);
+            if (!(rho > 0.0)) return fail(h, ARLBM_EPOSITIVITY, "initial density must be > 0");
+            if (!(p > 0.0)) return fail(h, ARLBM_EPOSITIVITY, "initial pressure must be > 0");
+        }
+    } else if (c.system == ARLBM_SWE) {
+        for (int64_t i = 0; i < plane; ++i)
+            if (!(U0[i] >= 0.0)) return fail(h, ARLBM_EPOSITIVITY, "initial depth must be >= 0");
+    }
+    return ARLBM_OK;
+}
+
+int read_scalars(arlbm_lattice *h, DevScalars *out)
+{
+    HIPCHK(h, hipMemcpyAsync(out, h->desc.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return ARLBM_OK;
+}
+
+// Device-side staging of the initial state into f[1] (free before step 0).
+int set_state_impl(arlbm_lattice *h, const double *U0, const double *bed, bool on_device, double t0)
+{
+    if (h->busy) return fail(h, ARLBM_EBUSY, "lattice is owned by a server");
+    const int64_t plane = h->desc.plane;
+    const int m = h->sz.m;
+    const bool need_bed = h->cfg.has_bed != 0;
+    if (!U0) return fail(h, ARLBM_EINVAL, "U0 is NULL");
+    if (need_bed && !bed) return fail(h, ARLBM_EINVAL, "configuration has a bed but bed is NULL");
+    double *stage = (double *)h->desc.f[1];
+    double *U0d = stage;
+    double *bedd = need_bed ? stage + (size_t)m * plane : nullptr;
+    if (on_device) {
+        HIPCHK(h, hipMemcpyAsync(U0d, U0, sizeof(double) * m * plane, hipMemcpyDeviceToDevice, h->stream));
+        if (need_bed)
+            HIPCHK(h, hipMemcpyAsync(bedd, bed, sizeof(double) * plane, hipMemcpyDeviceToDevice, h->stream));
+    } else {
+        int rc = check_state(h, U0, need_bed ? bed : nullptr);
+        if (rc) return rc;
+        HIPCHK(h, hipMemcpyAsync(U0d, U0, sizeof(double) * m * plane, hipMemcpyHostToDevice, h->stream));
+        if (need_bed)
+            HIPCHK(h, hipMemcpyAsync(bedd, bed, sizeof(double) * plane, hipMemcpyHostToDevice, h->stream));
+    }
+    DevScalars sc{};
+    sc.t = t0;
+    sc.first_bad_step = ~0ull;
+    HIPCHK(h, hipMemcpyAsync(h->desc.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, L_reduce(h, U0d, 2));
+    HIPCHK(h, L_init(h, U0d, bedd, 2));
+    DevScalars got{};
+    int rc = read_scalars(h, &got);
+    if (rc) return rc;
+    h->step = 0;
+    const double ab0 = *(double *)&got.abar[0][0];
+    const double ab1 = h->cfg.dim == 2 ? *(double *)&got.abar[0][1] : 0.0;
+    const double sa = ab0 + ab1;
+    if (!(sa > 0.0)) return fail(h, ARLBM_EDEGENERATE, "sum of wave-speed bounds is zero: time step undefined");
+    // Theorem 4.3: 0 < eps < (1/d)(1/CFL - 1) sum_j alpha_bar_j
+    const double bound = (1.0 / h->cfg.dim) * (1.0 / h->cfg.cfl - 1.0) * sa;
+    if (!(h->cfg.eps < bound)) return fail(h, ARLBM_EINVAL, "eps exceeds the stability bound of Theorem 4.3");
+    return ARLBM_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------
+// Single lattice
+// ------------------------------------------------------------------------
+
+extern "C" int arlbm_config_init(arlbm_config *c)
+{
+    if (!c) return ARLBM_EINVAL;
+    std::memset(c, 0, sizeof(*c));
+    c->abi_version = ARLBM_ABI_VERSION;
+    c->system = ARLBM_EULER;
+    c->dim = 1;
+    c->precision = ARLBM_F32;
+    c->nx = 64;
+    c->ny = 1;
+    c->x0 = 0.0;
+    c->x1 = 1.0;
+    c->y0 = 0.0;
+    c->y1 = 1.0;
+    for (int i = 0; i < 4; ++i) c->bc[i] = ARLBM_TRANSMISSIVE;
+    c->cfl = 0.5;
+    c->eps = 1e-10;
+    c->gamma = 1.4;
+    c->g = 9.81;
+    c->adv_speed[0] = 1.0;
+    c->adv_speed[1] = 0.0;
+    c->h_dry = 1e-6;
+    c->rho_floor = 1e-12;
+    c->p_floor = 1e-12;
+    c->has_bed = 0;
+    c->omega_mode = ARLBM_OMEGA_ADAPTIVE;
+    c->omega_fixed = 2.0;
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_query_sizes(const arlbm_config *cfg, arlbm_sizes *out)
+{
+    std::string e = check_config(cfg);
+    if (!e.empty()) return fail(nullptr, ARLBM_EINVAL, e);
+    if (!out) return fail(nullptr, ARLBM_EINVAL, "out is NULL");
+    fill_sizes(cfg, out);
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, void *stream, arlbm_lattice **out)
+{
+    if (!out) return fail(nullptr, ARLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::string e = check_config(cfg);
+    if (!e.empty()) return fail(nullptr, ARLBM_EINVAL, e);
+    arlbm_lattice *h = new arlbm_lattice();
+    h->cfg = *cfg;
+    fill_sizes(cfg, &h->sz);
+    h->stream = (hipStream_t)stream;
+    LatticeDesc &d = h->desc;
+    d.variant = variant_of(cfg->system, cfg->dim);
+    d.nx = (int32_t)cfg->nx;
+    d.ny = (int32_t)cfg->ny;
+    for (int i = 0; i < 4; ++i) d.bc[i] = cfg->bc[i];
+    if (cfg->dim == 1) d.bc[2] = d.bc[3] = ARLBM_PERIODIC;
+    d.omega_fixed_on = cfg->omega_mode == ARLBM_OMEGA_FIXED;
+    d.ncols = (int32_t)((cfg->nx + kOutW - 1) / kOutW);
+    d.band_h = cfg->dim == 2 ? choose_band(cfg->ny, d.ncols) : 1;
+    d.iter0 = 0;
+    d.plane = cfg->nx * cfg->ny;
+    d.dx = (cfg->x1 - cfg->x0) / (double)cfg->nx;
+    d.cfl = cfg->cfl;
+    d.eps = cfg->eps;
+    d.gamma = cfg->gamma;
+    d.g = cfg->g;
+    d.adv[0] = cfg->adv_speed[0];
+    d.adv[1] = cfg->dim == 2 ? cfg->adv_speed[1] : 0.0;
+    d.h_dry = cfg->h_dry;
+    d.rho_floor = cfg->rho_floor;
+    d.p_floor = cfg->p_floor;
+    d.omega_fixed = cfg->omega_fixed;
+    if (bufs) {
+        auto bad = [](const void *p) { return !p || ((uintptr_t)p % kAlign) != 0; };
+        if (bad(bufs->f[0]) || bad(bufs->f[1]) || bad(bufs->u[0]) || bad(bufs->u[1]) || bad(bufs->scalars) ||
+            (cfg->has_bed && bad(bufs->bed)) || (bufs->omega && ((uintptr_t)bufs->omega % kAlign) != 0)) {
+            delete h;
+            return fail(nullptr, ARLBM_EINVAL, "caller buffers must be non-NULL and 256-byte aligned");
+        }
+        for (int i = 0; i < 2; ++i) {
+            d.f[i] = bufs->f[i];
+            d.u[i] = bufs->u[i];
+        }
+        d.bed = cfg->has_bed ? bufs->bed : nullptr;
+        d.sc = (DevScalars *)bufs->scalars;
+        d.omega = bufs->omega;
+    } else {
+        h->owns = true;
+        hipError_t err = hipSuccess;
+        for (int i = 0; i < 2 && err == hipSuccess; ++i) {
+            err = hipMalloc(&d.f[i], h->sz.f_bytes);
+            if (err == hipSuccess) err = hipMalloc(&d.u[i], h->sz.u_bytes);
+        }
+        if (err == hipSuccess && cfg->has_bed) {
+            void *b = nullptr;
+            err = hipMalloc(&b, h->sz.bed_bytes);
+            d.bed = b;
+        }
+        if (err == hipSuccess) err = hipMalloc((void **)&d.sc, h->sz.scalar_bytes);
+        if (err != hipSuccess) {
+            free_owned(h);
+            delete h;
+            return fail(nullptr, err == hipErrorOutOfMemory ? ARLBM_ENOMEM : ARLBM_EDEVICE,
+                        std::string("device allocation failed: ") + hipGetErrorString(err));
+        }
+    }
+    hipError_t err = hipMalloc((void **)&h->d_partial, sizeof(double) * kConsBlocks * 4);
+    if (err != hipSuccess) {
+        free_owned(h);
+        delete h;
+        return fail(nullptr, ARLBM_ENOMEM, "device allocation failed");
+    }
+    *out = h;
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_set_state(arlbm_lattice *h, const double *U0, const double *bed, double t0)
+{
+    if (!h) return fail(nullptr, ARLBM_EINVAL, "handle is NULL");
+    return set_state_impl(h, U0, bed, false, t0);
+}
+
+extern "C" int arlbm_set_state_device(arlbm_lattice *h, const double *U0, const double *bed, double t0)
+{
+    if (!h) return fail(nullptr, ARLBM_EINVAL, "handle is NULL");
+    return set_state_impl(h, U0, bed, true, t0);
+}
+
+extern "C" int arlbm_step(arlbm_lattice *h, int64_t n)
+{
+    if (!h) return fail(nullptr, ARLBM_EINVAL, "handle is NULL");
+    if (h->busy) return fail(h, ARLBM_EBUSY, "lattice is owned by a server");
+    if (n < 0) return fail(h, ARLBM_EINVAL, "n must be >= 0");
+    for (int64_t i = 0; i < n; ++i) {
+        hipError_t e = L_step(h, h->step);
+        if (e != hipSuccess) return hip_fail(h, e, "step launch");
+        ++h->step;
+    }
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_sync(arlbm_lattice *h, arlbm_status *st)
+{
+    if (!h) return fail(nullptr, ARLBM_EINVAL, "handle is NULL");
+    DevScalars sc{};
+    int rc = read_scalars(h, &sc);
+    if (rc) return rc;
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->t = sc.t;
+        st->last_dt = sc.last_dt;
+        const int slot = (int)(h->step % 3);
+        st->abar[0] = *(double *)&sc.abar[slot][0];
+        st->abar[1] = h->cfg.dim == 2 ? *(double *)&sc.abar[slot][1] : 0.0;
+        st->step = h->step;
+        st->flags = sc.flags;
+        st->first_bad_step = sc.first_bad_step == ~0ull ? -1 : (int64_t)sc.first_bad_step;
+    }
+    if (sc.flags & ARLBM_FLAG_NONFINITE) return fail(h, ARLBM_ENONFINITE, "a moment became non-finite");
+    if (sc.flags & ARLBM_FLAG_DEGENERATE) return fail(h, ARLBM_EDEGENERATE, "sum of wave-speed bounds became zero");
+    if (sc.flags & ARLBM_FLAG_POSITIVITY) return fail(h, ARLBM_EPOSITIVITY, "a density, pressure or depth fell below its floor");
+    return ARLBM_OK;
+}
+
+static int read_plane_set(arlbm_lattice *h, const void *src, int64_t count, double *out)
+{
+    if (is_f64(h)) {
+        HIPCHK(h, hipMemcpyAsync(out, src, sizeof(double) * count, hipMemcpyDeviceToHost, h->stream));
+    } else {
+        double *stage = (double *)h->desc.f[(h->step + 1) & 1];
+        HIPCHK(h, f32::to_double(src, stage, count, h->stream));
+        HIPCHK(h, hipMemcpyAsync(out, stage, sizeof(double) * count, hipMemcpyDeviceToHost, h->stream));
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_read_moments(arlbm_lattice *h, double *U)
+{
+    if (!h || !U) return fail(h, ARLBM_EINVAL, "NULL argument");
+    return read_plane_set(h, h->desc.u[h->step & 1], (int64_t)h->sz.m * h->desc.plane, U);
+}
+
+extern "C" int arlbm_set_omega_export(arlbm_lattice *h, int on)
+{
+    if (!h) return fail(nullptr, ARLBM_EINVAL, "handle is NULL");
+    if (on && !h->desc.omega) {
+        void *p = nullptr;
+        HIPCHK(h, hipMalloc(&p, h->sz.omega_bytes));
+        HIPCHK(h, hipMemsetAsync(p, 0, h->sz.omega_bytes, h->stream));
+        h->desc.omega = p;
+        h->owns_omega = true;
+    } else if (!on && h->desc.omega) {
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        if (h->owns_omega) (void)hipFree(h->desc.omega);
+        h->desc.omega = nullptr;
+        h->owns_omega = false;
+    }
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_read_omega(arlbm_lattice *h, double *omega)
+{
+    if (!h || !omega) return fail(h, ARLBM_EINVAL, "NULL argument");
+    if (!h->desc.omega) return fail(h, ARLBM_EINVAL, "omega export is off");
+    return read_plane_set(h, h->desc.omega, h->desc.plane, omega);
+}
+
+extern "C" int arlbm_conservation(arlbm_lattice *h, double *sums)
+{
+    if (!h || !sums) return fail(h, ARLBM_EINVAL, "NULL argument");
+    const int m = h->sz.m;
+    const void *u = h->desc.u[h->step & 1];
+    hipError_t e = is_f64(h) ? f64::conservation(u, h->desc.plane, m, h->d_partial, kConsBlocks, h->stream)
+                             : f32::conservation(u, h->desc.plane, m, h->d_partial, kConsBlocks, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "conservation launch");
+    std::vector<double> part((size_t)m * kConsBlocks);
+    HIPCHK(h, hipMemcpyAsync(part.data(), h->d_partial, sizeof(double) * part.size(), hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int c = 0; c < m; ++c) {
+        double s = 0.0, comp = 0.0;
+        for (int b = 0; b < kConsBlocks; ++b) {
+            const double v = part[(size_t)c * kConsBlocks + b];
+            const double t = s + v;
+            comp += std::fabs(s) >= std::fabs(v) ? (s - t) + v : (v - t) + s;
+            s = t;
+        }
+        sums[c] = s + comp;
+    }
+    return ARLBM_OK;
+}
+
+namespace {
+struct StateHeader {
+    uint64_t magic;
+    int32_t precision, variant, nx, ny;
+    int64_t step;
+    uint64_t f_bytes, u_bytes;
+};
+constexpr uint64_t kMagic = 0x41524c424d535431ull;  // "ARLBMST1"
+}  // namespace
+
+extern "C" int arlbm_state_bytes(arlbm_lattice *h, size_t *bytes)
+{
+    if (!h || !bytes) return fail(h, ARLBM_EINVAL, "NULL argument");
+    *bytes = sizeof(StateHeader) + h->sz.f_bytes + h->sz.u_bytes + sizeof(DevScalars);
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_save_state(arlbm_lattice *h, void *blob, size_t bytes)
+{
+    size_t need = 0;
+    int rc = arlbm_state_bytes(h, &need);
+    if (rc) return rc;
+    if (!blob || bytes < need) return fail(h, ARLBM_EINVAL, "state buffer too small");
+    StateHeader hd{kMagic, h->cfg.precision, h->desc.variant, h->desc.nx, h->desc.ny, h->step, h->sz.f_bytes,
+                   h->sz.u_bytes};
+    char *p = (char *)blob;
+    std::memcpy(p, &hd, sizeof(hd));
+    p += sizeof(hd);
+    HIPCHK(h, hipMemcpyAsync(p, h->desc.f[h->step & 1], h->sz.f_bytes, hipMemcpyDeviceToHost, h->stream));
+    p += h->sz.f_bytes;
+    HIPCHK(h, hipMemcpyAsync(p, h->desc.u[h->step & 1], h->sz.u_bytes, hipMemcpyDeviceToHost, h->stream));
+    p += h->sz.u_bytes;
+    HIPCHK(h, hipMemcpyAsync(p, h->desc.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_load_state(arlbm_lattice *h, const void *blob, size_t bytes)
+{
+    size_t need = 0;
+    int rc = arlbm_state_bytes(h, &need);
+    if (rc) return rc;
+    if (!blob || bytes < need) return fail(h, ARLBM_EINVAL, "state buffer too small");
+    StateHeader hd;
+    std::memcpy(&hd, blob, sizeof(hd));
+    if (hd.magic != kMagic || hd.precision != h->cfg.precision || hd.variant != h->desc.variant ||
+        hd.nx != h->desc.nx || hd.ny != h->desc.ny || hd.f_bytes != h->sz.f_bytes || hd.u_bytes != h->sz.u_bytes)
+        return fail(h, ARLBM_EINVAL, "state blob does not match this lattice");
+    h->step = hd.step;
+    const char *p = (const char *)blob + sizeof(hd);
+    HIPCHK(h, hipMemcpyAsync(h->desc.f[h->step & 1], p, h->sz.f_bytes, hipMemcpyHostToDevice, h->stream));
+    p += h->sz.f_bytes;
+    HIPCHK(h, hipMemcpyAsync(h->desc.u[h->step & 1], p, h->sz.u_bytes, hipMemcpyHostToDevice, h->stream));
+    p += h->sz.u_bytes;
+    HIPCHK(h, hipMemcpyAsync(h->desc.sc, p, sizeof(DevScalars), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_destroy(arlbm_lattice *h)
+{
+    if (!h) return ARLBM_OK;
+    (void)hipStreamSynchronize(h->stream);
+    free_owned(h);
+    delete h;
+    return ARLBM_OK;
+}
+
+extern "C" const char *arlbm_last_error(const arlbm_lattice *h)
+{
+    return h ? h->err.c_str() : g_thread_err.c_str();
+}
+
+// Diagnostics used by the benchmark: registers of the fused step kernel.
+extern "C" int arlbm_step_kernel_vgprs(int32_t precision, int32_t system, int32_t dim)
+{
+    const int v = variant_of(system, dim);
+    return precision == ARLBM_F64 ? f64::step_kernel_vgprs(v) : f32::step_kernel_vgprs(v);
+}
+
+// ------------------------------------------------------------------------
+// Server
+// ------------------------------------------------------------------------
+
+namespace {
+struct Pending {
+    uint64_t id;
+    arlbm_config cfg;
+    std::vector<double> U0, bed;
+    int64_t nsteps;
+    double submit_s;
+    size_t bytes;
+};
+struct Resident {
+    uint64_t id;
+    arlbm_lattice *lat;
+    int64_t nsteps, iter0;
+    double submit_s, admit_s;
+    size_t bytes;
+};
+struct Done {
+    arlbm_completion c;
+    std::vector<double> U;
+};
+}  // namespace
+
+struct arlbm_server {
+    size_t budget = 0, in_use = 0;
+    int32_t precision = ARLBM_F32;
+    hipStream_t stream = nullptr;
+    uint64_t next_id = 1;
+    int64_t iter = 0;
+    std::deque<Pending> queue;
+    std::vector<Resident> resident;
+    std::deque<Done> done;
+    std::vector<Done> handed;  // results returned by the last poll
+    LatticeDesc *d_descs = nullptr;
+    WorkItem *d_items = nullptr;
+    size_t cap_descs = 0, cap_items = 0;
+    int32_t nitems = 0;
+    bool dirty = true;
+    std::string err;
+};
+
+namespace {
+
+int sfail(arlbm_server *s, int code, const std::string &msg)
+{
+    if (s) s->err = msg;
+    g_thread_err = msg;
+    return code;
+}
+
+int rebuild_table(arlbm_server *s)
+{
+    std::vector<LatticeDesc> descs;
+    std::vector<WorkItem> items;
+    for (size_t i = 0; i < s->resident.size(); ++i) {
+        LatticeDesc d = s->resident[i].lat->desc;
+        d.iter0 = s->resident[i].iter0;
+        descs.push_back(d);
+        const int64_t nb = d.variant >= V_ADV2 ? (d.ny + d.band_h - 1) / d.band_h : 1;
+        for (int64_t b = 0; b < nb; ++b)
+            for (int c = 0; c < d.ncols; ++c) items.push_back({(int32_t)i, c, (int32_t)b, (b == 0 && c == 0) ? 1 : 0});
+    }
+    hipError_t e;
+    if (descs.size() > s->cap_descs) {
+        if (s->d_descs) (void)hipFree(s->d_descs);
+        s->cap_descs = std::max<size_t>(descs.size() * 2, 64);
+        e = hipMalloc((void **)&s->d_descs, sizeof(LatticeDesc) * s->cap_descs);
+        if (e != hipSuccess) return sfail(s, ARLBM_ENOMEM, "descriptor table allocation failed");
+    }
+    if (items.size() > s->cap_items) {
+        if (s->d_items) (void)hipFree(s->d_items);
+        s->cap_items = std::max<size_t>(items.size() * 2, 4096);
+        e = hipMalloc((void **)&s->d_items, sizeof(WorkItem) * s->cap_items);
+        if (e != hipSuccess) return sfail(s, ARLBM_ENOMEM, "work table allocation failed");
+    }
+    // the stream is idle here (admission and retirement synchronise), so the
+    // synchronous copies cannot overtake a launch that still reads the table
+    if (!descs.empty()) {
+        e = hipMemcpy(s->d_descs, descs.data(), sizeof(LatticeDesc) * descs.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(s->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("table upload: ") + hipGetErrorString(e));
+    }
+    s->nitems = (int32_t)items.size();
+    s->dirty = false;
+    return ARLBM_OK;
+}
+
+}  // namespace
+
+extern "C" int arlbm_server_create(size_t budget, int32_t precision, void *stream, arlbm_server **out)
+{
+    if (!out) return sfail(nullptr, ARLBM_EINVAL, "out is NULL");
+    if (precision != ARLBM_F32 && precision != ARLBM_F64) return sfail(nullptr, ARLBM_EINVAL, "bad precision");
+    arlbm_server *s = new arlbm_server();
+    s->budget = budget;
+    s->precision = precision;
+    s->stream = (hipStream_t)stream;
+    *out = s;
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, const double *U0, const double *bed,
+                                   int64_t nsteps, uint64_t *id)
+{
+    if (!s || !cfg || !U0 || nsteps < 0) return sfail(s, ARLBM_EINVAL, "bad argument");
+    arlbm_config c = *cfg;
+    c.precision = s->precision;
+    std::string e = check_config(&c);
+    if (!e.empty()) return sfail(s, ARLBM_EINVAL, e);
+    if (c.has_bed && !bed) return sfail(s, ARLBM_EINVAL, "bed is NULL");
+    arlbm_sizes sz;
+    fill_sizes(&c, &sz);
+    if (sz.total_bytes > s->budget) return sfail(s, ARLBM_EBUDGET, "request can never fit the HBM budget");
+    Pending p;
+    p.id = s->next_id++;
+    p.cfg = c;
+    const size_t plane = (size_t)c.nx * c.ny;
+    p.U0.assign(U0, U0 + (size_t)sz.m * plane);
+    if (c.has_bed) p.bed.assign(bed, bed + plane);
+    p.nsteps = nsteps;
+    p.submit_s = now_s();
+    p.bytes = sz.total_bytes;
+    s->queue.push_back(std::move(p));
+    if (id) *id = s->queue.back().id;
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_server_iterate(arlbm_server *s, int32_t *n_res, int32_t *n_queued)
+{
+    if (!s) return sfail(nullptr, ARLBM_EINVAL, "server is NULL");
+    // retire lattices whose steps are complete
+    for (size_t i = 0; i < s->resident.size();) {
+        Resident &r = s->resident[i];
+        if (s->iter - r.iter0 >= r.nsteps) {
+            Done d{};
+            d.c.id = r.id;
+            d.c.steps = r.nsteps;
+            d.c.submit_s = r.submit_s;
+            d.c.admit_s = r.admit_s;
+            d.U.resize((size_t)r.lat->sz.m * r.lat->desc.plane);
+            r.lat->step = r.nsteps;  // the batched launches advanced it
+            r.lat->busy = false;
+            arlbm_status st{};
+            int rc = arlbm_sync(r.lat, &st);
+            d.c.t = st.t;
+            if (rc == ARLBM_OK) rc = arlbm_read_moments(r.lat, d.U.data());
+            d.c.status = rc;
+            d.c.done_s = now_s();
+            s->done.push_back(std::move(d));
+            s->in_use -= r.bytes;
+            arlbm_destroy(r.lat);
+            s->resident.erase(s->resident.begin() + i);
+            s->dirty = true;
+        } else {
+            ++i;
+        }
+    }
+    // admit queued requests in arrival order while the budget allows
+    while (!s->queue.empty() && s->in_use + s->queue.front().bytes <= s->budget) {
+        Pending p = std::move(s->queue.front());
+        s->queue.pop_front();
+        arlbm_lattice *lat = nullptr;
+        int rc = arlbm_create(&p.cfg, nullptr, s->stream, &lat);
+        if (rc == ARLBM_OK) rc = arlbm_set_state(lat, p.U0.data(), p.cfg.has_bed ? p.bed.data() : nullptr, 0.0);
+        if (rc != ARLBM_OK) {
+            Done d{};
+            d.c.id = p.id;
+            d.c.status = rc;
+            d.c.submit_s = p.submit_s;
+            d.c.done_s = now_s();
+            s->done.push_back(std::move(d));
+            if (lat) arlbm_destroy(lat);
+            continue;
+        }
+        lat->busy = true;
+        s->resident.push_back({p.id, lat, p.nsteps, s->iter, p.submit_s, now_s(), p.bytes});
+        s->in_use += p.bytes;
+        s->dirty = true;
+    }
+    if (s->dirty) {
+        hipError_t e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, hipGetErrorString(e));
+        int rc = rebuild_table(s);
+        if (rc) return rc;
+    }
+    if (!s->resident.empty()) {
+        hipError_t e = s->precision == ARLBM_F64
+                           ? f64::step_batched(s->d_descs, s->d_items, s->nitems, s->iter, s->stream)
+                           : f32::step_batched(s->d_descs, s->d_items, s->nitems, s->iter, s->stream);
+        if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("batched launch: ") + hipGetErrorString(e));
+        ++s->iter;
+    }
+    if (n_res) *n_res = (int32_t)s->resident.size();
+    if (n_queued) *n_queued = (int32_t)s->queue.size();
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_server_poll(arlbm_server *s, arlbm_completion *out, int32_t max, int32_t *n)
+{
+    if (!s || !n || (max > 0 && !out)) return sfail(s, ARLBM_EINVAL, "bad argument");
+    s->handed.clear();
+    int32_t k = 0;
+    while (k < max && !s->done.empty()) {
+        s->handed.push_back(std::move(s->done.front()));
+        s->done.pop_front();
+        ++k;
+    }
+    for (int32_t i = 0; i < k; ++i) {
+        Done &d = s->handed[i];
+        out[i] = d.c;
+        out[i].U = d.c.status == ARLBM_OK ? d.U.data() : nullptr;
+        out[i].u_count = d.c.status == ARLBM_OK ? (int64_t)d.U.size() : 0;
+    }
+    *n = k;
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_server_memory(arlbm_server *s, size_t *bytes)
+{
+    if (!s || !bytes) return sfail(s, ARLBM_EINVAL, "bad argument");
+    *bytes = s->in_use;
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_server_destroy(arlbm_server *s)
+{
+    if (!s) return ARLBM_OK;
+    (void)hipStreamSynchronize(s->stream);
+    for (auto &r : s->resident) arlbm_destroy(r.lat);
+    if (s->d_descs) (void)hipFree(s->d_descs);
+    if (s->d_items) (void)hipFree(s->d_items);
+    delete s;
+    return ARLBM_OK;
+}

@@ -1,0 +1,720 @@
+// Fused collide-and-stream step of the adaptive-relaxation LBM on gfx950.
+//
+// Work decomposition.  One wave64 owns a strip of 58 output columns and a
+// band of rows.  Lane l sits on column x = x0 - 3 + l, so the 3-cell halo on
+// each side is carried by the wave itself: x-neighbours come from lane
+// shuffles, no LDS and no barriers are used.  The wave marches up its band;
+// per row it loads the moments U (m planes, written by the previous step) and
+// the populations f (Q m planes), and keeps a rolling window in registers:
+//
+//   U rows j-2, j-1, j           -> nu at row j-1            (eqs. 2.13-2.14)
+//   nu rows j-3, j-2, j-1 (+x+-1) -> nu~, omega at row j-2   (eqs. 2.15-2.16)
+//   f, U, omega at row r = j-2   -> collided f*_k (source node, eq. 2.2)
+//   f*_{+y}(r-2), f*_{0,+x,-x}(r-1), f*_{-y}(r) -> pulled F_k at row r-1
+//   sum_k F_k, (2.8), second half source -> f^{n+1}, U^{n+1} written once.
+//
+// Every population is read once and written once per step (coalesced SoA
+// planes, x fastest); U adds m planes read and written.  The grid-wide
+// wave-speed bound of the next step (eq. 2.19) is reduced in registers, across
+// the wave by shuffles, and committed with one 64-bit atomic max per wave and
+// direction into a triple-buffered slot.  The kernel launch boundary is the
+// grid barrier that the global maximum needs.
+//
+// Ghost cells: U at ghost positions follows the boundary index map (periodic
+// wrap, or mirror U(-1-i) = U(i) with the normal momentum negated at
+// reflective walls); populations pulled from a mirror ghost are the
+// destination's own collided populations (transmissive: same direction;
+// reflective: the mirrored direction with the normal momentum negated).
+#pragma once
+
+#include "arlbm_internal.h"
+#include "physics.hpp"
+
+namespace arlbm {
+
+// ---------------------------------------------------------------- helpers --
+
+// Value held by lane l-1 (x - 1) / lane l+1 (x + 1); edge lanes get their own
+// value (those lanes only produce halo values that are never used).
+template <typename T>
+__device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1, kWave); }
+template <typename T>
+__device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, kWave); }
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o, kWave);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
+__device__ __forceinline__ double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+// Boundary index map for a coordinate in [-3, n+2] (clamped first: lanes
+// further out only carry unused halo values).  refl is set for a reflective
+// wall on the side the index fell off.
+__device__ __forceinline__ int bc_map(int i, int n, int lo, int hi, bool &refl)
+{
+    refl = false;
+    i = i < -kHalo ? -kHalo : (i > n - 1 + kHalo ? n - 1 + kHalo : i);
+    if (i < 0) {
+        if (lo == 0) return i + n;
+        refl = lo == 2;
+        return -1 - i;
+    }
+    if (i >= n) {
+        if (hi == 0) return i - n;
+        refl = hi == 2;
+        return 2 * n - 1 - i;
+    }
+    return i;
+}
+
+// Per-step coefficients of the Lax-Friedrichs-type equilibrium, computed in
+// FP64 from the wave-speed bounds of U^n (eqs. 2.19-2.21):
+//   dt = CFL dx / sum_j abar_j, lambda = dx / dt, alpha_j = abar_j + eps,
+//   a_0 = 1 - sum_j alpha_j / lambda, a_{+-j} = alpha_j / (2 lambda),
+//   b_{+j} = 1 / (2 lambda), b_{-j} = -1 / (2 lambda)   (general form 2.5).
+template <typename T>
+struct Coefs {
+    T a0, ap[2], bp, bm, hdt, omega_fixed;
+    double dt;
+};
+
+template <int D, typename T>
+__device__ __forceinline__ bool step_coefs(const LatticeDesc &L, int64_t n, Coefs<T> &cf)
+{
+    const DevScalars *sc = L.sc;
+    const int slot = (int)(n % 3);
+    const double ab0 = bitsd(sc->abar[slot][0]);
+    const double ab1 = D == 2 ? bitsd(sc->abar[slot][1]) : 0.0;
+    const double sa = D == 2 ? ab0 + ab1 : ab0;
+    if (!(sa > 0.0) || !(sa < 1.0e300)) return false;
+    const double dt = L.cfl * L.dx / sa;
+    const double lam = L.dx / dt;
+    const double al0 = ab0 + L.eps, al1 = ab1 + L.eps;
+    const double sum_alpha = D == 2 ? al0 + al1 : al0;
+    cf.a0 = T(1.0 - sum_alpha / lam);
+    cf.ap[0] = T(al0 / (2.0 * lam));
+    cf.ap[1] = T(al1 / (2.0 * lam));
+    cf.bp = T(1.0 / (2.0 * lam));
+    cf.bm = T(-1.0 / (2.0 * lam));
+    cf.hdt = T(0.5 * dt);
+    cf.omega_fixed = T(L.omega_fixed);
+    cf.dt = dt;
+    return true;
+}
+
+template <typename T>
+__device__ __forceinline__ Phys<T> make_phys(const LatticeDesc &L)
+{
+    Phys<T> P;
+    P.gamma = T(L.gamma);
+    P.gm1 = T(L.gamma - 1.0);
+    P.g = T(L.g);
+    P.half_g = T(0.5 * L.g);
+    P.adv[0] = T(L.adv[0]);
+    P.adv[1] = T(L.adv[1]);
+    P.dx = T(L.dx);
+    P.p_floor_t = T(L.p_floor);
+    P.rho_floor_t = T(L.rho_floor);
+    P.h_dry_t = T(L.h_dry);
+    P.h_dry = L.h_dry;
+    P.rho_floor = L.rho_floor;
+    P.p_floor = L.p_floor;
+    return P;
+}
+
+// Work of the lattice's first wave in a launch: advance t, record dt, clear
+// the slot that the next step will max into.
+__device__ __forceinline__ void scalar_update(const LatticeDesc &L, int64_t n, double dt)
+{
+    DevScalars *sc = L.sc;
+    sc->t = sc->t + dt;
+    sc->last_dt = dt;
+    const int clr = (int)((n + 2) % 3);
+    sc->abar[clr][0] = 0ull;
+    sc->abar[clr][1] = 0ull;
+}
+
+__device__ __forceinline__ void flag_degenerate(const LatticeDesc &L, int64_t n)
+{
+    atomicOr(&L.sc->flags, 4u);
+    atomicMin(&L.sc->first_bad_step, (unsigned long long)n);
+}
+
+// Commit the wave's bounds and flags for the next step.
+template <typename T>
+__device__ __forceinline__ void commit(const LatticeDesc &L, int64_t n, T s0, T s1, unsigned flags, int dims)
+{
+    const double m0 = (double)wave_max<T>(s0);
+    const double m1 = dims == 2 ? (double)wave_max<T>(s1) : 0.0;
+    const unsigned long long anyf = __ballot(flags != 0u);
+    unsigned fl = flags;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) fl |= __shfl_xor(fl, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        const int slot = (int)((n + 1) % 3);
+        atomicMax(&L.sc->abar[slot][0], dbits(m0));
+        if (dims == 2) atomicMax(&L.sc->abar[slot][1], dbits(m1));
+        if (anyf) {
+            atomicOr(&L.sc->flags, fl);
+            atomicMin(&L.sc->first_bad_step, (unsigned long long)n);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ bool finite_val(T v) { return __builtin_isfinite(v); }
+
+// ------------------------------------------------------------------ 1D ----
+
+template <int SYS, typename T>
+__device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int col, bool first)
+{
+    constexpr int D = 1, M = SysInfo<SYS, 1>::M, Q = 3;
+    const int64_t n = iter - L.iter0;
+    Coefs<T> cf;
+    if (!step_coefs<D, T>(L, n, cf)) {
+        if (first && (threadIdx.x & 63) == 0) flag_degenerate(L, n);
+        return;
+    }
+    const Phys<T> P = make_phys<T>(L);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nx = L.nx;
+    const int64_t plane = L.plane;
+    const T *fin = (const T *)L.f[n & 1];
+    T *fout = (T *)L.f[(n + 1) & 1];
+    const T *uin = (const T *)L.u[n & 1];
+    T *uout = (T *)L.u[(n + 1) & 1];
+    const int x = col * kOutW - kHalo + lane;
+    bool rx;
+    const int xm = bc_map(x, nx, L.bc[0], L.bc[1], rx);
+    const bool out = lane >= kHalo && lane < kWave - kHalo && x < nx;
+
+    // moments (with ghost map) and neighbours
+    T U[M], UL[M], UR[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) U[c] = uin[(int64_t)c * plane + xm];
+    if constexpr (SYS != 0)
+        if (rx) U[1] = -U[1];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        UL[c] = from_left(U[c]);
+        UR[c] = from_right(U[c]);
+    }
+    Prim<T> q;
+    primitives<SYS, D, T>(U, P, q);
+    // indicator nu (2.9)-(2.10), 3-point sum (2.11), omega (2.12)
+    T nu = T(0);
+    add_theta<SYS, D, T>(0, q, U, UL, UR, P, nu);
+    const T nuL = from_left(nu), nuR = from_right(nu);
+    const T nt = nuL + nu + nuR;
+    const T w = L.omega_fixed_on ? cf.omega_fixed : T(1) + T(1) / (T(1) + nt);
+    if (L.omega && out) ((T *)L.omega)[x] = w;
+
+    // bed slope by central differences
+    T db = T(0);
+    constexpr bool src = SYS == 2;
+    bool has_bed = false;
+    if constexpr (src) {
+        has_bed = L.bed != nullptr;
+        if (has_bed) {
+            const T b = ((const T *)L.bed)[xm];
+            db = (from_right(b) - from_left(b)) / (T(2) * P.dx);
+        }
+    }
+
+    // equilibrium (2.18) and collision at this source node
+    T F[M];
+    flux<SYS, D, T>(0, U, q, P, F);
+    T fs[Q][M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        const T u = U[c];
+        const T feq0 = cf.a0 * u;
+        const T feq1 = cf.ap[0] * u + cf.bp * F[c];
+        const T feq2 = cf.ap[0] * u + cf.bm * F[c];
+        const T f0 = fin[(int64_t)(0 * M + c) * plane + xm];
+        const T f1 = fin[(int64_t)(1 * M + c) * plane + xm];
+        const T f2 = fin[(int64_t)(2 * M + c) * plane + xm];
+        fs[0][c] = f0 - w * (f0 - feq0);
+        fs[1][c] = f1 - w * (f1 - feq1);
+        fs[2][c] = f2 - w * (f2 - feq2);
+    }
+    if constexpr (src) {
+        if (has_bed) {
+            const T S1 = -P.g * U[0] * db;
+            fs[0][1] = fs[0][1] + cf.hdt * (cf.a0 * S1);
+            fs[1][1] = fs[1][1] + cf.hdt * (cf.ap[0] * S1);
+            fs[2][1] = fs[2][1] + cf.hdt * (cf.ap[0] * S1);
+        }
+    }
+    // pull streaming: F_+(x) = f*_+(x-1), F_-(x) = f*_-(x+1)
+    T Fp[M], Fm[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        Fp[c] = from_left(fs[1][c]);
+        Fm[c] = from_right(fs[2][c]);
+    }
+    if (x == 0 && L.bc[0] != 0) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) Fp[c] = L.bc[0] == 1 ? fs[1][c] : (c == 1 ? -fs[2][c] : fs[2][c]);
+    }
+    if (x == nx - 1 && L.bc[1] != 0) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) Fm[c] = L.bc[1] == 1 ? fs[2][c] : (c == 1 ? -fs[1][c] : fs[1][c]);
+    }
+    // moments (2.8) and second half source
+    T fn[Q][M], Un[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        fn[0][c] = fs[0][c];
+        fn[1][c] = Fp[c];
+        fn[2][c] = Fm[c];
+    }
+    if constexpr (src) {
+        if (has_bed) {
+            const T h = fs[0][0] + Fp[0] + Fm[0];
+            const T S1 = -P.g * h * db;
+            fn[0][1] = fn[0][1] + cf.hdt * (cf.a0 * S1);
+            fn[1][1] = fn[1][1] + cf.hdt * (cf.ap[0] * S1);
+            fn[2][1] = fn[2][1] + cf.hdt * (cf.ap[0] * S1);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) Un[c] = fn[0][c] + fn[1][c] + fn[2][c];
+    T s0 = T(0);
+    unsigned flags = 0;
+    if (out) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+#pragma unroll
+            for (int c = 0; c < M; ++c) fout[(int64_t)(k * M + c) * plane + x] = fn[k][c];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            uout[(int64_t)c * plane + x] = Un[c];
+            if (!finite_val<T>(Un[c])) flags |= 1u;
+        }
+        Prim<T> qn;
+        primitives<SYS, D, T>(Un, P, qn);
+        flags |= qn.flags;
+        const T sp = max_speed<SYS, T>(0, qn, P);
+        if (finite_val<T>(sp)) s0 = sp;
+    }
+    if (first && lane == 0) scalar_update(L, n, cf.dt);
+    commit<T>(L, n, s0, T(0), flags, 1);
+}
+
+// ------------------------------------------------------------------ 2D ----
+
+template <int SYS, typename T>
+__device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int col, int band, bool first)
+{
+    constexpr int D = 2, M = SysInfo<SYS, 2>::M, Q = 5;
+    const int64_t n = iter - L.iter0;
+    Coefs<T> cf;
+    if (!step_coefs<D, T>(L, n, cf)) {
+        if (first && (threadIdx.x & 63) == 0) flag_degenerate(L, n);
+        return;
+    }
+    const Phys<T> P = make_phys<T>(L);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nx = L.nx, ny = L.ny;
+    const int64_t plane = L.plane;
+    const T *fin = (const T *)L.f[n & 1];
+    T *fout = (T *)L.f[(n + 1) & 1];
+    const T *uin = (const T *)L.u[n & 1];
+    T *uout = (T *)L.u[(n + 1) & 1];
+    const T *bed = (const T *)L.bed;
+    const int x = col * kOutW - kHalo + lane;
+    bool rx;
+    const int xm = bc_map(x, nx, L.bc[0], L.bc[1], rx);
+    const bool xout = lane >= kHalo && lane < kWave - kHalo && x < nx;
+    const int ya = band * L.band_h;
+    const int yb = ya + L.band_h < ny ? ya + L.band_h : ny;
+    const int bxl = L.bc[0], bxh = L.bc[1], byl = L.bc[2], byh = L.bc[3];
+    const bool use_bed = SYS == 2 && bed != nullptr;
+    const T two_dx = T(2) * P.dx;
+
+    auto loadU = [&](int j, T *out) {
+        bool ry;
+        const int jm = bc_map(j, ny, byl, byh, ry);
+        const T *base = uin + (int64_t)jm * nx + xm;
+#pragma unroll
+        for (int c = 0; c < M; ++c) out[c] = base[(int64_t)c * plane];
+        if constexpr (SYS != 0) {
+            if (rx) out[1] = -out[1];
+            if (ry) out[2] = -out[2];
+        }
+    };
+    auto loadB = [&](int j) -> T {
+        bool ry;
+        const int jm = bc_map(j, ny, byl, byh, ry);
+        return bed[(int64_t)jm * nx + xm];
+    };
+
+    T U0[M], U1[M], U2[M];           // U rows j-2, j-1, j
+    T N0 = 0, N0l = 0, N0r = 0;      // nu rows j-3, j-2, j-1 and x -+ 1
+    T N1 = 0, N1l = 0, N1r = 0;
+    T N2 = 0, N2l = 0, N2r = 0;
+    T B0 = 0, B1 = 0, B2 = 0;        // bed rows r-1, r, r+1
+    T dbx_prev = 0, dby_prev = 0;    // bed slope at the previous f* row
+    T P1[M], P2[M];                  // f*_{+y} of rows r-1 and r-2
+    T G0[M], Gpx[M], Gmx[M], Gmy[M]; // row r-1: f*_0, pulled +x, pulled -x, own f*_{-y}
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        U0[c] = U1[c] = U2[c] = T(0);
+        P1[c] = P2[c] = G0[c] = Gpx[c] = Gmx[c] = Gmy[c] = T(0);
+    }
+    T s0 = T(0), s1 = T(0);
+    unsigned flags = 0;
+    if (use_bed) {
+        B1 = loadB(ya - 2);
+        B2 = loadB(ya - 1);
+    }
+
+    for (int j = ya - 3; j <= yb + 2; ++j) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            U0[c] = U1[c];
+            U1[c] = U2[c];
+        }
+        loadU(j, U2);
+        if (j < ya - 1) continue;
+        // nu at row j-1 (eqs. 2.13-2.14)
+        {
+            Prim<T> qc;
+            primitives<SYS, D, T>(U1, P, qc);
+            T UL[M], UR[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                UL[c] = from_left(U1[c]);
+                UR[c] = from_right(U1[c]);
+            }
+            T nu = T(0);
+            add_theta<SYS, D, T>(0, qc, U1, UL, UR, P, nu);
+            add_theta<SYS, D, T>(1, qc, U1, U0, U2, P, nu);
+            N0 = N1; N0l = N1l; N0r = N1r;
+            N1 = N2; N1l = N2l; N1r = N2r;
+            N2 = nu;
+            N2l = from_left(nu);
+            N2r = from_right(nu);
+        }
+        if (j < ya + 1) continue;
+        const int r = j - 2;  // f* row: U0 holds U(r)
+        // 3x3 box sum (2.15) in row-major order, relaxation parameter (2.16)
+        const T nt = N0l + N0 + N0r + N1l + N1 + N1r + N2l + N2 + N2r;
+        const T w = L.omega_fixed_on ? cf.omega_fixed : T(1) + T(1) / (T(1) + nt);
+        if (L.omega && xout && r >= ya && r < yb) ((T *)L.omega)[(int64_t)r * nx + x] = w;
+        // bed slope at row r
+        T dbx = T(0), dby = T(0);
+        if (use_bed) {
+            B0 = B1;
+            B1 = B2;
+            B2 = loadB(r + 1);
+            dbx = (from_right(B1) - from_left(B1)) / two_dx;
+            dby = (B2 - B0) / two_dx;
+        }
+        // equilibrium (2.20) and collision at the source nodes of row r
+        T fs[Q][M];
+        {
+            bool ry;
+            const int rm = bc_map(r, ny, byl, byh, ry);
+            const T *fb = fin + (int64_t)rm * nx + xm;
+            Prim<T> q;
+            primitives<SYS, D, T>(U0, P, q);
+            T Fx[M], Fy[M];
+            flux<SYS, D, T>(0, U0, q, P, Fx);
+            flux<SYS, D, T>(1, U0, q, P, Fy);
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const T u = U0[c];
+                const T feq[Q] = {cf.a0 * u, cf.ap[0] * u + cf.bp * Fx[c], cf.ap[1] * u + cf.bp * Fy[c],
+                                  cf.ap[0] * u + cf.bm * Fx[c], cf.ap[1] * u + cf.bm * Fy[c]};
+#pragma unroll
+                for (int k = 0; k < Q; ++k) {
+                    const T fk = fb[(int64_t)(k * M + c) * plane];
+                    fs[k][c] = fk - w * (fk - feq[k]);
+                }
+            }
+            if (use_bed) {
+                const T S1 = -P.g * U0[0] * dbx, S2 = -P.g * U0[0] * dby;
+                const T ak[Q] = {cf.a0, cf.ap[0], cf.ap[1], cf.ap[0], cf.ap[1]};
+#pragma unroll
+                for (int k = 0; k < Q; ++k) {
+                    fs[k][1] = fs[k][1] + cf.hdt * (ak[k] * S1);
+                    fs[k][2] = fs[k][2] + cf.hdt * (ak[k] * S2);
+                }
+            }
+        }
+        // x pulls with the ghost map at the two x walls
+        T px[M], mx[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            px[c] = from_left(fs[1][c]);
+            mx[c] = from_right(fs[3][c]);
+        }
+        if (x == 0 && bxl != 0) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) px[c] = bxl == 1 ? fs[1][c] : (c == 1 ? -fs[3][c] : fs[3][c]);
+        }
+        if (x == nx - 1 && bxh != 0) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) mx[c] = bxh == 1 ? fs[3][c] : (c == 1 ? -fs[1][c] : fs[1][c]);
+        }
+        // destination row d = r-1: F_0, F_{+x}, F_{+y}, F_{-x}, F_{-y}
+        const int d = r - 1;
+        if (d >= ya && xout) {
+            T Fk[Q][M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                Fk[0][c] = G0[c];
+                Fk[1][c] = Gpx[c];
+                Fk[2][c] = P2[c];
+                Fk[3][c] = Gmx[c];
+                Fk[4][c] = fs[4][c];
+            }
+            if (d == ny - 1 && byh != 0) {
+#pragma unroll
+                for (int c = 0; c < M; ++c) Fk[4][c] = byh == 1 ? Gmy[c] : (c == 2 ? -P1[c] : P1[c]);
+            }
+            T sumF[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) sumF[c] = Fk[0][c] + Fk[1][c] + Fk[2][c] + Fk[3][c] + Fk[4][c];
+            if (use_bed) {
+                const T S1 = -P.g * sumF[0] * dbx_prev, S2 = -P.g * sumF[0] * dby_prev;
+                const T ak[Q] = {cf.a0, cf.ap[0], cf.ap[1], cf.ap[0], cf.ap[1]};
+#pragma unroll
+                for (int k = 0; k < Q; ++k) {
+                    Fk[k][1] = Fk[k][1] + cf.hdt * (ak[k] * S1);
+                    Fk[k][2] = Fk[k][2] + cf.hdt * (ak[k] * S2);
+                }
+            }
+            T Un[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) Un[c] = Fk[0][c] + Fk[1][c] + Fk[2][c] + Fk[3][c] + Fk[4][c];
+            const int64_t o = (int64_t)d * nx + x;
+#pragma unroll
+            for (int k = 0; k < Q; ++k)
+#pragma unroll
+                for (int c = 0; c < M; ++c) fout[(int64_t)(k * M + c) * plane + o] = Fk[k][c];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                uout[(int64_t)c * plane + o] = Un[c];
+                if (!finite_val<T>(Un[c])) flags |= 1u;
+            }
+            Prim<T> qn;
+            primitives<SYS, D, T>(Un, P, qn);
+            flags |= qn.flags;
+            const T v0 = max_speed<SYS, T>(0, qn, P), v1 = max_speed<SYS, T>(1, qn, P);
+            if (finite_val<T>(v0) && v0 > s0) s0 = v0;
+            if (finite_val<T>(v1) && v1 > s1) s1 = v1;
+        }
+        // roll the pulled-population window
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            P2[c] = P1[c];
+            P1[c] = fs[2][c];
+            G0[c] = fs[0][c];
+            Gpx[c] = px[c];
+            Gmx[c] = mx[c];
+            Gmy[c] = fs[4][c];
+        }
+        if (r == 0 && byl != 0) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) P2[c] = byl == 1 ? fs[2][c] : (c == 2 ? -fs[4][c] : fs[4][c]);
+        }
+        dbx_prev = dbx;
+        dby_prev = dby;
+    }
+    if (first && lane == 0) scalar_update(L, n, cf.dt);
+    commit<T>(L, n, s0, s1, flags, 2);
+}
+
+// -------------------------------------------------------------- kernels ---
+
+// Block -> work mapping that keeps consecutive work items on one XCD
+// (blocks are dealt round-robin over the 8 XCDs; gridDim.x is a multiple of 8).
+__device__ __forceinline__ int logical_wave()
+{
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int lb = (b & 7) * (nb >> 3) + (b >> 3);
+    return __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + (int)(threadIdx.x >> 6));
+}
+
+template <int SYS, int D, typename T>
+__global__ __launch_bounds__(kBlock) void k_step_single(LatticeDesc L, int64_t iter, int32_t nwork)
+{
+    const int w = logical_wave();
+    if (w >= nwork) return;
+    if constexpr (D == 1) {
+        strip1d<SYS, T>(L, iter, w, w == 0);
+    } else {
+        strip2d<SYS, T>(L, iter, w % L.ncols, w / L.ncols, w == 0);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_step_batched(const LatticeDesc *descs, const WorkItem *items,
+                                                          int32_t nitems, int64_t iter)
+{
+    const int w = logical_wave();
+    if (w >= nitems) return;
+    const WorkItem it = items[w];
+    const LatticeDesc &L = descs[it.lattice];
+    switch (L.variant) {
+    case V_ADV1: strip1d<0, T>(L, iter, it.col, it.first); break;
+    case V_EUL1: strip1d<1, T>(L, iter, it.col, it.first); break;
+    case V_SWE1: strip1d<2, T>(L, iter, it.col, it.first); break;
+    case V_ADV2: strip2d<0, T>(L, iter, it.col, it.band, it.first); break;
+    case V_EUL2: strip2d<1, T>(L, iter, it.col, it.band, it.first); break;
+    case V_SWE2: strip2d<2, T>(L, iter, it.col, it.band, it.first); break;
+    default: break;
+    }
+}
+
+// Wave-speed bound of the initial state: atomic max of max_r |lambda_j^(r)|.
+template <int SYS, int D, typename T>
+__global__ __launch_bounds__(kBlock) void k_reduce_abar(LatticeDesc L, const double *U0, int slot)
+{
+    constexpr int M = SysInfo<SYS, D>::M;
+    const Phys<T> P = make_phys<T>(L);
+    T s0 = T(0), s1 = T(0);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.plane;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        T U[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) U[c] = T(U0[(int64_t)c * L.plane + i]);
+        Prim<T> q;
+        primitives<SYS, D, T>(U, P, q);
+        const T v0 = max_speed<SYS, T>(0, q, P);
+        if (finite_val<T>(v0) && v0 > s0) s0 = v0;
+        if constexpr (D == 2) {
+            const T v1 = max_speed<SYS, T>(1, q, P);
+            if (finite_val<T>(v1) && v1 > s1) s1 = v1;
+        }
+    }
+    const double m0 = (double)wave_max<T>(s0), m1 = (double)wave_max<T>(s1);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&L.sc->abar[slot][0], dbits(m0));
+        if (D == 2) atomicMax(&L.sc->abar[slot][1], dbits(m1));
+    }
+}
+
+// f = f^eq(U0) with the coefficients of U0's bounds (slot_in); U = sum_k f_k;
+// bounds of U into slot 0; bed converted to the storage precision.
+template <int SYS, int D, typename T>
+__global__ __launch_bounds__(kBlock) void k_init(LatticeDesc L, const double *U0, const double *bed64, int slot_in)
+{
+    constexpr int M = SysInfo<SYS, D>::M, Q = SysInfo<SYS, D>::Q;
+    const Phys<T> P = make_phys<T>(L);
+    // coefficients of the initial state, same formulas as a step
+    const double ab0 = bitsd(L.sc->abar[slot_in][0]);
+    const double ab1 = D == 2 ? bitsd(L.sc->abar[slot_in][1]) : 0.0;
+    const double sa = D == 2 ? ab0 + ab1 : ab0;
+    const double dt = L.cfl * L.dx / sa;
+    const double lam = L.dx / dt;
+    const double al0 = ab0 + L.eps, al1 = ab1 + L.eps;
+    const double sum_alpha = D == 2 ? al0 + al1 : al0;
+    const T a0 = T(1.0 - sum_alpha / lam), ap0 = T(al0 / (2.0 * lam)), ap1 = T(al1 / (2.0 * lam));
+    const T bp = T(1.0 / (2.0 * lam)), bm = T(-1.0 / (2.0 * lam));
+    T *f = (T *)L.f[0];
+    T *u = (T *)L.u[0];
+    T s0 = T(0), s1 = T(0);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.plane;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        T U[M], Fx[M], Fy[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) U[c] = T(U0[(int64_t)c * L.plane + i]);
+        Prim<T> q;
+        primitives<SYS, D, T>(U, P, q);
+        flux<SYS, D, T>(0, U, q, P, Fx);
+        if constexpr (D == 2) flux<SYS, D, T>(1, U, q, P, Fy);
+        T Un[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            T feq[Q];
+            feq[0] = a0 * U[c];
+            if constexpr (D == 1) {
+                feq[1] = ap0 * U[c] + bp * Fx[c];
+                feq[2] = ap0 * U[c] + bm * Fx[c];
+            } else {
+                feq[1] = ap0 * U[c] + bp * Fx[c];
+                feq[2] = ap1 * U[c] + bp * Fy[c];
+                feq[3] = ap0 * U[c] + bm * Fx[c];
+                feq[4] = ap1 * U[c] + bm * Fy[c];
+            }
+            T s = feq[0];
+#pragma unroll
+            for (int k = 1; k < Q; ++k) s = s + feq[k];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) f[(int64_t)(k * M + c) * L.plane + i] = feq[k];
+            Un[c] = s;
+            u[(int64_t)c * L.plane + i] = s;
+        }
+        if (bed64 && L.bed) ((T *)L.bed)[i] = T(bed64[i]);
+        Prim<T> qn;
+        primitives<SYS, D, T>(Un, P, qn);
+        const T v0 = max_speed<SYS, T>(0, qn, P);
+        if (finite_val<T>(v0) && v0 > s0) s0 = v0;
+        if constexpr (D == 2) {
+            const T v1 = max_speed<SYS, T>(1, qn, P);
+            if (finite_val<T>(v1) && v1 > s1) s1 = v1;
+        }
+    }
+    const double m0 = (double)wave_max<T>(s0), m1 = (double)wave_max<T>(s1);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&L.sc->abar[0][0], dbits(m0));
+        if (D == 2) atomicMax(&L.sc->abar[0][1], dbits(m1));
+    }
+}
+
+// Per-block compensated (Neumaier) sums of each moment plane, in a fixed
+// order: partial[c * gridDim.x + block].
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_conservation(const T *u, int64_t plane, int m, double *partial)
+{
+    __shared__ double ss[kBlock], cc[kBlock];
+    const int64_t per = (plane + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < plane ? lo + per : plane;
+    for (int c = 0; c < m; ++c) {
+        double s = 0.0, e = 0.0;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            const double v = (double)u[(int64_t)c * plane + i];
+            const double t = s + v;
+            e += __builtin_fabs(s) >= __builtin_fabs(v) ? (s - t) + v : (v - t) + s;
+            s = t;
+        }
+        ss[threadIdx.x] = s;
+        cc[threadIdx.x] = e;
+        __syncthreads();
+        for (int h = kBlock / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) {
+                const double a = ss[threadIdx.x], b = ss[threadIdx.x + h];
+                const double t = a + b;
+                const double err = __builtin_fabs(a) >= __builtin_fabs(b) ? (a - t) + b : (b - t) + a;
+                ss[threadIdx.x] = t;
+                cc[threadIdx.x] = cc[threadIdx.x] + cc[threadIdx.x + h] + err;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[(int64_t)c * gridDim.x + blockIdx.x] = ss[0] + cc[0];
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_to_double(const T *src, double *dst, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (double)src[i];
+}
+
+}  // namespace arlbm
