@@ -153,8 +153,11 @@ int arlbm_set_state_device(arlbm_lattice *h, const double *U0_dev, const double 
 int arlbm_step(arlbm_lattice *h, int64_t n);
 
 /* Wait for the stream and report the status.  Returns ENONFINITE,
- * EPOSITIVITY or EDEGENERATE when the matching flag is set (status still
- * filled), else 0. */
+ * EDEGENERATE or EPOSITIVITY when the matching flag is set (status still
+ * filled), else 0.  EPOSITIVITY is advisory: the method has no positivity
+ * mechanism, so a state with a density, pressure or depth below its floor is
+ * still the method's result and stepping may continue; the two others mean
+ * the state is no longer usable. */
 int arlbm_sync(arlbm_lattice *h, arlbm_status *st);
 
 /* Copy the current moments U = sum_k f_k to host FP64 planes (synchronises). */
@@ -193,8 +196,9 @@ typedef struct arlbm_server arlbm_server;
 
 typedef struct arlbm_completion {
     uint64_t id;          /* id returned by submit                              */
-    int32_t status;       /* 0 or an ARLBM_E* code                              */
-    int32_t reserved;
+    int32_t status;       /* 0 or an ARLBM_E* code (EPOSITIVITY is reported in
+                             flags, with status 0)                             */
+    uint32_t flags;       /* ARLBM_FLAG_* bits seen during the run              */
     int64_t steps;        /* steps taken                                        */
     double t;             /* simulated time reached                             */
     double submit_s;      /* host clock (seconds) at submit                     */

@@ -65,7 +65,7 @@ class Status(C.Structure):
 
 
 class Completion(C.Structure):
-    _fields_ = [("id", C.c_uint64), ("status", C.c_int32), ("reserved", C.c_int32), ("steps", C.c_int64),
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int32), ("flags", C.c_uint32), ("steps", C.c_int64),
                 ("t", C.c_double), ("submit_s", C.c_double), ("admit_s", C.c_double), ("done_s", C.c_double),
                 ("U", C.POINTER(C.c_double)), ("u_count", C.c_int64)]
 
@@ -220,10 +220,12 @@ class Lattice:
     def step(self, n: int = 1):
         _check(lib().arlbm_step(self._h, int(n)), self._h)
 
-    def sync(self, check: bool = True) -> dict:
+    def sync(self, check: bool = True, strict: bool = False) -> dict:
+        """Wait for the stream.  With check, raise on a non-finite or
+        degenerate state (and, with strict, on the advisory positivity flag)."""
         st = Status()
         rc = lib().arlbm_sync(self._h, C.byref(st))
-        if check:
+        if check and (rc != EPOSITIVITY or strict):
             _check(rc, self._h)
         return {"rc": rc, "t": st.t, "last_dt": st.last_dt, "abar": [st.abar[0], st.abar[1]][: self.dim],
                 "step": st.step, "flags": st.flags, "first_bad_step": st.first_bad_step}
@@ -305,7 +307,8 @@ class Server:
         for i in range(n.value):
             c = arr[i]
             U = np.ctypeslib.as_array(c.U, shape=(c.u_count,)).copy() if c.status == OK and c.u_count else None
-            out.append({"id": c.id, "status": c.status, "steps": c.steps, "t": c.t, "submit_s": c.submit_s,
+            out.append({"id": c.id, "status": c.status, "flags": c.flags, "steps": c.steps, "t": c.t,
+                        "submit_s": c.submit_s,
                         "admit_s": c.admit_s, "done_s": c.done_s, "U": U})
         return out
 

@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libarlbm.so")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -33,10 +34,13 @@ def build(verbose: bool = False) -> str:
     k64 = os.path.join(OUT, "kernels_f64.o")
     rt = os.path.join(OUT, "runtime.o")
     kern = os.path.join(SRC, "kernels.hip")
-    _run([HIPCC, *DEVICE_FLAGS, "-DARLBM_F64=0", "-c", kern, "-o", k32], verbose)
+    # FP32: hardware reciprocal / square root (about 1 ulp) instead of the
+    # correctly rounded sequences, and denormals flushed to zero
+    _run([HIPCC, *DEVICE_FLAGS, "-DARLBM_F64=0", "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+          "-fgpu-flush-denormals-to-zero", "-c", kern, "-o", k32], verbose)
     _run([HIPCC, *DEVICE_FLAGS, "-DARLBM_F64=1", "-ffp-contract=off", "-c", kern, "-o", k64], verbose)
     _run([HIPCC, "-std=c++17", "-O2", "-fPIC", "-Wall", "-x", "c++", "-D__HIP_PLATFORM_AMD__",
-          "-I/opt/rocm/include", "-c", os.path.join(SRC, "runtime.cpp"), "-o", rt], verbose)
+          "-I/opt/rocm/include", "-I" + INCLUDE, "-c", os.path.join(SRC, "runtime.cpp"), "-o", rt], verbose)
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, k32, k64, rt], verbose)
     os.replace(tmp, LIB)

@@ -52,6 +52,9 @@ struct LatticeDesc {
     int32_t ncols;        // strips along x
     int64_t iter0;
     int64_t plane;        // nx * ny
+    int64_t pstride;      // elements between planes: plane + a 64-element sink tail
+    int32_t omega_on;     // omega export plane present (else omega is a 64-slot sink)
+    int32_t pad_;
     double dx, cfl, eps, gamma, g, adv[2], h_dry, rho_floor, p_floor, omega_fixed;
 };
 
@@ -76,10 +79,12 @@ struct WorkItem {
     hipError_t step_single(const LatticeDesc &h, int64_t iter, hipStream_t s);                        \
     hipError_t step_batched(const LatticeDesc *d_descs, const WorkItem *d_items, int32_t nitems,      \
                             int64_t iter, hipStream_t s);                                              \
-    hipError_t conservation(const void *u, int64_t plane, int m, double *partial, int nblocks,        \
-                            hipStream_t s);                                                            \
-    hipError_t to_double(const void *src, double *dst, int64_t n, hipStream_t s);                     \
+    hipError_t conservation(const void *u, int64_t plane, int64_t pstride, int m, double *partial,    \
+                            int nblocks, hipStream_t s);                                               \
+    hipError_t to_double(const void *src, double *dst, int64_t plane, int64_t pstride, int m,         \
+                         hipStream_t s);                                                               \
     int step_kernel_vgprs(int variant);                                                                \
+    int step_waves_per_cu(int variant);                                                                \
     }                                                                                                  \
     }
 

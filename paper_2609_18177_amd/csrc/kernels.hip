@@ -50,8 +50,11 @@ static hipError_t step_impl(const LatticeDesc &h, int64_t iter, hipStream_t s)
 {
     const int64_t nbands = D == 2 ? (h.ny + h.band_h - 1) / h.band_h : 1;
     const int64_t nwork = (int64_t)h.ncols * nbands;
-    hipLaunchKernelGGL((k_step_single<SYS, D, real>), dim3(grid_for(nwork, kWavesPerBlock)), dim3(kBlock), 0, s,
-                       h, iter, (int32_t)nwork);
+    const dim3 g(grid_for(nwork, kWavesPerBlock)), b(kBlock);
+    if (SYS == 2 && D == 2 && h.bed)
+        hipLaunchKernelGGL((k_step_single<SYS, D, true, real>), g, b, 0, s, h, iter, (int32_t)nwork);
+    else
+        hipLaunchKernelGGL((k_step_single<SYS, D, false, real>), g, b, 0, s, h, iter, (int32_t)nwork);
     return hipGetLastError();
 }
 
@@ -95,17 +98,37 @@ hipError_t step_batched(const LatticeDesc *d_descs, const WorkItem *d_items, int
     return hipGetLastError();
 }
 
-hipError_t conservation(const void *u, int64_t plane, int m, double *partial, int nblocks, hipStream_t s)
+hipError_t conservation(const void *u, int64_t plane, int64_t pstride, int m, double *partial, int nblocks,
+                        hipStream_t s)
 {
-    hipLaunchKernelGGL((k_conservation<real>), dim3(nblocks), dim3(kBlock), 0, s, (const real *)u, plane, m,
+    hipLaunchKernelGGL((k_conservation<real>), dim3(nblocks), dim3(kBlock), 0, s, (const real *)u, plane, pstride, m,
                        partial);
     return hipGetLastError();
 }
 
-hipError_t to_double(const void *src, double *dst, int64_t n, hipStream_t s)
+hipError_t to_double(const void *src, double *dst, int64_t plane, int64_t pstride, int m, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_to_double<real>), dim3(cell_grid(n)), dim3(kBlock), 0, s, (const real *)src, dst, n);
+    hipLaunchKernelGGL((k_to_double<real>), dim3(cell_grid(plane * m)), dim3(kBlock), 0, s, (const real *)src, dst,
+                       plane, pstride, m);
     return hipGetLastError();
+}
+
+// Waves of the single-lattice step kernel resident per CU at full occupancy.
+int step_waves_per_cu(int variant)
+{
+    const void *fn = nullptr;
+    switch (variant) {
+    case V_ADV1: fn = (const void *)&k_step_single<0, 1, false, real>; break;
+    case V_EUL1: fn = (const void *)&k_step_single<1, 1, false, real>; break;
+    case V_SWE1: fn = (const void *)&k_step_single<2, 1, false, real>; break;
+    case V_ADV2: fn = (const void *)&k_step_single<0, 2, false, real>; break;
+    case V_EUL2: fn = (const void *)&k_step_single<1, 2, false, real>; break;
+    case V_SWE2: fn = (const void *)&k_step_single<2, 2, true, real>; break;
+    default: return 0;
+    }
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kBlock, 0) != hipSuccess) return 0;
+    return blocks * kWavesPerBlock;
 }
 
 int step_kernel_vgprs(int variant)
@@ -113,12 +136,12 @@ int step_kernel_vgprs(int variant)
     hipFuncAttributes a;
     const void *fn = nullptr;
     switch (variant) {
-    case V_ADV1: fn = (const void *)&k_step_single<0, 1, real>; break;
-    case V_EUL1: fn = (const void *)&k_step_single<1, 1, real>; break;
-    case V_SWE1: fn = (const void *)&k_step_single<2, 1, real>; break;
-    case V_ADV2: fn = (const void *)&k_step_single<0, 2, real>; break;
-    case V_EUL2: fn = (const void *)&k_step_single<1, 2, real>; break;
-    case V_SWE2: fn = (const void *)&k_step_single<2, 2, real>; break;
+    case V_ADV1: fn = (const void *)&k_step_single<0, 1, false, real>; break;
+    case V_EUL1: fn = (const void *)&k_step_single<1, 1, false, real>; break;
+    case V_SWE1: fn = (const void *)&k_step_single<2, 1, false, real>; break;
+    case V_ADV2: fn = (const void *)&k_step_single<0, 2, false, real>; break;
+    case V_EUL2: fn = (const void *)&k_step_single<1, 2, false, real>; break;
+    case V_SWE2: fn = (const void *)&k_step_single<2, 2, true, real>; break;
     default: return -1;
     }
     if (hipFuncGetAttributes(&a, fn) != hipSuccess) return -1;

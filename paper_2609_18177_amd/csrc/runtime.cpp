@@ -17,7 +17,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/arlbm.h"
+#include "arlbm.h"
 #include "arlbm_internal.h"
 
 using namespace arlbm;
@@ -50,7 +50,9 @@ std::string check_config(const arlbm_config *c)
     if (c->nx < 4) return "nx must be >= 4";
     if (c->dim == 1 && c->ny != 1) return "ny must be 1 in 1D";
     if (c->dim == 2 && c->ny < 4) return "ny must be >= 4";
-    if (c->nx > (1 << 26) || c->ny > (1 << 26) || c->nx * c->ny > ((int64_t)1 << 34)) return "lattice too large";
+    if (c->nx > (1 << 26) || c->ny > (1 << 26)) return "lattice too large";
+    // kernels address cells within a plane with 32-bit offsets
+    if (c->nx * c->ny > (int64_t)0x7fffffff) return "a plane exceeds 2^31 cells";
     if (!(c->x1 > c->x0)) return "x1 must exceed x0";
     if (c->dim == 2) {
         if (!(c->y1 > c->y0)) return "y1 must exceed y0";
@@ -82,29 +84,62 @@ std::string check_config(const arlbm_config *c)
     return "";
 }
 
+// Planes are stored at a stride of nx*ny rounded up past a 64-element tail
+// (the kernels' store sink), a multiple of 64 elements.
+int64_t plane_stride(const arlbm_config *c)
+{
+    const int64_t plane = c->nx * c->ny;
+    return (plane + 64 + 63) / 64 * 64;
+}
+
 void fill_sizes(const arlbm_config *c, arlbm_sizes *o)
 {
     const int m = num_fields(c->system, c->dim), q = q_of(c->dim);
     const size_t s = c->precision == ARLBM_F64 ? 8 : 4;
-    const size_t plane = (size_t)c->nx * (size_t)c->ny;
+    const size_t ps = (size_t)plane_stride(c);
     o->m = m;
     o->q = q;
-    o->f_bytes = align_up((size_t)q * m * plane * s);
-    o->u_bytes = align_up((size_t)m * plane * s);
-    o->bed_bytes = c->has_bed ? align_up(plane * s) : 0;
+    o->f_bytes = align_up((size_t)q * m * ps * s);
+    o->u_bytes = align_up((size_t)m * ps * s);
+    o->bed_bytes = c->has_bed ? align_up(ps * s) : 0;
     o->scalar_bytes = align_up(sizeof(DevScalars));
-    o->omega_bytes = align_up(plane * s);
+    o->omega_bytes = align_up(ps * s);
     o->total_bytes = 2 * o->f_bytes + 2 * o->u_bytes + o->bed_bytes + o->scalar_bytes;
     o->alignment = kAlign;
 }
 
-// Rows per strip: long strips amortise the 3-row warm-up; shorter ones give
-// enough waves to fill 256 CUs.
-int choose_band(int64_t ny, int ncols)
+// Rows per strip.  Each strip pays a warm-up of 3 extra moment rows and 2
+// extra indicator rows, so strips should be long; but the grid should also
+// fill the GPU in one round: the number of strips is kept at or just below
+// the number of waves the GPU holds at once (CUs x resident waves per CU), so
+// no short second round runs on a mostly idle chip.
+#ifndef ARLBM_BAND_WAVE_SCALE
+#define ARLBM_BAND_WAVE_SCALE 1.0
+#endif
+int choose_band(int64_t ny, int ncols, int64_t resident_waves)
 {
-    int h = 64;
-    while (h > 16 && (int64_t)ncols * ((ny + h - 1) / h) < 4096) h /= 2;
-    return h;
+    if (resident_waves <= 0) resident_waves = 4096;
+    resident_waves = (int64_t)(resident_waves * ARLBM_BAND_WAVE_SCALE);
+    int64_t nb = resident_waves / ncols;
+    if (nb < 1) nb = 1;
+    int64_t h = (ny + nb - 1) / nb;
+    if (h < 8) h = 8;
+    if (h > ny) h = ny;
+    return (int)h;
+}
+
+int64_t resident_waves(int precision, int variant)
+{
+    static int cus = -1;
+    if (cus < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            v = 256;
+        cus = v;
+    }
+    const int w = precision == ARLBM_F64 ? f64::step_waves_per_cu(variant) : f32::step_waves_per_cu(variant);
+    return (int64_t)cus * (w > 0 ? w : 16);
 }
 
 }  // namespace
@@ -119,6 +154,7 @@ struct arlbm_lattice {
     bool busy = false;
     int64_t step = 0;
     double *d_partial = nullptr;
+    void *omega_sink = nullptr;  // 64-slot sink the kernels write omega to when export is off
     std::string err;
 };
 
@@ -168,7 +204,8 @@ void free_owned(arlbm_lattice *h)
         if (h->desc.bed) (void)hipFree((void *)h->desc.bed);
         if (h->desc.sc) (void)hipFree(h->desc.sc);
     }
-    if (h->owns_omega && h->desc.omega) (void)hipFree(h->desc.omega);
+    if (h->owns_omega && h->desc.omega && h->desc.omega != h->omega_sink) (void)hipFree(h->desc.omega);
+    if (h->omega_sink) (void)hipFree(h->omega_sink);
     if (h->d_partial) (void)hipFree(h->d_partial);
 }
 
@@ -315,9 +352,10 @@ extern "C" int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, 
     if (cfg->dim == 1) d.bc[2] = d.bc[3] = ARLBM_PERIODIC;
     d.omega_fixed_on = cfg->omega_mode == ARLBM_OMEGA_FIXED;
     d.ncols = (int32_t)((cfg->nx + kOutW - 1) / kOutW);
-    d.band_h = cfg->dim == 2 ? choose_band(cfg->ny, d.ncols) : 1;
+    d.band_h = cfg->dim == 2 ? choose_band(cfg->ny, d.ncols, resident_waves(cfg->precision, d.variant)) : 1;
     d.iter0 = 0;
     d.plane = cfg->nx * cfg->ny;
+    d.pstride = plane_stride(cfg);
     d.dx = (cfg->x1 - cfg->x0) / (double)cfg->nx;
     d.cfl = cfg->cfl;
     d.eps = cfg->eps;
@@ -364,6 +402,13 @@ extern "C" int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, 
         }
     }
     hipError_t err = hipMalloc((void **)&h->d_partial, sizeof(double) * kConsBlocks * 4);
+    if (err == hipSuccess) err = hipMalloc(&h->omega_sink, 64 * sizeof(double));
+    if (err == hipSuccess && !d.omega) {
+        d.omega = h->omega_sink;
+        d.omega_on = 0;
+    } else {
+        d.omega_on = d.omega ? 1 : 0;
+    }
     if (err != hipSuccess) {
         free_owned(h);
         delete h;
@@ -421,14 +466,17 @@ extern "C" int arlbm_sync(arlbm_lattice *h, arlbm_status *st)
     return ARLBM_OK;
 }
 
-static int read_plane_set(arlbm_lattice *h, const void *src, int64_t count, double *out)
+// Copy m strided device planes (stride pstride) to dense host FP64 planes.
+static int read_planes(arlbm_lattice *h, const void *src, int m, double *out)
 {
+    const int64_t plane = h->desc.plane, ps = h->desc.pstride;
     if (is_f64(h)) {
-        HIPCHK(h, hipMemcpyAsync(out, src, sizeof(double) * count, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipMemcpy2DAsync(out, sizeof(double) * plane, src, sizeof(double) * ps, sizeof(double) * plane, m,
+                                   hipMemcpyDeviceToHost, h->stream));
     } else {
         double *stage = (double *)h->desc.f[(h->step + 1) & 1];
-        HIPCHK(h, f32::to_double(src, stage, count, h->stream));
-        HIPCHK(h, hipMemcpyAsync(out, stage, sizeof(double) * count, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, f32::to_double(src, stage, plane, ps, m, h->stream));
+        HIPCHK(h, hipMemcpyAsync(out, stage, sizeof(double) * plane * m, hipMemcpyDeviceToHost, h->stream));
     }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return ARLBM_OK;
@@ -437,22 +485,24 @@ static int read_plane_set(arlbm_lattice *h, const void *src, int64_t count, doub
 extern "C" int arlbm_read_moments(arlbm_lattice *h, double *U)
 {
     if (!h || !U) return fail(h, ARLBM_EINVAL, "NULL argument");
-    return read_plane_set(h, h->desc.u[h->step & 1], (int64_t)h->sz.m * h->desc.plane, U);
+    return read_planes(h, h->desc.u[h->step & 1], h->sz.m, U);
 }
 
 extern "C" int arlbm_set_omega_export(arlbm_lattice *h, int on)
 {
     if (!h) return fail(nullptr, ARLBM_EINVAL, "handle is NULL");
-    if (on && !h->desc.omega) {
+    if (on && !h->desc.omega_on) {
         void *p = nullptr;
         HIPCHK(h, hipMalloc(&p, h->sz.omega_bytes));
         HIPCHK(h, hipMemsetAsync(p, 0, h->sz.omega_bytes, h->stream));
         h->desc.omega = p;
+        h->desc.omega_on = 1;
         h->owns_omega = true;
-    } else if (!on && h->desc.omega) {
+    } else if (!on && h->desc.omega_on) {
         HIPCHK(h, hipStreamSynchronize(h->stream));
         if (h->owns_omega) (void)hipFree(h->desc.omega);
-        h->desc.omega = nullptr;
+        h->desc.omega = h->omega_sink;
+        h->desc.omega_on = 0;
         h->owns_omega = false;
     }
     return ARLBM_OK;
@@ -461,8 +511,8 @@ extern "C" int arlbm_set_omega_export(arlbm_lattice *h, int on)
 extern "C" int arlbm_read_omega(arlbm_lattice *h, double *omega)
 {
     if (!h || !omega) return fail(h, ARLBM_EINVAL, "NULL argument");
-    if (!h->desc.omega) return fail(h, ARLBM_EINVAL, "omega export is off");
-    return read_plane_set(h, h->desc.omega, h->desc.plane, omega);
+    if (!h->desc.omega_on) return fail(h, ARLBM_EINVAL, "omega export is off");
+    return read_planes(h, h->desc.omega, 1, omega);
 }
 
 extern "C" int arlbm_conservation(arlbm_lattice *h, double *sums)
@@ -470,8 +520,10 @@ extern "C" int arlbm_conservation(arlbm_lattice *h, double *sums)
     if (!h || !sums) return fail(h, ARLBM_EINVAL, "NULL argument");
     const int m = h->sz.m;
     const void *u = h->desc.u[h->step & 1];
-    hipError_t e = is_f64(h) ? f64::conservation(u, h->desc.plane, m, h->d_partial, kConsBlocks, h->stream)
-                             : f32::conservation(u, h->desc.plane, m, h->d_partial, kConsBlocks, h->stream);
+    hipError_t e = is_f64(h) ? f64::conservation(u, h->desc.plane, h->desc.pstride, m, h->d_partial, kConsBlocks,
+                                                 h->stream)
+                             : f32::conservation(u, h->desc.plane, h->desc.pstride, m, h->d_partial, kConsBlocks,
+                                                 h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "conservation launch");
     std::vector<double> part((size_t)m * kConsBlocks);
     HIPCHK(h, hipMemcpyAsync(part.data(), h->d_partial, sizeof(double) * part.size(), hipMemcpyDeviceToHost,
@@ -718,6 +770,8 @@ extern "C" int arlbm_server_iterate(arlbm_server *s, int32_t *n_res, int32_t *n_
             arlbm_status st{};
             int rc = arlbm_sync(r.lat, &st);
             d.c.t = st.t;
+            d.c.flags = st.flags;
+            if (rc == ARLBM_EPOSITIVITY) rc = ARLBM_OK;  // advisory: the moments are still the result
             if (rc == ARLBM_OK) rc = arlbm_read_moments(r.lat, d.U.data());
             d.c.status = rc;
             d.c.done_s = now_s();

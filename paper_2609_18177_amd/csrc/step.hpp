@@ -20,6 +20,12 @@
 // direction into a triple-buffered slot.  The kernel launch boundary is the
 // grid barrier that the global maximum needs.
 //
+// Plane layout: plane c of a buffer starts at c * pstride, pstride >= nx ny + 64.
+// The 64-element tail of every plane is a sink: lanes that must not write
+// (halo lanes, warm-up rows) store there, so the steady-state loop carries no
+// conditional memory operation and the compiler can keep the prefetched loads
+// and the stores of the previous row in flight across iterations.
+//
 // Ghost cells: U at ghost positions follows the boundary index map (periodic
 // wrap, or mirror U(-1-i) = U(i) with the normal momentum negated at
 // reflective walls); populations pulled from a mirror ghost are the
@@ -34,12 +40,40 @@ namespace arlbm {
 
 // ---------------------------------------------------------------- helpers --
 
-// Value held by lane l-1 (x - 1) / lane l+1 (x + 1); edge lanes get their own
-// value (those lanes only produce halo values that are never used).
+// Value held by lane l-1 (x - 1) / lane l+1 (x + 1), by one DPP wavefront
+// shift (wave_shr:1 / wave_shl:1); the edge lane keeps its own value (edge
+// lanes only produce halo values that are never used).
+template <int CTRL>
+__device__ __forceinline__ int dpp_shift(int v) { return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false); }
+template <int CTRL, typename T>
+__device__ __forceinline__ T wave_shift(T v)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, dpp_shift<CTRL>(__builtin_bit_cast(int, v)));
+    } else {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = (unsigned)dpp_shift<CTRL>((int)(unsigned)b);
+        const unsigned hi = (unsigned)dpp_shift<CTRL>((int)(unsigned)(b >> 32));
+        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+    }
+}
 template <typename T>
-__device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1, kWave); }
+__device__ __forceinline__ T from_left(T v) { return wave_shift<0x138>(v); }   // wave_shr:1
 template <typename T>
-__device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, kWave); }
+__device__ __forceinline__ T from_right(T v) { return wave_shift<0x130>(v); }  // wave_shl:1
+
+// Loads and stores of one plane at a 32-bit per-lane element offset from the
+// plane's (uniform) base pointer.
+template <typename T>
+__device__ __forceinline__ T ldo(const T *base, unsigned elem_off)
+{
+    return base[elem_off];
+}
+template <typename T>
+__device__ __forceinline__ void sto(T *base, unsigned elem_off, T v)
+{
+    base[elem_off] = v;
+}
 
 template <typename T>
 __device__ __forceinline__ T wave_max(T v)
@@ -187,7 +221,7 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
     const Phys<T> P = make_phys<T>(L);
     const int lane = threadIdx.x & (kWave - 1);
     const int nx = L.nx;
-    const int64_t plane = L.plane;
+    const int64_t plane = L.pstride;
     const T *fin = (const T *)L.f[n & 1];
     T *fout = (T *)L.f[(n + 1) & 1];
     const T *uin = (const T *)L.u[n & 1];
@@ -200,7 +234,7 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
     // moments (with ghost map) and neighbours
     T U[M], UL[M], UR[M];
 #pragma unroll
-    for (int c = 0; c < M; ++c) U[c] = uin[(int64_t)c * plane + xm];
+    for (int c = 0; c < M; ++c) U[c] = ldo(uin + (size_t)c * plane, (unsigned)xm);
     if constexpr (SYS != 0)
         if (rx) U[1] = -U[1];
 #pragma unroll
@@ -216,7 +250,7 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
     const T nuL = from_left(nu), nuR = from_right(nu);
     const T nt = nuL + nu + nuR;
     const T w = L.omega_fixed_on ? cf.omega_fixed : T(1) + T(1) / (T(1) + nt);
-    if (L.omega && out) ((T *)L.omega)[x] = w;
+    if (L.omega_on && out) ((T *)L.omega)[x] = w;
 
     // bed slope by central differences
     T db = T(0);
@@ -240,9 +274,10 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
         const T feq0 = cf.a0 * u;
         const T feq1 = cf.ap[0] * u + cf.bp * F[c];
         const T feq2 = cf.ap[0] * u + cf.bm * F[c];
-        const T f0 = fin[(int64_t)(0 * M + c) * plane + xm];
-        const T f1 = fin[(int64_t)(1 * M + c) * plane + xm];
-        const T f2 = fin[(int64_t)(2 * M + c) * plane + xm];
+        const unsigned xo = (unsigned)xm;
+        const T f0 = ldo(fin + (size_t)(0 * M + c) * plane, xo);
+        const T f1 = ldo(fin + (size_t)(1 * M + c) * plane, xo);
+        const T f2 = ldo(fin + (size_t)(2 * M + c) * plane, xo);
         fs[0][c] = f0 - w * (f0 - feq0);
         fs[1][c] = f1 - w * (f1 - feq1);
         fs[2][c] = f2 - w * (f2 - feq2);
@@ -295,10 +330,10 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
 #pragma unroll
         for (int k = 0; k < Q; ++k)
 #pragma unroll
-            for (int c = 0; c < M; ++c) fout[(int64_t)(k * M + c) * plane + x] = fn[k][c];
+            for (int c = 0; c < M; ++c) sto(fout + (size_t)(k * M + c) * plane, (unsigned)x, fn[k][c]);
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            uout[(int64_t)c * plane + x] = Un[c];
+            sto(uout + (size_t)c * plane, (unsigned)x, Un[c]);
             if (!finite_val<T>(Un[c])) flags |= 1u;
         }
         Prim<T> qn;
@@ -313,7 +348,8 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
 
 // ------------------------------------------------------------------ 2D ----
 
-template <int SYS, typename T>
+
+template <int SYS, bool BED, typename T>
 __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int col, int band, bool first)
 {
     constexpr int D = 2, M = SysInfo<SYS, 2>::M, Q = 5;
@@ -326,12 +362,13 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     const Phys<T> P = make_phys<T>(L);
     const int lane = threadIdx.x & (kWave - 1);
     const int nx = L.nx, ny = L.ny;
-    const int64_t plane = L.plane;
+    const int64_t ps = L.pstride;
     const T *fin = (const T *)L.f[n & 1];
     T *fout = (T *)L.f[(n + 1) & 1];
     const T *uin = (const T *)L.u[n & 1];
     T *uout = (T *)L.u[(n + 1) & 1];
     const T *bed = (const T *)L.bed;
+    T *om = (T *)L.omega;
     const int x = col * kOutW - kHalo + lane;
     bool rx;
     const int xm = bc_map(x, nx, L.bc[0], L.bc[1], rx);
@@ -339,32 +376,44 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     const int ya = band * L.band_h;
     const int yb = ya + L.band_h < ny ? ya + L.band_h : ny;
     const int bxl = L.bc[0], bxh = L.bc[1], byl = L.bc[2], byh = L.bc[3];
-    const bool use_bed = SYS == 2 && bed != nullptr;
+    const unsigned sink = (unsigned)(L.plane + lane);          // this lane's slot in a plane's tail
+    const unsigned osink = L.omega_on ? sink : (unsigned)lane;  // omega sink (64-element buffer when off)
     const T two_dx = T(2) * P.dx;
 
     auto loadU = [&](int j, T *out) {
         bool ry;
         const int jm = bc_map(j, ny, byl, byh, ry);
-        const T *base = uin + (int64_t)jm * nx + xm;
+        const unsigned off = (unsigned)(jm * nx + xm);
 #pragma unroll
-        for (int c = 0; c < M; ++c) out[c] = base[(int64_t)c * plane];
+        for (int c = 0; c < M; ++c) out[c] = ldo(uin + (size_t)c * ps, off);
         if constexpr (SYS != 0) {
             if (rx) out[1] = -out[1];
             if (ry) out[2] = -out[2];
         }
     };
+    auto loadF = [&](int r, T (*out)[M]) {
+        bool ry;
+        const int rm = bc_map(r, ny, byl, byh, ry);
+        const unsigned off = (unsigned)(rm * nx + xm);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+#pragma unroll
+            for (int c = 0; c < M; ++c) out[k][c] = ldo(fin + (size_t)(k * M + c) * ps, off);
+    };
     auto loadB = [&](int j) -> T {
         bool ry;
         const int jm = bc_map(j, ny, byl, byh, ry);
-        return bed[(int64_t)jm * nx + xm];
+        return ldo(bed, (unsigned)(jm * nx + xm));
     };
 
     T U0[M], U1[M], U2[M];           // U rows j-2, j-1, j
-    T N0 = 0, N0l = 0, N0r = 0;      // nu rows j-3, j-2, j-1 and x -+ 1
+    T Unx[M];                        // U row j+1 (in flight)
+    T fnx[Q][M];                     // f row j-1 (in flight)
+    T N0 = 0, N0l = 0, N0r = 0;      // nu rows j-3, j-2, j-1 and at x -+ 1
     T N1 = 0, N1l = 0, N1r = 0;
     T N2 = 0, N2l = 0, N2r = 0;
-    T B0 = 0, B1 = 0, B2 = 0;        // bed rows r-1, r, r+1
-    T dbx_prev = 0, dby_prev = 0;    // bed slope at the previous f* row
+    T B0 = 0, B1 = 0, B2 = 0, Bnx = 0; // bed rows r-1, r, r+1; row r+2 in flight
+    T dbx_prev = 0, dby_prev = 0;    // bed slope of the previous f* row
     T P1[M], P2[M];                  // f*_{+y} of rows r-1 and r-2
     T G0[M], Gpx[M], Gmx[M], Gmy[M]; // row r-1: f*_0, pulled +x, pulled -x, own f*_{-y}
 #pragma unroll
@@ -374,59 +423,89 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     }
     T s0 = T(0), s1 = T(0);
     unsigned flags = 0;
-    if (use_bed) {
-        B1 = loadB(ya - 2);
-        B2 = loadB(ya - 1);
-    }
 
-    for (int j = ya - 3; j <= yb + 2; ++j) {
+    auto nu_row = [&]() {  // nu at the row of U1 (eqs. 2.13-2.14)
+        Prim<T> qc;
+        primitives<SYS, D, T>(U1, P, qc);
+        T UL[M], UR[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            UL[c] = from_left(U1[c]);
+            UR[c] = from_right(U1[c]);
+        }
+        T nu = T(0);
+        add_theta<SYS, D, T>(0, qc, U1, UL, UR, P, nu);
+        add_theta<SYS, D, T>(1, qc, U1, U0, U2, P, nu);
+        N0 = N1; N0l = N1l; N0r = N1r;
+        N1 = N2; N1l = N2l; N1r = N2r;
+        N2 = nu;
+        N2l = from_left(nu);
+        N2r = from_right(nu);
+    };
+    auto roll_U = [&](int j) {  // U2 <- row j (prefetched), then prefetch row j+1
 #pragma unroll
         for (int c = 0; c < M; ++c) {
             U0[c] = U1[c];
             U1[c] = U2[c];
+            U2[c] = Unx[c];
         }
-        loadU(j, U2);
-        if (j < ya - 1) continue;
-        // nu at row j-1 (eqs. 2.13-2.14)
-        {
-            Prim<T> qc;
-            primitives<SYS, D, T>(U1, P, qc);
-            T UL[M], UR[M];
+        loadU(j + 1, Unx);
+    };
+
+    // The population row is loaded one iteration ahead in FP32 (Q m extra
+    // registers); in FP64 that would halve the waves per SIMD, so the row is
+    // loaded in the iteration that uses it.
+    constexpr bool kPrefetchF = sizeof(T) == 4;
+
+    // prologue: moment rows ya-3 .. ya, indicator rows ya-2 .. ya-1
+    loadU(ya - 3, Unx);
+    if constexpr (BED) {
+        B1 = loadB(ya - 2);
+        B2 = loadB(ya - 1);
+        Bnx = loadB(ya);
+    }
+    roll_U(ya - 3);
+    roll_U(ya - 2);
+    roll_U(ya - 1);
+    nu_row();
+    roll_U(ya);
+    if constexpr (kPrefetchF) loadF(ya - 1, fnx);
+    nu_row();
+
+    // steady state: every iteration loads U(j+1) and f(j-1), computes nu at
+    // row j-1, omega and f* at row r = j-2, and writes destination row j-3
+    for (int j = ya + 1; j <= yb + 2; ++j) {
+        roll_U(j);
+        T fcur[Q][M];
+        const int r = j - 2;
+        if constexpr (kPrefetchF) {
 #pragma unroll
-            for (int c = 0; c < M; ++c) {
-                UL[c] = from_left(U1[c]);
-                UR[c] = from_right(U1[c]);
-            }
-            T nu = T(0);
-            add_theta<SYS, D, T>(0, qc, U1, UL, UR, P, nu);
-            add_theta<SYS, D, T>(1, qc, U1, U0, U2, P, nu);
-            N0 = N1; N0l = N1l; N0r = N1r;
-            N1 = N2; N1l = N2l; N1r = N2r;
-            N2 = nu;
-            N2l = from_left(nu);
-            N2r = from_right(nu);
+            for (int k = 0; k < Q; ++k)
+#pragma unroll
+                for (int c = 0; c < M; ++c) fcur[k][c] = fnx[k][c];
+            loadF(j - 1, fnx);
+        } else {
+            loadF(r, fcur);
         }
-        if (j < ya + 1) continue;
-        const int r = j - 2;  // f* row: U0 holds U(r)
+        T dbx = T(0), dby = T(0);
+        if constexpr (BED) {
+            B0 = B1;
+            B1 = B2;
+            B2 = Bnx;
+            Bnx = loadB(r + 2);
+        }
+        nu_row();
         // 3x3 box sum (2.15) in row-major order, relaxation parameter (2.16)
         const T nt = N0l + N0 + N0r + N1l + N1 + N1r + N2l + N2 + N2r;
         const T w = L.omega_fixed_on ? cf.omega_fixed : T(1) + T(1) / (T(1) + nt);
-        if (L.omega && xout && r >= ya && r < yb) ((T *)L.omega)[(int64_t)r * nx + x] = w;
-        // bed slope at row r
-        T dbx = T(0), dby = T(0);
-        if (use_bed) {
-            B0 = B1;
-            B1 = B2;
-            B2 = loadB(r + 1);
+        sto(om, (xout && r >= ya && r < yb && L.omega_on) ? (unsigned)(r * nx + x) : osink, w);
+        if constexpr (BED) {
             dbx = (from_right(B1) - from_left(B1)) / two_dx;
             dby = (B2 - B0) / two_dx;
         }
         // equilibrium (2.20) and collision at the source nodes of row r
         T fs[Q][M];
         {
-            bool ry;
-            const int rm = bc_map(r, ny, byl, byh, ry);
-            const T *fb = fin + (int64_t)rm * nx + xm;
             Prim<T> q;
             primitives<SYS, D, T>(U0, P, q);
             T Fx[M], Fy[M];
@@ -439,11 +518,11 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
                                   cf.ap[0] * u + cf.bm * Fx[c], cf.ap[1] * u + cf.bm * Fy[c]};
 #pragma unroll
                 for (int k = 0; k < Q; ++k) {
-                    const T fk = fb[(int64_t)(k * M + c) * plane];
+                    const T fk = fcur[k][c];
                     fs[k][c] = fk - w * (fk - feq[k]);
                 }
             }
-            if (use_bed) {
+            if constexpr (BED) {
                 const T S1 = -P.g * U0[0] * dbx, S2 = -P.g * U0[0] * dby;
                 const T ak[Q] = {cf.a0, cf.ap[0], cf.ap[1], cf.ap[0], cf.ap[1]};
 #pragma unroll
@@ -470,7 +549,7 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
         }
         // destination row d = r-1: F_0, F_{+x}, F_{+y}, F_{-x}, F_{-y}
         const int d = r - 1;
-        if (d >= ya && xout) {
+        {
             T Fk[Q][M];
 #pragma unroll
             for (int c = 0; c < M; ++c) {
@@ -487,7 +566,7 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
             T sumF[M];
 #pragma unroll
             for (int c = 0; c < M; ++c) sumF[c] = Fk[0][c] + Fk[1][c] + Fk[2][c] + Fk[3][c] + Fk[4][c];
-            if (use_bed) {
+            if constexpr (BED) {
                 const T S1 = -P.g * sumF[0] * dbx_prev, S2 = -P.g * sumF[0] * dby_prev;
                 const T ak[Q] = {cf.a0, cf.ap[0], cf.ap[1], cf.ap[0], cf.ap[1]};
 #pragma unroll
@@ -499,22 +578,25 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
             T Un[M];
 #pragma unroll
             for (int c = 0; c < M; ++c) Un[c] = Fk[0][c] + Fk[1][c] + Fk[2][c] + Fk[3][c] + Fk[4][c];
-            const int64_t o = (int64_t)d * nx + x;
+            const bool ok = xout && d >= ya;
+            const unsigned o = ok ? (unsigned)(d * nx + x) : sink;
 #pragma unroll
             for (int k = 0; k < Q; ++k)
 #pragma unroll
-                for (int c = 0; c < M; ++c) fout[(int64_t)(k * M + c) * plane + o] = Fk[k][c];
+                for (int c = 0; c < M; ++c) sto(fout + (size_t)(k * M + c) * ps, o, Fk[k][c]);
 #pragma unroll
-            for (int c = 0; c < M; ++c) {
-                uout[(int64_t)c * plane + o] = Un[c];
-                if (!finite_val<T>(Un[c])) flags |= 1u;
-            }
+            for (int c = 0; c < M; ++c) sto(uout + (size_t)c * ps, o, Un[c]);
             Prim<T> qn;
             primitives<SYS, D, T>(Un, P, qn);
-            flags |= qn.flags;
             const T v0 = max_speed<SYS, T>(0, qn, P), v1 = max_speed<SYS, T>(1, qn, P);
-            if (finite_val<T>(v0) && v0 > s0) s0 = v0;
-            if (finite_val<T>(v1) && v1 > s1) s1 = v1;
+            bool fin_ok = true;
+#pragma unroll
+            for (int c = 0; c < M; ++c) fin_ok = fin_ok && finite_val<T>(Un[c]);
+            if (ok) {
+                flags |= qn.flags | (fin_ok ? 0u : 1u);
+                if (finite_val<T>(v0) && v0 > s0) s0 = v0;
+                if (finite_val<T>(v1) && v1 > s1) s1 = v1;
+            }
         }
         // roll the pulled-population window
 #pragma unroll
@@ -548,15 +630,18 @@ __device__ __forceinline__ int logical_wave()
     return __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + (int)(threadIdx.x >> 6));
 }
 
-template <int SYS, int D, typename T>
-__global__ __launch_bounds__(kBlock) void k_step_single(LatticeDesc L, int64_t iter, int32_t nwork)
+#ifndef ARLBM_STEP_MIN_WAVES
+#define ARLBM_STEP_MIN_WAVES 1
+#endif
+template <int SYS, int D, bool BED, typename T>
+__global__ __launch_bounds__(kBlock, ARLBM_STEP_MIN_WAVES) void k_step_single(LatticeDesc L, int64_t iter, int32_t nwork)
 {
     const int w = logical_wave();
     if (w >= nwork) return;
     if constexpr (D == 1) {
         strip1d<SYS, T>(L, iter, w, w == 0);
     } else {
-        strip2d<SYS, T>(L, iter, w % L.ncols, w / L.ncols, w == 0);
+        strip2d<SYS, BED, T>(L, iter, w % L.ncols, w / L.ncols, w == 0);
     }
 }
 
@@ -572,9 +657,12 @@ __global__ __launch_bounds__(kBlock) void k_step_batched(const LatticeDesc *desc
     case V_ADV1: strip1d<0, T>(L, iter, it.col, it.first); break;
     case V_EUL1: strip1d<1, T>(L, iter, it.col, it.first); break;
     case V_SWE1: strip1d<2, T>(L, iter, it.col, it.first); break;
-    case V_ADV2: strip2d<0, T>(L, iter, it.col, it.band, it.first); break;
-    case V_EUL2: strip2d<1, T>(L, iter, it.col, it.band, it.first); break;
-    case V_SWE2: strip2d<2, T>(L, iter, it.col, it.band, it.first); break;
+    case V_ADV2: strip2d<0, false, T>(L, iter, it.col, it.band, it.first); break;
+    case V_EUL2: strip2d<1, false, T>(L, iter, it.col, it.band, it.first); break;
+    case V_SWE2:
+        if (L.bed) strip2d<2, true, T>(L, iter, it.col, it.band, it.first);
+        else strip2d<2, false, T>(L, iter, it.col, it.band, it.first);
+        break;
     default: break;
     }
 }
@@ -654,9 +742,9 @@ __global__ __launch_bounds__(kBlock) void k_init(LatticeDesc L, const double *U0
 #pragma unroll
             for (int k = 1; k < Q; ++k) s = s + feq[k];
 #pragma unroll
-            for (int k = 0; k < Q; ++k) f[(int64_t)(k * M + c) * L.plane + i] = feq[k];
+            for (int k = 0; k < Q; ++k) f[(int64_t)(k * M + c) * L.pstride + i] = feq[k];
             Un[c] = s;
-            u[(int64_t)c * L.plane + i] = s;
+            u[(int64_t)c * L.pstride + i] = s;
         }
         if (bed64 && L.bed) ((T *)L.bed)[i] = T(bed64[i]);
         Prim<T> qn;
@@ -678,7 +766,8 @@ __global__ __launch_bounds__(kBlock) void k_init(LatticeDesc L, const double *U0
 // Per-block compensated (Neumaier) sums of each moment plane, in a fixed
 // order: partial[c * gridDim.x + block].
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_conservation(const T *u, int64_t plane, int m, double *partial)
+__global__ __launch_bounds__(kBlock) void k_conservation(const T *u, int64_t plane, int64_t pstride, int m,
+                                                          double *partial)
 {
     __shared__ double ss[kBlock], cc[kBlock];
     const int64_t per = (plane + gridDim.x - 1) / gridDim.x;
@@ -687,7 +776,7 @@ __global__ __launch_bounds__(kBlock) void k_conservation(const T *u, int64_t pla
     for (int c = 0; c < m; ++c) {
         double s = 0.0, e = 0.0;
         for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-            const double v = (double)u[(int64_t)c * plane + i];
+            const double v = (double)u[(int64_t)c * pstride + i];
             const double t = s + v;
             e += __builtin_fabs(s) >= __builtin_fabs(v) ? (s - t) + v : (v - t) + s;
             s = t;
@@ -710,11 +799,16 @@ __global__ __launch_bounds__(kBlock) void k_conservation(const T *u, int64_t pla
     }
 }
 
+// m planes at stride pstride -> dense FP64 planes of `plane` values.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_to_double(const T *src, double *dst, int64_t n)
+__global__ __launch_bounds__(kBlock) void k_to_double(const T *src, double *dst, int64_t plane, int64_t pstride,
+                                                       int m)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = (double)src[i];
+    const int64_t n = plane * m;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = i / plane, k = i - c * plane;
+        dst[i] = (double)src[c * pstride + k];
+    }
 }
 
 }  // namespace arlbm

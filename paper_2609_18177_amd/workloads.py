@@ -219,7 +219,10 @@ def swe_bed_2d(seed=0, n=4096, cfl=0.5, steps=2000, level=1.0) -> Problem:
     X, Y = np.meshgrid(x, x, indexing="xy")
     bed = np.zeros((n, n))
     for Hm, wm, cm in zip(H, w, cen):
-        bed += Hm * np.exp(-((X - cm[0]) ** 2 + (Y - cm[1]) ** 2) / (wm * wm))
+        # exp(-|x - c|^2 / w^2) as an outer product of its two 1D factors
+        gx = np.exp(-((x - cm[0]) ** 2) / (wm * wm))
+        gy = np.exp(-((x - cm[1]) ** 2) / (wm * wm))
+        bed += Hm * np.outer(gy, gx)
     inside = (X - dc[0]) ** 2 + (Y - dc[1]) ** 2 <= dr * dr
     h = np.where(inside, np.maximum(0.0, level - bed), 0.0)
     U0 = swe_conserved(h, 0 * h, 0 * h, dim=2)
