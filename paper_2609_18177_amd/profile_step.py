@@ -1,0 +1,130 @@
+"""Profile the fused step kernel with rocprofv3 and summarise into profiles/.
+
+Runs, each as its own rocprofv3 process on the benchmark's single-workload
+mode (the launch configuration bench.py times):
+
+1. ``--kernel-trace --stats``: average kernel duration;
+2. ``--pmc FETCH_SIZE`` and 3. ``--pmc WRITE_SIZE``: HBM kilobytes per
+   dispatch of the step kernel;
+4./5. the same two counters for a plain 1 GiB device copy, which calibrate
+   the counters (bytes the copy must move / what the counter reports).
+
+Writes ``profiles/<workload>_pmc.json`` (HBM bytes per launch, keyed to a
+hash of the kernel sources) and ``profiles/<workload>_rocprof.md`` (the
+figures and the commands).  Usage, on a GPU machine, from the repository
+root::
+
+    python -m paper_2609_18177_amd.profile_step --workload euler2d_f32 --raw gpurun_out/prof
+"""
+import argparse
+import csv
+import collections
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402  (kernel source hash; bench imports no GPU module at import time)
+
+KERNELS = {"euler2d_f32": "k_step_single<1, 2, false, float>",
+           "euler2d_f64": "k_step_single<1, 2, false, double>",
+           "swe2d_f32": "k_step_single<2, 2, true, float>"}
+WORKLOAD_NAMES = {"euler2d_f32": "euler2d_2048_f32", "euler2d_f64": "euler2d_2048_f64",
+                  "swe2d_f32": "swe2d_4096_f32"}
+
+
+def rocprof(args, raw, tag, prog, timeout):
+    out = os.path.join(raw, tag)
+    cmd = ["rocprofv3", *args, "--output-format", "csv", "-d", out, "-o", "run", "--", sys.executable, "-u", *prog]
+    print("+", " ".join(cmd), flush=True)
+    with open(os.path.join(raw, tag + ".log"), "w") as log:
+        subprocess.run(cmd, cwd=ROOT, stdout=log, stderr=subprocess.STDOUT, timeout=timeout, check=True)
+    rel = os.path.relpath(out, ROOT)
+    return out, " ".join(["rocprofv3", *args, "--output-format csv -d", rel, "-o run --", "python3 -u", *prog])
+
+
+def per_dispatch(csv_path, counter, name_part):
+    vals = collections.defaultdict(float)
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]:
+                vals[int(r["Dispatch_Id"])] += float(r["Counter_Value"])
+    v = sorted(vals.values())
+    return (sum(v) / len(v), len(v)) if v else (None, 0)
+
+
+def kernel_stats(csv_path, name_part):
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if name_part in r["Name"]:
+                return {"calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]), "min_ns": float(r["MinNs"]),
+                        "max_ns": float(r["MaxNs"])}
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", choices=sorted(KERNELS), default="euler2d_f32")
+    ap.add_argument("--raw", default="gpurun_out/prof")
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--profiles-dir", default=os.path.join(ROOT, "profiles"))
+    args = ap.parse_args()
+    raw = os.path.abspath(args.raw)
+    os.makedirs(raw, exist_ok=True)
+    prog = ["bench.py", "--only", args.workload, "--steps", str(args.steps), "--warmup", "10"]
+    kname = KERNELS[args.workload]
+    d, cmd_trace = rocprof(["--kernel-trace", "--stats"], raw, "trace", prog, 300)
+    stats = kernel_stats(os.path.join(d, "run_kernel_stats.csv"), kname)
+    pmc_prog = ["bench.py", "--only", args.workload, "--steps", "10", "--warmup", "2"]
+    d, cmd_fetch = rocprof(["--pmc", "FETCH_SIZE"], raw, "fetch", pmc_prog, 120)
+    fetch_kib, nf = per_dispatch(os.path.join(d, "run_counter_collection.csv"), "FETCH_SIZE", kname)
+    d, cmd_write = rocprof(["--pmc", "WRITE_SIZE"], raw, "write", pmc_prog, 120)
+    write_kib, nw = per_dispatch(os.path.join(d, "run_counter_collection.csv"), "WRITE_SIZE", kname)
+    cal_prog = ["bench.py", "--copy-calibration"]
+    d, cmd_cf = rocprof(["--pmc", "FETCH_SIZE"], raw, "copy_fetch", cal_prog, 120)
+    copy_fetch_kib, _ = per_dispatch(os.path.join(d, "run_counter_collection.csv"), "FETCH_SIZE", "copyBuffer")
+    d, cmd_cw = rocprof(["--pmc", "WRITE_SIZE"], raw, "copy_write", cal_prog, 120)
+    copy_write_kib, _ = per_dispatch(os.path.join(d, "run_counter_collection.csv"), "WRITE_SIZE", "copyBuffer")
+    gib = float(1 << 30)
+    read_scale = gib / (copy_fetch_kib * 1024.0)
+    write_scale = gib / (copy_write_kib * 1024.0)
+    read_b = fetch_kib * 1024.0 * read_scale
+    write_b = write_kib * 1024.0 * write_scale
+    wl = WORKLOAD_NAMES[args.workload]
+    rec = {"workload": wl, "kernel": kname, "kernel_source_sha256_16": bench.kernel_source_hash(),
+           "avg_kernel_ns": stats["avg_ns"] if stats else None, "kernel_calls": stats["calls"] if stats else None,
+           "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,
+           "copy_fetch_kib_for_1GiB": copy_fetch_kib, "copy_write_kib_for_1GiB": copy_write_kib,
+           "read_scale": read_scale, "write_scale": write_scale,
+           "hbm_read_bytes_per_launch": read_b, "hbm_write_bytes_per_launch": write_b,
+           "hbm_bytes_per_launch": read_b + write_b,
+           "commands": [cmd_trace, cmd_fetch, cmd_write, cmd_cf, cmd_cw]}
+    pdir = os.path.abspath(args.profiles_dir)
+    os.makedirs(pdir, exist_ok=True)
+    with open(os.path.join(pdir, f"{wl}_pmc.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    with open(os.path.join(pdir, f"{wl}_rocprof.md"), "w") as f:
+        f.write(f"# rocprofv3 summary: {kname}, workload {wl}\n\n")
+        f.write(f"Made by `python -m paper_2609_18177_amd.profile_step --workload {args.workload}` "
+                f"(kernel source hash {rec['kernel_source_sha256_16']}); the passes it ran:\n\n")
+        for c in rec["commands"]:
+            f.write(f"    {c}\n")
+        f.write("\n| quantity | value |\n|---|---|\n")
+        if stats:
+            f.write(f"| kernel calls (trace run) | {stats['calls']} |\n")
+            f.write(f"| average kernel duration | {stats['avg_ns'] / 1e3:.2f} us |\n")
+            f.write(f"| min / max duration | {stats['min_ns'] / 1e3:.2f} / {stats['max_ns'] / 1e3:.2f} us |\n")
+        f.write(f"| FETCH_SIZE per dispatch | {fetch_kib:.4g} KiB ({nf} dispatches) |\n")
+        f.write(f"| WRITE_SIZE per dispatch | {write_kib:.4g} KiB ({nw} dispatches) |\n")
+        f.write(f"| 1 GiB copy: FETCH_SIZE / WRITE_SIZE | {copy_fetch_kib:.4g} / {copy_write_kib:.4g} KiB |\n")
+        f.write(f"| calibration (bytes moved / counter bytes) read, write | {read_scale:.3f}, {write_scale:.3f} |\n")
+        f.write(f"| HBM read / write per launch (calibrated) | {read_b / 1e6:.1f} / {write_b / 1e6:.1f} MB |\n")
+        f.write(f"| HBM bytes per launch | {(read_b + write_b) / 1e6:.1f} MB |\n")
+    print(json.dumps(rec, indent=1))
+
+
+if __name__ == "__main__":
+    main()
