@@ -81,6 +81,8 @@ struct WorkItem {
                             int64_t iter, hipStream_t s);                                              \
     hipError_t conservation(const void *u, int64_t plane, int64_t pstride, int m, double *partial,    \
                             int nblocks, hipStream_t s);                                               \
+    hipError_t moments(const void *f, void *u, int64_t plane, int64_t pstride, int m, int q,          \
+                       hipStream_t s);                                                                 \
     hipError_t to_double(const void *src, double *dst, int64_t plane, int64_t pstride, int m,         \
                          hipStream_t s);                                                               \
     int step_kernel_vgprs(int variant);                                                                \

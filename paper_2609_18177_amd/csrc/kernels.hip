@@ -106,6 +106,13 @@ hipError_t conservation(const void *u, int64_t plane, int64_t pstride, int m, do
     return hipGetLastError();
 }
 
+hipError_t moments(const void *f, void *u, int64_t plane, int64_t pstride, int m, int q, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_moments<real>), dim3(cell_grid(plane)), dim3(kBlock), 0, s, (const real *)f, (real *)u, plane,
+                       pstride, m, q);
+    return hipGetLastError();
+}
+
 hipError_t to_double(const void *src, double *dst, int64_t plane, int64_t pstride, int m, hipStream_t s)
 {
     hipLaunchKernelGGL((k_to_double<real>), dim3(cell_grid(plane * m)), dim3(kBlock), 0, s, (const real *)src, dst,

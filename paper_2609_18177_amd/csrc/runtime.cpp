@@ -482,9 +482,22 @@ static int read_planes(arlbm_lattice *h, const void *src, int m, double *out)
     return ARLBM_OK;
 }
 
+// Form U = sum_k f_k of the current state in u[step & 1] (the step kernels
+// do not store the moments).
+static int form_moments(arlbm_lattice *h)
+{
+    void *u = h->desc.u[h->step & 1];
+    const void *f = h->desc.f[h->step & 1];
+    HIPCHK(h, is_f64(h) ? f64::moments(f, u, h->desc.plane, h->desc.pstride, h->sz.m, h->sz.q, h->stream)
+                        : f32::moments(f, u, h->desc.plane, h->desc.pstride, h->sz.m, h->sz.q, h->stream));
+    return ARLBM_OK;
+}
+
 extern "C" int arlbm_read_moments(arlbm_lattice *h, double *U)
 {
     if (!h || !U) return fail(h, ARLBM_EINVAL, "NULL argument");
+    int rc = form_moments(h);
+    if (rc) return rc;
     return read_planes(h, h->desc.u[h->step & 1], h->sz.m, U);
 }
 
@@ -519,6 +532,8 @@ extern "C" int arlbm_conservation(arlbm_lattice *h, double *sums)
 {
     if (!h || !sums) return fail(h, ARLBM_EINVAL, "NULL argument");
     const int m = h->sz.m;
+    int rc = form_moments(h);
+    if (rc) return rc;
     const void *u = h->desc.u[h->step & 1];
     hipError_t e = is_f64(h) ? f64::conservation(u, h->desc.plane, h->desc.pstride, m, h->d_partial, kConsBlocks,
                                                  h->stream)

@@ -4,8 +4,8 @@
 // band of rows.  Lane l sits on column x = x0 - 3 + l, so the 3-cell halo on
 // each side is carried by the wave itself: x-neighbours come from lane
 // shuffles, no LDS and no barriers are used.  The wave marches up its band;
-// per row it loads the moments U (m planes, written by the previous step) and
-// the populations f (Q m planes), and keeps a rolling window in registers:
+// per row it loads the populations f (Q m planes), forms the moments U of the
+// row two ahead from them, and keeps a rolling window in registers:
 //
 //   U rows j-2, j-1, j           -> nu at row j-1            (eqs. 2.13-2.14)
 //   nu rows j-3, j-2, j-1 (+x+-1) -> nu~, omega at row j-2   (eqs. 2.15-2.16)
@@ -13,8 +13,9 @@
 //   f*_{+y}(r-2), f*_{0,+x,-x}(r-1), f*_{-y}(r) -> pulled F_k at row r-1
 //   sum_k F_k, (2.8), second half source -> f^{n+1}, U^{n+1} written once.
 //
-// Every population is read once and written once per step (coalesced SoA
-// planes, x fastest); U adds m planes read and written.  The grid-wide
+// Every population is written once per step and read from HBM once (the
+// second read of a row, two iterations after the first, hits the caches);
+// the step stores nothing but the populations.  The grid-wide
 // wave-speed bound of the next step (eq. 2.19) is reduced in registers, across
 // the wave by shuffles, and committed with one 64-bit atomic max per wave and
 // direction into a triple-buffered slot.  The kernel launch boundary is the
@@ -224,8 +225,6 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
     const int64_t plane = L.pstride;
     const T *fin = (const T *)L.f[n & 1];
     T *fout = (T *)L.f[(n + 1) & 1];
-    const T *uin = (const T *)L.u[n & 1];
-    T *uout = (T *)L.u[(n + 1) & 1];
     const int x = col * kOutW - kHalo + lane;
     bool rx;
     const int xm = bc_map(x, nx, L.bc[0], L.bc[1], rx);
@@ -233,8 +232,14 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
 
     // moments (with ghost map) and neighbours
     T U[M], UL[M], UR[M];
+    const unsigned xo = (unsigned)xm;
+    T f[Q][M];
 #pragma unroll
-    for (int c = 0; c < M; ++c) U[c] = ldo(uin + (size_t)c * plane, (unsigned)xm);
+    for (int k = 0; k < Q; ++k)
+#pragma unroll
+        for (int c = 0; c < M; ++c) f[k][c] = ldo(fin + (size_t)(k * M + c) * plane, xo);
+#pragma unroll
+    for (int c = 0; c < M; ++c) U[c] = f[0][c] + f[1][c] + f[2][c];  // (2.3), velocity order
     if constexpr (SYS != 0)
         if (rx) U[1] = -U[1];
 #pragma unroll
@@ -274,10 +279,7 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
         const T feq0 = cf.a0 * u;
         const T feq1 = cf.ap[0] * u + cf.bp * F[c];
         const T feq2 = cf.ap[0] * u + cf.bm * F[c];
-        const unsigned xo = (unsigned)xm;
-        const T f0 = ldo(fin + (size_t)(0 * M + c) * plane, xo);
-        const T f1 = ldo(fin + (size_t)(1 * M + c) * plane, xo);
-        const T f2 = ldo(fin + (size_t)(2 * M + c) * plane, xo);
+        const T f0 = f[0][c], f1 = f[1][c], f2 = f[2][c];
         fs[0][c] = f0 - w * (f0 - feq0);
         fs[1][c] = f1 - w * (f1 - feq1);
         fs[2][c] = f2 - w * (f2 - feq2);
@@ -332,10 +334,8 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
 #pragma unroll
             for (int c = 0; c < M; ++c) sto(fout + (size_t)(k * M + c) * plane, (unsigned)x, fn[k][c]);
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-            sto(uout + (size_t)c * plane, (unsigned)x, Un[c]);
+        for (int c = 0; c < M; ++c)
             if (!finite_val<T>(Un[c])) flags |= 1u;
-        }
         Prim<T> qn;
         primitives<SYS, D, T>(Un, P, qn);
         flags |= qn.flags;
@@ -365,8 +365,6 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     const int64_t ps = L.pstride;
     const T *fin = (const T *)L.f[n & 1];
     T *fout = (T *)L.f[(n + 1) & 1];
-    const T *uin = (const T *)L.u[n & 1];
-    T *uout = (T *)L.u[(n + 1) & 1];
     const T *bed = (const T *)L.bed;
     T *om = (T *)L.omega;
     const int x = col * kOutW - kHalo + lane;
@@ -380,12 +378,21 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     const unsigned osink = L.omega_on ? sink : (unsigned)lane;  // omega sink (64-element buffer when off)
     const T two_dx = T(2) * P.dx;
 
+    // Moments of row j: U = sum_k f_k (2.3) of the population row, summed in
+    // velocity order; the ghost map negates the normal momentum at walls.
+    // The same row is read again two iterations later for the collision, from
+    // the L2 (or the last-level cache), not from HBM.
     auto loadU = [&](int j, T *out) {
         bool ry;
         const int jm = bc_map(j, ny, byl, byh, ry);
         const unsigned off = (unsigned)(jm * nx + xm);
 #pragma unroll
-        for (int c = 0; c < M; ++c) out[c] = ldo(uin + (size_t)c * ps, off);
+        for (int c = 0; c < M; ++c) {
+            T sum = ldo(fin + (size_t)(0 * M + c) * ps, off);
+#pragma unroll
+            for (int k = 1; k < Q; ++k) sum = sum + ldo(fin + (size_t)(k * M + c) * ps, off);
+            out[c] = sum;
+        }
         if constexpr (SYS != 0) {
             if (rx) out[1] = -out[1];
             if (ry) out[2] = -out[2];
@@ -584,8 +591,6 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
             for (int k = 0; k < Q; ++k)
 #pragma unroll
                 for (int c = 0; c < M; ++c) sto(fout + (size_t)(k * M + c) * ps, o, Fk[k][c]);
-#pragma unroll
-            for (int c = 0; c < M; ++c) sto(uout + (size_t)c * ps, o, Un[c]);
             Prim<T> qn;
             primitives<SYS, D, T>(Un, P, qn);
             const T v0 = max_speed<SYS, T>(0, qn, P), v1 = max_speed<SYS, T>(1, qn, P);
@@ -761,6 +766,19 @@ __global__ __launch_bounds__(kBlock) void k_init(LatticeDesc L, const double *U0
         atomicMax(&L.sc->abar[0][0], dbits(m0));
         if (D == 2) atomicMax(&L.sc->abar[0][1], dbits(m1));
     }
+}
+
+// Moments U = sum_k f_k of every cell (velocity order), for read-back and
+// conservation sums; the step kernels themselves never store U.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_moments(const T *f, T *u, int64_t plane, int64_t pstride, int m, int q)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < plane; i += (int64_t)gridDim.x * blockDim.x)
+        for (int c = 0; c < m; ++c) {
+            T s = f[(int64_t)c * pstride + i];
+            for (int k = 1; k < q; ++k) s = s + f[(int64_t)(k * m + c) * pstride + i];
+            u[(int64_t)c * pstride + i] = s;
+        }
 }
 
 // Per-block compensated (Neumaier) sums of each moment plane, in a fixed
