@@ -110,7 +110,7 @@ typedef struct arlbm_status {
     double t;             /* simulated time                                     */
     double last_dt;       /* delta t of the last step                           */
     double abar[2];       /* wave-speed bounds of the current state (eq. 2.19)  */
-    int64_t step;         /* steps taken since set_state                        */
+    int64_t step;         /* steps that advanced the state since set_state      */
     int64_t first_bad_step; /* first step whose result set a flag, or -1        */
     uint32_t flags;       /* ARLBM_FLAG_* bits seen so far                      */
     uint32_t reserved;
@@ -151,6 +151,14 @@ int arlbm_set_state_device(arlbm_lattice *h, const double *U0_dev, const double 
  * handle's stream, no host round trip).  Device-side problems are latched in
  * the status flags and reported by arlbm_sync. */
 int arlbm_step(arlbm_lattice *h, int64_t n);
+
+/* Whole steps until the simulated time reaches t_final (t >= t_final; the
+ * last step is not shortened, which keeps the scheme second order) or until
+ * max_steps steps were taken.  Synchronises a few times to size its batches
+ * of launches; a launch that finds t >= t_final leaves the state unchanged,
+ * so the result does not depend on the batching.  *steps_taken (may be NULL)
+ * receives the number of steps that advanced the state. */
+int arlbm_step_until(arlbm_lattice *h, double t_final, int64_t max_steps, int64_t *steps_taken);
 
 /* Wait for the stream and report the status.  Returns ENONFINITE,
  * EDEGENERATE or EPOSITIVITY when the matching flag is set (status still

@@ -89,6 +89,7 @@ def lib():
             "arlbm_set_state_device": ([vp, vp, vp, C.c_double], C.c_int),
             "arlbm_step": ([vp, C.c_int64], C.c_int),
             "arlbm_sync": ([vp, C.POINTER(Status)], C.c_int),
+            "arlbm_step_until": ([vp, C.c_double, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
             "arlbm_read_moments": ([vp, dp], C.c_int),
             "arlbm_set_omega_export": ([vp, C.c_int], C.c_int),
             "arlbm_read_omega": ([vp, dp], C.c_int),
@@ -219,6 +220,12 @@ class Lattice:
 
     def step(self, n: int = 1):
         _check(lib().arlbm_step(self._h, int(n)), self._h)
+
+    def step_until(self, t_final: float, max_steps: int = 10 ** 9) -> int:
+        """Whole steps until t >= t_final; returns the number of steps taken."""
+        n = C.c_int64()
+        _check(lib().arlbm_step_until(self._h, float(t_final), int(max_steps), C.byref(n)), self._h)
+        return n.value
 
     def sync(self, check: bool = True, strict: bool = False) -> dict:
         """Wait for the stream.  With check, raise on a non-finite or

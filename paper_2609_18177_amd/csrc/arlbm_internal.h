@@ -28,12 +28,15 @@ struct DevScalars {
     // integers, so the grid-wide max is an integer atomic max).  Three slots:
     // step n reads slot n%3, maxes into (n+1)%3 and clears (n+2)%3.
     unsigned long long abar[3][2];
-    double t;
     double last_dt;
     unsigned long long first_bad_step;  // min over flagged steps (~0 = none)
     unsigned int flags;
     unsigned int pad;
-    double reserved[6];
+    // time of the state step n reads (slot n%3; the step writes slot (n+1)%3,
+    // so every wave of a launch sees the same value)
+    double t[3];
+    unsigned long long null_launches;   // launches that found t >= t_stop (left the state as it was)
+    double reserved[3];
 };
 static_assert(sizeof(DevScalars) == 128, "DevScalars layout");
 
@@ -51,6 +54,7 @@ struct LatticeDesc {
     int32_t band_h;       // rows per strip (2D)
     int32_t ncols;        // strips along x
     int64_t iter0;
+    double t_stop;        // a launch whose state time is >= t_stop copies f unchanged (null step)
     int64_t plane;        // nx * ny
     int64_t pstride;      // elements between planes: plane + a 64-element sink tail
     int32_t omega_on;     // omega export plane present (else omega is a 64-slot sink)

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <climits>
 #include <cstdio>
 #include <cstring>
 #include <deque>
@@ -270,7 +271,7 @@ int set_state_impl(arlbm_lattice *h, const double *U0, const double *bed, bool o
             HIPCHK(h, hipMemcpyAsync(bedd, bed, sizeof(double) * plane, hipMemcpyHostToDevice, h->stream));
     }
     DevScalars sc{};
-    sc.t = t0;
+    sc.t[0] = t0;
     sc.first_bad_step = ~0ull;
     HIPCHK(h, hipMemcpyAsync(h->desc.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, L_reduce(h, U0d, 2));
@@ -354,6 +355,7 @@ extern "C" int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, 
     d.ncols = (int32_t)((cfg->nx + kOutW - 1) / kOutW);
     d.band_h = cfg->dim == 2 ? choose_band(cfg->ny, d.ncols, resident_waves(cfg->precision, d.variant)) : 1;
     d.iter0 = 0;
+    d.t_stop = HUGE_VAL;
     d.plane = cfg->nx * cfg->ny;
     d.pstride = plane_stride(cfg);
     d.dx = (cfg->x1 - cfg->x0) / (double)cfg->nx;
@@ -443,6 +445,46 @@ extern "C" int arlbm_step(arlbm_lattice *h, int64_t n)
     return ARLBM_OK;
 }
 
+extern "C" int arlbm_step_until(arlbm_lattice *h, double t_final, int64_t max_steps, int64_t *taken)
+{
+    if (!h) return fail(nullptr, ARLBM_EINVAL, "handle is NULL");
+    if (h->busy) return fail(h, ARLBM_EBUSY, "lattice is owned by a server");
+    if (max_steps < 0 || !(t_final == t_final)) return fail(h, ARLBM_EINVAL, "bad argument");
+    DevScalars sc{};
+    int rc = read_scalars(h, &sc);
+    if (rc) return rc;
+    const int64_t done0 = h->step - (int64_t)sc.null_launches;
+    int64_t real = 0;
+    h->desc.t_stop = t_final;
+    while (real < max_steps) {
+        const double t = sc.t[h->step % 3];
+        if (t >= t_final) break;
+        if (sc.flags & (ARLBM_FLAG_NONFINITE | ARLBM_FLAG_DEGENERATE)) break;
+        // launch the estimated remaining steps plus one; a launch that finds
+        // the state at or past t_final leaves it unchanged, so the surplus
+        // costs one copy of the populations and the result does not depend
+        // on the estimate
+        const double est = sc.last_dt > 0.0 ? (t_final - t) / sc.last_dt : 1.0;
+        int64_t k = est < 1e15 ? (int64_t)std::ceil(est) + 1 : 1;
+        if (k > max_steps - real) k = max_steps - real;
+        for (int64_t i = 0; i < k; ++i) {
+            hipError_t e = L_step(h, h->step);
+            if (e != hipSuccess) {
+                h->desc.t_stop = HUGE_VAL;
+                return hip_fail(h, e, "step launch");
+            }
+            ++h->step;
+        }
+        rc = read_scalars(h, &sc);
+        if (rc) break;
+        real = h->step - (int64_t)sc.null_launches - done0;
+    }
+    h->desc.t_stop = HUGE_VAL;
+    if (rc) return rc;
+    if (taken) *taken = real;
+    return ARLBM_OK;
+}
+
 extern "C" int arlbm_sync(arlbm_lattice *h, arlbm_status *st)
 {
     if (!h) return fail(nullptr, ARLBM_EINVAL, "handle is NULL");
@@ -451,12 +493,12 @@ extern "C" int arlbm_sync(arlbm_lattice *h, arlbm_status *st)
     if (rc) return rc;
     if (st) {
         std::memset(st, 0, sizeof(*st));
-        st->t = sc.t;
-        st->last_dt = sc.last_dt;
         const int slot = (int)(h->step % 3);
+        st->t = sc.t[slot];
+        st->last_dt = sc.last_dt;
         st->abar[0] = *(double *)&sc.abar[slot][0];
         st->abar[1] = h->cfg.dim == 2 ? *(double *)&sc.abar[slot][1] : 0.0;
-        st->step = h->step;
+        st->step = h->step - (int64_t)sc.null_launches;
         st->flags = sc.flags;
         st->first_bad_step = sc.first_bad_step == ~0ull ? -1 : (int64_t)sc.first_bad_step;
     }

@@ -170,17 +170,50 @@ __device__ __forceinline__ Phys<T> make_phys(const LatticeDesc &L)
 __device__ __forceinline__ void scalar_update(const LatticeDesc &L, int64_t n, double dt)
 {
     DevScalars *sc = L.sc;
-    sc->t = sc->t + dt;
+    sc->t[(n + 1) % 3] = sc->t[n % 3] + dt;
     sc->last_dt = dt;
     const int clr = (int)((n + 2) % 3);
     sc->abar[clr][0] = 0ull;
     sc->abar[clr][1] = 0ull;
 }
 
+// A launch whose state time has reached the stop time leaves the state
+// unchanged: populations are copied to the output buffer (the ping-pong
+// stays consistent), t and the wave-speed bounds carry over to the next slot.
+__device__ __forceinline__ bool stopped(const LatticeDesc &L, int64_t n)
+{
+    return L.sc->t[n % 3] >= L.t_stop;
+}
+__device__ __forceinline__ void null_scalars(const LatticeDesc &L, int64_t n)
+{
+    DevScalars *sc = L.sc;
+    sc->t[(n + 1) % 3] = sc->t[n % 3];
+    sc->null_launches = sc->null_launches + 1ull;
+    sc->abar[(n + 1) % 3][0] = sc->abar[n % 3][0];
+    sc->abar[(n + 1) % 3][1] = sc->abar[n % 3][1];
+    const int clr = (int)((n + 2) % 3);
+    sc->abar[clr][0] = 0ull;
+    sc->abar[clr][1] = 0ull;
+}
+template <typename T>
+__device__ __forceinline__ void null_copy(const LatticeDesc &L, int64_t n, int planes, int x, bool xout, int ya,
+                                          int yb, bool first)
+{
+    const T *fin = (const T *)L.f[n & 1];
+    T *fout = (T *)L.f[(n + 1) & 1];
+    if (xout)
+        for (int y = ya; y < yb; ++y)
+            for (int p = 0; p < planes; ++p) {
+                const unsigned o = (unsigned)(y * L.nx + x);
+                sto(fout + (size_t)p * L.pstride, o, ldo(fin + (size_t)p * L.pstride, o));
+            }
+    if (first && (threadIdx.x & 63) == 0) null_scalars(L, n);
+}
+
 __device__ __forceinline__ void flag_degenerate(const LatticeDesc &L, int64_t n)
 {
     atomicOr(&L.sc->flags, 4u);
-    atomicMin(&L.sc->first_bad_step, (unsigned long long)n);
+    atomicMin(&L.sc->first_bad_step, (unsigned long long)n - L.sc->null_launches);
 }
 
 // Commit the wave's bounds and flags for the next step.
@@ -199,7 +232,7 @@ __device__ __forceinline__ void commit(const LatticeDesc &L, int64_t n, T s0, T 
         if (dims == 2) atomicMax(&L.sc->abar[slot][1], dbits(m1));
         if (anyf) {
             atomicOr(&L.sc->flags, fl);
-            atomicMin(&L.sc->first_bad_step, (unsigned long long)n);
+            atomicMin(&L.sc->first_bad_step, (unsigned long long)n - L.sc->null_launches);
         }
     }
 }
@@ -223,6 +256,11 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
     const int lane = threadIdx.x & (kWave - 1);
     const int nx = L.nx;
     const int64_t plane = L.pstride;
+    if (stopped(L, n)) {
+        const int xs = col * kOutW - kHalo + lane;
+        null_copy<T>(L, n, Q * M, xs, lane >= kHalo && lane < kWave - kHalo && xs < nx, 0, 1, first);
+        return;
+    }
     const T *fin = (const T *)L.f[n & 1];
     T *fout = (T *)L.f[(n + 1) & 1];
     const int x = col * kOutW - kHalo + lane;
@@ -363,6 +401,12 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     const int lane = threadIdx.x & (kWave - 1);
     const int nx = L.nx, ny = L.ny;
     const int64_t ps = L.pstride;
+    if (stopped(L, n)) {
+        const int xs = col * kOutW - kHalo + lane;
+        const int y0 = band * L.band_h, y1 = y0 + L.band_h < ny ? y0 + L.band_h : ny;
+        null_copy<T>(L, n, Q * M, xs, lane >= kHalo && lane < kWave - kHalo && xs < nx, y0, y1, first);
+        return;
+    }
     const T *fin = (const T *)L.f[n & 1];
     T *fout = (T *)L.f[(n + 1) & 1];
     const T *bed = (const T *)L.bed;
