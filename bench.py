@@ -157,30 +157,32 @@ def run_latency_1d(torch, args):
     return out
 
 
-def run_serving(torch, args):
+def run_serving(torch, args, n_requests, rate_hz, fp64_check, tag="serving"):
     """Continuous batching: Poisson arrivals admitted by HBM budget into the
     batched FP32 kernel; latency = result read back - arrival."""
-    reqs = W.serving_requests(args.requests, rate_hz=args.rate, seed=0)
-    log(f"[serving] generating {len(reqs)} requests")
+    reqs = W.serving_requests(n_requests, rate_hz=rate_hz, seed=0)
+    log(f"[{tag}] generating {len(reqs)} requests")
     t0 = time.perf_counter()
     probs = [r.problem() for r in reqs]
-    log(f"[serving] generated in {time.perf_counter() - t0:.1f}s; budget {args.budget_gib} GiB")
+    log(f"[{tag}] generated in {time.perf_counter() - t0:.1f}s; budget {args.budget_gib} GiB")
     srv = A.Server(int(args.budget_gib * 2 ** 30), A.F32)
     cfgs = [A.config_from(p, precision=A.F32) for p in probs]
     results = {}
     nxt = 0
     peak_mem = 0
     iters = 0
+    busy = 0.0
     start = time.perf_counter()
     while len(results) < len(reqs):
         now = time.perf_counter() - start
         while nxt < len(reqs) and reqs[nxt].arrival_s <= now:
             p = probs[nxt]
-            rid = srv.submit(cfgs[nxt], p.U0, p.bed, reqs[nxt].steps)
-            results_key = rid
-            reqs[nxt].server_id = results_key
+            reqs[nxt].server_id = srv.submit(cfgs[nxt], p.U0, p.bed, reqs[nxt].steps)
             nxt += 1
+        ti = time.perf_counter()
         resident, queued = srv.iterate()
+        if resident:
+            busy += time.perf_counter() - ti
         iters += 1
         peak_mem = max(peak_mem, srv.memory())
         for c in srv.poll(256):
@@ -203,13 +205,15 @@ def run_serving(torch, args):
         lat.append(c["done_s"] - (start + r.arrival_s))
         lups += probs[r.rid].cells * r.steps
     lat = np.array(lat) * 1e3
+    span = max(reqs[-1].arrival_s, 1e-9)
     out = {"requests": len(reqs), "failed": bad, "wall_s": wall, "glups": lups / wall / 1e9,
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "iterations": iters, "peak_resident_bytes": int(peak_mem), "offered_lups": int(lups),
-           "rate_hz": args.rate, "budget_gib": args.budget_gib}
+           "offered_glups_over_arrivals": lups / span / 1e9, "arrival_span_s": span,
+           "iterate_time_fraction_with_work": busy / wall, "rate_hz": rate_hz, "budget_gib": args.budget_gib}
     # FP32 (batched) against the FP64 plain path on a subsample of requests
     errs = []
-    for r in reqs[: args.fp64_check]:
+    for r in reqs[:fp64_check]:
         p = probs[r.rid]
         L = A.Lattice(A.config_from(p, precision=A.F64), owner="torch")
         L.set_state(p.U0, p.bed)
@@ -221,7 +225,7 @@ def run_serving(torch, args):
     out["fp32_batched_vs_fp64_plain_rel_l1"] = {"n": len(errs), "max": max(errs) if errs else None,
                                                 "median": float(np.median(errs)) if errs else None}
     srv.close()
-    log(f"[serving] {out}")
+    log(f"[{tag}] {out}")
     return out
 
 
@@ -271,6 +275,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--budget-gib", type=float, default=4.0)
     ap.add_argument("--fp64-check", type=int, default=12)
+    ap.add_argument("--low-requests", type=int, default=64)
+    ap.add_argument("--low-rate", type=float, default=8.0)
     ap.add_argument("--latency-solves", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-serving", action="store_true")
@@ -322,7 +328,11 @@ def main():
                                "mass_drift_rel": sw["mass_drift_rel"], "flags": sw["flags"]}
     extra["euler1d_4096_latency"] = run_latency_1d(torch, args)
     if not args.no_serving:
-        extra["serving"] = run_serving(torch, args)
+        extra["serving"] = run_serving(torch, args, args.requests, args.rate, args.fp64_check)
+        # the default mix offers several times the capacity, so its latency is
+        # queueing; a run at a fraction of the capacity shows service latency
+        extra["serving_low_rate"] = run_serving(torch, args, args.low_requests, args.low_rate, 4,
+                                                tag="serving-low")
     cpu = None if args.no_cpu else run_cpu_baseline(args)
     line = {
         "metric": METRIC, "value": glups, "unit": "GLUPS", "n_gpus": 1, "steps": args.steps,
