@@ -13,9 +13,18 @@
  *   the source node and pull streaming (the implementation form of 2.2) ->
  *   implicit moment update (2.8) and second half source.
  *
- * Systems (Section 5): scalar advection, compressible Euler (gamma law) and
- * shallow water, in 1D (D1Q3) and 2D (D2Q5), with an optional shallow-water
+ * Systems (Section 5): scalar advection, compressible Euler (gamma law),
+ * shallow water, and reactive Euler with one-step Arrhenius kinetics
+ * (Section 5.4), in 1D (D1Q3) and 2D (D2Q5), with an optional shallow-water
  * bed-slope source S = (0, -g h db/dx, -g h db/dy) (not in the paper).
+ *
+ * Conserved fields per system (plane order):
+ *   advection      u
+ *   Euler          rho, rho u, [rho v,] rho E       E = p/(gamma-1) + rho|u|^2/2
+ *   shallow water  h, h u, [h v]
+ *   reactive       rho, rho u, [rho v,] rho E, rho Y
+ *                  rho E = p/(gamma-1) + rho|u|^2/2 + q rho Y, and the source
+ *                  S = (0, .., 0, -R), R = K rho Y exp(-T_i rho / p)
  *
  * Conventions
  *  - Every function returns 0 (ARLBM_OK) or a negative ARLBM_E* code.  No
@@ -39,10 +48,10 @@
 extern "C" {
 #endif
 
-#define ARLBM_ABI_VERSION 1
+#define ARLBM_ABI_VERSION 2
 
 /* Systems, boundary conditions, precisions, relaxation modes. */
-enum { ARLBM_ADVECTION = 0, ARLBM_EULER = 1, ARLBM_SWE = 2 };
+enum { ARLBM_ADVECTION = 0, ARLBM_EULER = 1, ARLBM_SWE = 2, ARLBM_REACTIVE = 3 };
 enum { ARLBM_PERIODIC = 0, ARLBM_TRANSMISSIVE = 1, ARLBM_REFLECTIVE = 2 };
 enum { ARLBM_F32 = 0, ARLBM_F64 = 1 };
 enum { ARLBM_OMEGA_ADAPTIVE = 0, ARLBM_OMEGA_FIXED = 1 };
@@ -65,7 +74,7 @@ enum { ARLBM_OMEGA_ADAPTIVE = 0, ARLBM_OMEGA_FIXED = 1 };
 
 typedef struct arlbm_config {
     int32_t abi_version;  /* ARLBM_ABI_VERSION                                  */
-    int32_t system;       /* ARLBM_ADVECTION / ARLBM_EULER / ARLBM_SWE          */
+    int32_t system;       /* ARLBM_ADVECTION / _EULER / _SWE / _REACTIVE        */
     int32_t dim;          /* 1 or 2                                             */
     int32_t precision;    /* ARLBM_F32 or ARLBM_F64: storage and arithmetic     */
     int64_t nx, ny;       /* cells; ny = 1 in 1D; nx, ny >= 4                   */
@@ -82,6 +91,9 @@ typedef struct arlbm_config {
     int32_t has_bed;      /* shallow water: bed-slope source on                 */
     int32_t omega_mode;   /* ARLBM_OMEGA_ADAPTIVE (eq. 2.16) or _FIXED          */
     double omega_fixed;   /* omega when fixed, in (0, 2]                        */
+    double q_heat;        /* reactive: heat release q (>= 0)                    */
+    double k_rate;        /* reactive: Arrhenius rate constant K (>= 0)         */
+    double t_act;         /* reactive: activation temperature T_i (>= 0)        */
 } arlbm_config;
 
 /* Byte sizes of the device buffers of one lattice (each 256-byte aligned). */

@@ -12,7 +12,7 @@ import numpy as np
 
 from . import build as _build
 
-ADVECTION, EULER, SWE = 0, 1, 2
+ADVECTION, EULER, SWE, REACTIVE = 0, 1, 2, 3
 PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
 
 
@@ -25,6 +25,7 @@ class OraCfg(C.Structure):
         ("adv", C.c_double * 2), ("h_dry", C.c_double), ("rho_floor", C.c_double),
         ("p_floor", C.c_double), ("has_bed", C.c_int32), ("omega_fixed_on", C.c_int32),
         ("omega_fixed", C.c_double),
+        ("q_heat", C.c_double), ("k_rate", C.c_double), ("t_act", C.c_double),
     ]
 
 
@@ -67,6 +68,10 @@ def lib():
         L.ora_left_eigvecs.argtypes = [C.POINTER(OraCfg), C.c_int, dp, dp]
         L.ora_lf_coeffs.argtypes = [C.c_int, dp, C.c_double, dp, dp]
         L.ora_equilibrium.argtypes = [C.POINTER(OraCfg), dp, dp, C.c_double, dp]
+        L.ora_source.argtypes = [C.POINTER(OraCfg), dp, dp, dp]
+        L.ora_moment_update.argtypes = [C.POINTER(OraCfg), dp, dp, C.c_double, dp]
+        L.ora_arrhenius_exp.argtypes = [C.c_double]
+        L.ora_arrhenius_exp.restype = C.c_double
         _lib = L
     return _lib
 
@@ -77,7 +82,8 @@ def num_fields(system, dim):
 
 def make_cfg(system, dim, nx, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=(PERIODIC,) * 4,
              cfl=0.5, eps=1e-10, gamma=1.4, g=9.81, adv=(1.0, 0.0), h_dry=1e-6,
-             rho_floor=1e-12, p_floor=1e-12, has_bed=False, omega_fixed=None):
+             rho_floor=1e-12, p_floor=1e-12, has_bed=False, omega_fixed=None,
+             q_heat=0.0, k_rate=0.0, t_act=0.0):
     c = OraCfg()
     c.system, c.dim, c.nx, c.ny = system, dim, nx, (ny if dim == 2 else 1)
     c.x0, c.x1, c.y0, c.y1 = x0, x1, y0, y1
@@ -89,6 +95,7 @@ def make_cfg(system, dim, nx, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=(PERIODIC
     c.has_bed = int(bool(has_bed))
     c.omega_fixed_on = int(omega_fixed is not None)
     c.omega_fixed = float(omega_fixed) if omega_fixed is not None else 0.0
+    c.q_heat, c.k_rate, c.t_act = q_heat, k_rate, t_act
     return c
 
 
@@ -217,3 +224,24 @@ def equilibrium(cfg, U, alpha, lam):
     lib().ora_equilibrium(C.byref(cfg), np.ascontiguousarray(U, dtype=np.float64),
                           np.ascontiguousarray(alpha, dtype=np.float64), float(lam), out)
     return out.reshape(Q, m)
+
+
+def source(cfg, U, db=(0.0, 0.0)):
+    m = num_fields(cfg.system, cfg.dim)
+    out = np.zeros(m)
+    lib().ora_source(C.byref(cfg), np.ascontiguousarray(U, dtype=np.float64),
+                     np.ascontiguousarray(db, dtype=np.float64), out)
+    return out
+
+
+def moment_update(cfg, sumF, half_dt, db=(0.0, 0.0)):
+    """(2.8) for one cell: U = sumF + (dt/2) S(U)."""
+    m = num_fields(cfg.system, cfg.dim)
+    out = np.zeros(m)
+    lib().ora_moment_update(C.byref(cfg), np.ascontiguousarray(sumF, dtype=np.float64),
+                            np.ascontiguousarray(db, dtype=np.float64), float(half_dt), out)
+    return out
+
+
+def arrhenius_exp(x):
+    return lib().ora_arrhenius_exp(float(x))

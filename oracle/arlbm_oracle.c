@@ -28,7 +28,20 @@
  *   - shallow water: a cell with h <= h_dry has u = v = 0 and zero momentum
  *     flux; the acoustic speed in L uses max(h, h_dry);
  *   - bed source S = (0, -g h db/dx, -g h db/dy), central differences of the
- *     cell-centred bed with mirrored ghosts (not in the paper).
+ *     cell-centred bed with mirrored ghosts (not in the paper);
+ *   - reactive Euler (Section 5.4): with E' = E - q rho Y the system is Euler
+ *     in (rho, m, E') plus the passively advected rho Y, so L = L' T where
+ *     L' holds the Euler rows (zero in the rho Y column) and the species row
+ *     (-Y, 0, .., 0, 1), and T maps U to (rho, m, E - q rho Y, rho Y);
+ *   - reactive Euler: (2.8) reduces to one scalar equation for rho Y, solved
+ *     by a safeguarded Newton iteration on the bracket [min(0,B), max(0,B)]
+ *     with B = sum_k F_k of rho Y (the sink R >= 0 for rho Y >= 0 puts the
+ *     root there), stopped when a Newton step no longer changes rho Y (or a
+ *     bisection lands on the current point) or after 40 iterations;
+ *   - the Arrhenius exponential is evaluated by one fixed algorithm (Cody-Waite
+ *     reduction by ln 2, degree-13 Taylor polynomial, scaling by 2^k), written
+ *     out here and, independently, in the GPU library, so that the FP64 paths
+ *     can agree bit for bit; it is pinned against the C library's exp.
  */
 #include "arlbm_oracle.h"
 
@@ -65,19 +78,52 @@ int ora_num_fields(int system, int dim)
     if (system == ORA_ADVECTION) return 1;
     if (system == ORA_EULER) return dim + 2;
     if (system == ORA_SWE) return dim + 1;
+    if (system == ORA_REACTIVE) return dim + 3;
     return 0;
 }
 
 typedef struct {
     double rho, vel[2], mom[2], E, p, c; /* Euler: rho; SWE: h in rho */
     double cL;                           /* SWE: speed used in L      */
+    double Z, Y;                         /* reactive: rho Y and Y     */
 } prim_t;
+
+/* exp(x) for the Arrhenius factor.  Cody-Waite argument reduction
+ * x = k ln2 + r, |r| <= ln2/2, with ln2 split into a head with trailing zero
+ * bits (k * head is exact) and a tail; exp(r) by its Taylor series to degree
+ * 13 (truncation below 5e-18 for |r| <= ln2/2) in Horner form; then 2^k. */
+double ora_arrhenius_exp(double x)
+{
+    const double inv_ln2 = 1.44269504088896338700e+00;
+    const double ln2_hi = 6.93147180369123816490e-01;
+    const double ln2_lo = 1.90821492927058770002e-10;
+    if (x != x) return x;
+    if (x < -746.0) return 0.0;
+    if (x > 710.0) return HUGE_VAL;
+    double k = nearbyint(x * inv_ln2);
+    double r = (x - k * ln2_hi) - k * ln2_lo;
+    double p = 1.0 / 6227020800.0;      /* 1/13! */
+    p = p * r + 1.0 / 479001600.0;      /* 1/12! */
+    p = p * r + 1.0 / 39916800.0;       /* 1/11! */
+    p = p * r + 1.0 / 3628800.0;        /* 1/10! */
+    p = p * r + 1.0 / 362880.0;         /* 1/9!  */
+    p = p * r + 1.0 / 40320.0;          /* 1/8!  */
+    p = p * r + 1.0 / 5040.0;           /* 1/7!  */
+    p = p * r + 1.0 / 720.0;            /* 1/6!  */
+    p = p * r + 1.0 / 120.0;            /* 1/5!  */
+    p = p * r + 1.0 / 24.0;             /* 1/4!  */
+    p = p * r + 1.0 / 6.0;              /* 1/3!  */
+    p = p * r + 0.5;                    /* 1/2!  */
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    return ldexp(p, (int)k);
+}
 
 static void primitives(const ora_cfg *c, const double *U, prim_t *P, int32_t *flags)
 {
     int d = c->dim;
     memset(P, 0, sizeof(*P));
-    if (c->system == ORA_EULER) {
+    if (c->system == ORA_EULER || c->system == ORA_REACTIVE) {
         P->rho = U[0];
         P->E = U[d + 1];
         for (int i = 0; i < d; ++i) {
@@ -85,7 +131,14 @@ static void primitives(const ora_cfg *c, const double *U, prim_t *P, int32_t *fl
             P->vel[i] = U[1 + i] / P->rho;
         }
         double q2 = P->vel[0] * P->vel[0] + P->vel[1] * P->vel[1];
-        P->p = (c->gamma - 1.0) * (P->E - 0.5 * P->rho * q2);
+        if (c->system == ORA_EULER) {
+            P->p = (c->gamma - 1.0) * (P->E - 0.5 * P->rho * q2);
+        } else {
+            /* rho E = p/(gamma-1) + rho |u|^2 / 2 + q rho Y (Section 5.4) */
+            P->Z = U[d + 2];
+            P->Y = P->Z / P->rho;
+            P->p = (c->gamma - 1.0) * ((P->E - 0.5 * P->rho * q2) - c->q_heat * P->Z);
+        }
         double pf = P->p > c->p_floor ? P->p : c->p_floor;
         double rf = P->rho > c->rho_floor ? P->rho : c->rho_floor;
         if (flags && (P->p <= c->p_floor || P->rho <= c->rho_floor)) *flags |= 2;
@@ -113,11 +166,12 @@ void ora_flux(const ora_cfg *c, int dir, const double *U, double *F)
     }
     prim_t P;
     primitives(c, U, &P, NULL);
-    if (c->system == ORA_EULER) {
+    if (c->system == ORA_EULER || c->system == ORA_REACTIVE) {
         F[0] = P.mom[dir];
         for (int i = 0; i < d; ++i)
             F[1 + i] = P.mom[dir] * P.vel[i] + (i == dir ? P.p : 0.0);
         F[d + 1] = P.vel[dir] * (P.E + P.p);
+        if (c->system == ORA_REACTIVE) F[d + 2] = P.vel[dir] * P.Z;
     } else {
         double ph = 0.5 * c->g * P.rho * P.rho;
         F[0] = P.mom[dir];
@@ -145,7 +199,7 @@ void ora_left_eigvecs(const ora_cfg *c, int dir, const double *U, double *L)
     }
     prim_t P;
     primitives(c, U, &P, NULL);
-    if (c->system == ORA_EULER) {
+    if (c->system == ORA_EULER || c->system == ORA_REACTIVE) {
         double cs = P.c;
         double q2 = P.vel[0] * P.vel[0] + P.vel[1] * P.vel[1];
         double b1 = (c->gamma - 1.0) / (cs * cs);
@@ -177,6 +231,15 @@ void ora_left_eigvecs(const ora_cfg *c, int dir, const double *U, double *L)
             L[2 * m + 0] = -P.vel[t];
             L[2 * m + 1 + t] = 1.0;
         }
+        if (c->system == ORA_REACTIVE) {
+            /* species row m-2 (speed u_n): (-Y, 0, .., 0, 1) in the variables
+             * (rho, m, E', rho Y); then every row times T: the rho Y entry
+             * gains -q times the energy entry */
+            int z = d + 2;
+            L[(m - 2) * m + 0] = -P.Y;
+            L[(m - 2) * m + z] = 1.0;
+            for (int r = 0; r < m; ++r) L[r * m + z] = L[r * m + z] - c->q_heat * L[r * m + e];
+        }
     } else {
         double cs = P.cL;
         double un = P.vel[dir];
@@ -193,16 +256,90 @@ void ora_left_eigvecs(const ora_cfg *c, int dir, const double *U, double *L)
     }
 }
 
-/* Source S(U) (2.1).  Only the shallow-water bed slope is non-zero here; it
- * depends on U through the depth alone, so (2.8) is solved in closed form. */
-static int has_source(const ora_cfg *c) { return c->system == ORA_SWE && c->has_bed; }
+/* Source S(U) (2.1): the shallow-water bed slope, which depends on U through
+ * the depth alone, so (2.8) is solved in closed form; and the Arrhenius sink
+ * of the reactive system, S = (0, .., 0, -R), R = K rho Y exp(-T_i / T),
+ * T = p / rho (Section 5.4). */
+static int has_bed(const ora_cfg *c) { return c->system == ORA_SWE && c->has_bed; }
+
+/* The Arrhenius rate R at rho Y = z, with rho, (E - rho |u|^2/2) fixed; and
+ * its derivative dR/dz (p depends on z through -q z). */
+static double arrhenius(const ora_cfg *c, double rho, double e_int, double z, double *dRdz)
+{
+    double p = (c->gamma - 1.0) * (e_int - c->q_heat * z);
+    double pf = p > c->p_floor ? p : c->p_floor;
+    double rf = rho > c->rho_floor ? rho : c->rho_floor;
+    double T = pf / rf;
+    double e = ora_arrhenius_exp(-(c->t_act / T));
+    double R = (c->k_rate * z) * e;
+    if (dRdz) {
+        /* d/dz exp(-T_i rho / p) = exp(..) * (-T_i rho (gamma-1) q / p^2) */
+        double dlog = p > c->p_floor ? (c->t_act * rf) * ((c->gamma - 1.0) * c->q_heat) / (pf * pf) : 0.0;
+        *dRdz = c->k_rate * e * (1.0 - z * dlog);
+    }
+    return R;
+}
+
+static void reactive_parts(const ora_cfg *c, const double *U, double *rho, double *e_int)
+{
+    int d = c->dim;
+    double u0 = U[1] / U[0], u1 = d == 2 ? U[2] / U[0] : 0.0;
+    double q2 = u0 * u0 + u1 * u1;
+    *rho = U[0];
+    *e_int = U[d + 1] - 0.5 * U[0] * q2;
+}
+
+void ora_source(const ora_cfg *c, const double *U, const double *db, double *S)
+{
+    int d = c->dim, m = ora_num_fields(c->system, d);
+    for (int i = 0; i < m; ++i) S[i] = 0.0;
+    if (has_bed(c))
+        for (int j = 0; j < d; ++j) S[1 + j] = -c->g * U[0] * db[j];
+    if (c->system == ORA_REACTIVE) {
+        double rho, e_int;
+        reactive_parts(c, U, &rho, &e_int);
+        S[m - 1] = -arrhenius(c, rho, e_int, U[m - 1], NULL);
+    }
+}
 
 static void source(const ora_cfg *c, const double *U, const double *db, double *S)
 {
-    int m = ora_num_fields(c->system, c->dim);
-    for (int i = 0; i < m; ++i) S[i] = 0.0;
-    if (!has_source(c)) return;
-    for (int j = 0; j < c->dim; ++j) S[1 + j] = -c->g * U[0] * db[j];
+    ora_source(c, U, db, S);
+}
+
+/* (2.8): U = sumF + (dt/2) S(U).  Bed source: S_h = 0 and S depends on h
+ * alone, so U = sumF + (dt/2) S(sumF).  Reactive: every component but rho Y
+ * equals sumF; rho Y = z solves g(z) = (z - B) + (dt/2) R(z) = 0. */
+void ora_moment_update(const ora_cfg *c, const double *sumF, const double *db, double half_dt,
+                       double *U)
+{
+    int d = c->dim, m = ora_num_fields(c->system, d);
+    double S[ORA_MMAX];
+    for (int i = 0; i < m; ++i) U[i] = sumF[i];
+    if (has_bed(c)) {
+        source(c, sumF, db, S);
+        for (int i = 0; i < m; ++i) U[i] = sumF[i] + half_dt * S[i];
+    }
+    if (c->system == ORA_REACTIVE) {
+        double rho, e_int;
+        reactive_parts(c, sumF, &rho, &e_int);
+        double B = sumF[m - 1];
+        double lo = B < 0.0 ? B : 0.0, hi = B < 0.0 ? 0.0 : B;
+        double z = B;
+        for (int it = 0; it < 40; ++it) {
+            double dR;
+            double g = (z - B) + half_dt * arrhenius(c, rho, e_int, z, &dR);
+            if (g == 0.0) break;
+            if (g > 0.0) hi = z; else lo = z;
+            double dg = 1.0 + half_dt * dR;
+            double zn = z - g / dg;
+            if (dg > 0.0 && zn == z) break; /* the Newton step no longer moves z */
+            if (!(dg > 0.0) || !(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
+            if (zn == z) break;
+            z = zn;
+        }
+        U[m - 1] = z;
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -239,7 +376,7 @@ static void equilibrium_ab(const ora_cfg *c, const double *U, const double *a,
                            const double *b, double *feq)
 {
     int d = c->dim, m = ora_num_fields(c->system, d), Q = 2 * d + 1;
-    double F[2][4];
+    double F[2][ORA_MMAX];
     for (int j = 0; j < d; ++j) ora_flux(c, j, U, F[j]);
     for (int k = 0; k < Q; ++k)
         for (int r = 0; r < m; ++r) {
@@ -334,7 +471,7 @@ ora_lattice *ora_create(const ora_cfg *cfg)
     L->Up = calloc((size_t)L->m * px2(L) * py2(L), sizeof(double));
     L->nup = calloc((size_t)px1(L) * py1(L), sizeof(double));
     L->fs = calloc((size_t)L->Q * L->m * px1(L) * py1(L), sizeof(double));
-    if (has_source(cfg)) {
+    if (has_bed(cfg)) {
         L->bed = calloc((size_t)L->ncell, sizeof(double));
         L->dbed = calloc((size_t)2 * L->ncell, sizeof(double));
     }
@@ -398,7 +535,7 @@ static void load_U(const ora_lattice *L, int i, int j, double *U)
 /* Wave-speed bounds alpha_bar_j (2.19): global max over interior cells. */
 static void alpha_bar(const ora_lattice *L, double *abar)
 {
-    double U[4];
+    double U[ORA_MMAX];
     for (int dir = 0; dir < L->d; ++dir) {
         double mx = 0.0;
         for (int j = 0; j < L->ny; ++j)
@@ -415,7 +552,8 @@ static void alpha_bar(const ora_lattice *L, double *abar)
 static void compute_nu(ora_lattice *L)
 {
     int d = L->d, m = L->m;
-    double Uz[4], Um[4], Upl[4], Lm[16], dm[4], dp[4], dU[4];
+    double Uz[ORA_MMAX], Um[ORA_MMAX], Upl[ORA_MMAX], Lm[ORA_MMAX * ORA_MMAX];
+    double dm[ORA_MMAX], dp[ORA_MMAX], dU[ORA_MMAX];
     for (int j = -gy1(L); j < L->ny + gy1(L); ++j)
         for (int i = -1; i < L->nx + 1; ++i) {
             load_U(L, i, j, Uz);
@@ -471,7 +609,7 @@ static void compute_omega(ora_lattice *L)
 int ora_init(ora_lattice *L, const double *U0, const double *bed, double t0)
 {
     int m = L->m, n = L->ncell;
-    if (has_source(&L->c)) {
+    if (has_bed(&L->c)) {
         if (!bed) return -2;
         memcpy(L->bed, bed, sizeof(double) * n);
         /* central differences with mirrored (or wrapped) ghost values */
@@ -507,7 +645,7 @@ int ora_init(ora_lattice *L, const double *U0, const double *bed, double t0)
     double dt = L->c.cfl * L->dx / sa;
     double lambda = L->dx / dt;
     for (int j = 0; j < L->d; ++j) alpha[j] = abar[j] + L->c.eps;
-    double U[4], feq[20];
+    double U[ORA_MMAX], feq[5 * ORA_MMAX];
     for (int j = 0; j < L->ny; ++j)
         for (int i = 0; i < L->nx; ++i) {
             load_U(L, i, j, U);
@@ -544,13 +682,13 @@ static int one_step(ora_lattice *L)
     compute_omega(L);
 
     /* collision at every interior source node */
-    double U[4], feq[20], S[4], db[2] = {0, 0};
-    int src = has_source(cf);
+    double U[ORA_MMAX], feq[5 * ORA_MMAX], S[ORA_MMAX], db[2] = {0, 0};
+    int bsrc = has_bed(cf);
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             load_U(L, i, j, U);
             equilibrium_ab(cf, U, a, b, feq);
-            if (src)
+            if (bsrc)
                 for (int dir = 0; dir < d; ++dir)
                     db[dir] = L->dbed[(size_t)dir * L->ncell + (size_t)j * nx + i];
             source(cf, U, db, S);
@@ -585,7 +723,7 @@ static int one_step(ora_lattice *L)
 
     /* pull streaming F_k(x) = f*_k(x - e_k), implicit moments (2.8), and the
      * second half source f_k = F_k + dt/2 s_k(U^{n+1}) */
-    double Fk[20], sumF[4];
+    double Fk[5 * ORA_MMAX], sumF[ORA_MMAX], Un[ORA_MMAX];
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             for (int c = 0; c < m; ++c) sumF[c] = 0.0;
@@ -597,12 +735,12 @@ static int one_step(ora_lattice *L)
                     sumF[c] += Fk[k * m + c];
                 }
             }
-            if (src)
+            if (bsrc)
                 for (int dir = 0; dir < d; ++dir)
                     db[dir] = L->dbed[(size_t)dir * L->ncell + (size_t)j * nx + i];
-            /* S depends on U only through the depth, and S_h = 0, so
-             * S(U^{n+1}) = S(sum_k F_k) and (2.8) is solved exactly. */
-            source(cf, sumF, db, S);
+            /* (2.8) for U^{n+1}, then S(U^{n+1}) for the second half source */
+            ora_moment_update(cf, sumF, db, hdt, Un);
+            source(cf, Un, db, S);
             for (int k = 0; k < Q; ++k)
                 for (int c = 0; c < m; ++c)
                     L->f[iF(L, k, c, i, j)] = Fk[k * m + c] + hdt * (a[k] * S[c]);

@@ -24,11 +24,12 @@
 extern "C" {
 #endif
 
-enum { ORA_ADVECTION = 0, ORA_EULER = 1, ORA_SWE = 2 };
+enum { ORA_ADVECTION = 0, ORA_EULER = 1, ORA_SWE = 2, ORA_REACTIVE = 3 };
+#define ORA_MMAX 5 /* most conserved fields: 2D reactive Euler */
 enum { ORA_PERIODIC = 0, ORA_TRANSMISSIVE = 1, ORA_REFLECTIVE = 2 };
 
 typedef struct ora_cfg {
-    int32_t system;     /* ORA_ADVECTION / ORA_EULER / ORA_SWE               */
+    int32_t system;     /* ORA_ADVECTION / ORA_EULER / ORA_SWE / ORA_REACTIVE */
     int32_t dim;        /* 1 or 2                                            */
     int32_t nx, ny;     /* cells; ny == 1 in 1D                              */
     double x0, x1, y0, y1;
@@ -43,6 +44,10 @@ typedef struct ora_cfg {
     int32_t has_bed;    /* shallow-water bed-slope source                    */
     int32_t omega_fixed_on;   /* 1: omega == omega_fixed everywhere          */
     double omega_fixed;
+    /* reactive Euler (Section 5.4): heat release q, rate constant K and
+     * activation temperature T_i of the Arrhenius rate R = K rho Y
+     * exp(-T_i / T), T = p / rho */
+    double q_heat, k_rate, t_act;
 } ora_cfg;
 
 typedef struct ora_lattice ora_lattice;
@@ -84,6 +89,14 @@ void ora_alpha_bar(const ora_lattice *L, double *abar);
 void ora_flux(const ora_cfg *c, int dir, const double *U, double *F);
 double ora_max_speed(const ora_cfg *c, int dir, const double *U);
 void ora_left_eigvecs(const ora_cfg *c, int dir, const double *U, double *L);
+/* Source S(U) of the system (shallow-water bed slopes db = (b_x, b_y) are
+ * ignored by the other systems). */
+void ora_source(const ora_cfg *c, const double *U, const double *db, double *S);
+/* Implicit moment update (2.8) of one cell: U = sumF + (dt/2) S(U). */
+void ora_moment_update(const ora_cfg *c, const double *sumF, const double *db, double half_dt,
+                       double *U);
+/* The exponential used by the Arrhenius rate (see the source file). */
+double ora_arrhenius_exp(double x);
 /* Lax-Friedrichs-type equilibrium coefficients a_k, b_kj of eq. (2.20)
  * written in the general form (2.5): b is Q x d row-major. */
 void ora_lf_coeffs(int dim, const double *alpha, double lambda, double *a,

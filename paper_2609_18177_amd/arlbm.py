@@ -17,11 +17,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libarlbm.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "arlbm.h")
 
-ADVECTION, EULER, SWE = 0, 1, 2
+ADVECTION, EULER, SWE, REACTIVE = 0, 1, 2, 3
 PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
 F32, F64 = 0, 1
 OMEGA_ADAPTIVE, OMEGA_FIXED = 0, 1
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EPOSITIVITY, EDEGENERATE, EBUSY, EBUDGET = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
@@ -44,6 +44,7 @@ class Config(C.Structure):
         ("adv_speed", C.c_double * 2), ("h_dry", C.c_double), ("rho_floor", C.c_double),
         ("p_floor", C.c_double), ("has_bed", C.c_int32), ("omega_mode", C.c_int32),
         ("omega_fixed", C.c_double),
+        ("q_heat", C.c_double), ("k_rate", C.c_double), ("t_act", C.c_double),
     ]
 
 
@@ -143,6 +144,7 @@ def config_from(problem=None, precision=F32, omega_fixed=None, **over) -> Config
         c.cfl, c.eps, c.gamma, c.g = problem.cfl, problem.eps, problem.gamma, problem.g
         c.adv_speed[0], c.adv_speed[1] = problem.adv
         c.has_bed = int(problem.bed is not None)
+        c.q_heat, c.k_rate, c.t_act = problem.q_heat, problem.k_rate, problem.t_act
     c.precision = precision
     if omega_fixed is not None:
         c.omega_mode, c.omega_fixed = OMEGA_FIXED, float(omega_fixed)

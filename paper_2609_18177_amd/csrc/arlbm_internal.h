@@ -15,11 +15,14 @@ constexpr int kOutW = kWave - 2 * kHalo;  // 58
 constexpr int kBlock = 256;               // 4 independent waves per block
 constexpr int kWavesPerBlock = kBlock / kWave;
 
-enum Variant : int32_t { V_ADV1 = 0, V_EUL1 = 1, V_SWE1 = 2, V_ADV2 = 3, V_EUL2 = 4, V_SWE2 = 5 };
+enum Variant : int32_t {
+    V_ADV1 = 0, V_EUL1 = 1, V_SWE1 = 2, V_REU1 = 3,
+    V_ADV2 = 4, V_EUL2 = 5, V_SWE2 = 6, V_REU2 = 7
+};
 
-__host__ __device__ constexpr int variant_of(int system, int dim) { return (dim == 2 ? 3 : 0) + system; }
+__host__ __device__ constexpr int variant_of(int system, int dim) { return (dim == 2 ? 4 : 0) + system; }
 __host__ __device__ constexpr int num_fields(int system, int dim) {
-    return system == 0 ? 1 : (system == 1 ? dim + 2 : dim + 1);
+    return system == 0 ? 1 : (system == 1 ? dim + 2 : (system == 2 ? dim + 1 : dim + 3));
 }
 
 // Per-lattice device scalars (FP64), kept resident between launches.
@@ -60,6 +63,7 @@ struct LatticeDesc {
     int32_t omega_on;     // omega export plane present (else omega is a 64-slot sink)
     int32_t pad_;
     double dx, cfl, eps, gamma, g, adv[2], h_dry, rho_floor, p_floor, omega_fixed;
+    double q_heat, k_rate, t_act;  // reactive Euler: heat release, rate constant, activation temperature
 };
 
 // One wave's work item in a batched launch.

@@ -66,6 +66,8 @@ static hipError_t step_impl(const LatticeDesc &h, int64_t iter, hipStream_t s)
     case V_ADV2: return CALL(0, 2);              \
     case V_EUL2: return CALL(1, 2);              \
     case V_SWE2: return CALL(2, 2);              \
+    case V_REU1: return CALL(3, 1);              \
+    case V_REU2: return CALL(3, 2);              \
     default: return hipErrorInvalidValue;        \
     }
 
@@ -131,6 +133,8 @@ int step_waves_per_cu(int variant)
     case V_ADV2: fn = (const void *)&k_step_single<0, 2, false, real>; break;
     case V_EUL2: fn = (const void *)&k_step_single<1, 2, false, real>; break;
     case V_SWE2: fn = (const void *)&k_step_single<2, 2, true, real>; break;
+    case V_REU1: fn = (const void *)&k_step_single<3, 1, false, real>; break;
+    case V_REU2: fn = (const void *)&k_step_single<3, 2, false, real>; break;
     default: return 0;
     }
     int blocks = 0;
@@ -149,6 +153,8 @@ int step_kernel_vgprs(int variant)
     case V_ADV2: fn = (const void *)&k_step_single<0, 2, false, real>; break;
     case V_EUL2: fn = (const void *)&k_step_single<1, 2, false, real>; break;
     case V_SWE2: fn = (const void *)&k_step_single<2, 2, true, real>; break;
+    case V_REU1: fn = (const void *)&k_step_single<3, 1, false, real>; break;
+    case V_REU2: fn = (const void *)&k_step_single<3, 2, false, real>; break;
     default: return -1;
     }
     if (hipFuncGetAttributes(&a, fn) != hipSuccess) return -1;

@@ -1,4 +1,4 @@
-// Per-cell physics of the three balance laws on the device: primitive
+// Per-cell physics of the four balance laws on the device: primitive
 // variables, physical fluxes F_j(U), the eigenvalue bound max_r |lambda_j^(r)|
 // and the characteristic projections L_j(U_i)(U_a - U_b) entering the
 // smoothness indicator (eqs. 2.13-2.14).
@@ -10,6 +10,13 @@
 // right eigenvectors whose acoustic and entropy columns start with 1 and whose
 // shear column is the unit tangential momentum.  Matrix-vector products sum
 // their non-zero terms in column order.
+//
+// Reactive Euler (Section 5.4), U = (rho, rho u[, rho v], rho E, rho Y):
+// p = (gamma-1)((E - (rho/2)|u|^2) - q rho Y).  With E' = E - q rho Y the
+// system is Euler in (rho, m, E') plus the advected rho Y, so its left
+// eigenvectors are the Euler rows with a rho Y entry of -q times their energy
+// entry, plus the species row (-Y, 0, .., 0, 1); rows in the order u-c,
+// entropy, [shear,] species, u+c.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +26,7 @@ namespace arlbm {
 template <typename T>
 struct Phys {
     T gamma, gm1, g, half_g, adv[2], dx, p_floor_t, rho_floor_t, h_dry_t;
+    T qh, kr, ti;  // reactive: heat release q, rate constant K, activation temperature T_i
     double h_dry, rho_floor, p_floor;
 };
 
@@ -36,7 +44,7 @@ __device__ __forceinline__ float dabs<float>(float v) { return __builtin_fabsf(v
 
 template <int SYS, int D>
 struct SysInfo {
-    static constexpr int M = SYS == 0 ? 1 : (SYS == 1 ? D + 2 : D + 1);
+    static constexpr int M = SYS == 0 ? 1 : (SYS == 1 ? D + 2 : (SYS == 2 ? D + 1 : D + 3));
     static constexpr int Q = 2 * D + 1;
 };
 
@@ -44,6 +52,7 @@ template <typename T>
 struct Prim {
     T rho, E, p, c, cL;
     T vel[2], mom[2];
+    T Z, Y;  // reactive: rho Y and Y
     unsigned flags;
 };
 
@@ -58,7 +67,8 @@ __device__ __forceinline__ void primitives(const T *U, const Phys<T> &P, Prim<T>
     q.flags = 0;
     q.vel[1] = T(0);
     q.mom[1] = T(0);
-    if constexpr (SYS == 1) {
+    q.Z = q.Y = T(0);
+    if constexpr (SYS == 1 || SYS == 3) {
         q.rho = U[0];
         q.E = U[D + 1];
         q.mom[0] = U[1];
@@ -71,7 +81,13 @@ __device__ __forceinline__ void primitives(const T *U, const Phys<T> &P, Prim<T>
         } else {
             q2 = q.vel[0] * q.vel[0];
         }
-        q.p = P.gm1 * (q.E - T(0.5) * q.rho * q2);
+        if constexpr (SYS == 1) {
+            q.p = P.gm1 * (q.E - T(0.5) * q.rho * q2);
+        } else {
+            q.Z = U[D + 2];
+            q.Y = q.Z / q.rho;
+            q.p = P.gm1 * ((q.E - T(0.5) * q.rho * q2) - P.qh * q.Z);
+        }
         const bool pok = double(q.p) > P.p_floor, rok = double(q.rho) > P.rho_floor;
         const T pf = pok ? q.p : P.p_floor_t;
         const T rf = rok ? q.rho : P.rho_floor_t;
@@ -105,12 +121,13 @@ __device__ __forceinline__ void flux(int dir, const T *U, const Prim<T> &q, cons
 {
     if constexpr (SYS == 0) {
         F[0] = P.adv[dir] * U[0];
-    } else if constexpr (SYS == 1) {
+    } else if constexpr (SYS == 1 || SYS == 3) {
         const T md = q.mom[dir], vd = q.vel[dir];
         F[0] = md;
 #pragma unroll
         for (int i = 0; i < D; ++i) F[1 + i] = (i == dir) ? md * q.vel[i] + q.p : md * q.vel[i];
         F[D + 1] = vd * (q.E + q.p);
+        if constexpr (SYS == 3) F[D + 2] = vd * q.Z;
     } else {
         const T md = q.mom[dir];
         const T ph = P.half_g * q.rho * q.rho;
@@ -201,6 +218,63 @@ __device__ __forceinline__ void add_theta(int dir, const Prim<T> &qc, const T *U
             nu = nu + theta<T>(dm2, dp2, dx);
             nu = nu + theta<T>(dm3, dp3, dx);
         }
+    } else if constexpr (SYS == 3) {
+        const T cs = qc.c;
+        T q2;
+        if constexpr (D == 2) q2 = qc.vel[0] * qc.vel[0] + qc.vel[1] * qc.vel[1];
+        else q2 = qc.vel[0] * qc.vel[0];
+        const T b1 = P.gm1 / (cs * cs);
+        const T b2 = T(0.5) * q2 * b1;
+        const T un = qc.vel[dir];
+        const T r0c0 = T(0.5) * (b2 + un / cs);
+        const T r0cn = T(-0.5) * (b1 * un + T(1) / cs);
+        const T r3c0 = T(0.5) * (b2 - un / cs);
+        const T r3cn = T(-0.5) * (b1 * un - T(1) / cs);
+        const T hb1 = T(0.5) * b1;
+        const T r1c0 = T(1) - b2;
+        const T zac = -(P.qh * hb1);  // rho Y entry of the acoustic rows
+        const T zen = P.qh * b1;      // rho Y entry of the entropy row
+        const T mY = -qc.Y;
+        if constexpr (D == 1) {
+            const T r1c1 = b1 * qc.vel[0];
+            // rows: u-c, u (entropy), u (species), u+c; columns: rho, rho u, E, rho Y
+            const T dm0 = r0c0 * a[0] + r0cn * a[1] + hb1 * a[2] + zac * a[3];
+            const T dp0 = r0c0 * b[0] + r0cn * b[1] + hb1 * b[2] + zac * b[3];
+            const T dm1 = r1c0 * a[0] + r1c1 * a[1] + (-b1) * a[2] + zen * a[3];
+            const T dp1 = r1c0 * b[0] + r1c1 * b[1] + (-b1) * b[2] + zen * b[3];
+            const T dm2 = mY * a[0] + a[3];
+            const T dp2 = mY * b[0] + b[3];
+            const T dm3 = r3c0 * a[0] + r3cn * a[1] + hb1 * a[2] + zac * a[3];
+            const T dp3 = r3c0 * b[0] + r3cn * b[1] + hb1 * b[2] + zac * b[3];
+            nu = nu + theta<T>(dm0, dp0, dx);
+            nu = nu + theta<T>(dm1, dp1, dx);
+            nu = nu + theta<T>(dm2, dp2, dx);
+            nu = nu + theta<T>(dm3, dp3, dx);
+        } else {
+            const int t = 1 - dir;
+            const T vt = qc.vel[t];
+            const T r0ct = T(-0.5) * b1 * vt;
+            const T r1c1 = b1 * qc.vel[0], r1c2 = b1 * qc.vel[1];
+            const T r0c1 = dir == 0 ? r0cn : r0ct, r0c2 = dir == 0 ? r0ct : r0cn;
+            const T r3c1 = dir == 0 ? r3cn : r0ct, r3c2 = dir == 0 ? r0ct : r3cn;
+            // rows: u-c, entropy, shear, species, u+c; columns: rho, rho u, rho v, E, rho Y
+            const T dm0 = r0c0 * a[0] + r0c1 * a[1] + r0c2 * a[2] + hb1 * a[3] + zac * a[4];
+            const T dp0 = r0c0 * b[0] + r0c1 * b[1] + r0c2 * b[2] + hb1 * b[3] + zac * b[4];
+            const T dm1 = r1c0 * a[0] + r1c1 * a[1] + r1c2 * a[2] + (-b1) * a[3] + zen * a[4];
+            const T dp1 = r1c0 * b[0] + r1c1 * b[1] + r1c2 * b[2] + (-b1) * b[3] + zen * b[4];
+            const T at = dir == 0 ? a[2] : a[1], bt = dir == 0 ? b[2] : b[1];
+            const T dm2 = (-vt) * a[0] + at;
+            const T dp2 = (-vt) * b[0] + bt;
+            const T dm3 = mY * a[0] + a[4];
+            const T dp3 = mY * b[0] + b[4];
+            const T dm4 = r3c0 * a[0] + r3c1 * a[1] + r3c2 * a[2] + hb1 * a[3] + zac * a[4];
+            const T dp4 = r3c0 * b[0] + r3c1 * b[1] + r3c2 * b[2] + hb1 * b[3] + zac * b[4];
+            nu = nu + theta<T>(dm0, dp0, dx);
+            nu = nu + theta<T>(dm1, dp1, dx);
+            nu = nu + theta<T>(dm2, dp2, dx);
+            nu = nu + theta<T>(dm3, dp3, dx);
+            nu = nu + theta<T>(dm4, dp4, dx);
+        }
     } else {
         const T cs = qc.cL;
         const T un = qc.vel[dir];
@@ -226,6 +300,97 @@ __device__ __forceinline__ void add_theta(int dir, const Prim<T> &qc, const T *U
             nu = nu + theta<T>(dm2, dp2, dx);
         }
     }
+}
+
+// ---------------------------------------------------------------- reactive --
+
+// exp(x) for the Arrhenius factor, by a fixed algorithm (so that FP64 results
+// do not depend on the math library): Cody-Waite reduction x = k ln2 + r,
+// |r| <= ln2/2, with ln2 split into a head whose trailing bits are zero (k
+// times the head is exact) and a tail; the Taylor series of exp(r) to degree
+// 13 in Horner form (truncation below 5e-18); scaling by 2^k.  Evaluated in
+// FP64 for both storage precisions.
+__device__ __forceinline__ double arrhenius_exp(double x)
+{
+    const double inv_ln2 = 1.44269504088896338700e+00;
+    const double ln2_hi = 6.93147180369123816490e-01;
+    const double ln2_lo = 1.90821492927058770002e-10;
+    if (x != x) return x;
+    if (x < -746.0) return 0.0;
+    if (x > 710.0) return __builtin_huge_val();
+    const double k = __builtin_rint(x * inv_ln2);
+    const double r = (x - k * ln2_hi) - k * ln2_lo;
+    double p = 1.0 / 6227020800.0;
+    p = p * r + 1.0 / 479001600.0;
+    p = p * r + 1.0 / 39916800.0;
+    p = p * r + 1.0 / 3628800.0;
+    p = p * r + 1.0 / 362880.0;
+    p = p * r + 1.0 / 40320.0;
+    p = p * r + 1.0 / 5040.0;
+    p = p * r + 1.0 / 720.0;
+    p = p * r + 1.0 / 120.0;
+    p = p * r + 1.0 / 24.0;
+    p = p * r + 1.0 / 6.0;
+    p = p * r + 0.5;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    return __builtin_ldexp(p, (int)k);
+}
+
+// Arrhenius rate R = K z exp(-T_i / T), T = p / rho, at rho Y = z with rho
+// and e_int = E - (rho/2)|u|^2 fixed; dRdz (if asked) its derivative in z.
+template <typename T>
+__device__ __forceinline__ T arrhenius_rate(const Phys<T> &P, T rho, T e_int, T z, T *dRdz)
+{
+    const T p = P.gm1 * (e_int - P.qh * z);
+    const bool pok = double(p) > P.p_floor, rok = double(rho) > P.rho_floor;
+    const T pf = pok ? p : P.p_floor_t;
+    const T rf = rok ? rho : P.rho_floor_t;
+    const T Tm = pf / rf;
+    const T e = T(arrhenius_exp(double(-(P.ti / Tm))));
+    const T R = (P.kr * z) * e;
+    if (dRdz) {
+        const T dlog = pok ? (P.ti * rf) * (P.gm1 * P.qh) / (pf * pf) : T(0);
+        *dRdz = P.kr * e * (T(1) - z * dlog);
+    }
+    return R;
+}
+
+// Internal energy part E - (rho/2)|u|^2 of a reactive state, in the same
+// association as the primitive variables.
+template <int D, typename T>
+__device__ __forceinline__ T reactive_eint(const T *U)
+{
+    const T u0 = U[1] / U[0];
+    const T u1 = D == 2 ? U[2] / U[0] : T(0);
+    const T q2 = u0 * u0 + u1 * u1;
+    return U[D + 1] - T(0.5) * U[0] * q2;
+}
+
+// rho Y component of (2.8): z solves g(z) = (z - B) + (dt/2) R(z) = 0 on the
+// bracket [min(0,B), max(0,B)], by Newton steps that fall back to bisection
+// when they leave the bracket (or the slope is not positive); stops when a
+// Newton step no longer changes z (or a bisection lands on z), or after 40
+// iterations.
+template <typename T>
+__device__ __forceinline__ T reactive_solve(const Phys<T> &P, T rho, T e_int, T B, T half_dt)
+{
+    T lo = B < T(0) ? B : T(0), hi = B < T(0) ? T(0) : B;
+    T z = B;
+    for (int it = 0; it < 40; ++it) {
+        T dR;
+        const T g = (z - B) + half_dt * arrhenius_rate<T>(P, rho, e_int, z, &dR);
+        if (g == T(0)) break;
+        if (g > T(0)) hi = z;
+        else lo = z;
+        const T dg = T(1) + half_dt * dR;
+        T zn = z - g / dg;
+        if (dg > T(0) && zn == z) break;  // the Newton step no longer moves z
+        if (!(dg > T(0)) || !(zn > lo && zn < hi)) zn = T(0.5) * (lo + hi);
+        if (zn == z) break;
+        z = zn;
+    }
+    return z;
 }
 
 }  // namespace arlbm

@@ -45,7 +45,7 @@ std::string check_config(const arlbm_config *c)
 {
     if (!c) return "config is NULL";
     if (c->abi_version != ARLBM_ABI_VERSION) return "abi_version mismatch";
-    if (c->system < 0 || c->system > 2) return "unknown system";
+    if (c->system < 0 || c->system > 3) return "unknown system";
     if (c->dim != 1 && c->dim != 2) return "dim must be 1 or 2";
     if (c->precision != ARLBM_F32 && c->precision != ARLBM_F64) return "precision must be F32 or F64";
     if (c->nx < 4) return "nx must be >= 4";
@@ -70,10 +70,15 @@ std::string check_config(const arlbm_config *c)
             if (c->bc[s] == ARLBM_REFLECTIVE) return "reflective walls need a momentum field (not advection)";
     if (!(c->cfl > 0.0 && c->cfl < 1.0)) return "CFL must lie in (0, 1)";
     if (!(c->eps > 0.0)) return "eps must be > 0";
-    if (c->system == ARLBM_EULER && !(c->gamma > 1.0)) return "gamma must be > 1";
+    const bool gas = c->system == ARLBM_EULER || c->system == ARLBM_REACTIVE;
+    if (gas && !(c->gamma > 1.0)) return "gamma must be > 1";
+    if (c->system == ARLBM_REACTIVE && !(c->q_heat >= 0.0 && c->k_rate >= 0.0 && c->t_act >= 0.0 &&
+                                         std::isfinite(c->q_heat) && std::isfinite(c->k_rate) &&
+                                         std::isfinite(c->t_act)))
+        return "q_heat, k_rate and t_act must be finite and >= 0";
     if (c->system == ARLBM_SWE && !(c->g > 0.0)) return "g must be > 0";
     if (c->system == ARLBM_SWE && !(c->h_dry > 0.0)) return "h_dry must be > 0";
-    if (c->system == ARLBM_EULER && !(c->rho_floor > 0.0 && c->p_floor > 0.0)) return "floors must be > 0";
+    if (gas && !(c->rho_floor > 0.0 && c->p_floor > 0.0)) return "floors must be > 0";
     if (c->has_bed && c->system != ARLBM_SWE) return "a bed source needs shallow water";
     if (c->system == ARLBM_ADVECTION) {
         double s = std::fabs(c->adv_speed[0]) + (c->dim == 2 ? std::fabs(c->adv_speed[1]) : 0.0);
@@ -234,7 +239,8 @@ int check_state(arlbm_lattice *h, const double *U0, const double *bed)
     if (bed)
         for (int64_t i = 0; i < plane; ++i)
             if (!std::isfinite(bed[i])) return fail(h, ARLBM_EPOSITIVITY, "bed is not finite");
-    if (c.system == ARLBM_EULER) {
+    if (c.system == ARLBM_EULER || c.system == ARLBM_REACTIVE) {
+        const int e = c.dim + 1;
         for (int64_t i = 0; i < plane; ++i) {
             const double rho = U0[i];
             double ke = 0.0;
@@ -242,7 +248,9 @@ int check_state(arlbm_lattice *h, const double *U0, const double *bed)
                 const double mom = U0[(1 + d) * plane + i];
                 ke += 0.5 * mom * mom / rho;
             }
-            const double p = (c.gamma - 1.0) * (U0[(m - 1) * plane + i] - ke);
+            double chem = 0.0;
+            if (c.system == ARLBM_REACTIVE) chem = c.q_heat * U0[(int64_t)(e + 1) * plane + i];
+            const double p = (c.gamma - 1.0) * (U0[(int64_t)e * plane + i] - ke - chem);
             if (!(rho > 0.0)) return fail(h, ARLBM_EPOSITIVITY, "initial density must be > 0");
             if (!(p > 0.0)) return fail(h, ARLBM_EPOSITIVITY, "initial pressure must be > 0");
         }
@@ -382,6 +390,9 @@ extern "C" int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, 
     d.rho_floor = cfg->rho_floor;
     d.p_floor = cfg->p_floor;
     d.omega_fixed = cfg->omega_fixed;
+    d.q_heat = cfg->q_heat;
+    d.k_rate = cfg->k_rate;
+    d.t_act = cfg->t_act;
     if (bufs) {
         auto bad = [](const void *p) { return !p || ((uintptr_t)p % kAlign) != 0; };
         if (bad(bufs->f[0]) || bad(bufs->f[1]) || bad(bufs->u[0]) || bad(bufs->u[1]) || bad(bufs->scalars) ||

@@ -159,6 +159,9 @@ __device__ __forceinline__ Phys<T> make_phys(const LatticeDesc &L)
     P.p_floor_t = T(L.p_floor);
     P.rho_floor_t = T(L.rho_floor);
     P.h_dry_t = T(L.h_dry);
+    P.qh = T(L.q_heat);
+    P.kr = T(L.k_rate);
+    P.ti = T(L.t_act);
     P.h_dry = L.h_dry;
     P.rho_floor = L.rho_floor;
     P.p_floor = L.p_floor;
@@ -330,6 +333,12 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
             fs[2][1] = fs[2][1] + cf.hdt * (cf.ap[0] * S1);
         }
     }
+    if constexpr (SYS == 3) {  // Arrhenius sink of rho Y, first half (2.6)
+        const T SY = -arrhenius_rate<T>(P, U[0], reactive_eint<D, T>(U), U[M - 1], nullptr);
+        fs[0][M - 1] = fs[0][M - 1] + cf.hdt * (cf.a0 * SY);
+        fs[1][M - 1] = fs[1][M - 1] + cf.hdt * (cf.ap[0] * SY);
+        fs[2][M - 1] = fs[2][M - 1] + cf.hdt * (cf.ap[0] * SY);
+    }
     // pull streaming: F_+(x) = f*_+(x-1), F_-(x) = f*_-(x+1)
     T Fp[M], Fm[M];
 #pragma unroll
@@ -361,6 +370,17 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
             fn[1][1] = fn[1][1] + cf.hdt * (cf.ap[0] * S1);
             fn[2][1] = fn[2][1] + cf.hdt * (cf.ap[0] * S1);
         }
+    }
+    if constexpr (SYS == 3) {  // (2.8) for rho Y, then the second half source
+        T sumF[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) sumF[c] = fs[0][c] + Fp[c] + Fm[c];
+        const T eint = reactive_eint<D, T>(sumF);
+        const T z = reactive_solve<T>(P, sumF[0], eint, sumF[M - 1], cf.hdt);
+        const T SY = -arrhenius_rate<T>(P, sumF[0], eint, z, nullptr);
+        fn[0][M - 1] = fn[0][M - 1] + cf.hdt * (cf.a0 * SY);
+        fn[1][M - 1] = fn[1][M - 1] + cf.hdt * (cf.ap[0] * SY);
+        fn[2][M - 1] = fn[2][M - 1] + cf.hdt * (cf.ap[0] * SY);
     }
 #pragma unroll
     for (int c = 0; c < M; ++c) Un[c] = fn[0][c] + fn[1][c] + fn[2][c];
@@ -509,7 +529,7 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     // once (4 Q m registers).  FP64 would need twice that and drop to one
     // wave per SIMD: it reads the row again in the iteration that collides it
     // (a cache hit when the caches hold the rows in between).
-    constexpr bool kRing = sizeof(T) == 4;
+    constexpr bool kRing = sizeof(T) == 4 && Q * M <= 20;
     // Shallow water (15 values per row) prefetches two rows ahead: measured
     // 2.6% faster there, 5% slower for 2D Euler (20 values per row).
     constexpr bool kPf2 = kRing && SYS == 2;
@@ -626,6 +646,12 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
                     fs[k][2] = fs[k][2] + cf.hdt * (ak[k] * S2);
                 }
             }
+            if constexpr (SYS == 3) {  // Arrhenius sink of rho Y, first half (2.6)
+                const T SY = -arrhenius_rate<T>(P, U0[0], reactive_eint<D, T>(U0), U0[M - 1], nullptr);
+                const T ak[Q] = {cf.a0, cf.ap[0], cf.ap[1], cf.ap[0], cf.ap[1]};
+#pragma unroll
+                for (int k = 0; k < Q; ++k) fs[k][M - 1] = fs[k][M - 1] + cf.hdt * (ak[k] * SY);
+            }
         }
         // x pulls with the ghost map at the two x walls
         T px[M], mx[M];
@@ -669,6 +695,14 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
                     Fk[k][1] = Fk[k][1] + cf.hdt * (ak[k] * S1);
                     Fk[k][2] = Fk[k][2] + cf.hdt * (ak[k] * S2);
                 }
+            }
+            if constexpr (SYS == 3) {  // (2.8) for rho Y, then the second half source
+                const T eint = reactive_eint<D, T>(sumF);
+                const T z = reactive_solve<T>(P, sumF[0], eint, sumF[M - 1], cf.hdt);
+                const T SY = -arrhenius_rate<T>(P, sumF[0], eint, z, nullptr);
+                const T ak[Q] = {cf.a0, cf.ap[0], cf.ap[1], cf.ap[0], cf.ap[1]};
+#pragma unroll
+                for (int k = 0; k < Q; ++k) Fk[k][M - 1] = Fk[k][M - 1] + cf.hdt * (ak[k] * SY);
             }
             T Un[M];
 #pragma unroll
@@ -756,6 +790,8 @@ __global__ __launch_bounds__(kBlock) void k_step_batched(const LatticeDesc *desc
         if (L.bed) strip2d<2, true, T>(L, iter, it.col, it.band, it.first);
         else strip2d<2, false, T>(L, iter, it.col, it.band, it.first);
         break;
+    case V_REU1: strip1d<3, T>(L, iter, it.col, it.first); break;
+    case V_REU2: strip2d<3, false, T>(L, iter, it.col, it.band, it.first); break;
     default: break;
     }
 }

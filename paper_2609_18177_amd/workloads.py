@@ -10,7 +10,9 @@ Conserved variables, one plane per field, cell-centred points
 * scalar advection: ``u``;
 * Euler (gamma-law gas): ``(rho, rho u[, rho v], E)`` with
   ``E = p/(gamma-1) + rho |u|^2 / 2``;
-* shallow water: ``(h, h u[, h v])``.
+* shallow water: ``(h, h u[, h v])``;
+* reactive Euler (Section 5.4): ``(rho, rho u[, rho v], rho E, rho Y)`` with
+  ``rho E = p/(gamma-1) + rho |u|^2 / 2 + q rho Y``.
 
 Workloads follow the structure of the paper's experiments (Section 5): smooth
 periodic sine waves, piecewise-constant Riemann data, four-quadrant 2D Riemann
@@ -25,7 +27,7 @@ from typing import List, Optional
 
 import numpy as np
 
-ADVECTION, EULER, SWE = 0, 1, 2
+ADVECTION, EULER, SWE, REACTIVE = 0, 1, 2, 3
 PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
 GAMMA = 1.4
 GRAVITY = 9.81
@@ -53,6 +55,9 @@ class Problem:
     g: float = GRAVITY
     adv: tuple = (1.0, 0.0)
     eps: float = 1e-10
+    q_heat: float = 0.0            # reactive: heat release
+    k_rate: float = 0.0            # reactive: Arrhenius rate constant
+    t_act: float = 0.0             # reactive: activation temperature
 
     @property
     def cells(self) -> int:
@@ -70,6 +75,14 @@ def euler_conserved(rho, u, v, p, gamma=GAMMA, dim=2):
     if dim == 1:
         return np.stack([rho, rho * u, E])
     return np.stack([rho, rho * u, rho * v, E])
+
+
+def reactive_conserved(rho, u, v, p, Y, q_heat, gamma, dim=2):
+    rho, u, v, p, Y = (np.asarray(a, dtype=np.float64) for a in (rho, u, v, p, Y))
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v) + q_heat * rho * Y
+    if dim == 1:
+        return np.stack([rho, rho * u, E, rho * Y])
+    return np.stack([rho, rho * u, rho * v, E, rho * Y])
 
 
 def swe_conserved(h, u, v, dim=2):
@@ -309,3 +322,102 @@ def serving_requests(count=512, rate_hz=200.0, seed=0, n1d=(1024, 65536),
         out.append(Request(i, t, kind, size, int(rng.integers(steps[0], steps[1] + 1)),
                            int(rng.integers(0, 2 ** 31))))
     return out
+
+
+# --------------------------------------------------------------------------
+# Reactive Euler (Section 5.4)
+# --------------------------------------------------------------------------
+
+# Example 5.11's kinetics.  The example does not state gamma; 1.2 is the value
+# of the paper's other reactive examples (a documented reading).
+DET1D = dict(q_heat=50.0, k_rate=145.68913, t_act=50.0, gamma=1.2)
+DET1D_BURNT = (2.5706, 6.86089, 80.02055, 0.0)   # (rho, u, p, Y) for x < 2
+DET1D_FRESH = (1.0, 0.0, 1.0, 1.0)               # x >= 2
+CIRC2D = dict(q_heat=50.0, k_rate=2566.4, t_act=50.0, gamma=1.2)
+
+
+def reactive_detonation_1d(n=15000, x1=100.0, xs=2.0, cfl=0.9, t_final=7.5, steps=10 ** 9) -> Problem:
+    """Example 5.11 data: a burnt driver state left of xs, fresh mixture
+    right of it, transmissive ends; dx = x1 / n (the paper: 1/150 on [0,100])."""
+    x = centres(n, 0.0, x1)
+    L = x < xs
+    st = [np.where(L, a, b) for a, b in zip(DET1D_BURNT, DET1D_FRESH)]
+    U0 = reactive_conserved(st[0], st[1], 0 * st[1], st[2], st[3], DET1D["q_heat"], DET1D["gamma"], dim=1)
+    return Problem("reactive_detonation_1d", REACTIVE, 1, n, 1, 0.0, x1, 0.0, 1.0,
+                   (TRANSMISSIVE,) * 4, cfl, steps, U0, t_final=t_final, gamma=DET1D["gamma"],
+                   q_heat=DET1D["q_heat"], k_rate=DET1D["k_rate"], t_act=DET1D["t_act"])
+
+
+def reactive_circle_2d(n=400, cfl=0.9, t_final=0.04, steps=10 ** 9) -> Problem:
+    """Example 5.12 data on [-1,1]^2: (rho,u,v,p,Y) = (1,0,0,80,0.2) inside
+    the circle of radius 0.6, (1,0,0,10,0.8) outside; transmissive."""
+    x = centres(n, -1.0, 1.0)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    inside = X * X + Y * Y <= 0.36
+    p = np.where(inside, 80.0, 10.0)
+    Yf = np.where(inside, 0.2, 0.8)
+    one = np.ones_like(X)
+    U0 = reactive_conserved(one, 0 * one, 0 * one, p, Yf, CIRC2D["q_heat"], CIRC2D["gamma"], dim=2)
+    return Problem("reactive_circle_2d", REACTIVE, 2, n, n, -1.0, 1.0, -1.0, 1.0,
+                   (TRANSMISSIVE,) * 4, cfl, steps, U0, t_final=t_final, gamma=CIRC2D["gamma"],
+                   q_heat=CIRC2D["q_heat"], k_rate=CIRC2D["k_rate"], t_act=CIRC2D["t_act"])
+
+
+def reactive_seeded_1d(seed=0, n=2048, cfl=0.5, steps=1000) -> Problem:
+    """Seeded reactive Riemann data on [0,1]: a hot, partly burnt state left
+    of 0.5 and a cool fresh mixture right of it, with kinetics drawn so that
+    the left state burns within a few hundred steps."""
+    rng = np.random.default_rng(1000 + seed)
+    gamma = 1.2
+    left = (rng.uniform(1.0, 2.5), rng.uniform(0.0, 2.0), rng.uniform(20.0, 80.0), rng.uniform(0.0, 0.5))
+    right = (rng.uniform(0.5, 1.5), rng.uniform(-0.5, 0.5), rng.uniform(0.5, 2.0), rng.uniform(0.8, 1.0))
+    q_heat = rng.uniform(10.0, 50.0)
+    t_act = rng.uniform(10.0, 40.0)
+    k_rate = rng.uniform(50.0, 500.0)
+    x = centres(n, 0.0, 1.0)
+    L = x < 0.5
+    st = [np.where(L, a, b) for a, b in zip(left, right)]
+    U0 = reactive_conserved(st[0], st[1], 0 * st[1], st[2], st[3], q_heat, gamma, dim=1)
+    return Problem(f"reactive1d_seed{seed}", REACTIVE, 1, n, 1, 0.0, 1.0, 0.0, 1.0,
+                   (TRANSMISSIVE,) * 4, cfl, steps, U0, gamma=gamma,
+                   q_heat=q_heat, k_rate=k_rate, t_act=t_act)
+
+
+def reactive_seeded_2d(seed=0, n=256, cfl=0.5, steps=200, bc=(TRANSMISSIVE,) * 4) -> Problem:
+    """Seeded 2D reactive data on [0,1]^2: hot burnt pockets (Gaussian bumps
+    of pressure and burnt fraction) in a fresh mixture, with a shear flow."""
+    rng = np.random.default_rng(2000 + seed)
+    gamma = 1.2
+    q_heat = rng.uniform(10.0, 50.0)
+    t_act = rng.uniform(10.0, 40.0)
+    k_rate = rng.uniform(50.0, 500.0)
+    x = centres(n, 0.0, 1.0)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    p = np.full_like(X, rng.uniform(0.5, 2.0))
+    burnt = np.zeros_like(X)
+    for _ in range(4):
+        cx, cy = rng.uniform(0.2, 0.8, size=2)
+        w = rng.uniform(0.04, 0.1)
+        g = np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / w ** 2)
+        p = p + rng.uniform(20.0, 60.0) * g
+        burnt = np.maximum(burnt, g)
+    Yf = 1.0 - 0.9 * burnt
+    rho = rng.uniform(0.8, 1.5) + 0.2 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)
+    u = rng.uniform(-0.5, 0.5) * np.sin(2 * np.pi * Y)
+    v = rng.uniform(-0.5, 0.5) * np.sin(2 * np.pi * X)
+    U0 = reactive_conserved(rho, u, v, p, Yf, q_heat, gamma, dim=2)
+    return Problem(f"reactive2d_seed{seed}", REACTIVE, 2, n, n, 0.0, 1.0, 0.0, 1.0,
+                   bc, cfl, steps, U0, gamma=gamma, q_heat=q_heat, k_rate=k_rate, t_act=t_act)
+
+
+def reactive_uniform(n=16, dim=1, rho=1.0, u=0.3, v=-0.2, p=1.0, Y=1.0, q_heat=20.0, k_rate=50.0,
+                     t_act=5.0, gamma=1.2, cfl=0.5, steps=100) -> Problem:
+    """A spatially uniform reacting state with periodic boundaries: every cell
+    follows the same ODE for rho Y while rho, rho u and rho E stay fixed."""
+    ny = n if dim == 2 else 1
+    shape = (ny, n) if dim == 2 else (n,)
+    one = np.ones(shape)
+    U0 = reactive_conserved(rho * one, u * one, (v if dim == 2 else 0.0) * one, p * one, Y * one,
+                            q_heat, gamma, dim=dim)
+    return Problem("reactive_uniform", REACTIVE, dim, n, ny, 0.0, 1.0, 0.0, 1.0,
+                   (PERIODIC,) * 4, cfl, steps, U0, gamma=gamma, q_heat=q_heat, k_rate=k_rate, t_act=t_act)

@@ -11,7 +11,7 @@ def ora_cfg_from(p, omega_fixed=None, eps=None, cfl=None, bc=None):
                       bc if bc is not None else p.bc,
                       p.cfl if cfl is None else cfl, p.eps if eps is None else eps,
                       p.gamma, p.g, p.adv, has_bed=p.bed is not None,
-                      omega_fixed=omega_fixed)
+                      omega_fixed=omega_fixed, q_heat=p.q_heat, k_rate=p.k_rate, t_act=p.t_act)
 
 
 def ora_from(p, **kw):

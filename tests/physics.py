@@ -116,3 +116,65 @@ def random_swe_state(rng, d):
     h = rng.uniform(0.1, 2.0)
     vel = rng.uniform(-1.5, 1.5, d)
     return np.concatenate([[h], h * vel])
+
+
+def reactive_flux(U, j, gamma=1.2, q_heat=0.0):
+    """Reactive Euler flux (Section 5.4): Euler flux with rho E including
+    q rho Y, plus rho Y u_j."""
+    U = np.asarray(U, dtype=np.float64)
+    d = U.shape[0] - 3
+    rho, E, Z = U[0], U[d + 1], U[d + 2]
+    vel = [U[1 + i] / rho for i in range(d)]
+    p = (gamma - 1.0) * (E - 0.5 * rho * sum(v * v for v in vel) - q_heat * Z)
+    F = [rho * vel[j]]
+    for i in range(d):
+        F.append(rho * vel[j] * vel[i] + (p if i == j else 0.0))
+    F.append(vel[j] * (E + p))
+    F.append(Z * vel[j])
+    return np.array(F)
+
+
+def reactive_right_eigvecs(U, j, gamma=1.2, q_heat=0.0):
+    """Columns in the order u_n - c, entropy, [shear], species, u_n + c.
+
+    With E' = E - q rho Y the system is Euler plus an advected scalar; its
+    right eigenvectors in (rho, m, E', rho Y) are Toro's columns extended by
+    Y (acoustic, entropy), 0 (shear) and the unit species column; mapping
+    back to (rho, m, E, rho Y) adds q times the last entry to the energy."""
+    U = np.asarray(U, dtype=np.float64)
+    d = U.shape[0] - 3
+    rho, E, Z = U[0], U[d + 1], U[d + 2]
+    Y = Z / rho
+    vel = np.array([U[1 + i] / rho for i in range(d)])
+    q2 = float(vel @ vel)
+    p = (gamma - 1.0) * (E - 0.5 * rho * q2 - q_heat * Z)
+    c = np.sqrt(gamma * p / rho)
+    Ep = E - q_heat * Z
+    H = (Ep + p) / rho
+    un = vel[j]
+    e = np.zeros(d)
+    e[j] = 1.0
+    cols = [np.concatenate([[1.0], vel - c * e, [H - un * c], [Y]]),
+            np.concatenate([[1.0], vel, [0.5 * q2], [Y]])]
+    if d == 2:
+        t = 1 - j
+        sh = np.zeros(d + 3)
+        sh[1 + t] = 1.0
+        sh[d + 1] = vel[t]
+        cols.append(sh)
+    sp = np.zeros(d + 3)
+    sp[d + 2] = 1.0
+    cols.append(sp)
+    cols.append(np.concatenate([[1.0], vel + c * e, [H + un * c], [Y]]))
+    R = np.array(cols).T
+    R[d + 1, :] = R[d + 1, :] + q_heat * R[d + 2, :]
+    return R
+
+
+def random_reactive_state(rng, d, gamma=1.2, q_heat=30.0):
+    rho = rng.uniform(0.5, 2.0)
+    vel = rng.uniform(-1.0, 1.0, size=d)
+    p = rng.uniform(0.5, 5.0)
+    Y = rng.uniform(0.0, 1.0)
+    E = p / (gamma - 1.0) + 0.5 * rho * float(vel @ vel) + q_heat * rho * Y
+    return np.concatenate([[rho], rho * vel, [E], [rho * Y]])

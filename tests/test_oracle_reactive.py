@@ -1,0 +1,287 @@
+"""Oracle pins for reactive Euler (Section 5.4, Examples 5.11-5.12), CPU.
+
+The paper prints only figures for its reactive examples, so the oracle's
+reactive parts are pinned by closed forms, reductions and invariants:
+
+* the Arrhenius exponential against the C library's exp;
+* flux against the PDE; left eigenvectors: L R = I against the textbook
+  right eigenvectors (Euler plus an advected scalar, mapped back from
+  E' = E - q rho Y) and L A = Lambda L with A from finite differences;
+* (2.8): the Newton root against a bracketing root finder, residual zero;
+* a spatially uniform state: the scheme is exactly the trapezoidal rule for
+  d(rho Y)/dt = -R (the equilibrium and the streaming drop out), second
+  order against an accurate ODE solution;
+* K = 0: the system is Euler in (rho, m, E - q rho Y) plus an advected scalar,
+  so the run equals the Euler oracle on that energy (to rounding);
+* conservation of rho, m, E under periodic boundaries, monotone burning;
+* mirror symmetry of Example 5.12's circular data.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+from scipy.optimize import brentq
+
+import oracle as O
+import physics as P
+from paper_2609_18177_amd import workloads as W
+from helpers import ora_from, ora_cfg_from, run_until, fsum
+
+
+def test_arrhenius_exp_matches_libm():
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([np.linspace(-708.0, 0.0, 40001), rng.uniform(-708, 700, 20000),
+                         [-1e-300, 0.0, -0.5 * math.log(2.0), 0.5 * math.log(2.0), 1.0, -1.0]])
+    for x in xs:
+        a, b = O.arrhenius_exp(x), math.exp(x)
+        assert abs(a - b) <= 4 * np.spacing(b), (x, a, b)
+    # subnormal results and underflow
+    for x in (-720.0, -740.0, -745.0):
+        assert abs(O.arrhenius_exp(x) - math.exp(x)) <= 4 * 5e-324
+    assert O.arrhenius_exp(-800.0) == 0.0
+    assert math.isnan(O.arrhenius_exp(float("nan")))
+
+
+def _cfg(d, q=30.0, K=100.0, Ti=20.0, gamma=1.2):
+    return O.make_cfg(O.REACTIVE, d, 8, 8, gamma=gamma, q_heat=q, k_rate=K, t_act=Ti)
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_reactive_flux_and_speed(d):
+    rng = np.random.default_rng(7 + d)
+    cfg = _cfg(d)
+    for _ in range(50):
+        U = P.random_reactive_state(rng, d, cfg.gamma, cfg.q_heat)
+        for j in range(d):
+            F = O.flux(cfg, j, U)
+            assert np.allclose(F, P.reactive_flux(U, j, cfg.gamma, cfg.q_heat), rtol=1e-14, atol=1e-14)
+            A = P.jacobian_fd(lambda V, jj: P.reactive_flux(V, jj, cfg.gamma, cfg.q_heat), U, j)
+            lam = np.max(np.abs(np.linalg.eigvals(A).real))
+            assert abs(O.max_speed(cfg, j, U) - lam) < 1e-6 * max(1.0, lam)
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_reactive_left_eigenvectors(d):
+    rng = np.random.default_rng(20 + d)
+    cfg = _cfg(d)
+    m = d + 3
+    for _ in range(40):
+        U = P.random_reactive_state(rng, d, cfg.gamma, cfg.q_heat)
+        for j in range(d):
+            L = O.left_eigvecs(cfg, j, U)
+            R = P.reactive_right_eigvecs(U, j, cfg.gamma, cfg.q_heat)
+            assert np.allclose(L @ R, np.eye(m), atol=1e-12), (L @ R)
+            A = P.jacobian_fd(lambda V, jj: P.reactive_flux(V, jj, cfg.gamma, cfg.q_heat), U, j)
+            rho, un = U[0], U[1 + j] / U[0]
+            p = (cfg.gamma - 1.0) * (U[d + 1] - 0.5 * np.sum(U[1:1 + d] ** 2) / rho - cfg.q_heat * U[d + 2])
+            c = math.sqrt(cfg.gamma * p / rho)
+            lam = [un - c, un] + ([un] if d == 2 else []) + [un, un + c]
+            scale = max(1.0, np.abs(A).max())
+            assert np.allclose(L @ A, np.diag(lam) @ L, atol=2e-5 * scale * np.abs(L).max())
+
+
+def test_reactive_eigenvectors_reduce_to_euler_at_q0():
+    rng = np.random.default_rng(3)
+    for d in (1, 2):
+        cr = _cfg(d, q=0.0)
+        ce = O.make_cfg(O.EULER, d, 8, 8, gamma=1.2)
+        for _ in range(10):
+            U = P.random_reactive_state(rng, d, 1.2, 0.0)
+            for j in range(d):
+                Lr, Le = O.left_eigvecs(cr, j, U), O.left_eigvecs(ce, j, U[:-1])
+                m = d + 2
+                rows = list(range(m - 1)) + [m]   # Euler rows: all but the species row
+                assert np.array_equal(Lr[rows][:, :m], Le)
+                assert np.all(Lr[rows][:, m] == 0.0)
+
+
+def _g(cfg, rho, eint, B, hdt, z):
+    p = (cfg.gamma - 1.0) * (eint - cfg.q_heat * z)
+    return (z - B) + hdt * cfg.k_rate * z * math.exp(-cfg.t_act * rho / p)
+
+
+@pytest.mark.parametrize("K,hdt", [(100.0, 1e-3), (2566.4, 2e-4), (1e5, 1e-2), (0.0, 1e-3)])
+def test_moment_update_solves_2_8(K, hdt):
+    rng = np.random.default_rng(int(K) % 97)
+    for d in (1, 2):
+        cfg = _cfg(d, q=40.0, K=K, Ti=30.0)
+        for _ in range(30):
+            sumF = P.random_reactive_state(rng, d, cfg.gamma, cfg.q_heat)
+            if rng.uniform() < 0.2:
+                sumF[-1] = -abs(sumF[-1]) * 1e-3      # slight undershoot of rho Y
+            U = O.moment_update(cfg, sumF, hdt)
+            assert np.array_equal(U[:-1], sumF[:-1])
+            rho = sumF[0]
+            eint = sumF[d + 1] - 0.5 * np.sum(sumF[1:1 + d] ** 2) / rho
+            B = sumF[-1]
+            if K == 0.0:
+                assert U[-1] == B
+                continue
+            lo, hi = min(0.0, B), max(0.0, B)
+            ref = brentq(lambda z: _g(cfg, rho, eint, B, hdt, z), lo, hi, xtol=1e-300, rtol=1e-15) \
+                if B != 0.0 else 0.0
+            assert abs(U[-1] - ref) <= 1e-13 * max(abs(B), 1e-300), (U[-1], ref, B)
+            S = O.source(cfg, U)
+            assert abs((U[-1] - B) - hdt * S[-1]) <= 1e-14 * max(abs(B), 1e-300)
+
+
+def _trapezoid_history(cfg, U0cell, dts):
+    """rho Y of one cell under z' = -R(z) by the trapezoidal rule with the
+    given steps (each implicit stage by a bracketing root finder)."""
+    d = cfg.dim
+    rho = U0cell[0]
+    eint = U0cell[d + 1] - 0.5 * np.sum(U0cell[1:1 + d] ** 2) / rho
+
+    def R(z):
+        p = (cfg.gamma - 1.0) * (eint - cfg.q_heat * z)
+        return cfg.k_rate * z * math.exp(-cfg.t_act * rho / p)
+
+    z = U0cell[-1]
+    out = []
+    for dt in dts:
+        rhs = z - 0.5 * dt * R(z)
+        z = brentq(lambda w: w + 0.5 * dt * R(w) - rhs, 0.0, max(z, 1e-300), xtol=1e-300, rtol=1e-15)
+        out.append(z)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_uniform_state_is_trapezoidal_rule(d):
+    p = W.reactive_uniform(n=8, dim=d, steps=60)
+    cfg = ora_cfg_from(p)
+    L = ora_from(p)
+    zs, dts = [], []
+    for _ in range(p.steps):
+        L.run(1)
+        U = L.moments()
+        dts.append(L.last_scalars()[1])
+        zs.append(U[-1].ravel())
+    zs = np.array(zs)
+    # every cell identical (to rounding), rho, momentum, energy unchanged
+    assert np.all(np.abs(zs - zs[:, :1]) <= 1e-15 * np.abs(zs[:, :1]) + 1e-300)
+    U = L.moments().reshape(d + 3, -1)
+    U0 = p.U0.reshape(d + 3, -1)
+    assert np.allclose(U[:-1], U0[:-1], rtol=2e-15, atol=1e-15)
+    ref = _trapezoid_history(cfg, U0[:, 0], dts)
+    # omega = 2 exactly on a uniform state, so the non-equilibrium part of the
+    # populations (created when delta t changes between steps) is undamped and
+    # stays of the order of the initial rho Y; its rounding sets an absolute
+    # floor of about 1e-16 of the initial rho Y once the mixture has burnt
+    z0 = U0[-1, 0]
+    assert np.allclose(zs[:, 0], ref, rtol=1e-12, atol=1e-15 * z0), np.max(np.abs(zs[:, 0] - ref))
+    assert zs[-1, 0] < 0.9 * U0[-1, 0]          # it burns
+
+
+def test_uniform_state_second_order_in_time():
+    errs = []
+    for cfl in (0.4, 0.2, 0.1):
+        p = W.reactive_uniform(n=256, dim=1, cfl=cfl, k_rate=80.0)
+        cfg = ora_cfg_from(p)
+        L = ora_from(p)
+        run_until(L, 0.05)
+        t = L.t
+        rho = p.U0[0, 0]
+        eint = p.U0[2, 0] - 0.5 * p.U0[1, 0] ** 2 / rho
+
+        def rhs(_, z):
+            pr = (cfg.gamma - 1.0) * (eint - cfg.q_heat * z[0])
+            return [-cfg.k_rate * z[0] * math.exp(-cfg.t_act * rho / pr)]
+
+        sol = solve_ivp(rhs, (0.0, t), [p.U0[3, 0]], method="DOP853", rtol=1e-13, atol=1e-15)
+        errs.append(abs(L.moments()[3, 0] - sol.y[0, -1]))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(1.85 < o < 2.15 for o in orders), (errs, orders)
+
+
+def _as_euler(p, energy_shift):
+    """The Euler problem in (rho, m, E - q rho Y) of a reactive problem."""
+    d = p.dim
+    U = p.U0[:d + 2].copy()
+    if energy_shift:
+        U[d + 1] = p.U0[d + 1] - p.q_heat * p.U0[d + 2]
+    return W.Problem(p.name + "_euler", W.EULER, d, p.nx, p.ny, p.x0, p.x1, p.y0, p.y1, p.bc, p.cfl,
+                     p.steps, U, gamma=p.gamma)
+
+
+@pytest.mark.parametrize("q,omega", [(0.0, None), (40.0, None), (40.0, 1.5)])
+@pytest.mark.parametrize("d", [1, 2])
+def test_no_reaction_reduces_to_euler(d, q, omega):
+    """K = 0 and uniform Y: the reactive run equals the Euler oracle in the
+    energy E - q rho Y to rounding (rho Y = Y rho is rounded, so the species
+    row adds indicator terms of order 1e-16 that the shocks amplify), and Y
+    stays uniform."""
+    if d == 1:
+        left, right = W.SOD
+        x = W.centres(400, 0.0, 1.0)
+        Lm = x < 0.5
+        st = [np.where(Lm, a, b) for a, b in zip(left, right)]
+        U0 = W.reactive_conserved(st[0], st[1], 0 * st[1], st[2], 0.7 + 0 * x, q, 1.4, dim=1)
+        p = W.Problem("r", W.REACTIVE, 1, 400, 1, 0.0, 1.0, 0.0, 1.0, (W.TRANSMISSIVE,) * 4, 0.5, 200, U0,
+                      gamma=1.4, q_heat=q)
+    else:
+        e = W.euler_seeded_2d(seed=2, n=48, steps=60)
+        rho = e.U0[0]
+        u, v = e.U0[1] / rho, e.U0[2] / rho
+        pr = (e.gamma - 1.0) * (e.U0[3] - 0.5 * rho * (u * u + v * v))
+        U0 = W.reactive_conserved(rho, u, v, pr, 0.7 + 0 * rho, q, e.gamma, dim=2)
+        p = W.Problem("r", W.REACTIVE, 2, 48, 48, 0.0, 1.0, 0.0, 1.0, e.bc, 0.5, 60, U0, gamma=e.gamma, q_heat=q)
+    pe = _as_euler(p, q != 0.0)
+    Lr = ora_from(p, omega_fixed=omega)
+    Lr.run(p.steps)
+    Le = ora_from(pe, omega_fixed=omega)
+    Le.run(p.steps)
+    Ur, Ue = Lr.moments(), Le.moments()
+    Urs = Ur[:d + 2].copy()
+    Urs[d + 1] = Ur[d + 1] - q * Ur[d + 2]
+    rel = np.max(np.abs(Urs - Ue)) / np.max(np.abs(Ue))
+    assert rel < 1e-11, rel
+    Y = Ur[d + 2] / Ur[0]
+    assert np.max(np.abs(Y - 0.7)) < 1e-13
+    assert abs(Lr.t - Le.t) <= 1e-14 * Le.t
+
+
+def test_periodic_conservation_and_burning():
+    p = W.reactive_seeded_2d(seed=1, n=40, steps=1, bc=(W.PERIODIC,) * 4)
+    L = ora_from(p)
+    m0 = [fsum(p.U0[c]) for c in range(5)]
+    z_prev = m0[4]
+    for _ in range(40):
+        L.run(1)
+        U = L.moments()
+        for c in range(4):
+            scale = fsum(np.abs(p.U0[c]))
+            assert abs(fsum(U[c]) - m0[c]) <= 1e-13 * scale, c
+        z = fsum(U[4])
+        assert z < z_prev
+        z_prev = z
+    assert L.flags == 0
+
+
+def test_circle_symmetry():
+    p = W.reactive_circle_2d(n=48, t_final=0.004)
+    L = run_until(ora_from(p), p.t_final)
+    rho = L.moments()[0]
+    assert np.max(np.abs(rho - rho.T)) < 1e-12
+    assert np.max(np.abs(rho - rho[::-1, :])) < 1e-12
+    assert np.max(np.abs(rho - rho[:, ::-1])) < 1e-12
+    # the trapezoidal source rule of (2.2) overshoots when (dt/2) K e^{-T_i/T}
+    # exceeds 1 (here about 1.3 in the hot disc: the 48^2 step is 8 times the
+    # paper's 400^2 one), so small negative mass fractions appear
+    Y = L.moments()[4] / rho
+    assert Y.min() > -0.01 and Y.max() < 1.0 + 1e-6
+
+
+def test_detonation_front_advances():
+    """Example 5.11 data at the paper's resolution (dx = 1/150) on a shorter
+    domain: the reaction front moves right, mass fractions stay in [0, 1] up
+    to small undershoots, no flag is raised."""
+    p = W.reactive_detonation_1d(n=1500, x1=10.0, t_final=0.4)
+    L = run_until(ora_from(p), p.t_final)
+    U = L.moments()
+    Y = U[3] / U[0]
+    x = W.centres(1500, 0.0, 10.0)
+    front = x[np.argmax(Y > 0.5)]
+    assert L.flags == 0
+    assert Y.min() > -0.02 and Y.max() < 1.02
+    assert front > 2.0 + 0.4 * 3.0, front
