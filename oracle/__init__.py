@@ -22,10 +22,11 @@ class OraCfg(C.Structure):
         ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
         ("bc", C.c_int32 * 4),
         ("cfl", C.c_double), ("eps", C.c_double), ("gamma", C.c_double), ("g", C.c_double),
-        ("adv", C.c_double * 2), ("h_dry", C.c_double), ("rho_floor", C.c_double),
+        ("adv", C.c_double * 3), ("h_dry", C.c_double), ("rho_floor", C.c_double),
         ("p_floor", C.c_double), ("has_bed", C.c_int32), ("omega_fixed_on", C.c_int32),
         ("omega_fixed", C.c_double),
         ("q_heat", C.c_double), ("k_rate", C.c_double), ("t_act", C.c_double),
+        ("nz", C.c_int32), ("z0", C.c_double), ("z1", C.c_double), ("bc_z", C.c_int32 * 2),
     ]
 
 
@@ -80,17 +81,21 @@ def num_fields(system, dim):
     return lib().ora_num_fields(system, dim)
 
 
-def make_cfg(system, dim, nx, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=(PERIODIC,) * 4,
-             cfl=0.5, eps=1e-10, gamma=1.4, g=9.81, adv=(1.0, 0.0), h_dry=1e-6,
+def make_cfg(system, dim, nx, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=(PERIODIC,) * 6,
+             cfl=0.5, eps=1e-10, gamma=1.4, g=9.81, adv=(1.0, 0.0, 0.0), h_dry=1e-6,
              rho_floor=1e-12, p_floor=1e-12, has_bed=False, omega_fixed=None,
-             q_heat=0.0, k_rate=0.0, t_act=0.0):
+             q_heat=0.0, k_rate=0.0, t_act=0.0, nz=1, z0=0.0, z1=1.0):
     c = OraCfg()
-    c.system, c.dim, c.nx, c.ny = system, dim, nx, (ny if dim == 2 else 1)
+    c.system, c.dim, c.nx, c.ny = system, dim, nx, (ny if dim >= 2 else 1)
+    c.nz, c.z0, c.z1 = (nz if dim == 3 else 1), z0, z1
+    for i in range(2):
+        c.bc_z[i] = bc[4 + i] if len(bc) > 4 else PERIODIC
     c.x0, c.x1, c.y0, c.y1 = x0, x1, y0, y1
     for i in range(4):
         c.bc[i] = bc[i]
     c.cfl, c.eps, c.gamma, c.g = cfl, eps, gamma, g
-    c.adv[0], c.adv[1] = adv
+    for i in range(3):
+        c.adv[i] = adv[i] if i < len(adv) else 0.0
     c.h_dry, c.rho_floor, c.p_floor = h_dry, rho_floor, p_floor
     c.has_bed = int(bool(has_bed))
     c.omega_fixed_on = int(omega_fixed is not None)
@@ -100,14 +105,14 @@ def make_cfg(system, dim, nx, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=(PERIODIC
 
 
 class Lattice:
-    """One oracle lattice: ``U0`` is an array of shape (m, ny, nx) or (m, nx)."""
+    """One oracle lattice: ``U0`` has shape (m, nx), (m, ny, nx) or (m, nz, ny, nx)."""
 
     def __init__(self, cfg: OraCfg):
         self.cfg = cfg
         self.d = cfg.dim
         self.m = num_fields(cfg.system, cfg.dim)
         self.Q = 2 * self.d + 1
-        self.nx, self.ny = cfg.nx, cfg.ny
+        self.nx, self.ny, self.nz = cfg.nx, cfg.ny, cfg.nz
         self._h = lib().ora_create(C.byref(cfg))
         if not self._h:
             raise ValueError("oracle rejected the configuration")
@@ -119,6 +124,8 @@ class Lattice:
             self._h = None
 
     def _shape(self, lead):
+        if self.d == 3:
+            return (lead, self.nz, self.ny, self.nx)
         return (lead, self.ny, self.nx) if self.d == 2 else (lead, self.nx)
 
     def init(self, U0, bed=None, t0=0.0):
@@ -168,7 +175,7 @@ class Lattice:
         return out
 
     def alpha_bar(self):
-        out = np.zeros(2)
+        out = np.zeros(3)
         lib().ora_alpha_bar(self._h, out)
         return out[: self.d]
 
@@ -185,7 +192,7 @@ class Lattice:
         return lib().ora_flags(self._h)
 
     def last_scalars(self):
-        ab = np.zeros(2)
+        ab = np.zeros(3)
         dt = C.c_double()
         lib().ora_last_scalars(self._h, ab, C.byref(dt))
         return ab[: self.d], dt.value

@@ -53,9 +53,9 @@
 
 struct ora_lattice {
     ora_cfg c;
-    int d, m, Q, nx, ny, ncell;
+    int d, m, Q, nx, ny, nz, ncell;
     double dx;
-    double *f;      /* [k][c][y][x], Q*m*ncell                       */
+    double *f;      /* [k][c][z][y][x], Q*m*ncell                    */
     double *bed;    /* [y][x] or NULL                                */
     double *dbed;   /* [dir][y][x] central-difference bed gradient   */
     double *omega;  /* omega used by the last step                   */
@@ -64,7 +64,7 @@ struct ora_lattice {
     double *fs;     /* padded collided populations, ghost depth 1    */
     double t;
     int64_t steps;
-    double last_abar[2], last_dt;
+    double last_abar[3], last_dt;
     int32_t flags;
 };
 
@@ -83,7 +83,7 @@ int ora_num_fields(int system, int dim)
 }
 
 typedef struct {
-    double rho, vel[2], mom[2], E, p, c; /* Euler: rho; SWE: h in rho */
+    double rho, vel[3], mom[3], E, p, c; /* Euler: rho; SWE: h in rho */
     double cL;                           /* SWE: speed used in L      */
     double Z, Y;                         /* reactive: rho Y and Y     */
 } prim_t;
@@ -131,6 +131,7 @@ static void primitives(const ora_cfg *c, const double *U, prim_t *P, int32_t *fl
             P->vel[i] = U[1 + i] / P->rho;
         }
         double q2 = P->vel[0] * P->vel[0] + P->vel[1] * P->vel[1];
+        if (d == 3) q2 = q2 + P->vel[2] * P->vel[2];
         if (c->system == ORA_EULER) {
             P->p = (c->gamma - 1.0) * (P->E - 0.5 * P->rho * q2);
         } else {
@@ -202,6 +203,7 @@ void ora_left_eigvecs(const ora_cfg *c, int dir, const double *U, double *L)
     if (c->system == ORA_EULER || c->system == ORA_REACTIVE) {
         double cs = P.c;
         double q2 = P.vel[0] * P.vel[0] + P.vel[1] * P.vel[1];
+        if (d == 3) q2 = q2 + P.vel[2] * P.vel[2];
         double b1 = (c->gamma - 1.0) / (cs * cs);
         double b2 = 0.5 * q2 * b1;
         double un = P.vel[dir];
@@ -225,11 +227,13 @@ void ora_left_eigvecs(const ora_cfg *c, int dir, const double *U, double *L)
         L[0 * m + e] = 0.5 * b1;
         L[(m - 1) * m + e] = 0.5 * b1;
         L[1 * m + e] = -b1;
-        if (d == 2) {
-            /* shear row (u_n): -v_t, unit weight on the tangential momentum */
-            int t = 1 - dir;
-            L[2 * m + 0] = -P.vel[t];
-            L[2 * m + 1 + t] = 1.0;
+        /* shear rows (u_n), one per tangential direction t in increasing
+         * order: -v_t, unit weight on the tangential momentum */
+        for (int t = 0, r = 2; t < d; ++t) {
+            if (t == dir) continue;
+            L[r * m + 0] = -P.vel[t];
+            L[r * m + 1 + t] = 1.0;
+            ++r;
         }
         if (c->system == ORA_REACTIVE) {
             /* species row m-2 (speed u_n): (-Y, 0, .., 0, 1) in the variables
@@ -283,8 +287,9 @@ static double arrhenius(const ora_cfg *c, double rho, double e_int, double z, do
 static void reactive_parts(const ora_cfg *c, const double *U, double *rho, double *e_int)
 {
     int d = c->dim;
-    double u0 = U[1] / U[0], u1 = d == 2 ? U[2] / U[0] : 0.0;
+    double u0 = U[1] / U[0], u1 = d >= 2 ? U[2] / U[0] : 0.0;
     double q2 = u0 * u0 + u1 * u1;
+    if (d == 3) q2 = q2 + (U[3] / U[0]) * (U[3] / U[0]);
     *rho = U[0];
     *e_int = U[d + 1] - 0.5 * U[0] * q2;
 }
@@ -347,14 +352,15 @@ void ora_moment_update(const ora_cfg *c, const double *sumF, const double *db, d
 /* Velocity set: e_0 = 0, e_j = unit j, e_{j+d} = -e_j (j = 1..d).         */
 /* ------------------------------------------------------------------------ */
 
-static void velocity(int d, int k, int *ex, int *ey)
+static void velocity(int d, int k, int *ex, int *ey, int *ez)
 {
     *ex = 0;
     *ey = 0;
+    *ez = 0;
     if (k == 0) return;
     int j = (k - 1) % d;
     int s = k <= d ? 1 : -1;
-    if (j == 0) *ex = s; else *ey = s;
+    if (j == 0) *ex = s; else if (j == 1) *ey = s; else *ez = s;
 }
 
 void ora_lf_coeffs(int dim, const double *alpha, double lambda, double *a, double *b)
@@ -376,7 +382,7 @@ static void equilibrium_ab(const ora_cfg *c, const double *U, const double *a,
                            const double *b, double *feq)
 {
     int d = c->dim, m = ora_num_fields(c->system, d), Q = 2 * d + 1;
-    double F[2][ORA_MMAX];
+    double F[3][ORA_MMAX];
     for (int j = 0; j < d; ++j) ora_flux(c, j, U, F[j]);
     for (int k = 0; k < Q; ++k)
         for (int r = 0; r < m; ++r) {
@@ -389,37 +395,48 @@ static void equilibrium_ab(const ora_cfg *c, const double *U, const double *a,
 void ora_equilibrium(const ora_cfg *c, const double *U, const double *alpha,
                      double lambda, double *feq)
 {
-    double a[5], b[10];
+    double a[7], b[21];
     ora_lf_coeffs(c->dim, alpha, lambda, a, b);
     equilibrium_ab(c, U, a, b, feq);
 }
 
 /* ------------------------------------------------------------------------ */
-/* Lattice storage and boundary index maps.                                 */
+/* Lattice storage and boundary index maps.  Arrays are [z][y][x]; y and z  */
+/* carry ghost layers only in the dimensions the lattice has.               */
 /* ------------------------------------------------------------------------ */
 
-static int px2(const ora_lattice *L) { return L->nx + 2 * G2; }
-static int gy2(const ora_lattice *L) { return L->d == 2 ? G2 : 0; }
-static int py2(const ora_lattice *L) { return L->ny + 2 * gy2(L); }
-static size_t iU(const ora_lattice *L, int c, int i, int j)
+static int gy(const ora_lattice *L, int depth) { return L->d >= 2 ? depth : 0; }
+static int gz(const ora_lattice *L, int depth) { return L->d == 3 ? depth : 0; }
+/* padded moments, ghost depth 2 */
+static size_t iU(const ora_lattice *L, int c, int i, int j, int l)
 {
-    return ((size_t)c * py2(L) + (size_t)(j + gy2(L))) * px2(L) + (size_t)(i + G2);
+    size_t px = (size_t)L->nx + 2 * G2, py = (size_t)L->ny + 2 * gy(L, G2), pz = (size_t)L->nz + 2 * gz(L, G2);
+    return (((size_t)c * pz + (size_t)(l + gz(L, G2))) * py + (size_t)(j + gy(L, G2))) * px + (size_t)(i + G2);
 }
-static int px1(const ora_lattice *L) { return L->nx + 2; }
-static int gy1(const ora_lattice *L) { return L->d == 2 ? 1 : 0; }
-static int py1(const ora_lattice *L) { return L->ny + 2 * gy1(L); }
-static size_t i1(const ora_lattice *L, int i, int j)
+/* padded nu / collided populations, ghost depth 1 */
+static size_t n1(const ora_lattice *L)
 {
-    return (size_t)(j + gy1(L)) * px1(L) + (size_t)(i + 1);
+    return ((size_t)L->nx + 2) * ((size_t)L->ny + 2 * gy(L, 1)) * ((size_t)L->nz + 2 * gz(L, 1));
 }
-static size_t iF(const ora_lattice *L, int k, int c, int i, int j)
+static size_t i1(const ora_lattice *L, int i, int j, int l)
 {
-    return (((size_t)k * L->m + c) * L->ny + j) * L->nx + i;
+    size_t px = (size_t)L->nx + 2, py = (size_t)L->ny + 2 * gy(L, 1);
+    return ((size_t)(l + gz(L, 1)) * py + (size_t)(j + gy(L, 1))) * px + (size_t)(i + 1);
 }
-static size_t iFs(const ora_lattice *L, int k, int c, int i, int j)
+static size_t iC(const ora_lattice *L, int i, int j, int l)
 {
-    return ((size_t)k * L->m + c) * (size_t)(px1(L) * py1(L)) + i1(L, i, j);
+    return ((size_t)l * L->ny + j) * L->nx + i;
 }
+static size_t iF(const ora_lattice *L, int k, int c, int i, int j, int l)
+{
+    return ((size_t)k * L->m + c) * (size_t)L->ncell + iC(L, i, j, l);
+}
+static size_t iFs(const ora_lattice *L, int k, int c, int i, int j, int l)
+{
+    return ((size_t)k * L->m + c) * n1(L) + i1(L, i, j, l);
+}
+static int bc_side(const ora_cfg *c, int side) { return side < 4 ? c->bc[side] : c->bc_z[side - 4]; }
+static int extent(const ora_lattice *L, int dir) { return dir == 0 ? L->nx : (dir == 1 ? L->ny : L->nz); }
 
 /* Mirror/wrap map of an index outside [0,n) onto the interior.  *refl is set
  * when the boundary on that side is a reflective wall. */
@@ -449,13 +466,15 @@ static int mirror_k(int d, int k, int dir)
 ora_lattice *ora_create(const ora_cfg *cfg)
 {
     int d = cfg->dim;
-    if (d != 1 && d != 2) return NULL;
-    if (cfg->nx < 4 || (d == 2 && cfg->ny < 4) || (d == 1 && cfg->ny != 1)) return NULL;
+    if (d < 1 || d > 3) return NULL;
+    if (cfg->nx < 4 || (d >= 2 && cfg->ny < 4) || (d == 1 && cfg->ny != 1)) return NULL;
+    if ((d == 3 && cfg->nz < 4) || (d < 3 && cfg->nz != 1)) return NULL;
+    if (d == 3 && cfg->system == ORA_SWE) return NULL;
     if (cfg->system == ORA_ADVECTION)
         for (int s = 0; s < 2 * d; ++s)
-            if (cfg->bc[s] == ORA_REFLECTIVE) return NULL;
+            if (bc_side(cfg, s) == ORA_REFLECTIVE) return NULL;
     for (int a = 0; a < d; ++a)
-        if ((cfg->bc[2 * a] == ORA_PERIODIC) != (cfg->bc[2 * a + 1] == ORA_PERIODIC))
+        if ((bc_side(cfg, 2 * a) == ORA_PERIODIC) != (bc_side(cfg, 2 * a + 1) == ORA_PERIODIC))
             return NULL;
     ora_lattice *L = calloc(1, sizeof(*L));
     L->c = *cfg;
@@ -464,13 +483,15 @@ ora_lattice *ora_create(const ora_cfg *cfg)
     L->Q = 2 * d + 1;
     L->nx = cfg->nx;
     L->ny = cfg->ny;
-    L->ncell = L->nx * L->ny;
+    L->nz = cfg->nz;
+    L->ncell = L->nx * L->ny * L->nz;
     L->dx = (cfg->x1 - cfg->x0) / cfg->nx;
     L->f = calloc((size_t)L->Q * L->m * L->ncell, sizeof(double));
     L->omega = calloc((size_t)L->ncell, sizeof(double));
-    L->Up = calloc((size_t)L->m * px2(L) * py2(L), sizeof(double));
-    L->nup = calloc((size_t)px1(L) * py1(L), sizeof(double));
-    L->fs = calloc((size_t)L->Q * L->m * px1(L) * py1(L), sizeof(double));
+    L->Up = calloc((size_t)L->m * ((size_t)L->nx + 2 * G2) * ((size_t)L->ny + 2 * gy(L, G2)) *
+                       ((size_t)L->nz + 2 * gz(L, G2)), sizeof(double));
+    L->nup = calloc(n1(L), sizeof(double));
+    L->fs = calloc((size_t)L->Q * L->m * n1(L), sizeof(double));
     if (has_bed(cfg)) {
         L->bed = calloc((size_t)L->ncell, sizeof(double));
         L->dbed = calloc((size_t)2 * L->ncell, sizeof(double));
@@ -492,44 +513,60 @@ void ora_destroy(ora_lattice *L)
 }
 
 /* Moments U = sum_k f_k (2.3) of the interior, then ghost layers of depth 2:
- * x map on interior rows first, then y map on all columns (corners). */
+ * the x map on interior rows first, then the y map on all columns, then the
+ * z map on all rows and columns (edges and corners take the maps in turn). */
 static void fill_moments(ora_lattice *L)
 {
-    int d = L->d, m = L->m, nx = L->nx, ny = L->ny;
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i)
-            for (int c = 0; c < m; ++c) {
-                double s = 0.0;
-                for (int k = 0; k < L->Q; ++k) s += L->f[iF(L, k, c, i, j)];
-                L->Up[iU(L, c, i, j)] = s;
-            }
-    int mom_ok = L->c.system != ORA_ADVECTION;
-    for (int j = 0; j < ny; ++j)
-        for (int i = -G2; i < nx + G2; ++i) {
-            if (i >= 0 && i < nx) continue;
-            int refl, si = bc_map(i, nx, L->c.bc[0], L->c.bc[1], &refl);
-            for (int c = 0; c < m; ++c) {
-                double v = L->Up[iU(L, c, si, j)];
-                if (refl && mom_ok && c == 1) v = -v;
-                L->Up[iU(L, c, i, j)] = v;
-            }
-        }
-    if (d == 2)
-        for (int j = -G2; j < ny + G2; ++j) {
-            if (j >= 0 && j < ny) continue;
-            int refl, sj = bc_map(j, ny, L->c.bc[2], L->c.bc[3], &refl);
-            for (int i = -G2; i < nx + G2; ++i)
+    int d = L->d, m = L->m, nx = L->nx, ny = L->ny, nz = L->nz;
+    for (int l = 0; l < nz; ++l)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i)
                 for (int c = 0; c < m; ++c) {
-                    double v = L->Up[iU(L, c, i, sj)];
-                    if (refl && mom_ok && c == 2) v = -v;
-                    L->Up[iU(L, c, i, j)] = v;
+                    double s = 0.0;
+                    for (int k = 0; k < L->Q; ++k) s += L->f[iF(L, k, c, i, j, l)];
+                    L->Up[iU(L, c, i, j, l)] = s;
                 }
+    int mom_ok = L->c.system != ORA_ADVECTION;
+    for (int l = 0; l < nz; ++l)
+        for (int j = 0; j < ny; ++j)
+            for (int i = -G2; i < nx + G2; ++i) {
+                if (i >= 0 && i < nx) continue;
+                int refl, si = bc_map(i, nx, L->c.bc[0], L->c.bc[1], &refl);
+                for (int c = 0; c < m; ++c) {
+                    double v = L->Up[iU(L, c, si, j, l)];
+                    if (refl && mom_ok && c == 1) v = -v;
+                    L->Up[iU(L, c, i, j, l)] = v;
+                }
+            }
+    if (d >= 2)
+        for (int l = 0; l < nz; ++l)
+            for (int j = -G2; j < ny + G2; ++j) {
+                if (j >= 0 && j < ny) continue;
+                int refl, sj = bc_map(j, ny, L->c.bc[2], L->c.bc[3], &refl);
+                for (int i = -G2; i < nx + G2; ++i)
+                    for (int c = 0; c < m; ++c) {
+                        double v = L->Up[iU(L, c, i, sj, l)];
+                        if (refl && mom_ok && c == 2) v = -v;
+                        L->Up[iU(L, c, i, j, l)] = v;
+                    }
+            }
+    if (d == 3)
+        for (int l = -G2; l < nz + G2; ++l) {
+            if (l >= 0 && l < nz) continue;
+            int refl, sl = bc_map(l, nz, L->c.bc_z[0], L->c.bc_z[1], &refl);
+            for (int j = -G2; j < ny + G2; ++j)
+                for (int i = -G2; i < nx + G2; ++i)
+                    for (int c = 0; c < m; ++c) {
+                        double v = L->Up[iU(L, c, i, j, sl)];
+                        if (refl && mom_ok && c == 3) v = -v;
+                        L->Up[iU(L, c, i, j, l)] = v;
+                    }
         }
 }
 
-static void load_U(const ora_lattice *L, int i, int j, double *U)
+static void load_U(const ora_lattice *L, int i, int j, int l, double *U)
 {
-    for (int c = 0; c < L->m; ++c) U[c] = L->Up[iU(L, c, i, j)];
+    for (int c = 0; c < L->m; ++c) U[c] = L->Up[iU(L, c, i, j, l)];
 }
 
 /* Wave-speed bounds alpha_bar_j (2.19): global max over interior cells. */
@@ -538,12 +575,13 @@ static void alpha_bar(const ora_lattice *L, double *abar)
     double U[ORA_MMAX];
     for (int dir = 0; dir < L->d; ++dir) {
         double mx = 0.0;
-        for (int j = 0; j < L->ny; ++j)
-            for (int i = 0; i < L->nx; ++i) {
-                load_U(L, i, j, U);
-                double s = ora_max_speed(&L->c, dir, U);
-                if (s > mx) mx = s;
-            }
+        for (int l = 0; l < L->nz; ++l)
+            for (int j = 0; j < L->ny; ++j)
+                for (int i = 0; i < L->nx; ++i) {
+                    load_U(L, i, j, l, U);
+                    double s = ora_max_speed(&L->c, dir, U);
+                    if (s > mx) mx = s;
+                }
         abar[dir] = mx;
     }
 }
@@ -554,56 +592,61 @@ static void compute_nu(ora_lattice *L)
     int d = L->d, m = L->m;
     double Uz[ORA_MMAX], Um[ORA_MMAX], Upl[ORA_MMAX], Lm[ORA_MMAX * ORA_MMAX];
     double dm[ORA_MMAX], dp[ORA_MMAX], dU[ORA_MMAX];
-    for (int j = -gy1(L); j < L->ny + gy1(L); ++j)
-        for (int i = -1; i < L->nx + 1; ++i) {
-            load_U(L, i, j, Uz);
-            double nu = 0.0;
-            for (int dir = 0; dir < d; ++dir) {
-                int ox = dir == 0, oy = dir == 1;
-                load_U(L, i - ox, j - oy, Um);
-                load_U(L, i + ox, j + oy, Upl);
-                ora_left_eigvecs(&L->c, dir, Uz, Lm);
-                /* Delta_{j,-} W = L_j(U_i)(U_i - U_{i-n_j}) */
-                for (int c = 0; c < m; ++c) dU[c] = Uz[c] - Um[c];
-                for (int r = 0; r < m; ++r) {
-                    double s = 0.0;
-                    for (int c = 0; c < m; ++c) s += Lm[r * m + c] * dU[c];
-                    dm[r] = s;
+    for (int l = -gz(L, 1); l < L->nz + gz(L, 1); ++l)
+        for (int j = -gy(L, 1); j < L->ny + gy(L, 1); ++j)
+            for (int i = -1; i < L->nx + 1; ++i) {
+                load_U(L, i, j, l, Uz);
+                double nu = 0.0;
+                for (int dir = 0; dir < d; ++dir) {
+                    int ox = dir == 0, oy = dir == 1, oz = dir == 2;
+                    load_U(L, i - ox, j - oy, l - oz, Um);
+                    load_U(L, i + ox, j + oy, l + oz, Upl);
+                    ora_left_eigvecs(&L->c, dir, Uz, Lm);
+                    /* Delta_{j,-} W = L_j(U_i)(U_i - U_{i-n_j}) */
+                    for (int c = 0; c < m; ++c) dU[c] = Uz[c] - Um[c];
+                    for (int r = 0; r < m; ++r) {
+                        double s = 0.0;
+                        for (int c = 0; c < m; ++c) s += Lm[r * m + c] * dU[c];
+                        dm[r] = s;
+                    }
+                    /* Delta_{j,+} W = L_j(U_i)(U_{i+n_j} - U_i) */
+                    for (int c = 0; c < m; ++c) dU[c] = Upl[c] - Uz[c];
+                    for (int r = 0; r < m; ++r) {
+                        double s = 0.0;
+                        for (int c = 0; c < m; ++c) s += Lm[r * m + c] * dU[c];
+                        dp[r] = s;
+                    }
+                    for (int r = 0; r < m; ++r) {
+                        double adm = fabs(dm[r]), adp = fabs(dp[r]);
+                        double theta = fabs(dp[r] - dm[r]) / (adm + adp + L->dx) + adm + adp;
+                        nu += theta;
+                    }
                 }
-                /* Delta_{j,+} W = L_j(U_i)(U_{i+n_j} - U_i) */
-                for (int c = 0; c < m; ++c) dU[c] = Upl[c] - Uz[c];
-                for (int r = 0; r < m; ++r) {
-                    double s = 0.0;
-                    for (int c = 0; c < m; ++c) s += Lm[r * m + c] * dU[c];
-                    dp[r] = s;
-                }
-                for (int r = 0; r < m; ++r) {
-                    double adm = fabs(dm[r]), adp = fabs(dp[r]);
-                    double theta = fabs(dp[r] - dm[r]) / (adm + adp + L->dx) + adm + adp;
-                    nu += theta;
-                }
+                L->nup[i1(L, i, j, l)] = nu;
             }
-            L->nup[i1(L, i, j)] = nu;
-        }
 }
 
-/* Box sum (2.15) over {-1,0,1}^d and relaxation parameter (2.16). */
+/* Box sum (2.15) over {-1,0,1}^d (z outermost, x innermost) and the
+ * relaxation parameter (2.16). */
 static void compute_omega(ora_lattice *L)
 {
     int d = L->d;
-    for (int j = 0; j < L->ny; ++j)
-        for (int i = 0; i < L->nx; ++i) {
-            double w;
-            if (L->c.omega_fixed_on) {
-                w = L->c.omega_fixed;
-            } else {
-                double nt = 0.0;
-                for (int kj = (d == 2 ? -1 : 0); kj <= (d == 2 ? 1 : 0); ++kj)
-                    for (int ki = -1; ki <= 1; ++ki) nt += L->nup[i1(L, i + ki, j + kj)];
-                w = 1.0 + 1.0 / (1.0 + nt);
+    int zr = d == 3 ? 1 : 0, yr = d >= 2 ? 1 : 0;
+    for (int l = 0; l < L->nz; ++l)
+        for (int j = 0; j < L->ny; ++j)
+            for (int i = 0; i < L->nx; ++i) {
+                double w;
+                if (L->c.omega_fixed_on) {
+                    w = L->c.omega_fixed;
+                } else {
+                    double nt = 0.0;
+                    for (int kl = -zr; kl <= zr; ++kl)
+                        for (int kj = -yr; kj <= yr; ++kj)
+                            for (int ki = -1; ki <= 1; ++ki) nt += L->nup[i1(L, i + ki, j + kj, l + kl)];
+                    w = 1.0 + 1.0 / (1.0 + nt);
+                }
+                L->omega[iC(L, i, j, l)] = w;
             }
-            L->omega[(size_t)j * L->nx + i] = w;
-        }
 }
 
 int ora_init(ora_lattice *L, const double *U0, const double *bed, double t0)
@@ -634,10 +677,11 @@ int ora_init(ora_lattice *L, const double *U0, const double *bed, double t0)
     /* moments of U0 at the cell centres, then f = f^eq(U0) with the step-0
      * coefficients, so that sum_k f_k = U0 (up to rounding). */
     for (int c = 0; c < m; ++c)
-        for (int j = 0; j < L->ny; ++j)
-            for (int i = 0; i < L->nx; ++i)
-                L->Up[iU(L, c, i, j)] = U0[((size_t)c * L->ny + j) * L->nx + i];
-    double abar[2] = {0, 0}, alpha[2];
+        for (int l = 0; l < L->nz; ++l)
+            for (int j = 0; j < L->ny; ++j)
+                for (int i = 0; i < L->nx; ++i)
+                    L->Up[iU(L, c, i, j, l)] = U0[(size_t)c * n + iC(L, i, j, l)];
+    double abar[3] = {0, 0, 0}, alpha[3];
     alpha_bar(L, abar);
     double sa = 0.0;
     for (int j = 0; j < L->d; ++j) sa += abar[j];
@@ -645,14 +689,15 @@ int ora_init(ora_lattice *L, const double *U0, const double *bed, double t0)
     double dt = L->c.cfl * L->dx / sa;
     double lambda = L->dx / dt;
     for (int j = 0; j < L->d; ++j) alpha[j] = abar[j] + L->c.eps;
-    double U[ORA_MMAX], feq[5 * ORA_MMAX];
-    for (int j = 0; j < L->ny; ++j)
-        for (int i = 0; i < L->nx; ++i) {
-            load_U(L, i, j, U);
-            ora_equilibrium(&L->c, U, alpha, lambda, feq);
-            for (int k = 0; k < L->Q; ++k)
-                for (int c = 0; c < m; ++c) L->f[iF(L, k, c, i, j)] = feq[k * m + c];
-        }
+    double U[ORA_MMAX], feq[7 * ORA_MMAX];
+    for (int l = 0; l < L->nz; ++l)
+        for (int j = 0; j < L->ny; ++j)
+            for (int i = 0; i < L->nx; ++i) {
+                load_U(L, i, j, l, U);
+                ora_equilibrium(&L->c, U, alpha, lambda, feq);
+                for (int k = 0; k < L->Q; ++k)
+                    for (int c = 0; c < m; ++c) L->f[iF(L, k, c, i, j, l)] = feq[k * m + c];
+            }
     L->t = t0;
     L->steps = 0;
     L->flags = 0;
@@ -661,12 +706,12 @@ int ora_init(ora_lattice *L, const double *U0, const double *bed, double t0)
 
 static int one_step(ora_lattice *L)
 {
-    int d = L->d, m = L->m, Q = L->Q, nx = L->nx, ny = L->ny;
+    int d = L->d, m = L->m, Q = L->Q, nx = L->nx, ny = L->ny, nz = L->nz;
     const ora_cfg *cf = &L->c;
     fill_moments(L);
 
     /* (2.19), (2.21): bounds, alpha_j = alpha_bar_j + eps, delta t, lambda */
-    double abar[2] = {0, 0}, alpha[2] = {0, 0};
+    double abar[3] = {0, 0, 0}, alpha[3] = {0, 0, 0};
     alpha_bar(L, abar);
     double sa = 0.0;
     for (int j = 0; j < d; ++j) sa += abar[j];
@@ -674,7 +719,7 @@ static int one_step(ora_lattice *L)
     double dt = cf->cfl * L->dx / sa;
     double lambda = L->dx / dt;
     for (int j = 0; j < d; ++j) alpha[j] = abar[j] + cf->eps;
-    double a[5], b[10];
+    double a[7], b[21];
     ora_lf_coeffs(d, alpha, lambda, a, b);
     double hdt = 0.5 * dt;
 
@@ -682,69 +727,74 @@ static int one_step(ora_lattice *L)
     compute_omega(L);
 
     /* collision at every interior source node */
-    double U[ORA_MMAX], feq[5 * ORA_MMAX], S[ORA_MMAX], db[2] = {0, 0};
+    double U[ORA_MMAX], feq[7 * ORA_MMAX], S[ORA_MMAX], db[2] = {0, 0};
     int bsrc = has_bed(cf);
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            load_U(L, i, j, U);
-            equilibrium_ab(cf, U, a, b, feq);
-            if (bsrc)
-                for (int dir = 0; dir < d; ++dir)
-                    db[dir] = L->dbed[(size_t)dir * L->ncell + (size_t)j * nx + i];
-            source(cf, U, db, S);
-            double w = L->omega[(size_t)j * nx + i];
-            for (int k = 0; k < Q; ++k)
-                for (int c = 0; c < m; ++c) {
-                    double fk = L->f[iF(L, k, c, i, j)];
-                    L->fs[iFs(L, k, c, i, j)] =
-                        fk - w * (fk - feq[k * m + c]) + hdt * (a[k] * S[c]);
-                }
-        }
+    for (int l = 0; l < nz; ++l)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                load_U(L, i, j, l, U);
+                equilibrium_ab(cf, U, a, b, feq);
+                if (bsrc)
+                    for (int dir = 0; dir < d; ++dir)
+                        db[dir] = L->dbed[(size_t)dir * L->ncell + (size_t)j * nx + i];
+                source(cf, U, db, S);
+                double w = L->omega[iC(L, i, j, l)];
+                for (int k = 0; k < Q; ++k)
+                    for (int c = 0; c < m; ++c) {
+                        double fk = L->f[iF(L, k, c, i, j, l)];
+                        L->fs[iFs(L, k, c, i, j, l)] =
+                            fk - w * (fk - feq[k * m + c]) + hdt * (a[k] * S[c]);
+                    }
+            }
 
-    /* ghost collided populations on the faces (depth 1) */
+    /* ghost collided populations on the faces (depth 1): for the face normal
+     * to dir, every cell of the face plane outside the lattice along dir */
     for (int side = 0; side < 2 * d; ++side) {
         int dir = side / 2, hi = side % 2;
-        int n_along = dir == 0 ? nx : ny, n_across = dir == 0 ? ny : nx;
+        int n_along = extent(L, dir);
         int g = hi ? n_along : -1;
-        for (int s = 0; s < n_across; ++s) {
-            int refl, mi = bc_map(g, n_along, cf->bc[2 * dir], cf->bc[2 * dir + 1], &refl);
-            int gi = dir == 0 ? g : s, gj = dir == 0 ? s : g;
-            int si = dir == 0 ? mi : s, sj = dir == 0 ? s : mi;
-            for (int k = 0; k < Q; ++k) {
-                int ks = refl ? mirror_k(d, k, dir) : k;
-                for (int c = 0; c < m; ++c) {
-                    double v = L->fs[iFs(L, ks, c, si, sj)];
-                    if (refl && c == 1 + dir) v = -v;
-                    L->fs[iFs(L, k, c, gi, gj)] = v;
+        int refl, mi = bc_map(g, n_along, bc_side(cf, 2 * dir), bc_side(cf, 2 * dir + 1), &refl);
+        for (int l = 0; l < (dir == 2 ? 1 : nz); ++l)
+            for (int j = 0; j < (dir == 1 ? 1 : ny); ++j)
+                for (int i = 0; i < (dir == 0 ? 1 : nx); ++i) {
+                    int gi = dir == 0 ? g : i, gj = dir == 1 ? g : j, gl = dir == 2 ? g : l;
+                    int si = dir == 0 ? mi : i, sj = dir == 1 ? mi : j, sl = dir == 2 ? mi : l;
+                    for (int k = 0; k < Q; ++k) {
+                        int ks = refl ? mirror_k(d, k, dir) : k;
+                        for (int c = 0; c < m; ++c) {
+                            double v = L->fs[iFs(L, ks, c, si, sj, sl)];
+                            if (refl && c == 1 + dir) v = -v;
+                            L->fs[iFs(L, k, c, gi, gj, gl)] = v;
+                        }
+                    }
                 }
-            }
-        }
     }
 
     /* pull streaming F_k(x) = f*_k(x - e_k), implicit moments (2.8), and the
      * second half source f_k = F_k + dt/2 s_k(U^{n+1}) */
-    double Fk[5 * ORA_MMAX], sumF[ORA_MMAX], Un[ORA_MMAX];
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            for (int c = 0; c < m; ++c) sumF[c] = 0.0;
-            for (int k = 0; k < Q; ++k) {
-                int ex, ey;
-                velocity(d, k, &ex, &ey);
-                for (int c = 0; c < m; ++c) {
-                    Fk[k * m + c] = L->fs[iFs(L, k, c, i - ex, j - ey)];
-                    sumF[c] += Fk[k * m + c];
+    double Fk[7 * ORA_MMAX], sumF[ORA_MMAX], Un[ORA_MMAX];
+    for (int l = 0; l < nz; ++l)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                for (int c = 0; c < m; ++c) sumF[c] = 0.0;
+                for (int k = 0; k < Q; ++k) {
+                    int ex, ey, ez;
+                    velocity(d, k, &ex, &ey, &ez);
+                    for (int c = 0; c < m; ++c) {
+                        Fk[k * m + c] = L->fs[iFs(L, k, c, i - ex, j - ey, l - ez)];
+                        sumF[c] += Fk[k * m + c];
+                    }
                 }
+                if (bsrc)
+                    for (int dir = 0; dir < d; ++dir)
+                        db[dir] = L->dbed[(size_t)dir * L->ncell + (size_t)j * nx + i];
+                /* (2.8) for U^{n+1}, then S(U^{n+1}) for the second half source */
+                ora_moment_update(cf, sumF, db, hdt, Un);
+                source(cf, Un, db, S);
+                for (int k = 0; k < Q; ++k)
+                    for (int c = 0; c < m; ++c)
+                        L->f[iF(L, k, c, i, j, l)] = Fk[k * m + c] + hdt * (a[k] * S[c]);
             }
-            if (bsrc)
-                for (int dir = 0; dir < d; ++dir)
-                    db[dir] = L->dbed[(size_t)dir * L->ncell + (size_t)j * nx + i];
-            /* (2.8) for U^{n+1}, then S(U^{n+1}) for the second half source */
-            ora_moment_update(cf, sumF, db, hdt, Un);
-            source(cf, Un, db, S);
-            for (int k = 0; k < Q; ++k)
-                for (int c = 0; c < m; ++c)
-                    L->f[iF(L, k, c, i, j)] = Fk[k * m + c] + hdt * (a[k] * S[c]);
-        }
 
     for (size_t q = 0; q < (size_t)Q * m * L->ncell; ++q)
         if (!isfinite(L->f[q])) {
@@ -753,8 +803,7 @@ static int one_step(ora_lattice *L)
         }
     L->t += dt;
     L->steps += 1;
-    L->last_abar[0] = abar[0];
-    L->last_abar[1] = abar[1];
+    for (int j = 0; j < 3; ++j) L->last_abar[j] = abar[j];
     L->last_dt = dt;
     return 0;
 }
@@ -774,12 +823,13 @@ int64_t ora_run(ora_lattice *L, int64_t nsteps, double t_final)
 void ora_moments(const ora_lattice *L, double *U)
 {
     for (int c = 0; c < L->m; ++c)
-        for (int j = 0; j < L->ny; ++j)
-            for (int i = 0; i < L->nx; ++i) {
-                double s = 0.0;
-                for (int k = 0; k < L->Q; ++k) s += L->f[iF(L, k, c, i, j)];
-                U[((size_t)c * L->ny + j) * L->nx + i] = s;
-            }
+        for (int l = 0; l < L->nz; ++l)
+            for (int j = 0; j < L->ny; ++j)
+                for (int i = 0; i < L->nx; ++i) {
+                    double s = 0.0;
+                    for (int k = 0; k < L->Q; ++k) s += L->f[iF(L, k, c, i, j, l)];
+                    U[(size_t)c * L->ncell + iC(L, i, j, l)] = s;
+                }
 }
 
 void ora_get_f(const ora_lattice *L, double *f)
@@ -801,10 +851,9 @@ double ora_time(const ora_lattice *L) { return L->t; }
 int64_t ora_steps(const ora_lattice *L) { return L->steps; }
 int32_t ora_flags(const ora_lattice *L) { return L->flags; }
 
-void ora_last_scalars(const ora_lattice *L, double *abar2, double *dt)
+void ora_last_scalars(const ora_lattice *L, double *abar3, double *dt)
 {
-    abar2[0] = L->last_abar[0];
-    abar2[1] = L->last_abar[1];
+    for (int j = 0; j < 3; ++j) abar3[j] = L->last_abar[j];
     *dt = L->last_dt;
 }
 
@@ -820,13 +869,14 @@ void ora_nu_field(ora_lattice *L, double *nu)
 {
     fill_moments(L);
     compute_nu(L);
-    for (int j = 0; j < L->ny; ++j)
-        for (int i = 0; i < L->nx; ++i) nu[(size_t)j * L->nx + i] = L->nup[i1(L, i, j)];
+    for (int l = 0; l < L->nz; ++l)
+        for (int j = 0; j < L->ny; ++j)
+            for (int i = 0; i < L->nx; ++i) nu[iC(L, i, j, l)] = L->nup[i1(L, i, j, l)];
 }
 
 void ora_alpha_bar(const ora_lattice *L, double *abar)
 {
     fill_moments((ora_lattice *)L);
-    abar[0] = abar[1] = 0.0;
+    for (int j = 0; j < L->d; ++j) abar[j] = 0.0;
     alpha_bar(L, abar);
 }

@@ -25,12 +25,12 @@ extern "C" {
 #endif
 
 enum { ORA_ADVECTION = 0, ORA_EULER = 1, ORA_SWE = 2, ORA_REACTIVE = 3 };
-#define ORA_MMAX 5 /* most conserved fields: 2D reactive Euler */
+#define ORA_MMAX 6 /* most conserved fields: 3D reactive Euler */
 enum { ORA_PERIODIC = 0, ORA_TRANSMISSIVE = 1, ORA_REFLECTIVE = 2 };
 
 typedef struct ora_cfg {
     int32_t system;     /* ORA_ADVECTION / ORA_EULER / ORA_SWE / ORA_REACTIVE */
-    int32_t dim;        /* 1 or 2                                            */
+    int32_t dim;        /* 1, 2 or 3                                         */
     int32_t nx, ny;     /* cells; ny == 1 in 1D                              */
     double x0, x1, y0, y1;
     int32_t bc[4];      /* x-lo, x-hi, y-lo, y-hi                            */
@@ -38,7 +38,7 @@ typedef struct ora_cfg {
     double eps;         /* alpha_j = alpha_bar_j + eps (Section 2.3)         */
     double gamma;       /* Euler ratio of specific heats                     */
     double g;           /* gravity for shallow water                         */
-    double adv[2];      /* advection velocity per direction                  */
+    double adv[3];      /* advection velocity per direction                  */
     double h_dry;       /* shallow-water dry threshold                       */
     double rho_floor, p_floor;
     int32_t has_bed;    /* shallow-water bed-slope source                    */
@@ -48,6 +48,11 @@ typedef struct ora_cfg {
      * activation temperature T_i of the Arrhenius rate R = K rho Y
      * exp(-T_i / T), T = p / rho */
     double q_heat, k_rate, t_act;
+    /* third dimension (D3Q7): cells nz (1 below 3D), extent [z0, z1] with
+     * (z1 - z0)/nz equal to dx, boundaries z-lo, z-hi */
+    int32_t nz;
+    double z0, z1;
+    int32_t bc_z[2];
 } ora_cfg;
 
 typedef struct ora_lattice ora_lattice;
@@ -55,7 +60,7 @@ typedef struct ora_lattice ora_lattice;
 /* Number of conserved fields m for a system in dimension d. */
 int ora_num_fields(int system, int dim);
 
-/* Lattice life cycle. U0 is m planes [c][y][x] of conserved variables at cell
+/* Lattice life cycle. U0 is m planes [c][z][y][x] of conserved variables at cell
  * centres; bed is one plane [y][x] (or NULL).  Returns NULL on bad input. */
 ora_lattice *ora_create(const ora_cfg *cfg);
 void ora_destroy(ora_lattice *L);
@@ -74,7 +79,7 @@ void ora_set_f(ora_lattice *L, const double *f);
 void ora_last_omega(const ora_lattice *L, double *omega);/* 1 plane        */
 double ora_time(const ora_lattice *L);
 int64_t ora_steps(const ora_lattice *L);
-void ora_last_scalars(const ora_lattice *L, double *abar2, double *dt);
+void ora_last_scalars(const ora_lattice *L, double *abar3, double *dt);
 int32_t ora_flags(const ora_lattice *L);
 
 /* Pieces of one step, exposed for the pin tests. */

@@ -58,10 +58,14 @@ class Problem:
     q_heat: float = 0.0            # reactive: heat release
     k_rate: float = 0.0            # reactive: Arrhenius rate constant
     t_act: float = 0.0             # reactive: activation temperature
+    nz: int = 1                    # 3D: cells along z, extent [z0, z1], boundaries (z-lo, z-hi)
+    z0: float = 0.0
+    z1: float = 1.0
+    bc_z: tuple = (PERIODIC, PERIODIC)
 
     @property
     def cells(self) -> int:
-        return self.nx * (self.ny if self.dim == 2 else 1)
+        return self.nx * (self.ny if self.dim >= 2 else 1) * (self.nz if self.dim == 3 else 1)
 
 
 def centres(n: int, a: float, b: float) -> np.ndarray:
@@ -421,3 +425,86 @@ def reactive_uniform(n=16, dim=1, rho=1.0, u=0.3, v=-0.2, p=1.0, Y=1.0, q_heat=2
                             q_heat, gamma, dim=dim)
     return Problem("reactive_uniform", REACTIVE, dim, n, ny, 0.0, 1.0, 0.0, 1.0,
                    (PERIODIC,) * 4, cfl, steps, U0, gamma=gamma, q_heat=q_heat, k_rate=k_rate, t_act=t_act)
+
+
+# --------------------------------------------------------------------------
+# Three dimensions (D3Q7; the formulation of Section 2.3 is general in d)
+# --------------------------------------------------------------------------
+
+def euler3_conserved(rho, u, v, w, p, gamma=GAMMA):
+    rho, u, v, w, p = (np.asarray(a, dtype=np.float64) for a in (rho, u, v, w, p))
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.stack([rho, rho * u, rho * v, rho * w, E])
+
+
+def _grid3(n):
+    x = centres(n, 0.0, 1.0)
+    return np.meshgrid(x, x, x, indexing="ij")[::-1]   # X, Y, Z with arrays [z][y][x]
+
+
+def advection_sine_3d(n=32, a=(1.0, 0.5, 0.25), cfl=0.5, steps=64, amp=1.0) -> Problem:
+    Z, Y, X = np.meshgrid(*(centres(n, 0.0, 1.0),) * 3, indexing="ij")
+    U0 = amp * np.sin(2 * np.pi * (X + Y + Z))[None]
+    return Problem("advection_sine_3d", ADVECTION, 3, n, n, 0.0, 1.0, 0.0, 1.0,
+                   (PERIODIC,) * 4, cfl, steps, U0, adv=tuple(a), nz=n, bc_z=(PERIODIC, PERIODIC))
+
+
+def euler_entropy_wave_3d(n=16, cfl=0.3, t_final=0.2, amp=0.2) -> Problem:
+    """rho = 1 + amp sin(2 pi (x + y + z)), u = v = w = p = 1, periodic: the
+    exact solution translates by (t, t, t)."""
+    Z, Y, X = np.meshgrid(*(centres(n, 0.0, 1.0),) * 3, indexing="ij")
+    rho = 1.0 + amp * np.sin(2 * np.pi * (X + Y + Z))
+    one = np.ones_like(rho)
+    U0 = euler3_conserved(rho, one, one, one, one)
+    return Problem("euler_entropy_3d", EULER, 3, n, n, 0.0, 1.0, 0.0, 1.0, (PERIODIC,) * 4, cfl, 10 ** 9,
+                   U0, t_final=t_final, nz=n, bc_z=(PERIODIC, PERIODIC))
+
+
+def octant_states(seed: int, gamma=GAMMA):
+    """Eight (rho, u, v, w, p) states drawn like the four-quadrant data."""
+    rng = np.random.default_rng(3000 + seed)
+    return [(rng.uniform(0.1, 1.5), rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(-1, 1),
+             rng.uniform(0.03, 1.5)) for _ in range(8)]
+
+
+def euler_octants_3d(seed=0, n=64, cfl=0.5, steps=100, bc=(TRANSMISSIVE,) * 6) -> Problem:
+    """3D Riemann data: one seeded state per octant around (0.5, 0.5, 0.5)."""
+    st = octant_states(seed)
+    Z, Y, X = np.meshgrid(*(centres(n, 0.0, 1.0),) * 3, indexing="ij")
+    idx = (X >= 0.5).astype(int) + 2 * (Y >= 0.5).astype(int) + 4 * (Z >= 0.5).astype(int)
+    arr = np.array(st)[idx]                       # (n, n, n, 5)
+    U0 = euler3_conserved(arr[..., 0], arr[..., 1], arr[..., 2], arr[..., 3], arr[..., 4])
+    return Problem(f"euler3d_seed{seed}", EULER, 3, n, n, 0.0, 1.0, 0.0, 1.0, tuple(bc[:4]), cfl, steps, U0,
+                   nz=n, bc_z=tuple(bc[4:6]))
+
+
+def euler_sphere_3d(n=48, cfl=0.5, steps=40, bc=(REFLECTIVE,) * 6) -> Problem:
+    """A 3D blast: (rho, p) = (1, 1) inside the sphere of radius 0.25 around
+    the centre, (0.125, 0.1) outside, at rest; symmetric under every axis
+    permutation and reflection."""
+    Z, Y, X = np.meshgrid(*(centres(n, 0.0, 1.0),) * 3, indexing="ij")
+    r2 = (X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2
+    inside = r2 <= 0.0625
+    rho = np.where(inside, 1.0, 0.125)
+    p = np.where(inside, 1.0, 0.1)
+    z = np.zeros_like(rho)
+    U0 = euler3_conserved(rho, z, z, z, p)
+    return Problem("euler_sphere_3d", EULER, 3, n, n, 0.0, 1.0, 0.0, 1.0, tuple(bc[:4]), cfl, steps, U0,
+                   nz=n, bc_z=tuple(bc[4:6]))
+
+
+def reactive_sphere_3d(n=32, cfl=0.5, steps=30, bc=(TRANSMISSIVE,) * 6) -> Problem:
+    """Example 5.12's reactive data on a sphere: (rho,u,v,w,p,Y) = (1,0,0,0,80,0.2)
+    inside radius 0.6 of [-1,1]^3, (1,0,0,0,10,0.8) outside."""
+    Z, Y, X = np.meshgrid(*(centres(n, -1.0, 1.0),) * 3, indexing="ij")
+    inside = X * X + Y * Y + Z * Z <= 0.36
+    p = np.where(inside, 80.0, 10.0)
+    Yf = np.where(inside, 0.2, 0.8)
+    one = np.ones_like(p)
+    g = CIRC2D["gamma"]
+    E = p / (g - 1.0) + CIRC2D["q_heat"] * one * Yf
+    z = np.zeros_like(p)
+    U0 = np.stack([one, z, z, z, E, one * Yf])
+    return Problem("reactive_sphere_3d", REACTIVE, 3, n, n, -1.0, 1.0, -1.0, 1.0, tuple(bc[:4]), cfl, steps, U0,
+                   gamma=g, q_heat=CIRC2D["q_heat"], k_rate=CIRC2D["k_rate"], t_act=CIRC2D["t_act"],
+                   nz=n, z0=-1.0, z1=1.0, bc_z=tuple(bc[4:6]))

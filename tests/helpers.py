@@ -8,10 +8,11 @@ import oracle as O
 
 def ora_cfg_from(p, omega_fixed=None, eps=None, cfl=None, bc=None):
     return O.make_cfg(p.system, p.dim, p.nx, p.ny, p.x0, p.x1, p.y0, p.y1,
-                      bc if bc is not None else p.bc,
+                      tuple(bc if bc is not None else p.bc) + tuple(p.bc_z),
                       p.cfl if cfl is None else cfl, p.eps if eps is None else eps,
                       p.gamma, p.g, p.adv, has_bed=p.bed is not None,
-                      omega_fixed=omega_fixed, q_heat=p.q_heat, k_rate=p.k_rate, t_act=p.t_act)
+                      omega_fixed=omega_fixed, q_heat=p.q_heat, k_rate=p.k_rate, t_act=p.t_act,
+                      nz=p.nz, z0=p.z0, z1=p.z1)
 
 
 def ora_from(p, **kw):

@@ -45,7 +45,8 @@ def jacobian_fd(flux, U, j, rel=1e-6):
 
 
 def euler_right_eigvecs(U, j, gamma=1.4):
-    """Columns: u_n - c, entropy, [shear], u_n + c (Toro, 1D and 2D)."""
+    """Columns: u_n - c, entropy, shear (one per tangential direction),
+    u_n + c (Toro's form, 1D to 3D)."""
     U = np.asarray(U, dtype=np.float64)
     d = U.shape[0] - 2
     rho, E = U[0], U[d + 1]
@@ -59,13 +60,14 @@ def euler_right_eigvecs(U, j, gamma=1.4):
     e[j] = 1.0
     cols = [np.concatenate([[1.0], vel - c * e, [H - un * c]]),
             np.concatenate([[1.0], vel, [0.5 * q2]])]
-    if d == 2:
-        t = 1 - j
-        et = np.zeros(2)
+    for t in range(d):          # shear columns, tangential directions in order
+        if t == j:
+            continue
+        et = np.zeros(d)
         et[t] = 1.0
         cols.append(np.concatenate([[0.0], et, [vel[t]]]))
     cols.append(np.concatenate([[1.0], vel + c * e, [H + un * c]]))
-    lam = [un - c, un] + ([un] if d == 2 else []) + [un + c]
+    lam = [un - c, un] + [un] * (d - 1) + [un + c]
     return np.array(cols).T, np.array(lam)
 
 
@@ -156,8 +158,9 @@ def reactive_right_eigvecs(U, j, gamma=1.2, q_heat=0.0):
     e[j] = 1.0
     cols = [np.concatenate([[1.0], vel - c * e, [H - un * c], [Y]]),
             np.concatenate([[1.0], vel, [0.5 * q2], [Y]])]
-    if d == 2:
-        t = 1 - j
+    for t in range(d):
+        if t == j:
+            continue
         sh = np.zeros(d + 3)
         sh[1 + t] = 1.0
         sh[d + 1] = vel[t]
