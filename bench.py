@@ -37,8 +37,10 @@ METRIC = "GLUPS + HBM GB/s, FP32 batched vs FP64 plain; p50/p99 solve latency"
 # algorithmic bytes per lattice update: one read + one write of Q*m values
 # (+ the bed plane read for shallow water with a bed)
 ALG_BYTES = {("euler2d", 4): 160, ("euler2d", 8): 320, ("swe2d", 4): 124, ("swe2d", 8): 248,
-             ("euler1d", 4): 72, ("euler1d", 8): 144, ("adv1d", 4): 24, ("adv1d", 8): 48}
+             ("euler1d", 4): 72, ("euler1d", 8): 144, ("adv1d", 4): 24, ("adv1d", 8): 48,
+             ("euler3d", 4): 280, ("euler3d", 8): 560}
 KERNEL_SOURCES = ["paper_2609_18177_amd/csrc/step.hpp", "paper_2609_18177_amd/csrc/physics.hpp",
+                  "paper_2609_18177_amd/csrc/step3d.hpp",
                   "paper_2609_18177_amd/csrc/kernels.hip", "paper_2609_18177_amd/build.py"]
 
 
@@ -130,6 +132,21 @@ def run_swe(torch, args, steps=None):
     m0 = math.fsum(p.U0[0].ravel().tolist())
     return {"ms": ms, "steps": steps, "cells": p.cells, "flags": st["flags"],
             "mass_drift_rel": float(sums[0] / m0 - 1.0)}
+
+
+def run_euler3d(torch, args, steps=None):
+    """3D Euler (D3Q7), seeded octant data on 256^3 cells, FP32: the
+    four-pass step (moments, indicator, relaxation, collide-and-pull)."""
+    p = W.euler_octants_3d(seed=0, n=256, steps=100)
+    steps = steps or args.steps3d
+    log(f"[euler3d] 256^3 FP32: warmup {args.warmup}, timed {steps}")
+    L, ms, st = time_steps(torch, p, A.F32, steps, args.warmup)
+    L.close()
+    ms_step = ms / steps
+    return {"glups": p.cells / (ms_step * 1e-3) / 1e9, "ms_per_step": ms_step, "cells": p.cells,
+            "alg_gbs": ALG_BYTES[("euler3d", 4)] * p.cells / (ms_step * 1e-3) / 1e9,
+            "alg_frac": ALG_BYTES[("euler3d", 4)] * p.cells / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "flags": st["flags"]}
 
 
 def run_latency_1d(torch, args):
@@ -268,7 +285,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--only", choices=["euler2d_f32", "euler2d_f64", "swe2d_f32"], default=None)
+    ap.add_argument("--only", choices=["euler2d_f32", "euler2d_f64", "swe2d_f32", "euler3d_f32"], default=None)
+    ap.add_argument("--steps3d", type=int, default=100)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--swe-steps", type=int, default=2000)
     ap.add_argument("--requests", type=int, default=512)
@@ -300,6 +318,10 @@ def main():
         r = run_swe(torch, args, steps=args.steps)
         log(f"[only] swe2d_f32 {r}")
         return
+    if args.only == "euler3d_f32":
+        r = run_euler3d(torch, args, steps=args.steps)
+        log(f"[only] euler3d_f32 {r}")
+        return
     if args.only == "euler2d_f64":
         p = W.euler_seeded_2d(0, n=2048, steps=1000)
         L, ms, st = time_steps(torch, p, A.F64, args.steps, args.warmup)
@@ -326,6 +348,7 @@ def main():
     extra["swe2d_4096_f32"] = {"glups": sw["cells"] / (ms_sw * 1e-3) / 1e9, "ms_per_step": ms_sw,
                                "alg_gbs": ALG_BYTES[("swe2d", 4)] * sw["cells"] / (ms_sw * 1e-3) / 1e9,
                                "mass_drift_rel": sw["mass_drift_rel"], "flags": sw["flags"]}
+    extra["euler3d_256_f32"] = run_euler3d(torch, args)
     extra["euler1d_4096_latency"] = run_latency_1d(torch, args)
     if not args.no_serving:
         extra["serving"] = run_serving(torch, args, args.requests, args.rate, args.fp64_check)

@@ -15,8 +15,10 @@
  *
  * Systems (Section 5): scalar advection, compressible Euler (gamma law),
  * shallow water, and reactive Euler with one-step Arrhenius kinetics
- * (Section 5.4), in 1D (D1Q3) and 2D (D2Q5), with an optional shallow-water
- * bed-slope source S = (0, -g h db/dx, -g h db/dy) (not in the paper).
+ * (Section 5.4), in 1D (D1Q3) and 2D (D2Q5), and (all but shallow water) in
+ * 3D (D3Q7: the formulation of Section 2.3 with d = 3), with an optional
+ * shallow-water bed-slope source S = (0, -g h db/dx, -g h db/dy) (not in the
+ * paper).
  *
  * Conserved fields per system (plane order):
  *   advection      u
@@ -48,7 +50,7 @@
 extern "C" {
 #endif
 
-#define ARLBM_ABI_VERSION 2
+#define ARLBM_ABI_VERSION 3
 
 /* Systems, boundary conditions, precisions, relaxation modes. */
 enum { ARLBM_ADVECTION = 0, ARLBM_EULER = 1, ARLBM_SWE = 2, ARLBM_REACTIVE = 3 };
@@ -75,17 +77,18 @@ enum { ARLBM_OMEGA_ADAPTIVE = 0, ARLBM_OMEGA_FIXED = 1 };
 typedef struct arlbm_config {
     int32_t abi_version;  /* ARLBM_ABI_VERSION                                  */
     int32_t system;       /* ARLBM_ADVECTION / _EULER / _SWE / _REACTIVE        */
-    int32_t dim;          /* 1 or 2                                             */
+    int32_t dim;          /* 1, 2 or 3 (3D: not shallow water)                  */
     int32_t precision;    /* ARLBM_F32 or ARLBM_F64: storage and arithmetic     */
-    int64_t nx, ny;       /* cells; ny = 1 in 1D; nx, ny >= 4                   */
-    double x0, x1, y0, y1;/* domain; in 2D (x1-x0)/nx must equal (y1-y0)/ny     */
-    int32_t bc[4];        /* x-lo, x-hi, y-lo, y-hi; periodic must be paired;
-                             reflective is rejected for advection              */
+    int64_t nx, ny, nz;   /* cells; ny = 1 in 1D, nz = 1 below 3D; else >= 4    */
+    double x0, x1, y0, y1, z0, z1; /* domain; the spacing is the same on every
+                             axis the lattice has: (x1-x0)/nx = (y1-y0)/ny = ..  */
+    int32_t bc[6];        /* x-lo, x-hi, y-lo, y-hi, z-lo, z-hi; periodic must be
+                             paired; reflective is rejected for advection      */
     double cfl;           /* in (0, 1): delta t = CFL dx / sum_j alpha_bar_j    */
     double eps;           /* alpha_j = alpha_bar_j + eps, eps > 0 (paper: 1e-10)*/
     double gamma;         /* Euler ratio of specific heats (> 1)                */
     double g;             /* shallow-water gravity (> 0)                        */
-    double adv_speed[2];  /* advection velocity per direction                   */
+    double adv_speed[3];  /* advection velocity per direction                   */
     double h_dry;         /* shallow-water dry threshold (FP64 compare)         */
     double rho_floor, p_floor; /* Euler floors used in the sound speed          */
     int32_t has_bed;      /* shallow water: bed-slope source on                 */
@@ -121,7 +124,7 @@ typedef struct arlbm_buffers {
 typedef struct arlbm_status {
     double t;             /* simulated time                                     */
     double last_dt;       /* delta t of the last step                           */
-    double abar[2];       /* wave-speed bounds of the current state (eq. 2.19)  */
+    double abar[3];       /* wave-speed bounds of the current state (eq. 2.19)  */
     int64_t step;         /* steps that advanced the state since set_state      */
     int64_t first_bad_step; /* first step whose result set a flag, or -1        */
     uint32_t flags;       /* ARLBM_FLAG_* bits seen so far                      */
@@ -130,9 +133,9 @@ typedef struct arlbm_status {
 
 typedef struct arlbm_lattice arlbm_lattice;
 
-/* Fill *cfg with defaults: ABI version, EULER, 1D, F32, nx = 64, ny = 1,
+/* Fill *cfg with defaults: ABI version, EULER, 1D, F32, nx = 64, ny = nz = 1,
  * unit domain, transmissive, CFL 0.5, eps 1e-10, gamma 1.4, g 9.81,
- * advection speed (1, 0), h_dry 1e-6, floors 1e-12, adaptive omega. */
+ * advection speed (1, 0, 0), h_dry 1e-6, floors 1e-12, adaptive omega. */
 int arlbm_config_init(arlbm_config *cfg);
 
 /* Validate cfg and report buffer sizes.  EINVAL on a bad configuration. */
@@ -235,7 +238,8 @@ int arlbm_server_create(size_t hbm_budget, int32_t precision, void *stream,
                         arlbm_server **out);
 
 /* Queue a request: a configuration, host FP64 initial planes (and bed) copied
- * at submit time, and a step count.  EBUDGET if it can never fit the budget. */
+ * at submit time, and a step count.  EBUDGET if it can never fit the budget;
+ * EINVAL for a 3D lattice (served lattices are 1D or 2D). */
 int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, const double *U0,
                         const double *bed, int64_t nsteps, uint64_t *id);
 

@@ -21,7 +21,7 @@ ADVECTION, EULER, SWE, REACTIVE = 0, 1, 2, 3
 PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
 F32, F64 = 0, 1
 OMEGA_ADAPTIVE, OMEGA_FIXED = 0, 1
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EPOSITIVITY, EDEGENERATE, EBUSY, EBUDGET = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
@@ -37,11 +37,12 @@ class ArlbmError(RuntimeError):
 class Config(C.Structure):
     _fields_ = [
         ("abi_version", C.c_int32), ("system", C.c_int32), ("dim", C.c_int32), ("precision", C.c_int32),
-        ("nx", C.c_int64), ("ny", C.c_int64),
+        ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
         ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
-        ("bc", C.c_int32 * 4),
+        ("z0", C.c_double), ("z1", C.c_double),
+        ("bc", C.c_int32 * 6),
         ("cfl", C.c_double), ("eps", C.c_double), ("gamma", C.c_double), ("g", C.c_double),
-        ("adv_speed", C.c_double * 2), ("h_dry", C.c_double), ("rho_floor", C.c_double),
+        ("adv_speed", C.c_double * 3), ("h_dry", C.c_double), ("rho_floor", C.c_double),
         ("p_floor", C.c_double), ("has_bed", C.c_int32), ("omega_mode", C.c_int32),
         ("omega_fixed", C.c_double),
         ("q_heat", C.c_double), ("k_rate", C.c_double), ("t_act", C.c_double),
@@ -60,7 +61,7 @@ class Buffers(C.Structure):
 
 
 class Status(C.Structure):
-    _fields_ = [("t", C.c_double), ("last_dt", C.c_double), ("abar", C.c_double * 2),
+    _fields_ = [("t", C.c_double), ("last_dt", C.c_double), ("abar", C.c_double * 3),
                 ("step", C.c_int64), ("first_bad_step", C.c_int64), ("flags", C.c_uint32),
                 ("reserved", C.c_uint32)]
 
@@ -137,12 +138,16 @@ def config_from(problem=None, precision=F32, omega_fixed=None, **over) -> Config
     _check(lib().arlbm_config_init(C.byref(c)))
     if problem is not None:
         c.system, c.dim = problem.system, problem.dim
-        c.nx, c.ny = problem.nx, (problem.ny if problem.dim == 2 else 1)
+        c.nx, c.ny = problem.nx, (problem.ny if problem.dim >= 2 else 1)
+        c.nz = problem.nz if problem.dim == 3 else 1
         c.x0, c.x1, c.y0, c.y1 = problem.x0, problem.x1, problem.y0, problem.y1
+        c.z0, c.z1 = problem.z0, problem.z1
         for i in range(4):
             c.bc[i] = problem.bc[i]
+        c.bc[4], c.bc[5] = problem.bc_z
         c.cfl, c.eps, c.gamma, c.g = problem.cfl, problem.eps, problem.gamma, problem.g
-        c.adv_speed[0], c.adv_speed[1] = problem.adv
+        for i in range(3):
+            c.adv_speed[i] = problem.adv[i] if i < len(problem.adv) else 0.0
         c.has_bed = int(problem.bed is not None)
         c.q_heat, c.k_rate, c.t_act = problem.q_heat, problem.k_rate, problem.t_act
     c.precision = precision
@@ -150,7 +155,7 @@ def config_from(problem=None, precision=F32, omega_fixed=None, **over) -> Config
         c.omega_mode, c.omega_fixed = OMEGA_FIXED, float(omega_fixed)
     for k, v in over.items():
         if k == "bc":
-            for i in range(4):
+            for i in range(len(v)):
                 c.bc[i] = v[i]
         else:
             setattr(c, k, v)
@@ -177,7 +182,7 @@ class Lattice:
         self.cfg = cfg
         self.sizes = query_sizes(cfg)
         self.m, self.q = self.sizes.m, self.sizes.q
-        self.dim, self.nx, self.ny = cfg.dim, cfg.nx, cfg.ny
+        self.dim, self.nx, self.ny, self.nz = cfg.dim, cfg.nx, cfg.ny, cfg.nz
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -205,6 +210,8 @@ class Lattice:
 
     # ------------------------------------------------------------------
     def _shape(self, lead):
+        if self.dim == 3:
+            return (lead, self.nz, self.ny, self.nx)
         return (lead, self.ny, self.nx) if self.dim == 2 else (lead, self.nx)
 
     def set_state(self, U0: np.ndarray, bed: Optional[np.ndarray] = None, t0: float = 0.0):
@@ -236,7 +243,7 @@ class Lattice:
         rc = lib().arlbm_sync(self._h, C.byref(st))
         if check and (rc != EPOSITIVITY or strict):
             _check(rc, self._h)
-        return {"rc": rc, "t": st.t, "last_dt": st.last_dt, "abar": [st.abar[0], st.abar[1]][: self.dim],
+        return {"rc": rc, "t": st.t, "last_dt": st.last_dt, "abar": [st.abar[0], st.abar[1], st.abar[2]][: self.dim],
                 "step": st.step, "flags": st.flags, "first_bad_step": st.first_bad_step}
 
     def moments(self) -> np.ndarray:

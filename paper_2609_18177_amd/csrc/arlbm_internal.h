@@ -17,10 +17,11 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 
 enum Variant : int32_t {
     V_ADV1 = 0, V_EUL1 = 1, V_SWE1 = 2, V_REU1 = 3,
-    V_ADV2 = 4, V_EUL2 = 5, V_SWE2 = 6, V_REU2 = 7
+    V_ADV2 = 4, V_EUL2 = 5, V_SWE2 = 6, V_REU2 = 7,
+    V_ADV3 = 8, V_EUL3 = 9, V_REU3 = 11
 };
 
-__host__ __device__ constexpr int variant_of(int system, int dim) { return (dim == 2 ? 4 : 0) + system; }
+__host__ __device__ constexpr int variant_of(int system, int dim) { return (dim - 1) * 4 + system; }
 __host__ __device__ constexpr int num_fields(int system, int dim) {
     return system == 0 ? 1 : (system == 1 ? dim + 2 : (system == 2 ? dim + 1 : dim + 3));
 }
@@ -30,7 +31,7 @@ struct DevScalars {
     // alpha_bar bit patterns (non-negative doubles order like unsigned
     // integers, so the grid-wide max is an integer atomic max).  Three slots:
     // step n reads slot n%3, maxes into (n+1)%3 and clears (n+2)%3.
-    unsigned long long abar[3][2];
+    unsigned long long abar[3][3];
     double last_dt;
     unsigned long long first_bad_step;  // min over flagged steps (~0 = none)
     unsigned int flags;
@@ -39,7 +40,6 @@ struct DevScalars {
     // so every wave of a launch sees the same value)
     double t[3];
     unsigned long long null_launches;   // launches that found t >= t_stop (left the state as it was)
-    double reserved[3];
 };
 static_assert(sizeof(DevScalars) == 128, "DevScalars layout");
 
@@ -52,18 +52,19 @@ struct LatticeDesc {
     const void *bed;
     void *omega;
     DevScalars *sc;
-    int32_t variant, nx, ny, bc[4];
+    int32_t variant, nx, ny, nz, bc[6];
     int32_t omega_fixed_on;
     int32_t band_h;       // rows per strip (2D)
     int32_t ncols;        // strips along x
     int64_t iter0;
     double t_stop;        // a launch whose state time is >= t_stop copies f unchanged (null step)
-    int64_t plane;        // nx * ny
+    int64_t plane;        // nx * ny * nz
     int64_t pstride;      // elements between planes: plane + a 64-element sink tail
     int32_t omega_on;     // omega export plane present (else omega is a 64-slot sink)
     int32_t pad_;
-    double dx, cfl, eps, gamma, g, adv[2], h_dry, rho_floor, p_floor, omega_fixed;
+    double dx, cfl, eps, gamma, g, adv[3], h_dry, rho_floor, p_floor, omega_fixed;
     double q_heat, k_rate, t_act;  // reactive Euler: heat release, rate constant, activation temperature
+    void *nu3;                     // 3D: padded indicator (nx+2)(ny+2)(nz+2), then omega of the cells
 };
 
 // One wave's work item in a batched launch.

@@ -4,6 +4,7 @@
 // written expression order).
 #include "arlbm_internal.h"
 #include "step.hpp"
+#include "step3d.hpp"
 
 #if ARLBM_F64
 #define ARLBM_NS f64
@@ -48,13 +49,23 @@ static hipError_t init_impl(const LatticeDesc &h, const double *U0, const double
 template <int SYS, int D>
 static hipError_t step_impl(const LatticeDesc &h, int64_t iter, hipStream_t s)
 {
-    const int64_t nbands = D == 2 ? (h.ny + h.band_h - 1) / h.band_h : 1;
-    const int64_t nwork = (int64_t)h.ncols * nbands;
-    const dim3 g(grid_for(nwork, kWavesPerBlock)), b(kBlock);
-    if (SYS == 2 && D == 2 && h.bed)
-        hipLaunchKernelGGL((k_step_single<SYS, D, true, real>), g, b, 0, s, h, iter, (int32_t)nwork);
-    else
-        hipLaunchKernelGGL((k_step_single<SYS, D, false, real>), g, b, 0, s, h, iter, (int32_t)nwork);
+    if constexpr (D == 3) {
+        // indicator on the padded lattice (from the moments the previous
+        // step or the initialisation left in u[n&1]), relaxation parameter,
+        // collide and pull (which also writes the moments of the new state)
+        const int64_t npad = (int64_t)(h.nx + 2) * (h.ny + 2) * (h.nz + 2);
+        hipLaunchKernelGGL((k3_nu<SYS, real>), dim3(cell_grid(npad)), dim3(kBlock), 0, s, h, iter);
+        hipLaunchKernelGGL((k3_omega<real>), dim3(cell_grid(h.plane)), dim3(kBlock), 0, s, h, iter);
+        hipLaunchKernelGGL((k3_collide<SYS, real>), dim3(cell_grid(h.plane)), dim3(kBlock), 0, s, h, iter);
+    } else {
+        const int64_t nbands = D == 2 ? (h.ny + h.band_h - 1) / h.band_h : 1;
+        const int64_t nwork = (int64_t)h.ncols * nbands;
+        const dim3 g(grid_for(nwork, kWavesPerBlock)), b(kBlock);
+        if (SYS == 2 && D == 2 && h.bed)
+            hipLaunchKernelGGL((k_step_single<SYS, D, true, real>), g, b, 0, s, h, iter, (int32_t)nwork);
+        else
+            hipLaunchKernelGGL((k_step_single<SYS, D, false, real>), g, b, 0, s, h, iter, (int32_t)nwork);
+    }
     return hipGetLastError();
 }
 
@@ -68,6 +79,9 @@ static hipError_t step_impl(const LatticeDesc &h, int64_t iter, hipStream_t s)
     case V_SWE2: return CALL(2, 2);              \
     case V_REU1: return CALL(3, 1);              \
     case V_REU2: return CALL(3, 2);              \
+    case V_ADV3: return CALL(0, 3);              \
+    case V_EUL3: return CALL(1, 3);              \
+    case V_REU3: return CALL(3, 3);              \
     default: return hipErrorInvalidValue;        \
     }
 
@@ -135,6 +149,9 @@ int step_waves_per_cu(int variant)
     case V_SWE2: fn = (const void *)&k_step_single<2, 2, true, real>; break;
     case V_REU1: fn = (const void *)&k_step_single<3, 1, false, real>; break;
     case V_REU2: fn = (const void *)&k_step_single<3, 2, false, real>; break;
+    case V_ADV3: fn = (const void *)&k3_collide<0, real>; break;
+    case V_EUL3: fn = (const void *)&k3_collide<1, real>; break;
+    case V_REU3: fn = (const void *)&k3_collide<3, real>; break;
     default: return 0;
     }
     int blocks = 0;
@@ -155,6 +172,9 @@ int step_kernel_vgprs(int variant)
     case V_SWE2: fn = (const void *)&k_step_single<2, 2, true, real>; break;
     case V_REU1: fn = (const void *)&k_step_single<3, 1, false, real>; break;
     case V_REU2: fn = (const void *)&k_step_single<3, 2, false, real>; break;
+    case V_ADV3: fn = (const void *)&k3_collide<0, real>; break;
+    case V_EUL3: fn = (const void *)&k3_collide<1, real>; break;
+    case V_REU3: fn = (const void *)&k3_collide<3, real>; break;
     default: return -1;
     }
     if (hipFuncGetAttributes(&a, fn) != hipSuccess) return -1;

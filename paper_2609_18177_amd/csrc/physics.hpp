@@ -25,7 +25,7 @@ namespace arlbm {
 
 template <typename T>
 struct Phys {
-    T gamma, gm1, g, half_g, adv[2], dx, p_floor_t, rho_floor_t, h_dry_t;
+    T gamma, gm1, g, half_g, adv[3], dx, p_floor_t, rho_floor_t, h_dry_t;
     T qh, kr, ti;  // reactive: heat release q, rate constant K, activation temperature T_i
     double h_dry, rho_floor, p_floor;
 };
@@ -51,7 +51,7 @@ struct SysInfo {
 template <typename T>
 struct Prim {
     T rho, E, p, c, cL;
-    T vel[2], mom[2];
+    T vel[3], mom[3];
     T Z, Y;  // reactive: rho Y and Y
     unsigned flags;
 };
@@ -65,8 +65,8 @@ template <int SYS, int D, typename T>
 __device__ __forceinline__ void primitives(const T *U, const Phys<T> &P, Prim<T> &q)
 {
     q.flags = 0;
-    q.vel[1] = T(0);
-    q.mom[1] = T(0);
+    q.vel[1] = q.vel[2] = T(0);
+    q.mom[1] = q.mom[2] = T(0);
     q.Z = q.Y = T(0);
     if constexpr (SYS == 1 || SYS == 3) {
         q.rho = U[0];
@@ -74,10 +74,15 @@ __device__ __forceinline__ void primitives(const T *U, const Phys<T> &P, Prim<T>
         q.mom[0] = U[1];
         q.vel[0] = U[1] / q.rho;
         T q2;
-        if constexpr (D == 2) {
+        if constexpr (D >= 2) {
             q.mom[1] = U[2];
             q.vel[1] = U[2] / q.rho;
             q2 = q.vel[0] * q.vel[0] + q.vel[1] * q.vel[1];
+            if constexpr (D == 3) {
+                q.mom[2] = U[3];
+                q.vel[2] = U[3] / q.rho;
+                q2 = q2 + q.vel[2] * q.vel[2];
+            }
         } else {
             q2 = q.vel[0] * q.vel[0];
         }
@@ -169,6 +174,56 @@ __device__ __forceinline__ void add_theta(int dir, const Prim<T> &qc, const T *U
     const T dx = P.dx;
     if constexpr (SYS == 0) {
         nu = nu + theta<T>(a[0], b[0], dx);
+    } else if constexpr ((SYS == 1 || SYS == 3) && D == 3) {
+        // 3D: rows u-c, entropy, shear (two tangential directions in
+        // increasing order), [species,] u+c; columns rho, m_x, m_y, m_z, E[, rho Y]
+        const T cs = qc.c;
+        const T q2 = (qc.vel[0] * qc.vel[0] + qc.vel[1] * qc.vel[1]) + qc.vel[2] * qc.vel[2];
+        const T b1 = P.gm1 / (cs * cs);
+        const T b2 = T(0.5) * q2 * b1;
+        const T un = qc.vel[dir];
+        const T hb1 = T(0.5) * b1;
+        const T r0c0 = T(0.5) * (b2 + un / cs), r0cn = T(-0.5) * (b1 * un + T(1) / cs);
+        const T r3c0 = T(0.5) * (b2 - un / cs), r3cn = T(-0.5) * (b1 * un - T(1) / cs);
+        T r0[3], r3[3], r1[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const T tang = T(-0.5) * b1 * qc.vel[i];
+            r0[i] = i == dir ? r0cn : tang;
+            r3[i] = i == dir ? r3cn : tang;
+            r1[i] = b1 * qc.vel[i];
+        }
+        const T r1c0 = T(1) - b2;
+        T dm0 = r0c0 * a[0] + r0[0] * a[1] + r0[1] * a[2] + r0[2] * a[3] + hb1 * a[4];
+        T dp0 = r0c0 * b[0] + r0[0] * b[1] + r0[1] * b[2] + r0[2] * b[3] + hb1 * b[4];
+        T dm1 = r1c0 * a[0] + r1[0] * a[1] + r1[1] * a[2] + r1[2] * a[3] + (-b1) * a[4];
+        T dp1 = r1c0 * b[0] + r1[0] * b[1] + r1[1] * b[2] + r1[2] * b[3] + (-b1) * b[4];
+        T dm4 = r3c0 * a[0] + r3[0] * a[1] + r3[1] * a[2] + r3[2] * a[3] + hb1 * a[4];
+        T dp4 = r3c0 * b[0] + r3[0] * b[1] + r3[1] * b[2] + r3[2] * b[3] + hb1 * b[4];
+        if constexpr (SYS == 3) {
+            const T zac = -(P.qh * hb1), zen = P.qh * b1;
+            dm0 = dm0 + zac * a[5];
+            dp0 = dp0 + zac * b[5];
+            dm1 = dm1 + zen * a[5];
+            dp1 = dp1 + zen * b[5];
+            dm4 = dm4 + zac * a[5];
+            dp4 = dp4 + zac * b[5];
+        }
+        const int t1 = dir == 0 ? 1 : 0, t2 = dir == 2 ? 1 : 2;
+        const T dm2 = (-qc.vel[t1]) * a[0] + a[1 + t1];
+        const T dp2 = (-qc.vel[t1]) * b[0] + b[1 + t1];
+        const T dm3 = (-qc.vel[t2]) * a[0] + a[1 + t2];
+        const T dp3 = (-qc.vel[t2]) * b[0] + b[1 + t2];
+        nu = nu + theta<T>(dm0, dp0, dx);
+        nu = nu + theta<T>(dm1, dp1, dx);
+        nu = nu + theta<T>(dm2, dp2, dx);
+        nu = nu + theta<T>(dm3, dp3, dx);
+        if constexpr (SYS == 3) {
+            const T dms = (-qc.Y) * a[0] + a[5];
+            const T dps = (-qc.Y) * b[0] + b[5];
+            nu = nu + theta<T>(dms, dps, dx);
+        }
+        nu = nu + theta<T>(dm4, dp4, dx);
     } else if constexpr (SYS == 1) {
         const T cs = qc.c;
         T q2;
@@ -362,8 +417,12 @@ template <int D, typename T>
 __device__ __forceinline__ T reactive_eint(const T *U)
 {
     const T u0 = U[1] / U[0];
-    const T u1 = D == 2 ? U[2] / U[0] : T(0);
-    const T q2 = u0 * u0 + u1 * u1;
+    const T u1 = D >= 2 ? U[2] / U[0] : T(0);
+    T q2 = u0 * u0 + u1 * u1;
+    if constexpr (D == 3) {
+        const T u2 = U[3] / U[0];
+        q2 = q2 + u2 * u2;
+    }
     return U[D + 1] - T(0.5) * U[0] * q2;
 }
 

@@ -46,19 +46,28 @@ std::string check_config(const arlbm_config *c)
     if (!c) return "config is NULL";
     if (c->abi_version != ARLBM_ABI_VERSION) return "abi_version mismatch";
     if (c->system < 0 || c->system > 3) return "unknown system";
-    if (c->dim != 1 && c->dim != 2) return "dim must be 1 or 2";
+    if (c->dim < 1 || c->dim > 3) return "dim must be 1, 2 or 3";
     if (c->precision != ARLBM_F32 && c->precision != ARLBM_F64) return "precision must be F32 or F64";
     if (c->nx < 4) return "nx must be >= 4";
     if (c->dim == 1 && c->ny != 1) return "ny must be 1 in 1D";
-    if (c->dim == 2 && c->ny < 4) return "ny must be >= 4";
-    if (c->nx > (1 << 26) || c->ny > (1 << 26)) return "lattice too large";
+    if (c->dim >= 2 && c->ny < 4) return "ny must be >= 4";
+    if (c->dim < 3 && c->nz != 1) return "nz must be 1 below 3D";
+    if (c->dim == 3 && c->nz < 4) return "nz must be >= 4";
+    if (c->dim == 3 && c->system == ARLBM_SWE) return "shallow water is 1D or 2D";
+    if (c->nx > (1 << 26) || c->ny > (1 << 26) || c->nz > (1 << 26)) return "lattice too large";
     // kernels address cells within a plane with 32-bit offsets
-    if (c->nx * c->ny > (int64_t)0x7fffffff) return "a plane exceeds 2^31 cells";
+    if (c->nx * c->ny * c->nz > (int64_t)0x7fffffff) return "a plane exceeds 2^31 cells";
     if (!(c->x1 > c->x0)) return "x1 must exceed x0";
-    if (c->dim == 2) {
+    const double dx = (c->x1 - c->x0) / (double)c->nx;
+    if (c->dim >= 2) {
         if (!(c->y1 > c->y0)) return "y1 must exceed y0";
-        const double dx = (c->x1 - c->x0) / (double)c->nx, dy = (c->y1 - c->y0) / (double)c->ny;
+        const double dy = (c->y1 - c->y0) / (double)c->ny;
         if (std::fabs(dx - dy) > 1e-12 * dx) return "dx must equal dy (uniform lattice)";
+    }
+    if (c->dim == 3) {
+        if (!(c->z1 > c->z0)) return "z1 must exceed z0";
+        const double dz = (c->z1 - c->z0) / (double)c->nz;
+        if (std::fabs(dx - dz) > 1e-12 * dx) return "dx must equal dz (uniform lattice)";
     }
     for (int s = 0; s < 2 * c->dim; ++s)
         if (c->bc[s] < 0 || c->bc[s] > 2) return "unknown boundary condition";
@@ -81,7 +90,8 @@ std::string check_config(const arlbm_config *c)
     if (gas && !(c->rho_floor > 0.0 && c->p_floor > 0.0)) return "floors must be > 0";
     if (c->has_bed && c->system != ARLBM_SWE) return "a bed source needs shallow water";
     if (c->system == ARLBM_ADVECTION) {
-        double s = std::fabs(c->adv_speed[0]) + (c->dim == 2 ? std::fabs(c->adv_speed[1]) : 0.0);
+        double s = std::fabs(c->adv_speed[0]) + (c->dim >= 2 ? std::fabs(c->adv_speed[1]) : 0.0) +
+                   (c->dim == 3 ? std::fabs(c->adv_speed[2]) : 0.0);
         if (!(s > 0.0)) return "advection speed must be non-zero";
     }
     if (c->omega_mode != ARLBM_OMEGA_ADAPTIVE && c->omega_mode != ARLBM_OMEGA_FIXED) return "unknown omega mode";
@@ -94,7 +104,7 @@ std::string check_config(const arlbm_config *c)
 // (the kernels' store sink), a multiple of 64 elements.
 int64_t plane_stride(const arlbm_config *c)
 {
-    const int64_t plane = c->nx * c->ny;
+    const int64_t plane = c->nx * c->ny * c->nz;
     return (plane + 64 + 63) / 64 * 64;
 }
 
@@ -106,7 +116,12 @@ void fill_sizes(const arlbm_config *c, arlbm_sizes *o)
     o->m = m;
     o->q = q;
     o->f_bytes = align_up((size_t)q * m * ps * s);
-    o->u_bytes = align_up((size_t)m * ps * s);
+    // in 3D the moment buffers are a ping-pong kept current by the step, and
+    // behind U the second one holds the padded indicator and omega of the
+    // cells between the passes of a step
+    size_t u_elems = (size_t)m * ps;
+    if (c->dim == 3) u_elems += (size_t)(c->nx + 2) * (c->ny + 2) * (c->nz + 2) + (size_t)ps;
+    o->u_bytes = align_up(u_elems * s);
     o->bed_bytes = c->has_bed ? align_up(ps * s) : 0;
     o->scalar_bytes = align_up(sizeof(DevScalars));
     o->omega_bytes = align_up(ps * s);
@@ -302,8 +317,9 @@ int set_state_impl(arlbm_lattice *h, const double *U0, const double *bed, bool o
     if (rc) return rc;
     h->step = 0;
     const double ab0 = *(double *)&got.abar[0][0];
-    const double ab1 = h->cfg.dim == 2 ? *(double *)&got.abar[0][1] : 0.0;
-    const double sa = ab0 + ab1;
+    const double ab1 = h->cfg.dim >= 2 ? *(double *)&got.abar[0][1] : 0.0;
+    const double ab2 = h->cfg.dim == 3 ? *(double *)&got.abar[0][2] : 0.0;
+    const double sa = (ab0 + ab1) + ab2;
     if (!(sa > 0.0)) return fail(h, ARLBM_EDEGENERATE, "sum of wave-speed bounds is zero: time step undefined");
     // Theorem 4.3: 0 < eps < (1/d)(1/CFL - 1) sum_j alpha_bar_j
     const double bound = (1.0 / h->cfg.dim) * (1.0 / h->cfg.cfl - 1.0) * sa;
@@ -327,17 +343,21 @@ extern "C" int arlbm_config_init(arlbm_config *c)
     c->precision = ARLBM_F32;
     c->nx = 64;
     c->ny = 1;
+    c->nz = 1;
     c->x0 = 0.0;
     c->x1 = 1.0;
     c->y0 = 0.0;
     c->y1 = 1.0;
-    for (int i = 0; i < 4; ++i) c->bc[i] = ARLBM_TRANSMISSIVE;
+    c->z0 = 0.0;
+    c->z1 = 1.0;
+    for (int i = 0; i < 6; ++i) c->bc[i] = ARLBM_TRANSMISSIVE;
     c->cfl = 0.5;
     c->eps = 1e-10;
     c->gamma = 1.4;
     c->g = 9.81;
     c->adv_speed[0] = 1.0;
     c->adv_speed[1] = 0.0;
+    c->adv_speed[2] = 0.0;
     c->h_dry = 1e-6;
     c->rho_floor = 1e-12;
     c->p_floor = 1e-12;
@@ -370,14 +390,16 @@ extern "C" int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, 
     d.variant = variant_of(cfg->system, cfg->dim);
     d.nx = (int32_t)cfg->nx;
     d.ny = (int32_t)cfg->ny;
-    for (int i = 0; i < 4; ++i) d.bc[i] = cfg->bc[i];
+    d.nz = (int32_t)cfg->nz;
+    for (int i = 0; i < 6; ++i) d.bc[i] = cfg->bc[i];
     if (cfg->dim == 1) d.bc[2] = d.bc[3] = ARLBM_PERIODIC;
+    if (cfg->dim <= 2) d.bc[4] = d.bc[5] = ARLBM_PERIODIC;
     d.omega_fixed_on = cfg->omega_mode == ARLBM_OMEGA_FIXED;
     d.ncols = (int32_t)((cfg->nx + kOutW - 1) / kOutW);
     d.band_h = cfg->dim == 2 ? choose_band(cfg->ny, d.ncols, resident_waves(cfg->precision, d.variant), 4 * (int64_t)num_cus()) : 1;
     d.iter0 = 0;
     d.t_stop = HUGE_VAL;
-    d.plane = cfg->nx * cfg->ny;
+    d.plane = cfg->nx * cfg->ny * cfg->nz;
     d.pstride = plane_stride(cfg);
     d.dx = (cfg->x1 - cfg->x0) / (double)cfg->nx;
     d.cfl = cfg->cfl;
@@ -385,7 +407,8 @@ extern "C" int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, 
     d.gamma = cfg->gamma;
     d.g = cfg->g;
     d.adv[0] = cfg->adv_speed[0];
-    d.adv[1] = cfg->dim == 2 ? cfg->adv_speed[1] : 0.0;
+    d.adv[1] = cfg->dim >= 2 ? cfg->adv_speed[1] : 0.0;
+    d.adv[2] = cfg->dim == 3 ? cfg->adv_speed[2] : 0.0;
     d.h_dry = cfg->h_dry;
     d.rho_floor = cfg->rho_floor;
     d.p_floor = cfg->p_floor;
@@ -427,7 +450,10 @@ extern "C" int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, 
                         std::string("device allocation failed: ") + hipGetErrorString(err));
         }
     }
-    hipError_t err = hipMalloc((void **)&h->d_partial, sizeof(double) * kConsBlocks * 4);
+    if (cfg->dim == 3)
+        d.nu3 = (char *)d.u[1] + (size_t)h->sz.m * d.pstride * (cfg->precision == ARLBM_F64 ? 8 : 4);
+    // per-block conservation partials of up to 6 fields (3D reactive Euler)
+    hipError_t err = hipMalloc((void **)&h->d_partial, sizeof(double) * kConsBlocks * 6);
     if (err == hipSuccess) err = hipMalloc(&h->omega_sink, 64 * sizeof(double));
     if (err == hipSuccess && !d.omega) {
         d.omega = h->omega_sink;
@@ -521,7 +547,8 @@ extern "C" int arlbm_sync(arlbm_lattice *h, arlbm_status *st)
         st->t = sc.t[slot];
         st->last_dt = sc.last_dt;
         st->abar[0] = *(double *)&sc.abar[slot][0];
-        st->abar[1] = h->cfg.dim == 2 ? *(double *)&sc.abar[slot][1] : 0.0;
+        st->abar[1] = h->cfg.dim >= 2 ? *(double *)&sc.abar[slot][1] : 0.0;
+        st->abar[2] = h->cfg.dim == 3 ? *(double *)&sc.abar[slot][2] : 0.0;
         st->step = h->step - (int64_t)sc.null_launches;
         st->flags = sc.flags;
         st->first_bad_step = sc.first_bad_step == ~0ull ? -1 : (int64_t)sc.first_bad_step;
@@ -626,11 +653,11 @@ extern "C" int arlbm_conservation(arlbm_lattice *h, double *sums)
 namespace {
 struct StateHeader {
     uint64_t magic;
-    int32_t precision, variant, nx, ny;
+    int32_t precision, variant, nx, ny, nz, pad;
     int64_t step;
     uint64_t f_bytes, u_bytes;
 };
-constexpr uint64_t kMagic = 0x41524c424d535431ull;  // "ARLBMST1"
+constexpr uint64_t kMagic = 0x41524c424d535432ull;  // "ARLBMST2"
 }  // namespace
 
 extern "C" int arlbm_state_bytes(arlbm_lattice *h, size_t *bytes)
@@ -646,7 +673,8 @@ extern "C" int arlbm_save_state(arlbm_lattice *h, void *blob, size_t bytes)
     int rc = arlbm_state_bytes(h, &need);
     if (rc) return rc;
     if (!blob || bytes < need) return fail(h, ARLBM_EINVAL, "state buffer too small");
-    StateHeader hd{kMagic, h->cfg.precision, h->desc.variant, h->desc.nx, h->desc.ny, h->step, h->sz.f_bytes,
+    StateHeader hd{kMagic, h->cfg.precision, h->desc.variant, h->desc.nx, h->desc.ny, h->desc.nz, 0, h->step,
+                   h->sz.f_bytes,
                    h->sz.u_bytes};
     char *p = (char *)blob;
     std::memcpy(p, &hd, sizeof(hd));
@@ -669,7 +697,8 @@ extern "C" int arlbm_load_state(arlbm_lattice *h, const void *blob, size_t bytes
     StateHeader hd;
     std::memcpy(&hd, blob, sizeof(hd));
     if (hd.magic != kMagic || hd.precision != h->cfg.precision || hd.variant != h->desc.variant ||
-        hd.nx != h->desc.nx || hd.ny != h->desc.ny || hd.f_bytes != h->sz.f_bytes || hd.u_bytes != h->sz.u_bytes)
+        hd.nx != h->desc.nx || hd.ny != h->desc.ny || hd.nz != h->desc.nz || hd.f_bytes != h->sz.f_bytes ||
+        hd.u_bytes != h->sz.u_bytes)
         return fail(h, ARLBM_EINVAL, "state blob does not match this lattice");
     h->step = hd.step;
     const char *p = (const char *)blob + sizeof(hd);
@@ -815,6 +844,7 @@ extern "C" int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, con
     c.precision = s->precision;
     std::string e = check_config(&c);
     if (!e.empty()) return sfail(s, ARLBM_EINVAL, e);
+    if (c.dim == 3) return sfail(s, ARLBM_EINVAL, "served lattices are 1D or 2D");
     if (c.has_bed && !bed) return sfail(s, ARLBM_EINVAL, "bed is NULL");
     arlbm_sizes sz;
     fill_sizes(&c, &sz);

@@ -117,7 +117,7 @@ __device__ __forceinline__ int bc_map(int i, int n, int lo, int hi, bool &refl)
 //   b_{+j} = 1 / (2 lambda), b_{-j} = -1 / (2 lambda)   (general form 2.5).
 template <typename T>
 struct Coefs {
-    T a0, ap[2], bp, bm, hdt, omega_fixed;
+    T a0, ap[3], bp, bm, hdt, omega_fixed;
     double dt;
 };
 
@@ -127,16 +127,18 @@ __device__ __forceinline__ bool step_coefs(const LatticeDesc &L, int64_t n, Coef
     const DevScalars *sc = L.sc;
     const int slot = (int)(n % 3);
     const double ab0 = bitsd(sc->abar[slot][0]);
-    const double ab1 = D == 2 ? bitsd(sc->abar[slot][1]) : 0.0;
-    const double sa = D == 2 ? ab0 + ab1 : ab0;
+    const double ab1 = D >= 2 ? bitsd(sc->abar[slot][1]) : 0.0;
+    const double ab2 = D == 3 ? bitsd(sc->abar[slot][2]) : 0.0;
+    const double sa = D == 3 ? (ab0 + ab1) + ab2 : (D == 2 ? ab0 + ab1 : ab0);
     if (!(sa > 0.0) || !(sa < 1.0e300)) return false;
     const double dt = L.cfl * L.dx / sa;
     const double lam = L.dx / dt;
-    const double al0 = ab0 + L.eps, al1 = ab1 + L.eps;
-    const double sum_alpha = D == 2 ? al0 + al1 : al0;
+    const double al0 = ab0 + L.eps, al1 = ab1 + L.eps, al2 = ab2 + L.eps;
+    const double sum_alpha = D == 3 ? (al0 + al1) + al2 : (D == 2 ? al0 + al1 : al0);
     cf.a0 = T(1.0 - sum_alpha / lam);
     cf.ap[0] = T(al0 / (2.0 * lam));
     cf.ap[1] = T(al1 / (2.0 * lam));
+    cf.ap[2] = T(al2 / (2.0 * lam));
     cf.bp = T(1.0 / (2.0 * lam));
     cf.bm = T(-1.0 / (2.0 * lam));
     cf.hdt = T(0.5 * dt);
@@ -155,6 +157,7 @@ __device__ __forceinline__ Phys<T> make_phys(const LatticeDesc &L)
     P.half_g = T(0.5 * L.g);
     P.adv[0] = T(L.adv[0]);
     P.adv[1] = T(L.adv[1]);
+    P.adv[2] = T(L.adv[2]);
     P.dx = T(L.dx);
     P.p_floor_t = T(L.p_floor);
     P.rho_floor_t = T(L.rho_floor);
@@ -178,6 +181,7 @@ __device__ __forceinline__ void scalar_update(const LatticeDesc &L, int64_t n, d
     const int clr = (int)((n + 2) % 3);
     sc->abar[clr][0] = 0ull;
     sc->abar[clr][1] = 0ull;
+    sc->abar[clr][2] = 0ull;
 }
 
 // A launch whose state time has reached the stop time leaves the state
@@ -194,9 +198,11 @@ __device__ __forceinline__ void null_scalars(const LatticeDesc &L, int64_t n)
     sc->null_launches = sc->null_launches + 1ull;
     sc->abar[(n + 1) % 3][0] = sc->abar[n % 3][0];
     sc->abar[(n + 1) % 3][1] = sc->abar[n % 3][1];
+    sc->abar[(n + 1) % 3][2] = sc->abar[n % 3][2];
     const int clr = (int)((n + 2) % 3);
     sc->abar[clr][0] = 0ull;
     sc->abar[clr][1] = 0ull;
+    sc->abar[clr][2] = 0ull;
 }
 template <typename T>
 __device__ __forceinline__ void null_copy(const LatticeDesc &L, int64_t n, int planes, int x, bool xout, int ya,
@@ -221,10 +227,12 @@ __device__ __forceinline__ void flag_degenerate(const LatticeDesc &L, int64_t n)
 
 // Commit the wave's bounds and flags for the next step.
 template <typename T>
-__device__ __forceinline__ void commit(const LatticeDesc &L, int64_t n, T s0, T s1, unsigned flags, int dims)
+__device__ __forceinline__ void commit(const LatticeDesc &L, int64_t n, T s0, T s1, unsigned flags, int dims,
+                                       T s2 = T(0))
 {
     const double m0 = (double)wave_max<T>(s0);
-    const double m1 = dims == 2 ? (double)wave_max<T>(s1) : 0.0;
+    const double m1 = dims >= 2 ? (double)wave_max<T>(s1) : 0.0;
+    const double m2 = dims == 3 ? (double)wave_max<T>(s2) : 0.0;
     const unsigned long long anyf = __ballot(flags != 0u);
     unsigned fl = flags;
 #pragma unroll
@@ -232,7 +240,8 @@ __device__ __forceinline__ void commit(const LatticeDesc &L, int64_t n, T s0, T 
     if ((threadIdx.x & (kWave - 1)) == 0) {
         const int slot = (int)((n + 1) % 3);
         atomicMax(&L.sc->abar[slot][0], dbits(m0));
-        if (dims == 2) atomicMax(&L.sc->abar[slot][1], dbits(m1));
+        if (dims >= 2) atomicMax(&L.sc->abar[slot][1], dbits(m1));
+        if (dims == 3) atomicMax(&L.sc->abar[slot][2], dbits(m2));
         if (anyf) {
             atomicOr(&L.sc->flags, fl);
             atomicMin(&L.sc->first_bad_step, (unsigned long long)n - L.sc->null_launches);
@@ -802,7 +811,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_abar(LatticeDesc L, const dou
 {
     constexpr int M = SysInfo<SYS, D>::M;
     const Phys<T> P = make_phys<T>(L);
-    T s0 = T(0), s1 = T(0);
+    T s0 = T(0), s1 = T(0), s2 = T(0);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.plane;
          i += (int64_t)gridDim.x * blockDim.x) {
         T U[M];
@@ -812,15 +821,20 @@ __global__ __launch_bounds__(kBlock) void k_reduce_abar(LatticeDesc L, const dou
         primitives<SYS, D, T>(U, P, q);
         const T v0 = max_speed<SYS, T>(0, q, P);
         if (finite_val<T>(v0) && v0 > s0) s0 = v0;
-        if constexpr (D == 2) {
+        if constexpr (D >= 2) {
             const T v1 = max_speed<SYS, T>(1, q, P);
             if (finite_val<T>(v1) && v1 > s1) s1 = v1;
         }
+        if constexpr (D == 3) {
+            const T v2 = max_speed<SYS, T>(2, q, P);
+            if (finite_val<T>(v2) && v2 > s2) s2 = v2;
+        }
     }
-    const double m0 = (double)wave_max<T>(s0), m1 = (double)wave_max<T>(s1);
+    const double m0 = (double)wave_max<T>(s0), m1 = (double)wave_max<T>(s1), m2 = (double)wave_max<T>(s2);
     if ((threadIdx.x & 63) == 0) {
         atomicMax(&L.sc->abar[slot][0], dbits(m0));
-        if (D == 2) atomicMax(&L.sc->abar[slot][1], dbits(m1));
+        if (D >= 2) atomicMax(&L.sc->abar[slot][1], dbits(m1));
+        if (D == 3) atomicMax(&L.sc->abar[slot][2], dbits(m2));
     }
 }
 
@@ -833,39 +847,38 @@ __global__ __launch_bounds__(kBlock) void k_init(LatticeDesc L, const double *U0
     const Phys<T> P = make_phys<T>(L);
     // coefficients of the initial state, same formulas as a step
     const double ab0 = bitsd(L.sc->abar[slot_in][0]);
-    const double ab1 = D == 2 ? bitsd(L.sc->abar[slot_in][1]) : 0.0;
-    const double sa = D == 2 ? ab0 + ab1 : ab0;
+    const double ab1 = D >= 2 ? bitsd(L.sc->abar[slot_in][1]) : 0.0;
+    const double ab2 = D == 3 ? bitsd(L.sc->abar[slot_in][2]) : 0.0;
+    const double sa = D == 3 ? (ab0 + ab1) + ab2 : (D == 2 ? ab0 + ab1 : ab0);
     const double dt = L.cfl * L.dx / sa;
     const double lam = L.dx / dt;
-    const double al0 = ab0 + L.eps, al1 = ab1 + L.eps;
-    const double sum_alpha = D == 2 ? al0 + al1 : al0;
-    const T a0 = T(1.0 - sum_alpha / lam), ap0 = T(al0 / (2.0 * lam)), ap1 = T(al1 / (2.0 * lam));
+    const double al0 = ab0 + L.eps, al1 = ab1 + L.eps, al2 = ab2 + L.eps;
+    const double sum_alpha = D == 3 ? (al0 + al1) + al2 : (D == 2 ? al0 + al1 : al0);
+    const T a0 = T(1.0 - sum_alpha / lam);
+    const T ap[3] = {T(al0 / (2.0 * lam)), T(al1 / (2.0 * lam)), T(al2 / (2.0 * lam))};
     const T bp = T(1.0 / (2.0 * lam)), bm = T(-1.0 / (2.0 * lam));
     T *f = (T *)L.f[0];
     T *u = (T *)L.u[0];
-    T s0 = T(0), s1 = T(0);
+    T s0 = T(0), s1 = T(0), s2 = T(0);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.plane;
          i += (int64_t)gridDim.x * blockDim.x) {
-        T U[M], Fx[M], Fy[M];
+        T U[M], F[D][M];
 #pragma unroll
         for (int c = 0; c < M; ++c) U[c] = T(U0[(int64_t)c * L.plane + i]);
         Prim<T> q;
         primitives<SYS, D, T>(U, P, q);
-        flux<SYS, D, T>(0, U, q, P, Fx);
-        if constexpr (D == 2) flux<SYS, D, T>(1, U, q, P, Fy);
+#pragma unroll
+        for (int j = 0; j < D; ++j) flux<SYS, D, T>(j, U, q, P, F[j]);
         T Un[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
             T feq[Q];
             feq[0] = a0 * U[c];
-            if constexpr (D == 1) {
-                feq[1] = ap0 * U[c] + bp * Fx[c];
-                feq[2] = ap0 * U[c] + bm * Fx[c];
-            } else {
-                feq[1] = ap0 * U[c] + bp * Fx[c];
-                feq[2] = ap1 * U[c] + bp * Fy[c];
-                feq[3] = ap0 * U[c] + bm * Fx[c];
-                feq[4] = ap1 * U[c] + bm * Fy[c];
+            // velocities: k = 1..D the +j directions, k = D+1..2D the -j directions
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                feq[1 + j] = ap[j] * U[c] + bp * F[j][c];
+                feq[1 + D + j] = ap[j] * U[c] + bm * F[j][c];
             }
             T s = feq[0];
 #pragma unroll
@@ -880,15 +893,20 @@ __global__ __launch_bounds__(kBlock) void k_init(LatticeDesc L, const double *U0
         primitives<SYS, D, T>(Un, P, qn);
         const T v0 = max_speed<SYS, T>(0, qn, P);
         if (finite_val<T>(v0) && v0 > s0) s0 = v0;
-        if constexpr (D == 2) {
+        if constexpr (D >= 2) {
             const T v1 = max_speed<SYS, T>(1, qn, P);
             if (finite_val<T>(v1) && v1 > s1) s1 = v1;
         }
+        if constexpr (D == 3) {
+            const T v2 = max_speed<SYS, T>(2, qn, P);
+            if (finite_val<T>(v2) && v2 > s2) s2 = v2;
+        }
     }
-    const double m0 = (double)wave_max<T>(s0), m1 = (double)wave_max<T>(s1);
+    const double m0 = (double)wave_max<T>(s0), m1 = (double)wave_max<T>(s1), m2 = (double)wave_max<T>(s2);
     if ((threadIdx.x & 63) == 0) {
         atomicMax(&L.sc->abar[0][0], dbits(m0));
-        if (D == 2) atomicMax(&L.sc->abar[0][1], dbits(m1));
+        if (D >= 2) atomicMax(&L.sc->abar[0][1], dbits(m1));
+        if (D == 3) atomicMax(&L.sc->abar[0][2], dbits(m2));
     }
 }
 

@@ -1,0 +1,255 @@
+// One time step of the method on a D3Q7 lattice (Section 2.3 with d = 3:
+// e_0 = 0, e_j the unit vectors, e_{j+3} = -e_j), as three cell-parallel
+// passes.  The moments U = sum_k f_k (eq. 2.3) of the current state are kept
+// in the ping-pong buffer u[n&1]: written by the initialisation and by each
+// step for the next one.
+//
+//   k3_nu       indicator nu (eqs. 2.13-2.14) on the lattice padded by one
+//               ghost cell per side, from U with the boundary index maps;
+//   k3_omega    box sum over {-1,0,1}^3 (eq. 2.15, z outermost, x innermost)
+//               and omega (eq. 2.16) of every cell;
+//   k3_collide  per destination cell x and velocity k: collision at the
+//               source node x - e_k (eqs. 2.2, 2.5, 2.6, 2.20), pull, the
+//               moment update (2.8) and the second half source; the moments
+//               of the new populations into u[(n+1)&1]; the next step's
+//               wave-speed bounds (2.19) reduced across the wave and
+//               committed with one atomic max per wave and direction.
+//
+// Threads walk cells with x fastest, so every plane access is coalesced
+// (shifts by e_k move whole rows or planes).  A population pulled from a
+// ghost position outside a non-periodic face is the destination's own
+// collided population: the same velocity (transmissive) or the mirrored one
+// with the normal momentum negated (reflective), as in the 1D/2D kernels.
+#pragma once
+
+#include "step.hpp"
+
+namespace arlbm {
+
+// Cell index of (i, j, l) and the padded index of (i, j, l), i in [-1, nx].
+__device__ __forceinline__ int64_t cell3(const LatticeDesc &L, int i, int j, int l)
+{
+    return ((int64_t)l * L.ny + j) * L.nx + i;
+}
+__device__ __forceinline__ int64_t pad3(const LatticeDesc &L, int i, int j, int l)
+{
+    return ((int64_t)(l + 1) * (L.ny + 2) + (j + 1)) * (L.nx + 2) + (i + 1);
+}
+
+// U at any position within two cells of the lattice: each axis through its
+// boundary index map; reflective maps negate that axis's momentum.
+template <int M, typename T>
+__device__ __forceinline__ void load_U3(const LatticeDesc &L, const T *u, int i, int j, int l, bool mom, T *U)
+{
+    bool rx, ry, rz;
+    const int im = bc_map(i, L.nx, L.bc[0], L.bc[1], rx);
+    const int jm = bc_map(j, L.ny, L.bc[2], L.bc[3], ry);
+    const int lm = bc_map(l, L.nz, L.bc[4], L.bc[5], rz);
+    const int64_t c0 = cell3(L, im, jm, lm);
+#pragma unroll
+    for (int c = 0; c < M; ++c) U[c] = u[(int64_t)c * L.pstride + c0];
+    if (mom) {
+        if (rx) U[1] = -U[1];
+        if (ry) U[2] = -U[2];
+        if (rz) U[3] = -U[3];
+    }
+}
+
+template <int SYS, typename T>
+__global__ __launch_bounds__(kBlock) void k3_nu(LatticeDesc L, int64_t iter)
+{
+    constexpr int M = SysInfo<SYS, 3>::M;
+    const Phys<T> P = make_phys<T>(L);
+    const T *u = (const T *)L.u[(iter - L.iter0) & 1];
+    T *nu_out = (T *)L.nu3;
+    const int px = L.nx + 2, py = L.ny + 2;
+    const int64_t npad = (int64_t)px * py * (L.nz + 2);
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < npad;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(g % px) - 1;
+        const int j = (int)((g / px) % py) - 1;
+        const int l = (int)(g / ((int64_t)px * py)) - 1;
+        T Uc[M], Um[M], Up[M];
+        load_U3<M, T>(L, u, i, j, l, SYS != 0, Uc);
+        Prim<T> qc;
+        primitives<SYS, 3, T>(Uc, P, qc);
+        T nu = T(0);
+#pragma unroll
+        for (int dir = 0; dir < 3; ++dir) {
+            const int ox = dir == 0, oy = dir == 1, oz = dir == 2;
+            load_U3<M, T>(L, u, i - ox, j - oy, l - oz, SYS != 0, Um);
+            load_U3<M, T>(L, u, i + ox, j + oy, l + oz, SYS != 0, Up);
+            add_theta<SYS, 3, T>(dir, qc, Uc, Um, Up, P, nu);
+        }
+        nu_out[g] = nu;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k3_omega(LatticeDesc L, int64_t iter)
+{
+    const T *nu = (const T *)L.nu3;
+    const int64_t npad = (int64_t)(L.nx + 2) * (L.ny + 2) * (L.nz + 2);
+    T *w_out = (T *)L.nu3 + npad;
+    const T wfix = T(L.omega_fixed);
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < L.plane;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(c % L.nx);
+        const int j = (int)((c / L.nx) % L.ny);
+        const int l = (int)(c / ((int64_t)L.nx * L.ny));
+        T w;
+        if (L.omega_fixed_on) {
+            w = wfix;
+        } else {
+            T nt = T(0);
+#pragma unroll
+            for (int kl = -1; kl <= 1; ++kl)
+#pragma unroll
+                for (int kj = -1; kj <= 1; ++kj)
+#pragma unroll
+                    for (int ki = -1; ki <= 1; ++ki) nt = nt + nu[pad3(L, i + ki, j + kj, l + kl)];
+            w = T(1) + T(1) / (T(1) + nt);
+        }
+        w_out[c] = w;
+        if (L.omega_on) ((T *)L.omega)[c] = w;
+    }
+}
+
+template <int SYS, typename T>
+__global__ __launch_bounds__(kBlock) void k3_collide(LatticeDesc L, int64_t iter)
+{
+    constexpr int D = 3, M = SysInfo<SYS, 3>::M, Q = 7;
+    const int64_t n = iter - L.iter0;
+    const bool first_thread = blockIdx.x == 0 && threadIdx.x == 0;
+    const T *fin = (const T *)L.f[n & 1];
+    T *fout = (T *)L.f[(n + 1) & 1];
+    const int64_t ps = L.pstride;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const T *u = (const T *)L.u[n & 1];
+    T *uout = (T *)L.u[(n + 1) & 1];
+    if (L.sc->t[n % 3] >= L.t_stop) {  // null step: the state is at the stop time
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < L.plane; c += stride) {
+            for (int p = 0; p < Q * M; ++p) fout[(int64_t)p * ps + c] = fin[(int64_t)p * ps + c];
+            for (int p = 0; p < M; ++p) uout[(int64_t)p * ps + c] = u[(int64_t)p * ps + c];
+        }
+        if (first_thread) null_scalars(L, n);
+        return;
+    }
+    Coefs<T> cf;
+    if (!step_coefs<D, T>(L, n, cf)) {
+        if (first_thread) flag_degenerate(L, n);
+        return;
+    }
+    const Phys<T> P = make_phys<T>(L);
+    const T *wv = (const T *)L.nu3 + (int64_t)(L.nx + 2) * (L.ny + 2) * (L.nz + 2);
+    const T ak[Q] = {cf.a0, cf.ap[0], cf.ap[1], cf.ap[2], cf.ap[0], cf.ap[1], cf.ap[2]};
+    T smax[3] = {T(0), T(0), T(0)};
+    unsigned flags = 0;
+    // a grid-stride loop in which every lane of a wave runs the same number
+    // of iterations (the reduction below needs the whole wave)
+    const int64_t total = (L.plane + stride - 1) / stride * stride;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += stride) {
+        const bool live = c < L.plane;
+        const int64_t cc = live ? c : 0;
+        const int i = (int)(cc % L.nx);
+        const int j = (int)((cc / L.nx) % L.ny);
+        const int l = (int)(cc / ((int64_t)L.nx * L.ny));
+        const int pos[3] = {i, j, l};
+        const int ext[3] = {L.nx, L.ny, L.nz};
+        T Fk[Q][M];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            // velocity k: 0 rest; 1..3 +x,+y,+z; 4..6 -x,-y,-z
+            const int dir = k == 0 ? 0 : (k - 1) % 3;
+            const int sgn = k == 0 ? 0 : (k <= 3 ? 1 : -1);
+            int src[3] = {i, j, l};
+            src[dir] -= sgn;
+            int ks = k;
+            bool negate = false;
+            if (k != 0 && (src[dir] < 0 || src[dir] >= ext[dir])) {
+                const int side = src[dir] < 0 ? 2 * dir : 2 * dir + 1;
+                const int b = L.bc[side];
+                if (b == 0) {
+                    src[dir] = src[dir] < 0 ? ext[dir] - 1 : 0;  // periodic wrap
+                } else {
+                    src[dir] = pos[dir];  // the destination's own collided population
+                    if (b == 2) {
+                        ks = k <= 3 ? k + 3 : k - 3;
+                        negate = true;
+                    }
+                }
+            }
+            const int64_t s = cell3(L, src[0], src[1], src[2]);
+            T U[M];
+#pragma unroll
+            for (int c2 = 0; c2 < M; ++c2) U[c2] = u[(int64_t)c2 * ps + s];
+            Prim<T> q;
+            primitives<SYS, D, T>(U, P, q);
+            // a mirrored velocity keeps its axis, so a_k and the flux
+            // direction are those of k; only the sign of b_k follows ks
+            T F[M];
+            if (k != 0) flux<SYS, D, T>(dir, U, q, P, F);
+            const T w = wv[s];
+            const T a = k == 0 ? cf.a0 : cf.ap[dir];
+            const T bk = ks <= 3 ? cf.bp : cf.bm;
+            T SY = T(0);
+            if constexpr (SYS == 3) SY = -arrhenius_rate<T>(P, U[0], reactive_eint<D, T>(U), U[M - 1], nullptr);
+#pragma unroll
+            for (int c2 = 0; c2 < M; ++c2) {
+                const T fk = fin[(int64_t)(ks * M + c2) * ps + s];
+                const T feq = k == 0 ? a * U[c2] : a * U[c2] + bk * F[c2];
+                T fs = fk - w * (fk - feq);
+                if constexpr (SYS == 3)
+                    if (c2 == M - 1) fs = fs + cf.hdt * (a * SY);
+                Fk[k][c2] = (negate && c2 == 1 + dir) ? -fs : fs;
+            }
+        }
+        // moments (2.8) and the second half source
+        T sumF[M];
+#pragma unroll
+        for (int c2 = 0; c2 < M; ++c2) {
+            T sf = Fk[0][c2];
+#pragma unroll
+            for (int k = 1; k < Q; ++k) sf = sf + Fk[k][c2];
+            sumF[c2] = sf;
+        }
+        if constexpr (SYS == 3) {
+            const T eint = reactive_eint<D, T>(sumF);
+            const T z = reactive_solve<T>(P, sumF[0], eint, sumF[M - 1], cf.hdt);
+            const T SY = -arrhenius_rate<T>(P, sumF[0], eint, z, nullptr);
+#pragma unroll
+            for (int k = 0; k < Q; ++k) Fk[k][M - 1] = Fk[k][M - 1] + cf.hdt * (ak[k] * SY);
+        }
+        T Un[M];
+#pragma unroll
+        for (int c2 = 0; c2 < M; ++c2) {
+            T sn = Fk[0][c2];
+#pragma unroll
+            for (int k = 1; k < Q; ++k) sn = sn + Fk[k][c2];
+            Un[c2] = sn;
+        }
+        if (live) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k)
+#pragma unroll
+                for (int c2 = 0; c2 < M; ++c2) fout[(int64_t)(k * M + c2) * ps + c] = Fk[k][c2];
+#pragma unroll
+            for (int c2 = 0; c2 < M; ++c2) uout[(int64_t)c2 * ps + c] = Un[c2];
+            Prim<T> qn;
+            primitives<SYS, D, T>(Un, P, qn);
+            bool fin_ok = true;
+#pragma unroll
+            for (int c2 = 0; c2 < M; ++c2) fin_ok = fin_ok && finite_val<T>(Un[c2]);
+            flags |= qn.flags | (fin_ok ? 0u : 1u);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const T v = max_speed<SYS, T>(d, qn, P);
+                if (finite_val<T>(v) && v > smax[d]) smax[d] = v;
+            }
+        }
+    }
+    if (first_thread) scalar_update(L, n, cf.dt);
+    commit<T>(L, n, smax[0], smax[1], flags, 3, smax[2]);
+}
+
+}  // namespace arlbm

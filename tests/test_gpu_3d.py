@@ -1,0 +1,151 @@
+"""GPU checks of the D3Q7 path (Section 2.3 with d = 3) against the FP64 oracle.
+
+FP64 bit for bit on 3D Euler (seeded octant data; a centred sphere with
+reflective walls; periodic, transmissive and mixed boundaries; a ragged
+non-cubic lattice), 3D advection and 3D reactive Euler; FP32 within the
+stated bound; time-targeted runs, the omega export, conservation sums,
+checkpoint/resume, and the server's refusal of 3D lattices.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2609_18177_amd import arlbm as A
+from paper_2609_18177_amd import workloads as W
+from gpu_common import require_gpu, say, gpu_lattice, rel_l2_per_comp, rel_l1
+from helpers import ora_from, run_until, fsum
+
+pytestmark = pytest.mark.gpu
+
+# FP32 against the FP64 oracle, relative L1 over all fields (3D shock data
+# after 20-30 steps; the bound keeps about a 3x margin over the measured
+# values printed by the tests).
+TOL_FP32 = 3e-5
+
+
+def _cmp(p, steps, tag, tol32=TOL_FP32, omega_export=False):
+    Lo = ora_from(p)
+    Lo.run(steps)
+    Uo = Lo.moments()
+    G = gpu_lattice(p, A.F64, omega_export=omega_export)
+    G.step(steps)
+    st = G.sync()
+    U64 = G.moments()
+    om = G.omega() if omega_export else None
+    G.close()
+    G = gpu_lattice(p, A.F32)
+    G.step(steps)
+    G.sync()
+    e32 = rel_l1(G.moments(), Uo)
+    G.close()
+    say(f"[3d {tag}] cells {p.cells} steps {steps} bitwise={np.array_equal(U64, Uo)} "
+        f"rel L2 {rel_l2_per_comp(U64, Uo)} fp32 rel L1 {e32:.3e}")
+    assert np.array_equal(U64, Uo)
+    assert st["t"] == Lo.t and st["step"] == steps
+    assert e32 < tol32, e32
+    if omega_export:
+        assert np.array_equal(om, Lo.last_omega())
+    return U64
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_euler3d_octants_transmissive(seed):
+    require_gpu()
+    _cmp(W.euler_octants_3d(seed=seed, n=24, steps=20), 20, f"octants seed {seed}", omega_export=seed == 0)
+
+
+def test_euler3d_periodic_and_mixed():
+    require_gpu()
+    _cmp(W.euler_octants_3d(seed=2, n=20, steps=20, bc=(A.PERIODIC,) * 6), 20, "octants periodic")
+    bc = (A.TRANSMISSIVE, A.REFLECTIVE, A.PERIODIC, A.PERIODIC, A.REFLECTIVE, A.TRANSMISSIVE)
+    _cmp(W.euler_octants_3d(seed=3, n=20, steps=20, bc=bc), 20, "octants mixed")
+
+
+def test_euler3d_sphere_reflective_symmetric():
+    require_gpu()
+    U = _cmp(W.euler_sphere_3d(n=20, steps=15), 15, "sphere reflective")
+    rho = U[0]
+    for perm in ((0, 2, 1), (1, 0, 2), (2, 1, 0)):
+        assert np.max(np.abs(rho - rho.transpose(perm))) < 1e-12
+
+
+def test_euler3d_ragged_noncubic():
+    """17 x 13 x 11 cells of spacing 1/16 (not a multiple of any tile)."""
+    require_gpu()
+    h = 1.0 / 16
+    base = W.euler_octants_3d(seed=4, n=17)
+    Z, Y, X = np.meshgrid(*(W.centres(n, 0.0, n * h) for n in (11, 13, 17)), indexing="ij")
+    st = W.octant_states(4)
+    idx = (X >= 0.5).astype(int) + 2 * (Y >= 0.4).astype(int) + 4 * (Z >= 0.3).astype(int)
+    arr = np.array(st)[idx]
+    U0 = W.euler3_conserved(arr[..., 0], arr[..., 1], arr[..., 2], arr[..., 3], arr[..., 4])
+    p = W.Problem("ragged3d", W.EULER, 3, 17, 13, 0.0, 17 * h, 0.0, 13 * h, base.bc, 0.5, 15, U0,
+                  nz=11, z0=0.0, z1=11 * h, bc_z=base.bc_z)
+    _cmp(p, 15, "ragged 17x13x11")
+
+
+def test_advection3d_periodic():
+    require_gpu()
+    _cmp(W.advection_sine_3d(n=20, steps=20), 20, "advection", tol32=1e-5)
+
+
+def test_reactive3d_sphere():
+    require_gpu()
+    _cmp(W.reactive_sphere_3d(n=20, steps=10), 10, "reactive sphere", tol32=2e-3)
+
+
+def test_euler3d_step_until_and_checkpoint():
+    require_gpu()
+    p = W.euler_octants_3d(seed=6, n=16)
+    Lo = ora_from(p)
+    run_until(Lo, 0.03)
+    G = gpu_lattice(p, A.F64)
+    k = G.step_until(0.03)
+    assert k == Lo.steps and np.array_equal(G.moments(), Lo.moments())
+    blob = G.save_state()
+    H = gpu_lattice(p, A.F64)
+    H.load_state(blob)
+    run_until(Lo, 0.06)
+    kh = H.step_until(0.06)
+    st = H.sync()
+    say(f"[3d until] steps {k}+{kh} oracle {Lo.steps}")
+    assert k + kh == Lo.steps and st["t"] == Lo.t
+    assert np.array_equal(H.moments(), Lo.moments())
+    G.close()
+    H.close()
+
+
+@pytest.mark.parametrize("system", ["euler", "reactive"])
+def test_conservation_sums_3d(system):
+    """arlbm_conservation over 5 (Euler) and 6 (reactive) fields equals the
+    compensated sums of the read-back moments; rho, m, E stay conserved."""
+    require_gpu()
+    if system == "euler":
+        p = W.euler_octants_3d(seed=7, n=16, bc=(A.PERIODIC,) * 6)
+    else:
+        p = W.reactive_sphere_3d(n=16, bc=(A.PERIODIC,) * 6)
+    m = p.U0.shape[0]
+    G = gpu_lattice(p, A.F64)
+    G.step(12)
+    sums = G.conservation()
+    U = G.moments()
+    for c in range(m):
+        ref = fsum(U[c])
+        assert abs(sums[c] - ref) <= 1e-12 * max(1.0, fsum(np.abs(U[c]))), (c, sums[c], ref)
+    for c in range(m - (1 if system == "reactive" else 0)):
+        # a field that starts at zero (momentum of data at rest) is scaled by
+        # its magnitude at the end
+        scale = max(fsum(np.abs(p.U0[c])), fsum(np.abs(U[c])))
+        assert abs(sums[c] - fsum(p.U0[c])) <= 1e-12 * scale, c
+    G.close()
+
+
+def test_server_refuses_3d():
+    require_gpu()
+    p = W.euler_octants_3d(seed=0, n=8)
+    srv = A.Server(1 << 30, A.F32)
+    with pytest.raises(A.ArlbmError) as e:
+        srv.submit(A.config_from(p, precision=A.F32), p.U0, None, 5)
+    assert e.value.code == A.EINVAL
+    srv.close()

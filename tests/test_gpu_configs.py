@@ -222,7 +222,7 @@ def test_nonfinite_state_is_reported_with_its_step():
     G = gpu_lattice(p, A.F64)
     G.step(5)
     blob = bytearray(G.save_state())
-    hdr = 48  # state header size (magic, precision, variant, nx, ny, step, f_bytes, u_bytes)
+    hdr = 56  # state header size (magic, precision, variant, nx, ny, nz, pad, step, f_bytes, u_bytes)
     view = np.frombuffer(blob, dtype=np.float64, count=512, offset=hdr)
     poisoned = view.copy()
     poisoned[100] = np.nan
