@@ -31,9 +31,12 @@ import bench  # noqa: E402  (kernel source hash; bench imports no GPU module at 
 
 KERNELS = {"euler2d_f32": "k_step_single<1, 2, false, float>",
            "euler2d_f64": "k_step_single<1, 2, false, double>",
-           "swe2d_f32": "k_step_single<2, 2, true, float>"}
+           "swe2d_f32": "k_step_single<2, 2, true, float>",
+           "euler3d_f32": "k3_collide<1, float>"}
+# further kernels of a step (3D: the indicator and relaxation passes)
+EXTRA_KERNELS = {"euler3d_f32": ["k3_nu<1, float>", "k3_omega<float>"]}
 WORKLOAD_NAMES = {"euler2d_f32": "euler2d_2048_f32", "euler2d_f64": "euler2d_2048_f64",
-                  "swe2d_f32": "swe2d_4096_f32"}
+                  "swe2d_f32": "swe2d_4096_f32", "euler3d_f32": "euler3d_256_f32"}
 
 
 def rocprof(args, raw, tag, prog, timeout):
@@ -78,11 +81,17 @@ def main():
     kname = KERNELS[args.workload]
     d, cmd_trace = rocprof(["--kernel-trace", "--stats"], raw, "trace", prog, 300)
     stats = kernel_stats(os.path.join(d, "run_kernel_stats.csv"), kname)
+    extra_names = EXTRA_KERNELS.get(args.workload, [])
+    extra_stats = {k: kernel_stats(os.path.join(d, "run_kernel_stats.csv"), k) for k in extra_names}
     pmc_prog = ["bench.py", "--only", args.workload, "--steps", "10", "--warmup", "2"]
     d, cmd_fetch = rocprof(["--pmc", "FETCH_SIZE"], raw, "fetch", pmc_prog, 120)
     fetch_kib, nf = per_dispatch(os.path.join(d, "run_counter_collection.csv"), "FETCH_SIZE", kname)
+    extra_fetch = {k: per_dispatch(os.path.join(d, "run_counter_collection.csv"), "FETCH_SIZE", k)[0]
+                   for k in extra_names}
     d, cmd_write = rocprof(["--pmc", "WRITE_SIZE"], raw, "write", pmc_prog, 120)
     write_kib, nw = per_dispatch(os.path.join(d, "run_counter_collection.csv"), "WRITE_SIZE", kname)
+    extra_write = {k: per_dispatch(os.path.join(d, "run_counter_collection.csv"), "WRITE_SIZE", k)[0]
+                   for k in extra_names}
     cal_prog = ["bench.py", "--copy-calibration"]
     d, cmd_cf = rocprof(["--pmc", "FETCH_SIZE"], raw, "copy_fetch", cal_prog, 120)
     copy_fetch_kib, _ = per_dispatch(os.path.join(d, "run_counter_collection.csv"), "FETCH_SIZE", "copyBuffer")
@@ -102,6 +111,12 @@ def main():
            "hbm_read_bytes_per_launch": read_b, "hbm_write_bytes_per_launch": write_b,
            "hbm_bytes_per_launch": read_b + write_b,
            "commands": [cmd_trace, cmd_fetch, cmd_write, cmd_cf, cmd_cw]}
+    if extra_names:
+        rec["other_kernels_of_the_step"] = {
+            k: {"avg_kernel_ns": extra_stats[k]["avg_ns"] if extra_stats[k] else None,
+                "hbm_read_bytes": extra_fetch[k] * 1024.0 * read_scale if extra_fetch[k] else None,
+                "hbm_write_bytes": extra_write[k] * 1024.0 * write_scale if extra_write[k] else None}
+            for k in extra_names}
     pdir = os.path.abspath(args.profiles_dir)
     os.makedirs(pdir, exist_ok=True)
     with open(os.path.join(pdir, f"{wl}_pmc.json"), "w") as f:
@@ -123,6 +138,11 @@ def main():
         f.write(f"| calibration (bytes moved / counter bytes) read, write | {read_scale:.3f}, {write_scale:.3f} |\n")
         f.write(f"| HBM read / write per launch (calibrated) | {read_b / 1e6:.1f} / {write_b / 1e6:.1f} MB |\n")
         f.write(f"| HBM bytes per launch | {(read_b + write_b) / 1e6:.1f} MB |\n")
+        for k, v in rec.get("other_kernels_of_the_step", {}).items():
+            ns = v["avg_kernel_ns"]
+            rb, wb = v["hbm_read_bytes"], v["hbm_write_bytes"]
+            f.write(f"| other kernel of the step: {k} | {ns / 1e3 if ns else float('nan'):.2f} us, "
+                    f"HBM read/write {rb / 1e6 if rb else float('nan'):.1f} / {wb / 1e6 if wb else float('nan'):.1f} MB |\n")
     print(json.dumps(rec, indent=1))
 
 
