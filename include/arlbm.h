@@ -262,7 +262,8 @@ int arlbm_server_destroy(arlbm_server *s);
 /* ------------------------------------------------------------------------ */
 
 /* Vector registers per lane of the fused step kernel for a precision, system
- * and dimension (from the code object), or -1. */
+ * and dimension (from the code object; in 2D the kernel that a lattice of
+ * even nx runs), or -1. */
 int arlbm_step_kernel_vgprs(int32_t precision, int32_t system, int32_t dim);
 
 #ifdef __cplusplus

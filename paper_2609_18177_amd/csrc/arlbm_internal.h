@@ -6,12 +6,17 @@
 
 namespace arlbm {
 
-// Cells produced per wave along x: a wave of 64 lanes covers x0-3 .. x0+60,
-// the 3-cell halo on each side feeds the radius-2 indicator stencil and the
-// radius-1 pull (omega is needed one cell beyond the outputs).
+// Cells produced per wave along x.  With one column per lane a wave of 64
+// lanes covers x0-3 .. x0+60: the 3-cell halo on each side feeds the
+// radius-2 indicator stencil and the radius-1 pull (omega is needed one cell
+// beyond the outputs).  With V columns per lane the halo is rounded up to
+// whole lanes, so that every lane's V columns start V-aligned.
 constexpr int kWave = 64;
 constexpr int kHalo = 3;
 constexpr int kOutW = kWave - 2 * kHalo;  // 58
+__host__ __device__ constexpr int strip_halo(int v) { return (kHalo + v - 1) / v * v; }
+__host__ __device__ constexpr int strip_out_w(int v) { return kWave * v - 2 * strip_halo(v); }
+static_assert(strip_out_w(1) == kOutW && strip_out_w(2) == 120, "strip geometry");
 constexpr int kBlock = 256;               // 4 independent waves per block
 constexpr int kWavesPerBlock = kBlock / kWave;
 
@@ -59,9 +64,9 @@ struct LatticeDesc {
     int64_t iter0;
     double t_stop;        // a launch whose state time is >= t_stop copies f unchanged (null step)
     int64_t plane;        // nx * ny * nz
-    int64_t pstride;      // elements between planes: plane + a 64-element sink tail
-    int32_t omega_on;     // omega export plane present (else omega is a 64-slot sink)
-    int32_t pad_;
+    int64_t pstride;      // elements between planes: plane + a 128-element sink tail
+    int32_t omega_on;     // omega export plane present (else omega is a 128-slot sink)
+    int32_t cpl;          // 2D: columns per lane of the step's strips (1, or 2 when nx is even)
     double dx, cfl, eps, gamma, g, adv[3], h_dry, rho_floor, p_floor, omega_fixed;
     double q_heat, k_rate, t_act;  // reactive Euler: heat release, rate constant, activation temperature
     void *nu3;                     // 3D: padded indicator (nx+2)(ny+2)(nz+2), then omega of the cells
@@ -94,8 +99,8 @@ struct WorkItem {
                        hipStream_t s);                                                                 \
     hipError_t to_double(const void *src, double *dst, int64_t plane, int64_t pstride, int m,         \
                          hipStream_t s);                                                               \
-    int step_kernel_vgprs(int variant);                                                                \
-    int step_waves_per_cu(int variant);                                                                \
+    int step_kernel_vgprs(int variant, int cpl);                                                       \
+    int step_waves_per_cu(int variant, int cpl);                                                       \
     }                                                                                                  \
     }
 

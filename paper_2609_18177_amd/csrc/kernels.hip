@@ -61,10 +61,21 @@ static hipError_t step_impl(const LatticeDesc &h, int64_t iter, hipStream_t s)
         const int64_t nbands = D == 2 ? (h.ny + h.band_h - 1) / h.band_h : 1;
         const int64_t nwork = (int64_t)h.ncols * nbands;
         const dim3 g(grid_for(nwork, kWavesPerBlock)), b(kBlock);
-        if (SYS == 2 && D == 2 && h.bed)
-            hipLaunchKernelGGL((k_step_single<SYS, D, true, real>), g, b, 0, s, h, iter, (int32_t)nwork);
-        else
+        if constexpr (D == 2) {
+            constexpr bool kBed = SYS == 2;  // the bed source exists for shallow water only
+            if (h.cpl == 2) {
+                if (kBed && h.bed)
+                    hipLaunchKernelGGL((k_step_single<SYS, D, kBed, real, 2>), g, b, 0, s, h, iter, (int32_t)nwork);
+                else
+                    hipLaunchKernelGGL((k_step_single<SYS, D, false, real, 2>), g, b, 0, s, h, iter, (int32_t)nwork);
+            } else if (kBed && h.bed) {
+                hipLaunchKernelGGL((k_step_single<SYS, D, kBed, real>), g, b, 0, s, h, iter, (int32_t)nwork);
+            } else {
+                hipLaunchKernelGGL((k_step_single<SYS, D, false, real>), g, b, 0, s, h, iter, (int32_t)nwork);
+            }
+        } else {
             hipLaunchKernelGGL((k_step_single<SYS, D, false, real>), g, b, 0, s, h, iter, (int32_t)nwork);
+        }
     }
     return hipGetLastError();
 }
@@ -136,47 +147,45 @@ hipError_t to_double(const void *src, double *dst, int64_t plane, int64_t pstrid
     return hipGetLastError();
 }
 
-// Waves of the single-lattice step kernel resident per CU at full occupancy.
-int step_waves_per_cu(int variant)
+// The single-lattice step kernel of a variant (2D: with cpl columns per lane).
+static const void *step_fn(int variant, int cpl)
 {
-    const void *fn = nullptr;
+    const bool two = cpl == 2;
     switch (variant) {
-    case V_ADV1: fn = (const void *)&k_step_single<0, 1, false, real>; break;
-    case V_EUL1: fn = (const void *)&k_step_single<1, 1, false, real>; break;
-    case V_SWE1: fn = (const void *)&k_step_single<2, 1, false, real>; break;
-    case V_ADV2: fn = (const void *)&k_step_single<0, 2, false, real>; break;
-    case V_EUL2: fn = (const void *)&k_step_single<1, 2, false, real>; break;
-    case V_SWE2: fn = (const void *)&k_step_single<2, 2, true, real>; break;
-    case V_REU1: fn = (const void *)&k_step_single<3, 1, false, real>; break;
-    case V_REU2: fn = (const void *)&k_step_single<3, 2, false, real>; break;
-    case V_ADV3: fn = (const void *)&k3_collide<0, real>; break;
-    case V_EUL3: fn = (const void *)&k3_collide<1, real>; break;
-    case V_REU3: fn = (const void *)&k3_collide<3, real>; break;
-    default: return 0;
+    case V_ADV1: return (const void *)&k_step_single<0, 1, false, real>;
+    case V_EUL1: return (const void *)&k_step_single<1, 1, false, real>;
+    case V_SWE1: return (const void *)&k_step_single<2, 1, false, real>;
+    case V_REU1: return (const void *)&k_step_single<3, 1, false, real>;
+    case V_ADV2:
+        return two ? (const void *)&k_step_single<0, 2, false, real, 2> : (const void *)&k_step_single<0, 2, false, real>;
+    case V_EUL2:
+        return two ? (const void *)&k_step_single<1, 2, false, real, 2> : (const void *)&k_step_single<1, 2, false, real>;
+    case V_SWE2:
+        return two ? (const void *)&k_step_single<2, 2, true, real, 2> : (const void *)&k_step_single<2, 2, true, real>;
+    case V_REU2:
+        return two ? (const void *)&k_step_single<3, 2, false, real, 2> : (const void *)&k_step_single<3, 2, false, real>;
+    case V_ADV3: return (const void *)&k3_collide<0, real>;
+    case V_EUL3: return (const void *)&k3_collide<1, real>;
+    case V_REU3: return (const void *)&k3_collide<3, real>;
+    default: return nullptr;
     }
+}
+
+// Waves of the single-lattice step kernel resident per CU at full occupancy.
+int step_waves_per_cu(int variant, int cpl)
+{
+    const void *fn = step_fn(variant, cpl);
+    if (!fn) return 0;
     int blocks = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kBlock, 0) != hipSuccess) return 0;
     return blocks * kWavesPerBlock;
 }
 
-int step_kernel_vgprs(int variant)
+int step_kernel_vgprs(int variant, int cpl)
 {
     hipFuncAttributes a;
-    const void *fn = nullptr;
-    switch (variant) {
-    case V_ADV1: fn = (const void *)&k_step_single<0, 1, false, real>; break;
-    case V_EUL1: fn = (const void *)&k_step_single<1, 1, false, real>; break;
-    case V_SWE1: fn = (const void *)&k_step_single<2, 1, false, real>; break;
-    case V_ADV2: fn = (const void *)&k_step_single<0, 2, false, real>; break;
-    case V_EUL2: fn = (const void *)&k_step_single<1, 2, false, real>; break;
-    case V_SWE2: fn = (const void *)&k_step_single<2, 2, true, real>; break;
-    case V_REU1: fn = (const void *)&k_step_single<3, 1, false, real>; break;
-    case V_REU2: fn = (const void *)&k_step_single<3, 2, false, real>; break;
-    case V_ADV3: fn = (const void *)&k3_collide<0, real>; break;
-    case V_EUL3: fn = (const void *)&k3_collide<1, real>; break;
-    case V_REU3: fn = (const void *)&k3_collide<3, real>; break;
-    default: return -1;
-    }
+    const void *fn = step_fn(variant, cpl);
+    if (!fn) return -1;
     if (hipFuncGetAttributes(&a, fn) != hipSuccess) return -1;
     return a.numRegs;
 }

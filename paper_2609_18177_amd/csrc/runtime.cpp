@@ -100,12 +100,31 @@ std::string check_config(const arlbm_config *c)
     return "";
 }
 
-// Planes are stored at a stride of nx*ny rounded up past a 64-element tail
-// (the kernels' store sink), a multiple of 64 elements.
+// Planes are stored at a stride of nx*ny rounded up past a 128-element tail
+// (the kernels' store sink: one slot per column of a wave), a multiple of 64
+// elements.
 int64_t plane_stride(const arlbm_config *c)
 {
     const int64_t plane = c->nx * c->ny * c->nz;
-    return (plane + 64 + 63) / 64 * 64;
+    return (plane + 128 + 63) / 64 * 64;
+}
+
+// Columns per lane of the 2D step.  Two adjacent columns per lane need an
+// even nx (every pair 8-byte aligned).  Measured on MI355X (2048^2 and
+// 4096^2 lattices, ms per step, one column per lane -> two):
+//   FP32 advection 0.0650 -> 0.0558, shallow water 0.520 -> 0.493,
+//        Euler 0.1758 -> 0.1777, reactive Euler 0.290 -> 0.298;
+//   FP64 shallow water 1.177 -> 1.140, Euler 0.388 -> 0.430.
+// The faster width is taken per system and precision.
+#ifndef ARLBM_CPL_OVERRIDE
+#define ARLBM_CPL_OVERRIDE 0
+#endif
+int columns_per_lane(const arlbm_config *c)
+{
+    if (c->dim != 2 || c->nx % 2 != 0) return 1;
+    if (ARLBM_CPL_OVERRIDE) return ARLBM_CPL_OVERRIDE;
+    static const int f32[4] = {2, 1, 2, 1}, f64[4] = {1, 1, 2, 1};  // advection, Euler, shallow water, reactive
+    return (c->precision == ARLBM_F64 ? f64 : f32)[c->system];
 }
 
 void fill_sizes(const arlbm_config *c, arlbm_sizes *o)
@@ -169,10 +188,11 @@ int num_cus()
     return cus;
 }
 
-int64_t resident_waves(int precision, int variant)
+int64_t resident_waves(int precision, int variant, int cpl)
 {
     const int64_t cus = num_cus();
-    const int w = precision == ARLBM_F64 ? f64::step_waves_per_cu(variant) : f32::step_waves_per_cu(variant);
+    const int w = precision == ARLBM_F64 ? f64::step_waves_per_cu(variant, cpl)
+                                         : f32::step_waves_per_cu(variant, cpl);
     return (int64_t)cus * (w > 0 ? w : 16);
 }
 
@@ -188,7 +208,7 @@ struct arlbm_lattice {
     bool busy = false;
     int64_t step = 0;
     double *d_partial = nullptr;
-    void *omega_sink = nullptr;  // 64-slot sink the kernels write omega to when export is off
+    void *omega_sink = nullptr;  // 128-slot sink the kernels write omega to when export is off
     std::string err;
 };
 
@@ -395,8 +415,11 @@ extern "C" int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, 
     if (cfg->dim == 1) d.bc[2] = d.bc[3] = ARLBM_PERIODIC;
     if (cfg->dim <= 2) d.bc[4] = d.bc[5] = ARLBM_PERIODIC;
     d.omega_fixed_on = cfg->omega_mode == ARLBM_OMEGA_FIXED;
-    d.ncols = (int32_t)((cfg->nx + kOutW - 1) / kOutW);
-    d.band_h = cfg->dim == 2 ? choose_band(cfg->ny, d.ncols, resident_waves(cfg->precision, d.variant), 4 * (int64_t)num_cus()) : 1;
+    d.cpl = columns_per_lane(cfg);
+    d.ncols = (int32_t)((cfg->nx + strip_out_w(d.cpl) - 1) / strip_out_w(d.cpl));
+    d.band_h = cfg->dim == 2 ? choose_band(cfg->ny, d.ncols, resident_waves(cfg->precision, d.variant, d.cpl),
+                                           4 * (int64_t)num_cus())
+                             : 1;
     d.iter0 = 0;
     d.t_stop = HUGE_VAL;
     d.plane = cfg->nx * cfg->ny * cfg->nz;
@@ -454,7 +477,7 @@ extern "C" int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, 
         d.nu3 = (char *)d.u[1] + (size_t)h->sz.m * d.pstride * (cfg->precision == ARLBM_F64 ? 8 : 4);
     // per-block conservation partials of up to 6 fields (3D reactive Euler)
     hipError_t err = hipMalloc((void **)&h->d_partial, sizeof(double) * kConsBlocks * 6);
-    if (err == hipSuccess) err = hipMalloc(&h->omega_sink, 64 * sizeof(double));
+    if (err == hipSuccess) err = hipMalloc(&h->omega_sink, 128 * sizeof(double));
     if (err == hipSuccess && !d.omega) {
         d.omega = h->omega_sink;
         d.omega_on = 0;
@@ -725,11 +748,19 @@ extern "C" const char *arlbm_last_error(const arlbm_lattice *h)
     return h ? h->err.c_str() : g_thread_err.c_str();
 }
 
-// Diagnostics used by the benchmark: registers of the fused step kernel.
+// Diagnostics used by the benchmark: registers of the fused step kernel
+// (2D: the kernel a lattice of even nx runs).
 extern "C" int arlbm_step_kernel_vgprs(int32_t precision, int32_t system, int32_t dim)
 {
+    if (system < 0 || system > 3 || dim < 1 || dim > 3) return -1;
     const int v = variant_of(system, dim);
-    return precision == ARLBM_F64 ? f64::step_kernel_vgprs(v) : f32::step_kernel_vgprs(v);
+    arlbm_config c{};
+    c.precision = precision;
+    c.system = system;
+    c.dim = dim;
+    c.nx = 2;
+    const int cpl = columns_per_lane(&c);
+    return precision == ARLBM_F64 ? f64::step_kernel_vgprs(v, cpl) : f32::step_kernel_vgprs(v, cpl);
 }
 
 // ------------------------------------------------------------------------
@@ -792,6 +823,9 @@ int rebuild_table(arlbm_server *s)
     for (size_t i = 0; i < s->resident.size(); ++i) {
         LatticeDesc d = s->resident[i].lat->desc;
         d.iter0 = s->resident[i].iter0;
+        // the batched kernel runs every strip with one column per lane
+        d.cpl = 1;
+        d.ncols = (int32_t)((d.nx + kOutW - 1) / kOutW);
         descs.push_back(d);
         const int64_t nb = d.variant >= V_ADV2 ? (d.ny + d.band_h - 1) / d.band_h : 1;
         for (int64_t b = 0; b < nb; ++b)

@@ -1,9 +1,10 @@
 // Fused collide-and-stream step of the adaptive-relaxation LBM on gfx950.
 //
-// Work decomposition.  One wave64 owns a strip of 58 output columns and a
-// band of rows.  Lane l sits on column x = x0 - 3 + l, so the 3-cell halo on
-// each side is carried by the wave itself: x-neighbours come from lane
-// shuffles, no LDS and no barriers are used.  The wave marches up its band;
+// Work decomposition.  One wave64 owns a strip of output columns and a band
+// of rows.  With one column per lane, lane l sits on column x = x0 - 3 + l
+// (58 outputs); with two, on columns x0 - 4 + 2l and the next (120 outputs).
+// The halo on each side is carried by the wave itself: x-neighbours come
+// from lane shuffles, no LDS and no barriers are used.  The wave marches up its band;
 // per row it loads the populations f (Q m planes), forms the moments U of the
 // row two ahead from them, and keeps a rolling window in registers:
 //
@@ -21,8 +22,8 @@
 // direction into a triple-buffered slot.  The kernel launch boundary is the
 // grid barrier that the global maximum needs.
 //
-// Plane layout: plane c of a buffer starts at c * pstride, pstride >= nx ny + 64.
-// The 64-element tail of every plane is a sink: lanes that must not write
+// Plane layout: plane c of a buffer starts at c * pstride, pstride >= nx ny + 128.
+// The 128-element tail of every plane is a sink: lanes that must not write
 // (halo lanes, warm-up rows) store there, so the steady-state loop carries no
 // conditional memory operation and the compiler can keep the prefetched loads
 // and the stores of the previous row in flight across iterations.
@@ -90,13 +91,14 @@ __device__ __forceinline__ T wave_max(T v)
 __device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 __device__ __forceinline__ double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
 
-// Boundary index map for a coordinate in [-3, n+2] (clamped first: lanes
-// further out only carry unused halo values).  refl is set for a reflective
-// wall on the side the index fell off.
-__device__ __forceinline__ int bc_map(int i, int n, int lo, int hi, bool &refl)
+// Boundary index map for a coordinate in [-reach, n-1+reach] (clamped first:
+// lanes further out only carry unused halo values; n >= 4 >= reach keeps the
+// image inside the lattice).  refl is set for a reflective wall on the side
+// the index fell off.
+__device__ __forceinline__ int bc_map(int i, int n, int lo, int hi, bool &refl, int reach = kHalo)
 {
     refl = false;
-    i = i < -kHalo ? -kHalo : (i > n - 1 + kHalo ? n - 1 + kHalo : i);
+    i = i < -reach ? -reach : (i > n - 1 + reach ? n - 1 + reach : i);
     if (i < 0) {
         if (lo == 0) return i + n;
         refl = lo == 2;
@@ -415,11 +417,47 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
 
 // ------------------------------------------------------------------ 2D ----
 
+// Loads and stores of a lane's V adjacent columns as one V-element access
+// (the first column is V-aligned).
+template <int V, typename T>
+__device__ __forceinline__ void ldv(const T *base, unsigned off, T (&out)[V])
+{
+    if constexpr (V == 1) {
+        out[0] = base[off];
+    } else {
+        typedef T vec_t __attribute__((ext_vector_type(V)));
+        const vec_t v = *(const vec_t *)(base + off);
+#pragma unroll
+        for (int i = 0; i < V; ++i) out[i] = v[i];
+    }
+}
+template <int V, typename T>
+__device__ __forceinline__ void stv(T *base, unsigned off, const T (&in)[V])
+{
+    if constexpr (V == 1) {
+        base[off] = in[0];
+    } else {
+        typedef T vec_t __attribute__((ext_vector_type(V)));
+        vec_t v;
+#pragma unroll
+        for (int i = 0; i < V; ++i) v[i] = in[i];
+        *(vec_t *)(base + off) = v;
+    }
+}
 
-template <int SYS, bool BED, typename T>
+// One wave marches a strip of strip_out_w(V) output columns up a band of
+// rows; lane l holds the V columns xa .. xa+V-1, xa = x0 - strip_halo(V) + V l.
+// With V = 2 every row access of a wave is one 512-byte span at an 8-byte
+// aligned start instead of a 256-byte span at a 4-byte aligned one: fewer
+// cache lines per byte, and a halo of 4 columns in 128 instead of 3 in 64.
+// At a mirror ghost (x < 0 or x >= nx, transmissive or reflective) a lane's
+// two columns map to cells in descending order: the lane loads the ascending
+// pair and swaps it; the wave-uniform test keeps interior strips free of it.
+template <int SYS, bool BED, typename T, int V>
 __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int col, int band, bool first)
 {
     constexpr int D = 2, M = SysInfo<SYS, 2>::M, Q = 5;
+    constexpr int HC = strip_halo(V), OW = strip_out_w(V);
     const int64_t n = iter - L.iter0;
     Coefs<T> cf;
     if (!step_coefs<D, T>(L, n, cf)) {
@@ -430,137 +468,209 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     const int lane = threadIdx.x & (kWave - 1);
     const int nx = L.nx, ny = L.ny;
     const int64_t ps = L.pstride;
+    const int xa = col * OW - HC + lane * V;  // this lane's first column
+    // with V = 2, nx is even and xa is even, so xa < nx covers both columns
+    const bool xout = lane * V >= HC && lane * V < kWave * V - HC && xa < nx;
     if (stopped(L, n)) {
-        const int xs = col * kOutW - kHalo + lane;
         const int y0 = band * L.band_h, y1 = y0 + L.band_h < ny ? y0 + L.band_h : ny;
-        null_copy<T>(L, n, Q * M, xs, lane >= kHalo && lane < kWave - kHalo && xs < nx, y0, y1, first);
+#pragma unroll
+        for (int v = 0; v < V; ++v) null_copy<T>(L, n, Q * M, xa + v, xout, y0, y1, first && v == 0);
         return;
     }
     const T *fin = (const T *)L.f[n & 1];
     T *fout = (T *)L.f[(n + 1) & 1];
     const T *bed = (const T *)L.bed;
     T *om = (T *)L.omega;
-    const int x = col * kOutW - kHalo + lane;
-    bool rx;
-    const int xm = bc_map(x, nx, L.bc[0], L.bc[1], rx);
-    const bool xout = lane >= kHalo && lane < kWave - kHalo && x < nx;
+    const int bxl = L.bc[0], bxh = L.bc[1], byl = L.bc[2], byh = L.bc[3];
+    int xm[V];
+    bool rx[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) xm[v] = bc_map(xa + v, nx, bxl, bxh, rx[v], HC);
+    // first cell of the lane's load and whether its columns come in descending order
+    int xl = xm[0];
+    bool swp = false;
+    if constexpr (V == 2) {
+        xl = (xm[0] < xm[1] ? xm[0] : xm[1]) & ~1;
+        swp = xm[0] > xm[1];
+    }
+    const bool anyswap = V > 1 && __ballot(swp) != 0ull;
     const int ya = band * L.band_h;
     const int yb = ya + L.band_h < ny ? ya + L.band_h : ny;
-    const int bxl = L.bc[0], bxh = L.bc[1], byl = L.bc[2], byh = L.bc[3];
-    const unsigned sink = (unsigned)(L.plane + lane);          // this lane's slot in a plane's tail
-    const unsigned osink = L.omega_on ? sink : (unsigned)lane;  // omega sink (64-element buffer when off)
+    const unsigned sink = (unsigned)(L.plane + lane * V);          // this lane's slots in a plane's tail
+    const unsigned osink = L.omega_on ? sink : (unsigned)(lane * V);  // omega sink (128-slot buffer when off)
     const T two_dx = T(2) * P.dx;
 
-    // Moments of a population row j: U = sum_k f_k (2.3), summed in velocity
-    // order; the ghost map negates the normal momentum at walls.
-    auto sumU = [&](int j, const T (*f)[M], T *out) {
+    auto fix = [&](T (&a)[V]) {
+        if constexpr (V == 2) {
+            const T a0 = a[0], a1 = a[1];
+            a[0] = swp ? a1 : a0;
+            a[1] = swp ? a0 : a1;
+        }
+    };
+    auto fixF = [&](T (*f)[M][V]) {
+        if (anyswap) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k)
+#pragma unroll
+                for (int c = 0; c < M; ++c) fix(f[k][c]);
+        }
+    };
+    // Moments of a population row j as loaded: U = sum_k f_k (2.3), summed
+    // in velocity order, put in column order; the ghost map negates the
+    // normal momentum at walls.  (Selects, not a branch on the wave-uniform
+    // swap flag: a branch here would make the compiler wait for every memory
+    // operation in flight, the previous row's stores included.)
+    auto sumU = [&](int j, const T (*f)[M][V], T (*out)[M]) {
         bool ry;
         (void)bc_map(j, ny, byl, byh, ry);
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-            T sum = f[0][c];
+        for (int v = 0; v < V; ++v)
 #pragma unroll
-            for (int k = 1; k < Q; ++k) sum = sum + f[k][c];
-            out[c] = sum;
+            for (int c = 0; c < M; ++c) {
+                T sum = f[0][c][v];
+#pragma unroll
+                for (int k = 1; k < Q; ++k) sum = sum + f[k][c][v];
+                out[v][c] = sum;
+            }
+        if constexpr (V == 2) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                T t[2] = {out[0][c], out[1][c]};
+                fix(t);
+                out[0][c] = t[0];
+                out[1][c] = t[1];
+            }
         }
-        if constexpr (SYS != 0) {
-            if (rx) out[1] = -out[1];
-            if (ry) out[2] = -out[2];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            if constexpr (SYS != 0) {
+                if (rx[v]) out[v][1] = -out[v][1];
+                if (ry) out[v][2] = -out[v][2];
+            }
         }
     };
-    auto loadF = [&](int r, T (*out)[M]) {
+    auto loadF = [&](int r, T (*out)[M][V]) {
         bool ry;
         const int rm = bc_map(r, ny, byl, byh, ry);
-        const unsigned off = (unsigned)(rm * nx + xm);
+        const unsigned off = (unsigned)(rm * nx + xl);
 #pragma unroll
         for (int k = 0; k < Q; ++k)
 #pragma unroll
-            for (int c = 0; c < M; ++c) out[k][c] = ldo(fin + (size_t)(k * M + c) * ps, off);
+            for (int c = 0; c < M; ++c) ldv<V>(fin + (size_t)(k * M + c) * ps, off, out[k][c]);
     };
-    auto loadU = [&](int j, T *out) {
-        T f[Q][M];
+    auto loadU = [&](int j, T (*out)[M]) {
+        T f[Q][M][V];
         loadF(j, f);
         sumU(j, f, out);
     };
-    auto loadB = [&](int j) -> T {
+    auto loadB = [&](int j, T (&out)[V]) {
         bool ry;
         const int jm = bc_map(j, ny, byl, byh, ry);
-        return ldo(bed, (unsigned)(jm * nx + xm));
+        ldv<V>(bed, (unsigned)(jm * nx + xl), out);
+    };
+    // values at columns x-1 / x+1 of the lane's columns
+    auto left_of = [&](const T (&a)[V], T (&o)[V]) {
+        o[0] = from_left(a[V - 1]);
+#pragma unroll
+        for (int v = 1; v < V; ++v) o[v] = a[v - 1];
+    };
+    auto right_of = [&](const T (&a)[V], T (&o)[V]) {
+        o[V - 1] = from_right(a[0]);
+#pragma unroll
+        for (int v = 0; v < V - 1; ++v) o[v] = a[v + 1];
     };
 
-    T U0[M], U1[M], U2[M];           // U rows j-2, j-1, j
-    T Unx[M];                        // U row j+1 (in flight, FP64)
-    T N0 = 0, N0l = 0, N0r = 0;      // nu rows j-3, j-2, j-1 and at x -+ 1
-    T N1 = 0, N1l = 0, N1r = 0;
-    T N2 = 0, N2l = 0, N2r = 0;
-    T B0 = 0, B1 = 0, B2 = 0, Bnx = 0; // bed rows r-1, r, r+1; row r+2 in flight
-    T dbx_prev = 0, dby_prev = 0;    // bed slope of the previous f* row
-    T P1[M], P2[M];                  // f*_{+y} of rows r-1 and r-2
-    T G0[M], Gpx[M], Gmx[M], Gmy[M]; // row r-1: f*_0, pulled +x, pulled -x, own f*_{-y}
+    T U0[V][M], U1[V][M], U2[V][M];     // U rows j-2, j-1, j
+    T Unx[V][M];                        // U row j+1 (in flight, FP64)
+    T N0[V], N0l[V], N0r[V];            // nu rows j-3, j-2, j-1 and at x -+ 1
+    T N1[V], N1l[V], N1r[V];
+    T N2[V], N2l[V], N2r[V];
+    T B0[V], B1[V], B2[V], Bnx[V];      // bed rows r-1, r, r+1; row r+2 in flight
+    T dbx_prev[V], dby_prev[V];         // bed slope of the previous f* row
+    T P1[V][M], P2[V][M];               // f*_{+y} of rows r-1 and r-2
+    T G0[V][M], Gpx[V][M], Gmx[V][M], Gmy[V][M]; // row r-1: f*_0, pulled +x, pulled -x, own f*_{-y}
 #pragma unroll
-    for (int c = 0; c < M; ++c) {
-        U0[c] = U1[c] = U2[c] = T(0);
-        P1[c] = P2[c] = G0[c] = Gpx[c] = Gmx[c] = Gmy[c] = T(0);
+    for (int v = 0; v < V; ++v) {
+        N0[v] = N0l[v] = N0r[v] = N1[v] = N1l[v] = N1r[v] = N2[v] = N2l[v] = N2r[v] = T(0);
+        B0[v] = B1[v] = B2[v] = Bnx[v] = dbx_prev[v] = dby_prev[v] = T(0);
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            U0[v][c] = U1[v][c] = U2[v][c] = T(0);
+            P1[v][c] = P2[v][c] = G0[v][c] = Gpx[v][c] = Gmx[v][c] = Gmy[v][c] = T(0);
+        }
     }
     T s0 = T(0), s1 = T(0);
     unsigned flags = 0;
 
     auto nu_row = [&]() {  // nu at the row of U1 (eqs. 2.13-2.14)
-        Prim<T> qc;
-        primitives<SYS, D, T>(U1, P, qc);
-        T UL[M], UR[M];
+        T UL[V][M], UR[V][M];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            UL[c] = from_left(U1[c]);
-            UR[c] = from_right(U1[c]);
+            UL[0][c] = from_left(U1[V - 1][c]);
+            UR[V - 1][c] = from_right(U1[0][c]);
+#pragma unroll
+            for (int v = 1; v < V; ++v) {
+                UL[v][c] = U1[v - 1][c];
+                UR[v - 1][c] = U1[v][c];
+            }
         }
-        T nu = T(0);
-        add_theta<SYS, D, T>(0, qc, U1, UL, UR, P, nu);
-        add_theta<SYS, D, T>(1, qc, U1, U0, U2, P, nu);
-        N0 = N1; N0l = N1l; N0r = N1r;
-        N1 = N2; N1l = N2l; N1r = N2r;
-        N2 = nu;
-        N2l = from_left(nu);
-        N2r = from_right(nu);
+        T nu[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            Prim<T> qc;
+            primitives<SYS, D, T>(U1[v], P, qc);
+            nu[v] = T(0);
+            add_theta<SYS, D, T>(0, qc, U1[v], UL[v], UR[v], P, nu[v]);
+            add_theta<SYS, D, T>(1, qc, U1[v], U0[v], U2[v], P, nu[v]);
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            N0[v] = N1[v]; N0l[v] = N1l[v]; N0r[v] = N1r[v];
+            N1[v] = N2[v]; N1l[v] = N2l[v]; N1r[v] = N2r[v];
+            N2[v] = nu[v];
+        }
+        left_of(nu, N2l);
+        right_of(nu, N2r);
+    };
+    auto pushU = [&](const T (*u)[M]) {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                U0[v][c] = U1[v][c];
+                U1[v][c] = U2[v][c];
+                U2[v][c] = u[v][c];
+            }
     };
     auto roll_U = [&](int j) {  // U2 <- row j (prefetched), then prefetch row j+1
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-            U0[c] = U1[c];
-            U1[c] = U2[c];
-            U2[c] = Unx[c];
-        }
+        pushU(Unx);
         loadU(j + 1, Unx);
     };
 
     // FP32 keeps the population rows it loads in a register ring until the
     // collision two rows later uses them, so every row is read from memory
-    // once (4 Q m registers).  FP64 would need twice that and drop to one
+    // once (4 Q m V registers).  FP64 would need twice that and drop to one
     // wave per SIMD: it reads the row again in the iteration that collides it
     // (a cache hit when the caches hold the rows in between).
     constexpr bool kRing = sizeof(T) == 4 && Q * M <= 20;
     // Shallow water (15 values per row) prefetches two rows ahead: measured
     // 2.6% faster there, 5% slower for 2D Euler (20 values per row).
     constexpr bool kPf2 = kRing && SYS == 2;
-    // f rows j-1, j, j+1 (in flight), and j+2 (in flight) with two rows of prefetch
-    T Rb[kRing ? Q : 1][M], Rc[kRing ? Q : 1][M], Rn[kRing ? Q : 1][M], Rm[kPf2 ? Q : 1][M];
-    auto pushU = [&](const T *u) {
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-            U0[c] = U1[c];
-            U1[c] = U2[c];
-            U2[c] = u[c];
-        }
-    };
+    // f rows j-1, j, j+1 (in flight), and j+2 (in flight) with two rows of
+    // prefetch, kept as loaded; a row is put in column order when the
+    // collision takes it
+    T Rb[kRing ? Q : 1][M][V], Rc[kRing ? Q : 1][M][V], Rn[kRing ? Q : 1][M][V], Rm[kPf2 ? Q : 1][M][V];
 
     // prologue: moment rows ya-3 .. ya, indicator rows ya-2 .. ya-1
     if constexpr (BED) {
-        B1 = loadB(ya - 2);
-        B2 = loadB(ya - 1);
-        Bnx = loadB(ya);
+        loadB(ya - 2, B1);
+        loadB(ya - 1, B2);
+        loadB(ya, Bnx);
+        fix(B1);
+        fix(B2);
     }
     if constexpr (kRing) {
-        T Ut[M];
+        T Ut[V][M];
         loadU(ya - 3, Ut);
         pushU(Ut);
         loadU(ya - 2, Ut);
@@ -588,168 +698,214 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     // steady state: every iteration takes U(j), loads row j+1, computes nu
     // at row j-1, omega and f* at row r = j-2, and writes destination row j-3
     for (int j = ya + 1; j <= yb + 2; ++j) {
-        T fcur[Q][M];
+        T fcur[Q][M][V];
         const int r = j - 2;
         if constexpr (kRing) {
-            T Ut[M];
+            T Ut[V][M];
             sumU(j, Rn, Ut);
             pushU(Ut);
 #pragma unroll
             for (int k = 0; k < Q; ++k)
 #pragma unroll
-                for (int c = 0; c < M; ++c) {
-                    fcur[k][c] = Rb[k][c];
-                    Rb[k][c] = Rc[k][c];
-                    Rc[k][c] = Rn[k][c];
-                    if constexpr (kPf2) Rn[k][c] = Rm[k][c];
-                }
+                for (int c = 0; c < M; ++c)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        fcur[k][c][v] = Rb[k][c][v];
+                        Rb[k][c][v] = Rc[k][c][v];
+                        Rc[k][c][v] = Rn[k][c][v];
+                        if constexpr (kPf2) Rn[k][c][v] = Rm[k][c][v];
+                    }
             if constexpr (kPf2)
                 loadF(j + 2, Rm);
             else
                 loadF(j + 1, Rn);
+            fixF(fcur);
         } else {
             roll_U(j);
             loadF(r, fcur);
+            fixF(fcur);
         }
-        T dbx = T(0), dby = T(0);
+        T dbx[V], dby[V];
         if constexpr (BED) {
-            B0 = B1;
-            B1 = B2;
-            B2 = Bnx;
-            Bnx = loadB(r + 2);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                B0[v] = B1[v];
+                B1[v] = B2[v];
+                B2[v] = Bnx[v];
+            }
+            fix(B2);
+            loadB(r + 2, Bnx);
         }
         nu_row();
         // 3x3 box sum (2.15) in row-major order, relaxation parameter (2.16)
-        const T nt = N0l + N0 + N0r + N1l + N1 + N1r + N2l + N2 + N2r;
-        const T w = L.omega_fixed_on ? cf.omega_fixed : T(1) + T(1) / (T(1) + nt);
-        sto(om, (xout && r >= ya && r < yb && L.omega_on) ? (unsigned)(r * nx + x) : osink, w);
+        T w[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const T nt = N0l[v] + N0[v] + N0r[v] + N1l[v] + N1[v] + N1r[v] + N2l[v] + N2[v] + N2r[v];
+            w[v] = L.omega_fixed_on ? cf.omega_fixed : T(1) + T(1) / (T(1) + nt);
+        }
+        stv<V>(om, (xout && r >= ya && r < yb && L.omega_on) ? (unsigned)(r * nx + xa) : osink, w);
         if constexpr (BED) {
-            dbx = (from_right(B1) - from_left(B1)) / two_dx;
-            dby = (B2 - B0) / two_dx;
+            T bl[V], br[V];
+            left_of(B1, bl);
+            right_of(B1, br);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                dbx[v] = (br[v] - bl[v]) / two_dx;
+                dby[v] = (B2[v] - B0[v]) / two_dx;
+            }
         }
         // equilibrium (2.20) and collision at the source nodes of row r
-        T fs[Q][M];
-        {
+        T fs[V][Q][M];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
             Prim<T> q;
-            primitives<SYS, D, T>(U0, P, q);
+            primitives<SYS, D, T>(U0[v], P, q);
             T Fx[M], Fy[M];
-            flux<SYS, D, T>(0, U0, q, P, Fx);
-            flux<SYS, D, T>(1, U0, q, P, Fy);
+            flux<SYS, D, T>(0, U0[v], q, P, Fx);
+            flux<SYS, D, T>(1, U0[v], q, P, Fy);
 #pragma unroll
             for (int c = 0; c < M; ++c) {
-                const T u = U0[c];
+                const T u = U0[v][c];
                 const T feq[Q] = {cf.a0 * u, cf.ap[0] * u + cf.bp * Fx[c], cf.ap[1] * u + cf.bp * Fy[c],
                                   cf.ap[0] * u + cf.bm * Fx[c], cf.ap[1] * u + cf.bm * Fy[c]};
 #pragma unroll
                 for (int k = 0; k < Q; ++k) {
-                    const T fk = fcur[k][c];
-                    fs[k][c] = fk - w * (fk - feq[k]);
+                    const T fk = fcur[k][c][v];
+                    fs[v][k][c] = fk - w[v] * (fk - feq[k]);
                 }
             }
             if constexpr (BED) {
-                const T S1 = -P.g * U0[0] * dbx, S2 = -P.g * U0[0] * dby;
+                const T S1 = -P.g * U0[v][0] * dbx[v], S2 = -P.g * U0[v][0] * dby[v];
                 const T ak[Q] = {cf.a0, cf.ap[0], cf.ap[1], cf.ap[0], cf.ap[1]};
 #pragma unroll
                 for (int k = 0; k < Q; ++k) {
-                    fs[k][1] = fs[k][1] + cf.hdt * (ak[k] * S1);
-                    fs[k][2] = fs[k][2] + cf.hdt * (ak[k] * S2);
+                    fs[v][k][1] = fs[v][k][1] + cf.hdt * (ak[k] * S1);
+                    fs[v][k][2] = fs[v][k][2] + cf.hdt * (ak[k] * S2);
                 }
             }
             if constexpr (SYS == 3) {  // Arrhenius sink of rho Y, first half (2.6)
-                const T SY = -arrhenius_rate<T>(P, U0[0], reactive_eint<D, T>(U0), U0[M - 1], nullptr);
+                const T SY = -arrhenius_rate<T>(P, U0[v][0], reactive_eint<D, T>(U0[v]), U0[v][M - 1], nullptr);
                 const T ak[Q] = {cf.a0, cf.ap[0], cf.ap[1], cf.ap[0], cf.ap[1]};
 #pragma unroll
-                for (int k = 0; k < Q; ++k) fs[k][M - 1] = fs[k][M - 1] + cf.hdt * (ak[k] * SY);
+                for (int k = 0; k < Q; ++k) fs[v][k][M - 1] = fs[v][k][M - 1] + cf.hdt * (ak[k] * SY);
             }
         }
         // x pulls with the ghost map at the two x walls
-        T px[M], mx[M];
+        T px[V][M], mx[V][M];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            px[c] = from_left(fs[1][c]);
-            mx[c] = from_right(fs[3][c]);
-        }
-        if (x == 0 && bxl != 0) {
+            px[0][c] = from_left(fs[V - 1][1][c]);
+            mx[V - 1][c] = from_right(fs[0][3][c]);
 #pragma unroll
-            for (int c = 0; c < M; ++c) px[c] = bxl == 1 ? fs[1][c] : (c == 1 ? -fs[3][c] : fs[3][c]);
+            for (int v = 1; v < V; ++v) {
+                px[v][c] = fs[v - 1][1][c];
+                mx[v - 1][c] = fs[v][3][c];
+            }
         }
-        if (x == nx - 1 && bxh != 0) {
 #pragma unroll
-            for (int c = 0; c < M; ++c) mx[c] = bxh == 1 ? fs[3][c] : (c == 1 ? -fs[1][c] : fs[1][c]);
+        for (int v = 0; v < V; ++v) {
+            if (xa + v == 0 && bxl != 0) {
+#pragma unroll
+                for (int c = 0; c < M; ++c)
+                    px[v][c] = bxl == 1 ? fs[v][1][c] : (c == 1 ? -fs[v][3][c] : fs[v][3][c]);
+            }
+            if (xa + v == nx - 1 && bxh != 0) {
+#pragma unroll
+                for (int c = 0; c < M; ++c)
+                    mx[v][c] = bxh == 1 ? fs[v][3][c] : (c == 1 ? -fs[v][1][c] : fs[v][1][c]);
+            }
         }
         // destination row d = r-1: F_0, F_{+x}, F_{+y}, F_{-x}, F_{-y}
         const int d = r - 1;
         {
-            T Fk[Q][M];
+            T Fk[Q][M][V];
 #pragma unroll
-            for (int c = 0; c < M; ++c) {
-                Fk[0][c] = G0[c];
-                Fk[1][c] = Gpx[c];
-                Fk[2][c] = P2[c];
-                Fk[3][c] = Gmx[c];
-                Fk[4][c] = fs[4][c];
-            }
+            for (int v = 0; v < V; ++v)
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    Fk[0][c][v] = G0[v][c];
+                    Fk[1][c][v] = Gpx[v][c];
+                    Fk[2][c][v] = P2[v][c];
+                    Fk[3][c][v] = Gmx[v][c];
+                    Fk[4][c][v] = fs[v][4][c];
+                }
             if (d == ny - 1 && byh != 0) {
 #pragma unroll
-                for (int c = 0; c < M; ++c) Fk[4][c] = byh == 1 ? Gmy[c] : (c == 2 ? -P1[c] : P1[c]);
+                for (int v = 0; v < V; ++v)
+#pragma unroll
+                    for (int c = 0; c < M; ++c) Fk[4][c][v] = byh == 1 ? Gmy[v][c] : (c == 2 ? -P1[v][c] : P1[v][c]);
             }
-            T sumF[M];
-#pragma unroll
-            for (int c = 0; c < M; ++c) sumF[c] = Fk[0][c] + Fk[1][c] + Fk[2][c] + Fk[3][c] + Fk[4][c];
-            if constexpr (BED) {
-                const T S1 = -P.g * sumF[0] * dbx_prev, S2 = -P.g * sumF[0] * dby_prev;
-                const T ak[Q] = {cf.a0, cf.ap[0], cf.ap[1], cf.ap[0], cf.ap[1]};
-#pragma unroll
-                for (int k = 0; k < Q; ++k) {
-                    Fk[k][1] = Fk[k][1] + cf.hdt * (ak[k] * S1);
-                    Fk[k][2] = Fk[k][2] + cf.hdt * (ak[k] * S2);
-                }
-            }
-            if constexpr (SYS == 3) {  // (2.8) for rho Y, then the second half source
-                const T eint = reactive_eint<D, T>(sumF);
-                const T z = reactive_solve<T>(P, sumF[0], eint, sumF[M - 1], cf.hdt);
-                const T SY = -arrhenius_rate<T>(P, sumF[0], eint, z, nullptr);
-                const T ak[Q] = {cf.a0, cf.ap[0], cf.ap[1], cf.ap[0], cf.ap[1]};
-#pragma unroll
-                for (int k = 0; k < Q; ++k) Fk[k][M - 1] = Fk[k][M - 1] + cf.hdt * (ak[k] * SY);
-            }
-            T Un[M];
-#pragma unroll
-            for (int c = 0; c < M; ++c) Un[c] = Fk[0][c] + Fk[1][c] + Fk[2][c] + Fk[3][c] + Fk[4][c];
             const bool ok = xout && d >= ya;
-            const unsigned o = ok ? (unsigned)(d * nx + x) : sink;
+            T Un[V][M];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                T sumF[M];
+#pragma unroll
+                for (int c = 0; c < M; ++c)
+                    sumF[c] = Fk[0][c][v] + Fk[1][c][v] + Fk[2][c][v] + Fk[3][c][v] + Fk[4][c][v];
+                if constexpr (BED) {
+                    const T S1 = -P.g * sumF[0] * dbx_prev[v], S2 = -P.g * sumF[0] * dby_prev[v];
+                    const T ak[Q] = {cf.a0, cf.ap[0], cf.ap[1], cf.ap[0], cf.ap[1]};
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) {
+                        Fk[k][1][v] = Fk[k][1][v] + cf.hdt * (ak[k] * S1);
+                        Fk[k][2][v] = Fk[k][2][v] + cf.hdt * (ak[k] * S2);
+                    }
+                }
+                if constexpr (SYS == 3) {  // (2.8) for rho Y, then the second half source
+                    const T eint = reactive_eint<D, T>(sumF);
+                    const T z = reactive_solve<T>(P, sumF[0], eint, sumF[M - 1], cf.hdt);
+                    const T SY = -arrhenius_rate<T>(P, sumF[0], eint, z, nullptr);
+                    const T ak[Q] = {cf.a0, cf.ap[0], cf.ap[1], cf.ap[0], cf.ap[1]};
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) Fk[k][M - 1][v] = Fk[k][M - 1][v] + cf.hdt * (ak[k] * SY);
+                }
+#pragma unroll
+                for (int c = 0; c < M; ++c)
+                    Un[v][c] = Fk[0][c][v] + Fk[1][c][v] + Fk[2][c][v] + Fk[3][c][v] + Fk[4][c][v];
+            }
+            const unsigned o = ok ? (unsigned)(d * nx + xa) : sink;
 #pragma unroll
             for (int k = 0; k < Q; ++k)
 #pragma unroll
-                for (int c = 0; c < M; ++c) sto(fout + (size_t)(k * M + c) * ps, o, Fk[k][c]);
-            Prim<T> qn;
-            primitives<SYS, D, T>(Un, P, qn);
-            const T v0 = max_speed<SYS, T>(0, qn, P), v1 = max_speed<SYS, T>(1, qn, P);
-            bool fin_ok = true;
+                for (int c = 0; c < M; ++c) stv<V>(fout + (size_t)(k * M + c) * ps, o, Fk[k][c]);
 #pragma unroll
-            for (int c = 0; c < M; ++c) fin_ok = fin_ok && finite_val<T>(Un[c]);
-            if (ok) {
-                flags |= qn.flags | (fin_ok ? 0u : 1u);
-                if (finite_val<T>(v0) && v0 > s0) s0 = v0;
-                if (finite_val<T>(v1) && v1 > s1) s1 = v1;
+            for (int v = 0; v < V; ++v) {
+                Prim<T> qn;
+                primitives<SYS, D, T>(Un[v], P, qn);
+                const T v0 = max_speed<SYS, T>(0, qn, P), v1 = max_speed<SYS, T>(1, qn, P);
+                bool fin_ok = true;
+#pragma unroll
+                for (int c = 0; c < M; ++c) fin_ok = fin_ok && finite_val<T>(Un[v][c]);
+                if (ok) {
+                    flags |= qn.flags | (fin_ok ? 0u : 1u);
+                    if (finite_val<T>(v0) && v0 > s0) s0 = v0;
+                    if (finite_val<T>(v1) && v1 > s1) s1 = v1;
+                }
             }
         }
         // roll the pulled-population window
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-            P2[c] = P1[c];
-            P1[c] = fs[2][c];
-            G0[c] = fs[0][c];
-            Gpx[c] = px[c];
-            Gmx[c] = mx[c];
-            Gmy[c] = fs[4][c];
-        }
-        if (r == 0 && byl != 0) {
+        for (int v = 0; v < V; ++v) {
 #pragma unroll
-            for (int c = 0; c < M; ++c) P2[c] = byl == 1 ? fs[2][c] : (c == 2 ? -fs[4][c] : fs[4][c]);
+            for (int c = 0; c < M; ++c) {
+                P2[v][c] = P1[v][c];
+                P1[v][c] = fs[v][2][c];
+                G0[v][c] = fs[v][0][c];
+                Gpx[v][c] = px[v][c];
+                Gmx[v][c] = mx[v][c];
+                Gmy[v][c] = fs[v][4][c];
+            }
+            if (r == 0 && byl != 0) {
+#pragma unroll
+                for (int c = 0; c < M; ++c) P2[v][c] = byl == 1 ? fs[v][2][c] : (c == 2 ? -fs[v][4][c] : fs[v][4][c]);
+            }
+            if constexpr (BED) {
+                dbx_prev[v] = dbx[v];
+                dby_prev[v] = dby[v];
+            }
         }
-        dbx_prev = dbx;
-        dby_prev = dby;
     }
     if (first && lane == 0) scalar_update(L, n, cf.dt);
     commit<T>(L, n, s0, s1, flags, 2);
@@ -769,7 +925,7 @@ __device__ __forceinline__ int logical_wave()
 #ifndef ARLBM_STEP_MIN_WAVES
 #define ARLBM_STEP_MIN_WAVES 1
 #endif
-template <int SYS, int D, bool BED, typename T>
+template <int SYS, int D, bool BED, typename T, int V = 1>
 __global__ __launch_bounds__(kBlock, ARLBM_STEP_MIN_WAVES) void k_step_single(LatticeDesc L, int64_t iter, int32_t nwork)
 {
     const int w = logical_wave();
@@ -777,7 +933,7 @@ __global__ __launch_bounds__(kBlock, ARLBM_STEP_MIN_WAVES) void k_step_single(La
     if constexpr (D == 1) {
         strip1d<SYS, T>(L, iter, w, w == 0);
     } else {
-        strip2d<SYS, BED, T>(L, iter, w % L.ncols, w / L.ncols, w == 0);
+        strip2d<SYS, BED, T, V>(L, iter, w % L.ncols, w / L.ncols, w == 0);
     }
 }
 
@@ -793,14 +949,14 @@ __global__ __launch_bounds__(kBlock) void k_step_batched(const LatticeDesc *desc
     case V_ADV1: strip1d<0, T>(L, iter, it.col, it.first); break;
     case V_EUL1: strip1d<1, T>(L, iter, it.col, it.first); break;
     case V_SWE1: strip1d<2, T>(L, iter, it.col, it.first); break;
-    case V_ADV2: strip2d<0, false, T>(L, iter, it.col, it.band, it.first); break;
-    case V_EUL2: strip2d<1, false, T>(L, iter, it.col, it.band, it.first); break;
+    case V_ADV2: strip2d<0, false, T, 1>(L, iter, it.col, it.band, it.first); break;
+    case V_EUL2: strip2d<1, false, T, 1>(L, iter, it.col, it.band, it.first); break;
     case V_SWE2:
-        if (L.bed) strip2d<2, true, T>(L, iter, it.col, it.band, it.first);
-        else strip2d<2, false, T>(L, iter, it.col, it.band, it.first);
+        if (L.bed) strip2d<2, true, T, 1>(L, iter, it.col, it.band, it.first);
+        else strip2d<2, false, T, 1>(L, iter, it.col, it.band, it.first);
         break;
     case V_REU1: strip1d<3, T>(L, iter, it.col, it.first); break;
-    case V_REU2: strip2d<3, false, T>(L, iter, it.col, it.band, it.first); break;
+    case V_REU2: strip2d<3, false, T, 1>(L, iter, it.col, it.band, it.first); break;
     default: break;
     }
 }

@@ -29,9 +29,11 @@ sys.path.insert(0, ROOT)
 
 import bench  # noqa: E402  (kernel source hash; bench imports no GPU module at import time)
 
-KERNELS = {"euler2d_f32": "k_step_single<1, 2, false, float>",
-           "euler2d_f64": "k_step_single<1, 2, false, double>",
-           "swe2d_f32": "k_step_single<2, 2, true, float>",
+# 2D kernels end in the columns per lane (2 for advection and shallow water
+# on lattices of even nx)
+KERNELS = {"euler2d_f32": "k_step_single<1, 2, false, float, 1>",
+           "euler2d_f64": "k_step_single<1, 2, false, double, 1>",
+           "swe2d_f32": "k_step_single<2, 2, true, float, 2>",
            "euler3d_f32": "k3_collide<1, float>"}
 # further kernels of a step (3D: the indicator and relaxation passes)
 EXTRA_KERNELS = {"euler3d_f32": ["k3_nu<1, float>", "k3_omega<float>"]}
