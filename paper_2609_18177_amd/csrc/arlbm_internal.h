@@ -64,9 +64,11 @@ struct LatticeDesc {
     int64_t iter0;
     double t_stop;        // a launch whose state time is >= t_stop copies f unchanged (null step)
     int64_t plane;        // nx * ny * nz
-    int64_t pstride;      // elements between planes: plane + a 128-element sink tail
+    int64_t pstride;      // elements between planes: plane + a sink tail of 64 cpl elements
     int32_t omega_on;     // omega export plane present (else omega is a 128-slot sink)
     int32_t cpl;          // 2D: columns per lane of the step's strips (1, or 2 when nx is even)
+    int32_t buf;          // 2D: population buffers below 4 GiB, addressed by buffer resources
+    int32_t pad_;
     double dx, cfl, eps, gamma, g, adv[3], h_dry, rho_floor, p_floor, omega_fixed;
     double q_heat, k_rate, t_act;  // reactive Euler: heat release, rate constant, activation temperature
     void *nu3;                     // 3D: padded indicator (nx+2)(ny+2)(nz+2), then omega of the cells

@@ -63,16 +63,20 @@ static hipError_t step_impl(const LatticeDesc &h, int64_t iter, hipStream_t s)
         const dim3 g(grid_for(nwork, kWavesPerBlock)), b(kBlock);
         if constexpr (D == 2) {
             constexpr bool kBed = SYS == 2;  // the bed source exists for shallow water only
+            const bool bed = kBed && h.bed;
+#define ARLBM_L2(BED, V, BUF) hipLaunchKernelGGL((k_step_single<SYS, D, BED, real, V, BUF>), g, b, 0, s, h, iter, (int32_t)nwork)
             if (h.cpl == 2) {
-                if (kBed && h.bed)
-                    hipLaunchKernelGGL((k_step_single<SYS, D, kBed, real, 2>), g, b, 0, s, h, iter, (int32_t)nwork);
-                else
-                    hipLaunchKernelGGL((k_step_single<SYS, D, false, real, 2>), g, b, 0, s, h, iter, (int32_t)nwork);
-            } else if (kBed && h.bed) {
-                hipLaunchKernelGGL((k_step_single<SYS, D, kBed, real>), g, b, 0, s, h, iter, (int32_t)nwork);
+                if (h.buf) {
+                    if (bed) ARLBM_L2(kBed, 2, true); else ARLBM_L2(false, 2, true);
+                } else {
+                    if (bed) ARLBM_L2(kBed, 2, false); else ARLBM_L2(false, 2, false);
+                }
+            } else if (h.buf) {
+                if (bed) ARLBM_L2(kBed, 1, true); else ARLBM_L2(false, 1, true);
             } else {
-                hipLaunchKernelGGL((k_step_single<SYS, D, false, real>), g, b, 0, s, h, iter, (int32_t)nwork);
+                if (bed) ARLBM_L2(kBed, 1, false); else ARLBM_L2(false, 1, false);
             }
+#undef ARLBM_L2
         } else {
             hipLaunchKernelGGL((k_step_single<SYS, D, false, real>), g, b, 0, s, h, iter, (int32_t)nwork);
         }
@@ -147,23 +151,25 @@ hipError_t to_double(const void *src, double *dst, int64_t plane, int64_t pstrid
     return hipGetLastError();
 }
 
-// The single-lattice step kernel of a variant (2D: with cpl columns per lane).
+// The single-lattice step kernel of a variant (2D: with cpl columns per lane,
+// buffer-resource addressing).
+template <int SYS, bool BED>
+static const void *step_fn2(int cpl)
+{
+    return cpl == 2 ? (const void *)&k_step_single<SYS, 2, BED, real, 2, true>
+                    : (const void *)&k_step_single<SYS, 2, BED, real, 1, true>;
+}
 static const void *step_fn(int variant, int cpl)
 {
-    const bool two = cpl == 2;
     switch (variant) {
     case V_ADV1: return (const void *)&k_step_single<0, 1, false, real>;
     case V_EUL1: return (const void *)&k_step_single<1, 1, false, real>;
     case V_SWE1: return (const void *)&k_step_single<2, 1, false, real>;
     case V_REU1: return (const void *)&k_step_single<3, 1, false, real>;
-    case V_ADV2:
-        return two ? (const void *)&k_step_single<0, 2, false, real, 2> : (const void *)&k_step_single<0, 2, false, real>;
-    case V_EUL2:
-        return two ? (const void *)&k_step_single<1, 2, false, real, 2> : (const void *)&k_step_single<1, 2, false, real>;
-    case V_SWE2:
-        return two ? (const void *)&k_step_single<2, 2, true, real, 2> : (const void *)&k_step_single<2, 2, true, real>;
-    case V_REU2:
-        return two ? (const void *)&k_step_single<3, 2, false, real, 2> : (const void *)&k_step_single<3, 2, false, real>;
+    case V_ADV2: return step_fn2<0, false>(cpl);
+    case V_EUL2: return step_fn2<1, false>(cpl);
+    case V_SWE2: return step_fn2<2, true>(cpl);
+    case V_REU2: return step_fn2<3, false>(cpl);
     case V_ADV3: return (const void *)&k3_collide<0, real>;
     case V_EUL3: return (const void *)&k3_collide<1, real>;
     case V_REU3: return (const void *)&k3_collide<3, real>;

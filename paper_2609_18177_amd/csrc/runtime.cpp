@@ -100,15 +100,6 @@ std::string check_config(const arlbm_config *c)
     return "";
 }
 
-// Planes are stored at a stride of nx*ny rounded up past a 128-element tail
-// (the kernels' store sink: one slot per column of a wave), a multiple of 64
-// elements.
-int64_t plane_stride(const arlbm_config *c)
-{
-    const int64_t plane = c->nx * c->ny * c->nz;
-    return (plane + 128 + 63) / 64 * 64;
-}
-
 // Columns per lane of the 2D step.  Two adjacent columns per lane need an
 // even nx (every pair 8-byte aligned).  Measured on MI355X (2048^2 and
 // 4096^2 lattices, ms per step, one column per lane -> two):
@@ -125,6 +116,15 @@ int columns_per_lane(const arlbm_config *c)
     if (ARLBM_CPL_OVERRIDE) return ARLBM_CPL_OVERRIDE;
     static const int f32[4] = {2, 1, 2, 1}, f64[4] = {1, 1, 2, 1};  // advection, Euler, shallow water, reactive
     return (c->precision == ARLBM_F64 ? f64 : f32)[c->system];
+}
+
+// Planes are stored at a stride of nx*ny rounded up past a tail of 64
+// elements per column of a lane (the kernels' store sink: one slot per
+// column of a wave), a multiple of 64 elements.
+int64_t plane_stride(const arlbm_config *c)
+{
+    const int64_t plane = c->nx * c->ny * c->nz;
+    return (plane + 64 * columns_per_lane(c) + 63) / 64 * 64;
 }
 
 void fill_sizes(const arlbm_config *c, arlbm_sizes *o)
@@ -416,6 +416,12 @@ extern "C" int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, 
     if (cfg->dim <= 2) d.bc[4] = d.bc[5] = ARLBM_PERIODIC;
     d.omega_fixed_on = cfg->omega_mode == ARLBM_OMEGA_FIXED;
     d.cpl = columns_per_lane(cfg);
+    // buffer-resource addressing: every plane offset and cell offset of the
+    // population buffer in 32 bits
+#ifndef ARLBM_BUF_MAX_BYTES
+#define ARLBM_BUF_MAX_BYTES 0xffffffffull
+#endif
+    d.buf = cfg->dim == 2 && h->sz.f_bytes <= ARLBM_BUF_MAX_BYTES ? 1 : 0;
     d.ncols = (int32_t)((cfg->nx + strip_out_w(d.cpl) - 1) / strip_out_w(d.cpl));
     d.band_h = cfg->dim == 2 ? choose_band(cfg->ny, d.ncols, resident_waves(cfg->precision, d.variant, d.cpl),
                                            4 * (int64_t)num_cus())

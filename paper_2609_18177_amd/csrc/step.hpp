@@ -22,8 +22,8 @@
 // direction into a triple-buffered slot.  The kernel launch boundary is the
 // grid barrier that the global maximum needs.
 //
-// Plane layout: plane c of a buffer starts at c * pstride, pstride >= nx ny + 128.
-// The 128-element tail of every plane is a sink: lanes that must not write
+// Plane layout: plane c of a buffer starts at c * pstride, pstride >= nx ny +
+// 64 V (V columns per lane).  That tail of every plane is a sink: lanes that must not write
 // (halo lanes, warm-up rows) store there, so the steady-state loop carries no
 // conditional memory operation and the compiler can keep the prefetched loads
 // and the stores of the previous row in flight across iterations.
@@ -64,6 +64,12 @@ __device__ __forceinline__ T from_left(T v) { return wave_shift<0x138>(v); }   /
 template <typename T>
 __device__ __forceinline__ T from_right(T v) { return wave_shift<0x130>(v); }  // wave_shl:1
 
+// Compile-time phase of an unrolled loop.
+template <int N>
+struct Phase {
+    static constexpr int value = N;
+};
+
 // Loads and stores of one plane at a 32-bit per-lane element offset from the
 // plane's (uniform) base pointer.
 template <typename T>
@@ -86,6 +92,17 @@ __device__ __forceinline__ T wave_max(T v)
         v = w > v ? w : v;
     }
     return v;
+}
+
+// Relaxation parameter from the summed indicator (2.12/2.16): 1 + 1/(1 + nt).
+// FP32 takes the hardware reciprocal (1 ulp), FP64 the IEEE quotient.
+template <typename T>
+__device__ __forceinline__ T omega_of(T nt)
+{
+    if constexpr (sizeof(T) == 4)
+        return T(1) + __builtin_amdgcn_rcpf(T(1) + nt);
+    else
+        return T(1) + T(1) / (T(1) + nt);
 }
 
 __device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
@@ -306,7 +323,7 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
     add_theta<SYS, D, T>(0, q, U, UL, UR, P, nu);
     const T nuL = from_left(nu), nuR = from_right(nu);
     const T nt = nuL + nu + nuR;
-    const T w = L.omega_fixed_on ? cf.omega_fixed : T(1) + T(1) / (T(1) + nt);
+    const T w = L.omega_fixed_on ? cf.omega_fixed : omega_of<T>(nt);
     if (L.omega_on && out) ((T *)L.omega)[x] = w;
 
     // bed slope by central differences
@@ -445,6 +462,78 @@ __device__ __forceinline__ void stv(T *base, unsigned off, const T (&in)[V])
     }
 }
 
+// Population planes of the 2D step, read from f^n and written to f^{n+1}.
+// BUF = false: 64-bit plane pointers.  BUF = true: one buffer resource per
+// buffer, the plane as a scalar byte offset and the cell as a 32-bit vector
+// byte offset, so a plane access costs no vector address arithmetic; used
+// when the whole population buffer spans less than 4 GiB.
+template <typename T, int V, bool BUF>
+struct PlaneIO;
+
+template <typename T, int V>
+struct PlaneIO<T, V, false> {
+    const T *in;
+    T *out;
+    int64_t ps;
+    __device__ __forceinline__ PlaneIO(const LatticeDesc &L, int64_t n)
+        : in((const T *)L.f[n & 1]), out((T *)L.f[(n + 1) & 1]), ps(L.pstride) {}
+    __device__ __forceinline__ void ld(int p, unsigned e, T (&o)[V]) const { ldv<V>(in + (size_t)p * ps, e, o); }
+    __device__ __forceinline__ void st(int p, unsigned e, const T (&v)[V]) const { stv<V>(out + (size_t)p * ps, e, v); }
+};
+
+template <typename T, int V>
+struct PlaneIO<T, V, true> {
+    // a lane's V values as one vector; loads and stores move it whole (the
+    // returned word vector is bit-cast as a unit, never indexed)
+    typedef T vec_t __attribute__((ext_vector_type(V == 1 ? 2 : V)));
+    static constexpr int kBytes = (int)sizeof(T) * V;
+    __amdgpu_buffer_rsrc_t rin, rout;
+    unsigned psb;  // plane stride in bytes
+    __device__ __forceinline__ PlaneIO(const LatticeDesc &L, int64_t n)
+        // raw buffers (stride 0): the range check covers the vector offset
+        // only, so num_records = 2^32 - 1 never clips; the descriptor's third
+        // word is the gfx9 untyped 32-bit format
+        : rin(__builtin_amdgcn_make_buffer_rsrc(L.f[n & 1], 0, -1, 0x00020000)),
+          rout(__builtin_amdgcn_make_buffer_rsrc(L.f[(n + 1) & 1], 0, -1, 0x00020000)),
+          psb((unsigned)(L.pstride * (int64_t)sizeof(T))) {}
+    __device__ __forceinline__ void ld(int p, unsigned e, T (&o)[V]) const
+    {
+        const int vo = (int)(e * (unsigned)sizeof(T)), so = (int)((unsigned)p * psb);
+        if constexpr (kBytes == 4) {
+            o[0] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rin, vo, so, 0));
+        } else if constexpr (V == 1) {
+            o[0] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rin, vo, so, 0));
+        } else if constexpr (kBytes == 8) {
+            const vec_t v = __builtin_bit_cast(vec_t, __builtin_amdgcn_raw_buffer_load_b64(rin, vo, so, 0));
+            o[0] = v[0];
+            o[1] = v[1];
+        } else {
+            const vec_t v = __builtin_bit_cast(vec_t, __builtin_amdgcn_raw_buffer_load_b128(rin, vo, so, 0));
+            o[0] = v[0];
+            o[1] = v[1];
+        }
+    }
+    __device__ __forceinline__ void st(int p, unsigned e, const T (&v)[V]) const
+    {
+        const int vo = (int)(e * (unsigned)sizeof(T)), so = (int)((unsigned)p * psb);
+        typedef unsigned w2_t __attribute__((__vector_size__(2 * sizeof(unsigned))));
+        typedef unsigned w4_t __attribute__((__vector_size__(4 * sizeof(unsigned))));
+        if constexpr (kBytes == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v[0]), rout, vo, so, 0);
+        } else if constexpr (V == 1) {
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(w2_t, v[0]), rout, vo, so, 0);
+        } else {
+            vec_t t;
+            t[0] = v[0];
+            t[1] = v[1];
+            if constexpr (kBytes == 8)
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(w2_t, t), rout, vo, so, 0);
+            else
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(w4_t, t), rout, vo, so, 0);
+        }
+    }
+};
+
 // One wave marches a strip of strip_out_w(V) output columns up a band of
 // rows; lane l holds the V columns xa .. xa+V-1, xa = x0 - strip_halo(V) + V l.
 // With V = 2 every row access of a wave is one 512-byte span at an 8-byte
@@ -453,7 +542,7 @@ __device__ __forceinline__ void stv(T *base, unsigned off, const T (&in)[V])
 // At a mirror ghost (x < 0 or x >= nx, transmissive or reflective) a lane's
 // two columns map to cells in descending order: the lane loads the ascending
 // pair and swaps it; the wave-uniform test keeps interior strips free of it.
-template <int SYS, bool BED, typename T, int V>
+template <int SYS, bool BED, typename T, int V, bool BUF = false>
 __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int col, int band, bool first)
 {
     constexpr int D = 2, M = SysInfo<SYS, 2>::M, Q = 5;
@@ -467,7 +556,6 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     const Phys<T> P = make_phys<T>(L);
     const int lane = threadIdx.x & (kWave - 1);
     const int nx = L.nx, ny = L.ny;
-    const int64_t ps = L.pstride;
     const int xa = col * OW - HC + lane * V;  // this lane's first column
     // with V = 2, nx is even and xa is even, so xa < nx covers both columns
     const bool xout = lane * V >= HC && lane * V < kWave * V - HC && xa < nx;
@@ -477,8 +565,7 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
         for (int v = 0; v < V; ++v) null_copy<T>(L, n, Q * M, xa + v, xout, y0, y1, first && v == 0);
         return;
     }
-    const T *fin = (const T *)L.f[n & 1];
-    T *fout = (T *)L.f[(n + 1) & 1];
+    const PlaneIO<T, V, BUF> io(L, n);
     const T *bed = (const T *)L.bed;
     T *om = (T *)L.omega;
     const int bxl = L.bc[0], bxh = L.bc[1], byl = L.bc[2], byh = L.bc[3];
@@ -556,7 +643,7 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
 #pragma unroll
         for (int k = 0; k < Q; ++k)
 #pragma unroll
-            for (int c = 0; c < M; ++c) ldv<V>(fin + (size_t)(k * M + c) * ps, off, out[k][c]);
+            for (int c = 0; c < M; ++c) io.ld(k * M + c, off, out[k][c]);
     };
     auto loadU = [&](int j, T (*out)[M]) {
         T f[Q][M][V];
@@ -649,17 +736,30 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
 
     // FP32 keeps the population rows it loads in a register ring until the
     // collision two rows later uses them, so every row is read from memory
-    // once (4 Q m V registers).  FP64 would need twice that and drop to one
-    // wave per SIMD: it reads the row again in the iteration that collides it
-    // (a cache hit when the caches hold the rows in between).
+    // once (4 Q m V registers).  FP64 would need twice the registers: it
+    // reads the row again in the iteration that collides it (a cache hit when
+    // the caches hold the rows in between).
     constexpr bool kRing = sizeof(T) == 4 && Q * M <= 20;
-    // Shallow water (15 values per row) prefetches two rows ahead: measured
-    // 2.6% faster there, 5% slower for 2D Euler (20 values per row).
-    constexpr bool kPf2 = kRing && SYS == 2;
+    // The ring's rotation copies a row still in flight, so the row loop waits
+    // for its loads within the step.  Unrolling the loop by the ring's period
+    // makes the slots fixed registers (no copy; the wait falls in the next
+    // row's step) at the price of a 4x body and more registers.  Measured on
+    // MI355X (ms per step, rotating -> unrolled): advection 0.0540 -> 0.0512,
+    // Euler 0.169 -> 0.179, shallow water 0.478 -> 0.492; so only advection
+    // unrolls (ARLBM_RING_UNROLL: 0 never, 1 always, 2 advection).
+#ifndef ARLBM_RING_UNROLL
+#define ARLBM_RING_UNROLL 2
+#endif
+    constexpr bool kUnroll = kRing && (ARLBM_RING_UNROLL == 1 || (ARLBM_RING_UNROLL == 2 && SYS == 0));
+    // Without the unrolled ring, shallow water (15 values per row) prefetches
+    // two rows ahead.
+    constexpr bool kPf2 = kRing && !kUnroll && SYS == 2;
     // f rows j-1, j, j+1 (in flight), and j+2 (in flight) with two rows of
     // prefetch, kept as loaded; a row is put in column order when the
-    // collision takes it
-    T Rb[kRing ? Q : 1][M][V], Rc[kRing ? Q : 1][M][V], Rn[kRing ? Q : 1][M][V], Rm[kPf2 ? Q : 1][M][V];
+    // collision takes it.  Unrolled: row x in slot (x - ya + 1) mod 4.
+    constexpr bool kRot = kRing && !kUnroll;
+    T Rb[kRot ? Q : 1][M][V], Rc[kRot ? Q : 1][M][V], Rn[kRot ? Q : 1][M][V], Rm[kPf2 ? Q : 1][M][V];
+    T R[kUnroll ? 4 : 1][kUnroll ? Q : 1][M][V];
 
     // prologue: moment rows ya-3 .. ya, indicator rows ya-2 .. ya-1
     if constexpr (BED) {
@@ -669,7 +769,22 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
         fix(B1);
         fix(B2);
     }
-    if constexpr (kRing) {
+    if constexpr (kUnroll) {
+        T Ut[V][M];
+        loadU(ya - 3, Ut);
+        pushU(Ut);
+        loadU(ya - 2, Ut);
+        pushU(Ut);
+        loadF(ya - 1, R[0]);
+        sumU(ya - 1, R[0], Ut);
+        pushU(Ut);
+        nu_row();
+        loadF(ya, R[1]);
+        sumU(ya, R[1], Ut);
+        pushU(Ut);
+        nu_row();
+        loadF(ya + 1, R[2]);
+    } else if constexpr (kRing) {
         T Ut[V][M];
         loadU(ya - 3, Ut);
         pushU(Ut);
@@ -695,36 +810,11 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
         nu_row();
     }
 
-    // steady state: every iteration takes U(j), loads row j+1, computes nu
-    // at row j-1, omega and f* at row r = j-2, and writes destination row j-3
-    for (int j = ya + 1; j <= yb + 2; ++j) {
-        T fcur[Q][M][V];
+    // steady state: the step of row j takes U(j), loads row j+1, computes nu
+    // at row j-1, omega and f* at row r = j-2 from its populations fcur, and
+    // writes destination row j-3
+    auto row = [&](int j, T (*fcur)[M][V]) __attribute__((always_inline)) {
         const int r = j - 2;
-        if constexpr (kRing) {
-            T Ut[V][M];
-            sumU(j, Rn, Ut);
-            pushU(Ut);
-#pragma unroll
-            for (int k = 0; k < Q; ++k)
-#pragma unroll
-                for (int c = 0; c < M; ++c)
-#pragma unroll
-                    for (int v = 0; v < V; ++v) {
-                        fcur[k][c][v] = Rb[k][c][v];
-                        Rb[k][c][v] = Rc[k][c][v];
-                        Rc[k][c][v] = Rn[k][c][v];
-                        if constexpr (kPf2) Rn[k][c][v] = Rm[k][c][v];
-                    }
-            if constexpr (kPf2)
-                loadF(j + 2, Rm);
-            else
-                loadF(j + 1, Rn);
-            fixF(fcur);
-        } else {
-            roll_U(j);
-            loadF(r, fcur);
-            fixF(fcur);
-        }
         T dbx[V], dby[V];
         if constexpr (BED) {
 #pragma unroll
@@ -742,7 +832,7 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const T nt = N0l[v] + N0[v] + N0r[v] + N1l[v] + N1[v] + N1r[v] + N2l[v] + N2[v] + N2r[v];
-            w[v] = L.omega_fixed_on ? cf.omega_fixed : T(1) + T(1) / (T(1) + nt);
+            w[v] = L.omega_fixed_on ? cf.omega_fixed : omega_of<T>(nt);
         }
         stv<V>(om, (xout && r >= ya && r < yb && L.omega_on) ? (unsigned)(r * nx + xa) : osink, w);
         if constexpr (BED) {
@@ -869,7 +959,7 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
 #pragma unroll
             for (int k = 0; k < Q; ++k)
 #pragma unroll
-                for (int c = 0; c < M; ++c) stv<V>(fout + (size_t)(k * M + c) * ps, o, Fk[k][c]);
+                for (int c = 0; c < M; ++c) io.st(k * M + c, o, Fk[k][c]);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 Prim<T> qn;
@@ -906,6 +996,60 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
                 dby_prev[v] = dby[v];
             }
         }
+    };
+    if constexpr (kUnroll) {
+        // phase S of the ring: row j in slot S+2, row j+1 loaded into slot
+        // S+3, row j-2 (fcur) in slot S
+        auto phase = [&](auto phase_tag, int j) __attribute__((always_inline)) {
+            constexpr int S = decltype(phase_tag)::value;
+            T Ut[V][M];
+            sumU(j, R[(S + 2) & 3], Ut);
+            pushU(Ut);
+            loadF(j + 1, R[(S + 3) & 3]);
+            fixF(R[S]);
+            row(j, R[S]);
+        };
+        const int nrows = yb + 2 - ya;  // steps j = ya+1 .. yb+2
+        int i = 0;
+        for (; i + 4 <= nrows; i += 4) {
+            phase(Phase<0>(), ya + 1 + i);
+            phase(Phase<1>(), ya + 2 + i);
+            phase(Phase<2>(), ya + 3 + i);
+            phase(Phase<3>(), ya + 4 + i);
+        }
+        if (i < nrows) phase(Phase<0>(), ya + 1 + i);
+        if (i + 1 < nrows) phase(Phase<1>(), ya + 2 + i);
+        if (i + 2 < nrows) phase(Phase<2>(), ya + 3 + i);
+    } else {
+        for (int j = ya + 1; j <= yb + 2; ++j) {
+            T fcur[Q][M][V];
+            if constexpr (kRing) {
+                T Ut[V][M];
+                sumU(j, Rn, Ut);
+                pushU(Ut);
+#pragma unroll
+                for (int k = 0; k < Q; ++k)
+#pragma unroll
+                    for (int c = 0; c < M; ++c)
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            fcur[k][c][v] = Rb[k][c][v];
+                            Rb[k][c][v] = Rc[k][c][v];
+                            Rc[k][c][v] = Rn[k][c][v];
+                            if constexpr (kPf2) Rn[k][c][v] = Rm[k][c][v];
+                        }
+                if constexpr (kPf2)
+                    loadF(j + 2, Rm);
+                else
+                    loadF(j + 1, Rn);
+                fixF(fcur);
+            } else {
+                roll_U(j);
+                loadF(j - 2, fcur);
+                fixF(fcur);
+            }
+            row(j, fcur);
+        }
     }
     if (first && lane == 0) scalar_update(L, n, cf.dt);
     commit<T>(L, n, s0, s1, flags, 2);
@@ -925,7 +1069,7 @@ __device__ __forceinline__ int logical_wave()
 #ifndef ARLBM_STEP_MIN_WAVES
 #define ARLBM_STEP_MIN_WAVES 1
 #endif
-template <int SYS, int D, bool BED, typename T, int V = 1>
+template <int SYS, int D, bool BED, typename T, int V = 1, bool BUF = false>
 __global__ __launch_bounds__(kBlock, ARLBM_STEP_MIN_WAVES) void k_step_single(LatticeDesc L, int64_t iter, int32_t nwork)
 {
     const int w = logical_wave();
@@ -933,7 +1077,7 @@ __global__ __launch_bounds__(kBlock, ARLBM_STEP_MIN_WAVES) void k_step_single(La
     if constexpr (D == 1) {
         strip1d<SYS, T>(L, iter, w, w == 0);
     } else {
-        strip2d<SYS, BED, T, V>(L, iter, w % L.ncols, w / L.ncols, w == 0);
+        strip2d<SYS, BED, T, V, BUF>(L, iter, w % L.ncols, w / L.ncols, w == 0);
     }
 }
 

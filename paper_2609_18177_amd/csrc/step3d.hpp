@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void k3_omega(LatticeDesc L, int64_t iter)
                 for (int kj = -1; kj <= 1; ++kj)
 #pragma unroll
                     for (int ki = -1; ki <= 1; ++ki) nt = nt + nu[pad3(L, i + ki, j + kj, l + kl)];
-            w = T(1) + T(1) / (T(1) + nt);
+            w = omega_of<T>(nt);
         }
         w_out[c] = w;
         if (L.omega_on) ((T *)L.omega)[c] = w;

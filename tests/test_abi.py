@@ -44,14 +44,14 @@ def test_query_sizes_layout():
     c = _cfg(system=A.EULER, dim=2, nx=100, ny=60, y1=0.6, precision=A.F32)
     s = A.query_sizes(c)
     assert (s.m, s.q) == (4, 5)
-    ps = (6000 + 128 + 63) // 64 * 64         # plane stride with the 128-element sink tail
+    ps = (6000 + 64 + 63) // 64 * 64          # plane stride with the 64-element sink tail
     assert s.f_bytes == (20 * ps * 4 + 255) // 256 * 256
     assert s.u_bytes == (4 * ps * 4 + 255) // 256 * 256
     assert s.total_bytes == 2 * s.f_bytes + 2 * s.u_bytes + s.scalar_bytes
     c.precision = A.F64
     assert A.query_sizes(c).f_bytes == (20 * ps * 8 + 255) // 256 * 256
     c2 = _cfg(system=A.SWE, dim=2, nx=64, ny=64, has_bed=1)
-    assert A.query_sizes(c2).bed_bytes == (64 * 64 + 128) * 4
+    assert A.query_sizes(c2).bed_bytes == (64 * 64 + 128) * 4  # two columns per lane: 128
 
 
 @pytest.mark.parametrize("bad", [
