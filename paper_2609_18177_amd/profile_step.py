@@ -30,10 +30,11 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402  (kernel source hash; bench imports no GPU module at import time)
 
 # 2D kernels end in the columns per lane (2 for advection and shallow water
-# on lattices of even nx)
-KERNELS = {"euler2d_f32": "k_step_single<1, 2, false, float, 1>",
-           "euler2d_f64": "k_step_single<1, 2, false, double, 1>",
-           "swe2d_f32": "k_step_single<2, 2, true, float, 2>",
+# on lattices of even nx) and the buffer-resource addressing flag (populations
+# below 4 GiB)
+KERNELS = {"euler2d_f32": "k_step_single<1, 2, false, float, 1, true>",
+           "euler2d_f64": "k_step_single<1, 2, false, double, 1, true>",
+           "swe2d_f32": "k_step_single<2, 2, true, float, 2, true>",
            "euler3d_f32": "k3_collide<1, float>"}
 # further kernels of a step (3D: the indicator and relaxation passes)
 EXTRA_KERNELS = {"euler3d_f32": ["k3_nu<1, float>", "k3_omega<float>"]}
@@ -83,6 +84,8 @@ def main():
     kname = KERNELS[args.workload]
     d, cmd_trace = rocprof(["--kernel-trace", "--stats"], raw, "trace", prog, 300)
     stats = kernel_stats(os.path.join(d, "run_kernel_stats.csv"), kname)
+    if stats is None:
+        raise SystemExit(f"kernel {kname} not found in the trace")
     extra_names = EXTRA_KERNELS.get(args.workload, [])
     extra_stats = {k: kernel_stats(os.path.join(d, "run_kernel_stats.csv"), k) for k in extra_names}
     pmc_prog = ["bench.py", "--only", args.workload, "--steps", "10", "--warmup", "2"]
