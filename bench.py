@@ -136,7 +136,8 @@ def run_swe(torch, args, steps=None):
 
 def run_euler3d(torch, args, steps=None):
     """3D Euler (D3Q7), seeded octant data on 256^3 cells, FP32: the
-    four-pass step (moments, indicator, relaxation, collide-and-pull)."""
+    three-pass step (indicator, relaxation, collide-and-pull with the moments
+    of the new state)."""
     p = W.euler_octants_3d(seed=0, n=256, steps=100)
     steps = steps or args.steps3d
     log(f"[euler3d] 256^3 FP32: warmup {args.warmup}, timed {steps}")

@@ -24,6 +24,14 @@ static int grid_for(int64_t items, int per_block)
     return (int)(b < 8 ? 8 : b);
 }
 
+// Grid of a 3D pass: a multiple of 8 blocks (one slab per XCD), at most 4096.
+static int slab_grid(int64_t cells)
+{
+    int64_t b = (cells + kBlock - 1) / kBlock;
+    b = (b + 7) / 8 * 8;
+    return (int)(b > 4096 ? 4096 : (b < 8 ? 8 : b));
+}
+
 static int cell_grid(int64_t cells)
 {
     int64_t b = (cells + kBlock - 1) / kBlock;
@@ -54,9 +62,9 @@ static hipError_t step_impl(const LatticeDesc &h, int64_t iter, hipStream_t s)
         // step or the initialisation left in u[n&1]), relaxation parameter,
         // collide and pull (which also writes the moments of the new state)
         const int64_t npad = (int64_t)(h.nx + 2) * (h.ny + 2) * (h.nz + 2);
-        hipLaunchKernelGGL((k3_nu<SYS, real>), dim3(cell_grid(npad)), dim3(kBlock), 0, s, h, iter);
-        hipLaunchKernelGGL((k3_omega<real>), dim3(cell_grid(h.plane)), dim3(kBlock), 0, s, h, iter);
-        hipLaunchKernelGGL((k3_collide<SYS, real>), dim3(cell_grid(h.plane)), dim3(kBlock), 0, s, h, iter);
+        hipLaunchKernelGGL((k3_nu<SYS, real>), dim3(slab_grid(npad)), dim3(kBlock), 0, s, h, iter);
+        hipLaunchKernelGGL((k3_omega<real>), dim3(slab_grid(h.plane)), dim3(kBlock), 0, s, h, iter);
+        hipLaunchKernelGGL((k3_collide<SYS, real>), dim3(slab_grid(h.plane)), dim3(kBlock), 0, s, h, iter);
     } else {
         const int64_t nbands = D == 2 ? (h.ny + h.band_h - 1) / h.band_h : 1;
         const int64_t nwork = (int64_t)h.ncols * nbands;

@@ -15,8 +15,11 @@
 //               wave-speed bounds (2.19) reduced across the wave and
 //               committed with one atomic max per wave and direction.
 //
-// Threads walk cells with x fastest, so every plane access is coalesced
-// (shifts by e_k move whole rows or planes).  A population pulled from a
+// Threads walk cells in column tiles marching in z (x fastest within a tile
+// row), so every plane access is coalesced (shifts by e_k move whole rows or
+// planes) and the neighbours a cell reads were fetched by the same XCD just
+// before.  Waves whose cells all lie one cell inside the lattice skip the
+// boundary maps and ghost rules.  A population pulled from a
 // ghost position outside a non-periodic face is the destination's own
 // collided population: the same velocity (transmissive) or the mirrored one
 // with the normal momentum negated (reflective), as in the 1D/2D kernels.
@@ -34,6 +37,69 @@ __device__ __forceinline__ int64_t cell3(const LatticeDesc &L, int i, int j, int
 __device__ __forceinline__ int64_t pad3(const LatticeDesc &L, int i, int j, int l)
 {
     return ((int64_t)(l + 1) * (L.ny + 2) + (j + 1)) * (L.nx + 2) + (i + 1);
+}
+
+// Cells of a 3D pass in XCD-contiguous slabs.  Blocks are dealt round-robin
+// over the 8 XCDs, so block b works on slab b mod 8 (cells [s S, (s+1) S),
+// S = ceil(total / 8)) and strides over it with the slab's other blocks: each
+// XCD sweeps one contiguous range, and the neighbours a cell reads (a row or
+// a plane away) were mostly fetched into that XCD's L2 shortly before.  The
+// grid is a multiple of 8 blocks.  Every thread of a wave runs the same
+// number of iterations (lim is a whole number of strides past begin).
+struct Slab {
+    int64_t begin, end, first, step, lim;
+};
+__device__ __forceinline__ Slab slab_of(int64_t total)
+{
+    Slab r;
+    const int b = blockIdx.x, nbx = gridDim.x >> 3;
+    const int64_t S = (total + 7) / 8;
+    r.begin = (int64_t)(b & 7) * S;
+    r.end = r.begin + S < total ? r.begin + S : total;
+    r.step = (int64_t)nbx * blockDim.x;
+    r.first = r.begin + (int64_t)(b >> 3) * blockDim.x + threadIdx.x;
+    const int64_t len = r.end > r.begin ? r.end - r.begin : 0;
+    r.lim = r.begin + (len + r.step - 1) / r.step * r.step;
+    return r;
+}
+
+// Column tiles of kTX x kTY cells marching in z.  An iteration index g maps
+// to (tile, z, offset in the tile) with the offset fastest, then z, then the
+// tile: cells a plane apart are kTX kTY iterations apart and those a row apart
+// kTX, so a cell's neighbours are fetched by the same XCD at about the same
+// time, and the working set of a tile column (a few planes of 1024 cells)
+// stays in L2 where a whole lattice plane would not.  Tiles overhanging the
+// lattice leave their outside cells idle.
+#ifndef ARLBM_3D_TX
+#define ARLBM_3D_TX 128
+#endif
+constexpr int kTileShift = 10, kTX = ARLBM_3D_TX, kTY = (1 << kTileShift) / kTX;
+static_assert(kTX * kTY == 1 << kTileShift, "tile size");
+struct Tiling {
+    int nx, ny, nz, ntx;
+    int64_t total;
+};
+__device__ __forceinline__ Tiling tiling_of(int nx, int ny, int nz)
+{
+    Tiling t;
+    t.nx = nx;
+    t.ny = ny;
+    t.nz = nz;
+    t.ntx = (nx + kTX - 1) / kTX;
+    const int nty = (ny + kTY - 1) / kTY;
+    t.total = ((int64_t)t.ntx * nty * nz) << kTileShift;
+    return t;
+}
+__device__ __forceinline__ bool tile_cell(const Tiling &t, int64_t g, int &i, int &j, int &l)
+{
+    const int o = (int)(g & ((1 << kTileShift) - 1));
+    const unsigned rest = (unsigned)(g >> kTileShift);
+    const unsigned tile = rest / (unsigned)t.nz;
+    l = (int)(rest - tile * (unsigned)t.nz);
+    const unsigned ty = tile / (unsigned)t.ntx;
+    i = (int)(tile - ty * (unsigned)t.ntx) * kTX + (o & (kTX - 1));
+    j = (int)ty * kTY + (o / kTX);
+    return i < t.nx && j < t.ny;
 }
 
 // U at any position within two cells of the lattice: each axis through its
@@ -64,24 +130,49 @@ __global__ __launch_bounds__(kBlock) void k3_nu(LatticeDesc L, int64_t iter)
     T *nu_out = (T *)L.nu3;
     const int px = L.nx + 2, py = L.ny + 2;
     const int64_t npad = (int64_t)px * py * (L.nz + 2);
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < npad;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(g % px) - 1;
-        const int j = (int)((g / px) % py) - 1;
-        const int l = (int)(g / ((int64_t)px * py)) - 1;
-        T Uc[M], Um[M], Up[M];
-        load_U3<M, T>(L, u, i, j, l, SYS != 0, Uc);
-        Prim<T> qc;
-        primitives<SYS, 3, T>(Uc, P, qc);
-        T nu = T(0);
+    const Tiling tl = tiling_of(px, py, L.nz + 2);
+    const Slab sl = slab_of(tl.total);
+    for (int64_t g = sl.first; g < sl.end; g += sl.step) {
+        int i, j, l;
+        if (!tile_cell(tl, g, i, j, l)) continue;
+        const int64_t gp = ((int64_t)l * py + j) * px + i;  // padded index
+        --i;
+        --j;
+        --l;
+        // cells whose neighbours are all inside the lattice read them
+        // directly; a wave with any other cell takes the boundary maps
+        const bool inner = i >= 1 && i <= L.nx - 2 && j >= 1 && j <= L.ny - 2 && l >= 1 && l <= L.nz - 2;
+        auto cell_nu = [&](auto inner_tag) __attribute__((always_inline)) {
+            constexpr bool kInner = decltype(inner_tag)::value;
+            const int64_t ps = L.pstride;
+            const int64_t c0 = kInner ? cell3(L, i, j, l) : 0;
+            auto ld = [&](int di, int dj, int dl, T *U) __attribute__((always_inline)) {
+                if constexpr (kInner) {
+                    const int64_t cn = c0 + ((int64_t)dl * L.ny + dj) * L.nx + di;
 #pragma unroll
-        for (int dir = 0; dir < 3; ++dir) {
-            const int ox = dir == 0, oy = dir == 1, oz = dir == 2;
-            load_U3<M, T>(L, u, i - ox, j - oy, l - oz, SYS != 0, Um);
-            load_U3<M, T>(L, u, i + ox, j + oy, l + oz, SYS != 0, Up);
-            add_theta<SYS, 3, T>(dir, qc, Uc, Um, Up, P, nu);
-        }
-        nu_out[g] = nu;
+                    for (int c = 0; c < M; ++c) U[c] = u[(int64_t)c * ps + cn];
+                } else {
+                    load_U3<M, T>(L, u, i + di, j + dj, l + dl, SYS != 0, U);
+                }
+            };
+            T Uc[M], Um[M], Up[M];
+            ld(0, 0, 0, Uc);
+            Prim<T> qc;
+            primitives<SYS, 3, T>(Uc, P, qc);
+            T nu = T(0);
+#pragma unroll
+            for (int dir = 0; dir < 3; ++dir) {
+                const int ox = dir == 0, oy = dir == 1, oz = dir == 2;
+                ld(-ox, -oy, -oz, Um);
+                ld(ox, oy, oz, Up);
+                add_theta<SYS, 3, T>(dir, qc, Uc, Um, Up, P, nu);
+            }
+            nu_out[gp] = nu;
+        };
+        if (__ballot(!inner) == 0ull)
+            cell_nu(Phase<1>());
+        else
+            cell_nu(Phase<0>());
     }
 }
 
@@ -92,11 +183,12 @@ __global__ __launch_bounds__(kBlock) void k3_omega(LatticeDesc L, int64_t iter)
     const int64_t npad = (int64_t)(L.nx + 2) * (L.ny + 2) * (L.nz + 2);
     T *w_out = (T *)L.nu3 + npad;
     const T wfix = T(L.omega_fixed);
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < L.plane;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(c % L.nx);
-        const int j = (int)((c / L.nx) % L.ny);
-        const int l = (int)(c / ((int64_t)L.nx * L.ny));
+    const Tiling tl = tiling_of(L.nx, L.ny, L.nz);
+    const Slab sl = slab_of(tl.total);
+    for (int64_t g = sl.first; g < sl.end; g += sl.step) {
+        int i, j, l;
+        if (!tile_cell(tl, g, i, j, l)) continue;
+        const int64_t c = cell3(L, i, j, l);
         T w;
         if (L.omega_fixed_on) {
             w = wfix;
@@ -124,11 +216,11 @@ __global__ __launch_bounds__(kBlock) void k3_collide(LatticeDesc L, int64_t iter
     const T *fin = (const T *)L.f[n & 1];
     T *fout = (T *)L.f[(n + 1) & 1];
     const int64_t ps = L.pstride;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const T *u = (const T *)L.u[n & 1];
     T *uout = (T *)L.u[(n + 1) & 1];
     if (L.sc->t[n % 3] >= L.t_stop) {  // null step: the state is at the stop time
-        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < L.plane; c += stride) {
+        const Slab sl = slab_of(L.plane);
+        for (int64_t c = sl.first; c < sl.end; c += sl.step) {
             for (int p = 0; p < Q * M; ++p) fout[(int64_t)p * ps + c] = fin[(int64_t)p * ps + c];
             for (int p = 0; p < M; ++p) uout[(int64_t)p * ps + c] = u[(int64_t)p * ps + c];
         }
@@ -145,18 +237,22 @@ __global__ __launch_bounds__(kBlock) void k3_collide(LatticeDesc L, int64_t iter
     const T ak[Q] = {cf.a0, cf.ap[0], cf.ap[1], cf.ap[2], cf.ap[0], cf.ap[1], cf.ap[2]};
     T smax[3] = {T(0), T(0), T(0)};
     unsigned flags = 0;
-    // a grid-stride loop in which every lane of a wave runs the same number
-    // of iterations (the reduction below needs the whole wave)
-    const int64_t total = (L.plane + stride - 1) / stride * stride;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += stride) {
-        const bool live = c < L.plane;
-        const int64_t cc = live ? c : 0;
-        const int i = (int)(cc % L.nx);
-        const int j = (int)((cc / L.nx) % L.ny);
-        const int l = (int)(cc / ((int64_t)L.nx * L.ny));
+    // every lane of a wave runs the same number of iterations (the reduction
+    // below needs the whole wave)
+    const Tiling tl = tiling_of(L.nx, L.ny, L.nz);
+    const Slab sl = slab_of(tl.total);
+    for (int64_t g = sl.first; g < sl.lim; g += sl.step) {
+        int i = 0, j = 0, l = 0;
+        const bool live = g < sl.end && tile_cell(tl, g, i, j, l);
+        if (!live) i = j = l = 0;
+        const int64_t c = cell3(L, i, j, l);
         const int pos[3] = {i, j, l};
         const int ext[3] = {L.nx, L.ny, L.nz};
         T Fk[Q][M];
+        // a wave whose cells all pull from inside the lattice skips the ghost rules
+        const bool inner = live && i >= 1 && i <= L.nx - 2 && j >= 1 && j <= L.ny - 2 && l >= 1 && l <= L.nz - 2;
+        auto pull = [&](auto inner_tag) __attribute__((always_inline)) {
+        constexpr bool kInner = decltype(inner_tag)::value;
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
             // velocity k: 0 rest; 1..3 +x,+y,+z; 4..6 -x,-y,-z
@@ -166,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k3_collide(LatticeDesc L, int64_t iter
             src[dir] -= sgn;
             int ks = k;
             bool negate = false;
-            if (k != 0 && (src[dir] < 0 || src[dir] >= ext[dir])) {
+            if (!kInner && k != 0 && (src[dir] < 0 || src[dir] >= ext[dir])) {
                 const int side = src[dir] < 0 ? 2 * dir : 2 * dir + 1;
                 const int b = L.bc[side];
                 if (b == 0) {
@@ -204,6 +300,11 @@ __global__ __launch_bounds__(kBlock) void k3_collide(LatticeDesc L, int64_t iter
                 Fk[k][c2] = (negate && c2 == 1 + dir) ? -fs : fs;
             }
         }
+        };
+        if (__ballot(!inner) == 0ull)
+            pull(Phase<1>());
+        else
+            pull(Phase<0>());
         // moments (2.8) and the second half source
         T sumF[M];
 #pragma unroll
