@@ -543,7 +543,8 @@ struct PlaneIO<T, V, true> {
 // two columns map to cells in descending order: the lane loads the ascending
 // pair and swaps it; the wave-uniform test keeps interior strips free of it.
 template <int SYS, bool BED, typename T, int V, bool BUF = false>
-__device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int col, int band, bool first)
+__device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int col, int band, bool first,
+                                        T *lds = nullptr)
 {
     constexpr int D = 2, M = SysInfo<SYS, 2>::M, Q = 5;
     constexpr int HC = strip_halo(V), OW = strip_out_w(V);
@@ -734,12 +735,15 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
         loadU(j + 1, Unx);
     };
 
-    // FP32 keeps the population rows it loads in a register ring until the
-    // collision two rows later uses them, so every row is read from memory
-    // once (4 Q m V registers).  FP64 would need twice the registers: it
-    // reads the row again in the iteration that collides it (a cache hit when
-    // the caches hold the rows in between).
+    // Every population row is read from memory once and kept until the
+    // collision two rows later uses it.  FP32 keeps the rows in a register
+    // ring (4 Q m V registers).  FP64 would need twice the registers: with an
+    // LDS buffer (lds != nullptr) rows j-1 and j go to two LDS slots of the
+    // wave (the row in flight stays in registers); without one it reads the
+    // row again in the iteration that collides it, from L2 when it is still
+    // there (measured: mostly not, 2.2x the algorithmic reads at 2048^2).
     constexpr bool kRing = sizeof(T) == 4 && Q * M <= 20;
+    const bool use_lds = sizeof(T) == 8 && lds != nullptr;
     // The ring's rotation copies a row still in flight, so the row loop waits
     // for its loads within the step.  Unrolling the loop by the ring's period
     // makes the slots fixed registers (no copy; the wait falls in the next
@@ -760,6 +764,23 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     constexpr bool kRot = kRing && !kUnroll;
     T Rb[kRot ? Q : 1][M][V], Rc[kRot ? Q : 1][M][V], Rn[kRot ? Q : 1][M][V], Rm[kPf2 ? Q : 1][M][V];
     T R[kUnroll ? 4 : 1][kUnroll ? Q : 1][M][V];
+    constexpr bool kLdsPath = sizeof(T) == 8;  // compiled for FP64 only
+    T Rl[kLdsPath ? Q : 1][M][V];              // FP64 LDS ring: the row in flight
+    // LDS slot (row & 1) of the wave: value i of lane l at ((slot Q m + i) 64 + l) V
+    auto lds_put = [&](int row, const T (*f)[M][V]) {
+        T *base = lds + ((row & 1) * Q * M * kWave + lane) * V;
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+#pragma unroll
+            for (int c = 0; c < M; ++c) stv<V>(base, (unsigned)((k * M + c) * kWave * V), f[k][c]);
+    };
+    auto lds_get = [&](int row, T (*f)[M][V]) {
+        const T *base = lds + ((row & 1) * Q * M * kWave + lane) * V;
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+#pragma unroll
+            for (int c = 0; c < M; ++c) ldv<V>(base, (unsigned)((k * M + c) * kWave * V), f[k][c]);
+    };
 
     // prologue: moment rows ya-3 .. ya, indicator rows ya-2 .. ya-1
     if constexpr (BED) {
@@ -800,6 +821,26 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
         nu_row();
         loadF(ya + 1, Rn);
         if constexpr (kPf2) loadF(ya + 2, Rm);
+    } else if (kLdsPath && use_lds) {
+        T Ut[V][M], Rt[Q][M][V];
+        loadU(ya - 3, Ut);
+        pushU(Ut);
+        loadU(ya - 2, Ut);
+        pushU(Ut);
+        loadF(ya - 1, Rt);
+        sumU(ya - 1, Rt, Ut);
+        lds_put(ya - 1, Rt);
+        pushU(Ut);
+        nu_row();
+        // the row in flight into the loop is requested before row ya, whose
+        // wait then covers it: the loop's wait for its row in flight need not
+        // drain the stores of the row before
+        loadF(ya + 1, Rl);
+        loadF(ya, Rt);
+        sumU(ya, Rt, Ut);
+        lds_put(ya, Rt);
+        pushU(Ut);
+        nu_row();
     } else {
         loadU(ya - 3, Unx);
         roll_U(ya - 3);
@@ -1043,6 +1084,16 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
                 else
                     loadF(j + 1, Rn);
                 fixF(fcur);
+            } else if (kLdsPath && use_lds) {
+                T Ut[V][M];
+                sumU(j, Rl, Ut);
+                pushU(Ut);
+                // row j-2 out of the slot that row j then takes (the LDS
+                // operations of a wave complete in order)
+                lds_get(j - 2, fcur);
+                lds_put(j, Rl);
+                loadF(j + 1, Rl);
+                fixF(fcur);
             } else {
                 roll_U(j);
                 loadF(j - 2, fcur);
@@ -1066,6 +1117,9 @@ __device__ __forceinline__ int logical_wave()
     return __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + (int)(threadIdx.x >> 6));
 }
 
+#ifndef ARLBM_LDS_RING_F64
+#define ARLBM_LDS_RING_F64 1
+#endif
 #ifndef ARLBM_STEP_MIN_WAVES
 #define ARLBM_STEP_MIN_WAVES 1
 #endif
@@ -1076,6 +1130,17 @@ __global__ __launch_bounds__(kBlock, ARLBM_STEP_MIN_WAVES) void k_step_single(La
     if (w >= nwork) return;
     if constexpr (D == 1) {
         strip1d<SYS, T>(L, iter, w, w == 0);
+    } else if constexpr (sizeof(T) == 8 && SYS != 0 &&
+                         kWavesPerBlock * 2 * 5 * SysInfo<SYS, 2>::M * kWave * V * sizeof(T) <= 160 * 1024) {
+        // two LDS row slots per wave (FP64; measured per step at 2048^2 and
+        // 4096^2: Euler 0.375 -> 0.318 ms, shallow water 1.086 -> 0.909,
+        // reactive 0.517 -> 0.493, advection 0.117 -> 0.126, so advection,
+        // whose rows are 5 values, reads them again; kernels whose slots would
+        // not fit the CU's 160 KB of LDS do too)
+        constexpr int kSlot = 5 * SysInfo<SYS, 2>::M * kWave * V;
+        __shared__ T ring[kWavesPerBlock * 2 * kSlot];
+        strip2d<SYS, BED, T, V, BUF>(L, iter, w % L.ncols, w / L.ncols, w == 0,
+                                     ARLBM_LDS_RING_F64 ? ring + (threadIdx.x >> 6) * 2 * kSlot : nullptr);
     } else {
         strip2d<SYS, BED, T, V, BUF>(L, iter, w % L.ncols, w / L.ncols, w == 0);
     }
