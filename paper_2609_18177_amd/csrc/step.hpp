@@ -742,6 +742,9 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     // wave (the row in flight stays in registers); without one it reads the
     // row again in the iteration that collides it, from L2 when it is still
     // there (measured: mostly not, 2.2x the algorithmic reads at 2048^2).
+    // FP32 reactive Euler (25 values per row) also reads rows again: its
+    // step is bound by the kinetics' arithmetic, and the LDS slots measured
+    // 3.5% slower there (0.281 -> 0.291 ms at 2048^2).
     constexpr bool kRing = sizeof(T) == 4 && Q * M <= 20;
     const bool use_lds = sizeof(T) == 8 && lds != nullptr;
     // The ring's rotation copies a row still in flight, so the row loop waits
