@@ -4,7 +4,7 @@
 // of rows.  With one column per lane, lane l sits on column x = x0 - 3 + l
 // (58 outputs); with two, on columns x0 - 4 + 2l and the next (120 outputs).
 // The halo on each side is carried by the wave itself: x-neighbours come
-// from lane shuffles, no LDS and no barriers are used.  The wave marches up its band;
+// from lane shuffles and no barriers are used.  The wave marches up its band;
 // per row it loads the populations f (Q m planes), forms the moments U of the
 // row two ahead from them, and keeps a rolling window in registers:
 //
@@ -14,19 +14,21 @@
 //   f*_{+y}(r-2), f*_{0,+x,-x}(r-1), f*_{-y}(r) -> pulled F_k at row r-1
 //   sum_k F_k, (2.8), second half source -> f^{n+1}, U^{n+1} written once.
 //
-// Every population is written once per step and read from HBM once (the
-// second read of a row, two iterations after the first, hits the caches);
-// the step stores nothing but the populations.  The grid-wide
+// Every population is written once per step and read from HBM once: the
+// loaded rows wait for the collision two rows later in a register ring
+// (FP32) or in two LDS slots of the wave (FP64); the step stores nothing but
+// the populations.  The grid-wide
 // wave-speed bound of the next step (eq. 2.19) is reduced in registers, across
 // the wave by shuffles, and committed with one 64-bit atomic max per wave and
 // direction into a triple-buffered slot.  The kernel launch boundary is the
 // grid barrier that the global maximum needs.
 //
 // Plane layout: plane c of a buffer starts at c * pstride, pstride >= nx ny +
-// 64 V (V columns per lane).  That tail of every plane is a sink: lanes that must not write
-// (halo lanes, warm-up rows) store there, so the steady-state loop carries no
-// conditional memory operation and the compiler can keep the prefetched loads
-// and the stores of the previous row in flight across iterations.
+// 64 V (V columns per lane).  That tail of every plane is a sink: lanes that
+// must not write (halo lanes, warm-up rows) store there, so the steady-state
+// loop carries no conditional memory operation and the compiler can keep the
+// prefetched loads and the stores of the previous row in flight across
+// iterations.
 //
 // Ghost cells: U at ghost positions follows the boundary index map (periodic
 // wrap, or mirror U(-1-i) = U(i) with the normal momentum negated at
