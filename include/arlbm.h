@@ -238,8 +238,9 @@ int arlbm_server_create(size_t hbm_budget, int32_t precision, void *stream,
                         arlbm_server **out);
 
 /* Queue a request: a configuration, host FP64 initial planes (and bed) copied
- * at submit time, and a step count.  EBUDGET if it can never fit the budget;
- * EINVAL for a 3D lattice (served lattices are 1D or 2D). */
+ * at submit time, and a step count.  EBUDGET if it can never fit the budget.
+ * 1D and 2D lattices advance in the iteration's batched launch; a 3D lattice
+ * runs its three passes as launches of its own after it, on the same stream. */
 int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, const double *U0,
                         const double *bed, int64_t nsteps, uint64_t *id);
 

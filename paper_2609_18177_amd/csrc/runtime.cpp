@@ -833,6 +833,7 @@ int rebuild_table(arlbm_server *s)
         d.cpl = 1;
         d.ncols = (int32_t)((d.nx + kOutW - 1) / kOutW);
         descs.push_back(d);
+        if (d.variant >= V_ADV3) continue;  // 3D lattices run their own passes
         const int64_t nb = d.variant >= V_ADV2 ? (d.ny + d.band_h - 1) / d.band_h : 1;
         for (int64_t b = 0; b < nb; ++b)
             for (int c = 0; c < d.ncols; ++c) items.push_back({(int32_t)i, c, (int32_t)b, (b == 0 && c == 0) ? 1 : 0});
@@ -884,7 +885,6 @@ extern "C" int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, con
     c.precision = s->precision;
     std::string e = check_config(&c);
     if (!e.empty()) return sfail(s, ARLBM_EINVAL, e);
-    if (c.dim == 3) return sfail(s, ARLBM_EINVAL, "served lattices are 1D or 2D");
     if (c.has_bed && !bed) return sfail(s, ARLBM_EINVAL, "bed is NULL");
     arlbm_sizes sz;
     fill_sizes(&c, &sz);
@@ -892,7 +892,7 @@ extern "C" int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, con
     Pending p;
     p.id = s->next_id++;
     p.cfg = c;
-    const size_t plane = (size_t)c.nx * c.ny;
+    const size_t plane = (size_t)c.nx * c.ny * c.nz;
     p.U0.assign(U0, U0 + (size_t)sz.m * plane);
     if (c.has_bed) p.bed.assign(bed, bed + plane);
     p.nsteps = nsteps;
@@ -964,10 +964,22 @@ extern "C" int arlbm_server_iterate(arlbm_server *s, int32_t *n_res, int32_t *n_
         if (rc) return rc;
     }
     if (!s->resident.empty()) {
-        hipError_t e = s->precision == ARLBM_F64
-                           ? f64::step_batched(s->d_descs, s->d_items, s->nitems, s->iter, s->stream)
-                           : f32::step_batched(s->d_descs, s->d_items, s->nitems, s->iter, s->stream);
+        hipError_t e = hipSuccess;
+        if (s->nitems > 0)
+            e = s->precision == ARLBM_F64 ? f64::step_batched(s->d_descs, s->d_items, s->nitems, s->iter, s->stream)
+                                          : f32::step_batched(s->d_descs, s->d_items, s->nitems, s->iter, s->stream);
         if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("batched launch: ") + hipGetErrorString(e));
+        // a 3D lattice's step is three passes over the whole lattice (the
+        // indicator needs every neighbour's moments first), launched on the
+        // same stream after the batched step
+        for (const Resident &r : s->resident) {
+            if (r.lat->desc.variant < V_ADV3) continue;
+            LatticeDesc d = r.lat->desc;
+            d.iter0 = r.iter0;
+            e = s->precision == ARLBM_F64 ? f64::step_single(d, s->iter, s->stream)
+                                          : f32::step_single(d, s->iter, s->stream);
+            if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("3D step launch: ") + hipGetErrorString(e));
+        }
         ++s->iter;
     }
     if (n_res) *n_res = (int32_t)s->resident.size();

@@ -4,8 +4,9 @@ FP64 bit for bit on 3D Euler (seeded octant data; a centred sphere with
 reflective walls; periodic, transmissive and mixed boundaries; a ragged
 non-cubic lattice), 3D advection and 3D reactive Euler; FP32 within the
 stated bound; time-targeted runs, the omega export, conservation sums,
-checkpoint/resume, and the server's refusal of 3D lattices.
+checkpoint/resume, and 3D lattices in the server's mix.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -141,11 +142,46 @@ def test_conservation_sums_3d(system):
     G.close()
 
 
-def test_server_refuses_3d():
-    require_gpu()
-    p = W.euler_octants_3d(seed=0, n=8)
-    srv = A.Server(1 << 30, A.F32)
-    with pytest.raises(A.ArlbmError) as e:
-        srv.submit(A.config_from(p, precision=A.F32), p.U0, None, 5)
-    assert e.value.code == A.EINVAL
+def _serve(probs, precision, one_at_a_time):
+    srv = A.Server(1 << 30, precision)
+    ids, res = [], {}
+    pending = list(probs)
+    while pending or len(res) < len(probs):
+        if pending and (not one_at_a_time or len(res) == len(ids)):
+            p = pending.pop(0)
+            ids.append(srv.submit(A.config_from(p, precision=precision), p.U0, p.bed, p.steps))
+        srv.iterate()
+        for c in srv.poll(16):
+            res[c["id"]] = c
     srv.close()
+    return [res[i] for i in ids]
+
+
+def test_3d_in_serving_mix():
+    """3D lattices served beside 1D and 2D ones (their passes launched after
+    the batched step): FP32 the same bits alone and in the mix and as a
+    single lattice; FP64 bit for bit with the oracle."""
+    require_gpu()
+    probs = [dataclasses.replace(W.euler_octants_3d(seed=1, n=24), steps=12),
+             W.euler_seeded_1d(3, n=3000, steps=40),
+             dataclasses.replace(W.reactive_sphere_3d(n=20), steps=9),
+             W.euler_seeded_2d(2, n=90, steps=30),
+             dataclasses.replace(W.advection_sine_3d(n=16), steps=15)]
+    mix, alone = _serve(probs, A.F32, False), _serve(probs, A.F32, True)
+    for p, a, b in zip(probs, alone, mix):
+        assert a["status"] == 0 and b["status"] == 0, p.name
+        assert np.array_equal(a["U"], b["U"]), p.name
+        if p.dim == 3:
+            G = gpu_lattice(p, A.F32)
+            G.step(p.steps)
+            G.sync()
+            assert np.array_equal(G.moments().reshape(-1), a["U"]), p.name
+            G.close()
+    mix64 = _serve(probs, A.F64, False)
+    for p, r in zip(probs, mix64):
+        Lo = ora_from(p)
+        Lo.run(p.steps)
+        assert r["status"] == 0 and r["steps"] == p.steps, p.name
+        assert np.array_equal(r["U"].reshape(Lo.moments().shape), Lo.moments()), p.name
+        assert r["t"] == Lo.t, p.name
+    say("[3d serving] alone == mix == single (FP32); FP64 served == oracle, 3D and 1D/2D")
