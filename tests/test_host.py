@@ -1,0 +1,57 @@
+"""Host-side checks that need no GPU: the plane layout the library reports
+for each strip width, the benchmark's refusal of more than one GPU, and that
+the committed rocprofv3 summaries were made from the current kernel sources
+(the benchmark reports HBM traffic only from a matching summary)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+from paper_2609_18177_amd import arlbm as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _swe_cfg(nx, ny, precision=A.F32):
+    c = A.Config()
+    c.abi_version = A.ABI_VERSION
+    c.system, c.dim, c.precision = A.SWE, 2, precision
+    c.nx, c.ny, c.nz = nx, ny, 1
+    c.x0, c.x1, c.y0, c.y1, c.z0, c.z1 = 0.0, 1.0, 0.0, ny / nx, 0.0, 1.0
+    c.cfl, c.eps, c.gamma, c.g = 0.5, 1e-10, 1.4, 9.81
+    c.h_dry, c.rho_floor, c.p_floor = 1e-6, 1e-12, 1e-12
+    c.has_bed = 1
+    return c
+
+
+@pytest.mark.parametrize("nx,precision,tail", [
+    (64, A.F32, 128),   # even nx: two columns per lane, a 128-element sink per plane
+    (65, A.F32, 64),    # odd nx: one column per lane
+    (64, A.F64, 128),   # FP64 shallow water also runs two columns per lane
+])
+def test_plane_tail_follows_strip_width(nx, precision, tail):
+    """The bed plane is one plane stride long (rounded up to 256 bytes)."""
+    size = 8 if precision == A.F64 else 4
+    s = A.query_sizes(_swe_cfg(nx, 64, precision))
+    stride = (nx * 64 + tail + 63) // 64 * 64
+    assert s.bed_bytes == (stride * size + 255) // 256 * 256
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+
+
+def test_profiles_match_kernel_sources():
+    sys.path.insert(0, ROOT)
+    import bench
+    h = bench.kernel_source_hash()
+    for name in ("euler2d_2048_f32", "euler2d_2048_f64", "swe2d_4096_f32", "euler3d_256_f32"):
+        with open(os.path.join(ROOT, "profiles", f"{name}_pmc.json")) as f:
+            rec = json.load(f)
+        assert rec["kernel_source_sha256_16"] == h, name
+        assert rec["hbm_bytes_per_launch"] > 0 and rec["avg_kernel_ns"] > 0, name
