@@ -822,16 +822,33 @@ int sfail(arlbm_server *s, int code, const std::string &msg)
     return code;
 }
 
+// Band height of the served 2D lattices, common to all of them: as tall as
+// keeps the launch at about ARLBM_SERVER_WAVES waves per SIMD from the 2D
+// lattices (each band pays five warm-up rows; one band height for all keeps
+// the waves' work even), at least 8 rows.  Measured on the default serving
+// mix (GLUPS): each lattice's own bands 16.6; 2 waves per SIMD 12.9, 8 16.1,
+// 32 17.4, 64 16.3, 128 16.4.  0 keeps each lattice's own bands.
+#ifndef ARLBM_SERVER_WAVES
+#define ARLBM_SERVER_WAVES 32
+#endif
 int rebuild_table(arlbm_server *s)
 {
     std::vector<LatticeDesc> descs;
     std::vector<WorkItem> items;
+    int64_t strip_rows = 0;
+    for (const Resident &r : s->resident) {
+        const LatticeDesc &d = r.lat->desc;
+        if (d.variant >= V_ADV2 && d.variant < V_ADV3) strip_rows += (d.nx + kOutW - 1) / kOutW * d.ny;
+    }
+    const int64_t target = 4 * (int64_t)num_cus() * std::max(ARLBM_SERVER_WAVES, 1);
+    const int64_t band = ARLBM_SERVER_WAVES > 0 ? std::max<int64_t>(8, strip_rows / target) : 0;
     for (size_t i = 0; i < s->resident.size(); ++i) {
         LatticeDesc d = s->resident[i].lat->desc;
         d.iter0 = s->resident[i].iter0;
         // the batched kernel runs every strip with one column per lane
         d.cpl = 1;
         d.ncols = (int32_t)((d.nx + kOutW - 1) / kOutW);
+        if (band > 0 && d.variant >= V_ADV2 && d.variant < V_ADV3) d.band_h = (int32_t)std::min<int64_t>(band, d.ny);
         descs.push_back(d);
         if (d.variant >= V_ADV3) continue;  // 3D lattices run their own passes
         const int64_t nb = d.variant >= V_ADV2 ? (d.ny + d.band_h - 1) / d.band_h : 1;
