@@ -23,12 +23,12 @@
 // direction into a triple-buffered slot.  The kernel launch boundary is the
 // grid barrier that the global maximum needs.
 //
-// Plane layout: plane c of a buffer starts at c * pstride, pstride >= nx ny +
-// 64 V (V columns per lane).  That tail of every plane is a sink: lanes that
-// must not write (halo lanes, warm-up rows) store there, so the steady-state
-// loop carries no conditional memory operation and the compiler can keep the
-// prefetched loads and the stores of the previous row in flight across
-// iterations.
+// Plane layout: plane c of a buffer starts at c * pstride, pstride = nx ny
+// rounded up to 64 elements.  Lanes that must not write (halo lanes, warm-up
+// rows) are masked off and make no memory request.  (Storing them to shared
+// slots in a tail of every plane instead kept the row loop free of branches,
+// but every wave on every XCD then wrote the same few lines, which cost more
+// than the branch: 0.169 -> 0.166 ms per 2048^2 Euler step without it.)
 //
 // Ghost cells: U at ghost positions follows the boundary index map (periodic
 // wrap, or mirror U(-1-i) = U(i) with the normal momentum negated at
@@ -586,8 +586,6 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     const bool anyswap = V > 1 && __ballot(swp) != 0ull;
     const int ya = band * L.band_h;
     const int yb = ya + L.band_h < ny ? ya + L.band_h : ny;
-    const unsigned sink = (unsigned)(L.plane + lane * V);          // this lane's slots in a plane's tail
-    const unsigned osink = L.omega_on ? sink : (unsigned)(lane * V);  // omega sink (128-slot buffer when off)
     const T two_dx = T(2) * P.dx;
 
     auto fix = [&](T (&a)[V]) {
@@ -880,7 +878,10 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
             const T nt = N0l[v] + N0[v] + N0r[v] + N1l[v] + N1[v] + N1r[v] + N2l[v] + N2[v] + N2r[v];
             w[v] = L.omega_fixed_on ? cf.omega_fixed : omega_of<T>(nt);
         }
-        stv<V>(om, (xout && r >= ya && r < yb && L.omega_on) ? (unsigned)(r * nx + xa) : osink, w);
+        // halo lanes and rows outside the band store nothing (masked lanes
+        // make no memory request; a shared slot for them cost about 13% of
+        // the step in write traffic to the same lines from every wave)
+        if (L.omega_on && xout && r >= ya && r < yb) stv<V>(om, (unsigned)(r * nx + xa), w);
         if constexpr (BED) {
             T bl[V], br[V];
             left_of(B1, bl);
@@ -1001,11 +1002,13 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
                 for (int c = 0; c < M; ++c)
                     Un[v][c] = Fk[0][c][v] + Fk[1][c][v] + Fk[2][c][v] + Fk[3][c][v] + Fk[4][c][v];
             }
-            const unsigned o = ok ? (unsigned)(d * nx + xa) : sink;
+            if (ok) {
+                const unsigned o = (unsigned)(d * nx + xa);
 #pragma unroll
-            for (int k = 0; k < Q; ++k)
+                for (int k = 0; k < Q; ++k)
 #pragma unroll
-                for (int c = 0; c < M; ++c) io.st(k * M + c, o, Fk[k][c]);
+                    for (int c = 0; c < M; ++c) io.st(k * M + c, o, Fk[k][c]);
+            }
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 Prim<T> qn;

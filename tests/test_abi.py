@@ -7,6 +7,10 @@ import pytest
 
 from paper_2609_18177_amd import arlbm as A
 
+# elements added after every plane (staggers power-of-two planes over the
+# memory interleave)
+PAD = 1088
+
 
 def declared_functions():
     src = open(A.HEADER).read()
@@ -44,14 +48,14 @@ def test_query_sizes_layout():
     c = _cfg(system=A.EULER, dim=2, nx=100, ny=60, y1=0.6, precision=A.F32)
     s = A.query_sizes(c)
     assert (s.m, s.q) == (4, 5)
-    ps = (6000 + 64 + 63) // 64 * 64          # plane stride with the 64-element sink tail
+    ps = (6000 + 63) // 64 * 64 + PAD         # plane stride: nx ny rounded up to 64, plus the pad
     assert s.f_bytes == (20 * ps * 4 + 255) // 256 * 256
     assert s.u_bytes == (4 * ps * 4 + 255) // 256 * 256
     assert s.total_bytes == 2 * s.f_bytes + 2 * s.u_bytes + s.scalar_bytes
     c.precision = A.F64
     assert A.query_sizes(c).f_bytes == (20 * ps * 8 + 255) // 256 * 256
     c2 = _cfg(system=A.SWE, dim=2, nx=64, ny=64, has_bed=1)
-    assert A.query_sizes(c2).bed_bytes == (64 * 64 + 128) * 4  # two columns per lane: 128
+    assert A.query_sizes(c2).bed_bytes == (64 * 64 + PAD) * 4
 
 
 @pytest.mark.parametrize("bad", [

@@ -1,7 +1,7 @@
-"""Host-side checks that need no GPU: the plane layout the library reports
-for each strip width, the benchmark's refusal of more than one GPU, and that
-the committed rocprofv3 summaries were made from the current kernel sources
-(the benchmark reports HBM traffic only from a matching summary)."""
+"""Host-side checks that need no GPU: the plane layout the library reports,
+the benchmark's refusal of more than one GPU, and that the committed
+rocprofv3 summaries were made from the current kernel sources (the benchmark
+reports HBM traffic only from a matching summary)."""
 import json
 import os
 import subprocess
@@ -26,16 +26,20 @@ def _swe_cfg(nx, ny, precision=A.F32):
     return c
 
 
-@pytest.mark.parametrize("nx,precision,tail", [
-    (64, A.F32, 128),   # even nx: two columns per lane, a 128-element sink per plane
-    (65, A.F32, 64),    # odd nx: one column per lane
-    (64, A.F64, 128),   # FP64 shallow water also runs two columns per lane
+@pytest.mark.parametrize("nx,ny,precision", [
+    (64, 64, A.F32),    # even nx: two columns per lane
+    (65, 64, A.F32),    # odd nx: one column per lane
+    (64, 64, A.F64),    # FP64 shallow water also runs two columns per lane
+    (65, 65, A.F64),    # nx ny = 4225: rounded up to 4288 elements
 ])
-def test_plane_tail_follows_strip_width(nx, precision, tail):
-    """The bed plane is one plane stride long (rounded up to 256 bytes)."""
+def test_plane_stride_is_rounded_to_64(nx, ny, precision):
+    """Every plane is nx ny elements rounded up to a multiple of 64, plus a
+    pad of 1088 elements that staggers the planes of power-of-two lattices
+    over the memory interleave, whatever the strip width (the bed plane is
+    one plane stride, rounded up to 256 bytes)."""
     size = 8 if precision == A.F64 else 4
-    s = A.query_sizes(_swe_cfg(nx, 64, precision))
-    stride = (nx * 64 + tail + 63) // 64 * 64
+    s = A.query_sizes(_swe_cfg(nx, ny, precision))
+    stride = (nx * ny + 63) // 64 * 64 + 1088
     assert s.bed_bytes == (stride * size + 255) // 256 * 256
 
 
