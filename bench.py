@@ -175,15 +175,16 @@ def run_latency_1d(torch, args):
     return out
 
 
-def run_serving(torch, args, n_requests, rate_hz, fp64_check, tag="serving"):
+def run_serving(torch, args, n_requests, rate_hz, fp64_check, tag="serving", budget_gib=None):
     """Continuous batching: Poisson arrivals admitted by HBM budget into the
     batched FP32 kernel; latency = result read back - arrival."""
+    budget_gib = args.budget_gib if budget_gib is None else budget_gib
     reqs = W.serving_requests(n_requests, rate_hz=rate_hz, seed=0)
     log(f"[{tag}] generating {len(reqs)} requests")
     t0 = time.perf_counter()
     probs = [r.problem() for r in reqs]
-    log(f"[{tag}] generated in {time.perf_counter() - t0:.1f}s; budget {args.budget_gib} GiB")
-    srv = A.Server(int(args.budget_gib * 2 ** 30), A.F32)
+    log(f"[{tag}] generated in {time.perf_counter() - t0:.1f}s; budget {budget_gib} GiB")
+    srv = A.Server(int(budget_gib * 2 ** 30), A.F32)
     cfgs = [A.config_from(p, precision=A.F32) for p in probs]
     results = {}
     nxt = 0
@@ -228,7 +229,7 @@ def run_serving(torch, args, n_requests, rate_hz, fp64_check, tag="serving"):
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "iterations": iters, "peak_resident_bytes": int(peak_mem), "offered_lups": int(lups),
            "offered_glups_over_arrivals": lups / span / 1e9, "arrival_span_s": span,
-           "iterate_time_fraction_with_work": busy / wall, "rate_hz": rate_hz, "budget_gib": args.budget_gib}
+           "iterate_time_fraction_with_work": busy / wall, "rate_hz": rate_hz, "budget_gib": budget_gib}
     # FP32 (batched) against the FP64 plain path on a subsample of requests
     errs = []
     for r in reqs[:fp64_check]:
@@ -293,6 +294,9 @@ def main():
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--budget-gib", type=float, default=4.0)
+    # a budget above the whole mix's footprint (about 30 GB at its peak), so
+    # that admission never waits for memory
+    ap.add_argument("--unlimited-gib", type=float, default=192.0)
     ap.add_argument("--fp64-check", type=int, default=12)
     ap.add_argument("--low-requests", type=int, default=64)
     ap.add_argument("--low-rate", type=float, default=8.0)
@@ -357,6 +361,10 @@ def main():
         # queueing; a run at a fraction of the capacity shows service latency
         extra["serving_low_rate"] = run_serving(torch, args, args.low_requests, args.low_rate, 4,
                                                 tag="serving-low")
+        # the default mix with a budget that never binds: every request is
+        # admitted on arrival
+        extra["serving_unlimited_budget"] = run_serving(torch, args, args.requests, args.rate, 4,
+                                                        tag="serving-unlimited", budget_gib=args.unlimited_gib)
     cpu = None if args.no_cpu else run_cpu_baseline(args)
     line = {
         "metric": METRIC, "value": glups, "unit": "GLUPS", "n_gpus": 1, "steps": args.steps,
