@@ -64,8 +64,8 @@ struct LatticeDesc {
     int64_t iter0;
     double t_stop;        // a launch whose state time is >= t_stop copies f unchanged (null step)
     int64_t plane;        // nx * ny * nz
-    int64_t pstride;      // elements between planes: plane + a sink tail of 64 cpl elements
-    int32_t omega_on;     // omega export plane present (else omega is a 128-slot sink)
+    int64_t pstride;      // elements between planes: plane rounded up to 64, plus a pad
+    int32_t omega_on;     // omega export plane present (else omega is null and never written)
     int32_t cpl;          // 2D: columns per lane of the step's strips (1, or 2 when nx is even)
     int32_t buf;          // 2D: population buffers below 4 GiB, addressed by buffer resources
     int32_t pad_;

@@ -24,7 +24,9 @@
 // grid barrier that the global maximum needs.
 //
 // Plane layout: plane c of a buffer starts at c * pstride, pstride = nx ny
-// rounded up to 64 elements.  Lanes that must not write (halo lanes, warm-up
+// rounded up to 64 elements plus a pad that keeps the planes of a
+// power-of-two lattice from all starting at the same offset of the memory
+// interleave.  Lanes that must not write (halo lanes, warm-up
 // rows) are masked off and make no memory request.  (Storing them to shared
 // slots in a tail of every plane instead kept the row loop free of branches,
 // but every wave on every XCD then wrote the same few lines, which cost more
