@@ -14,7 +14,9 @@ Checks per case: FP64 bit for bit with the oracle; FP32 against the oracle
 (relative L1 over all fields, bound below); the exported FP32 relaxation
 parameter of the first step against the oracle's; FP32 single lattice
 against the same lattice in the FP32 batched server (one column per lane),
-relative L1.
+relative L1.  A further test fills both population buffers with a byte
+pattern and checks that the steps write nothing outside the lattice cells
+of each plane (the masked halo lanes and warm-up rows).
 """
 import dataclasses
 
@@ -151,3 +153,69 @@ def test_two_columns_null_steps():
     say(f"[strips null steps] k={k} t={st['t']} bitwise={np.array_equal(U1, U2)}")
     assert k > 0 and st["step"] == k and st["t"] >= 0.02
     assert np.array_equal(U1, U2) and st["t"] == st2["t"]
+
+
+SENTINEL = 0xA5  # byte pattern of the padding (0xA5A5A5A5 is a finite float32, -2.9e-16)
+
+
+@pytest.mark.parametrize("name,prec", [
+    ("euler 250x70 transmissive", A.F32), ("euler 251x70 odd nx", A.F64),
+    ("swe bed 250x250 reflective", A.F32), ("swe bed 240x256 periodic", A.F64),
+    ("advection 130x40 periodic", A.F32), ("reactive 244x70 reflective", A.F32),
+])
+def test_steps_write_only_lattice_cells(name, prec):
+    """Masked lanes (halo lanes, warm-up rows) store nothing: after the step,
+    every byte of both population buffers outside the nx ny cells of each
+    plane (the pad after every plane, the tail of the buffer) still holds
+    the byte pattern written before, and the results equal a run on
+    buffers that were not pre-filled, bit for bit."""
+    require_gpu()
+    p = dataclasses.replace(CASES[name](), steps=7)
+    cfg = A.config_from(p, precision=prec)
+    size = 8 if prec == A.F64 else 4
+    planes = cfg.nx * cfg.ny
+    nplanes = (5 if p.dim == 2 else 3) * A.query_sizes(cfg).m
+    ref = gpu_lattice(p, prec)
+    ref.step(p.steps)
+    ref.sync()
+    Uref = ref.moments()
+    ref.close()
+    L = A.Lattice(cfg, owner="torch")
+    f_bytes = L.sizes.f_bytes
+    # the binding allocates f[0], u[0], f[1], u[1] in this order, each at a
+    # 256-byte aligned offset of its tensor
+    fts = [L._tensors[0], L._tensors[2]]
+    views = []
+    for t in fts:
+        off = (-t.data_ptr()) % 256
+        views.append(t[off:off + f_bytes])
+    views[0].fill_(SENTINEL)
+    L.set_state(p.U0, p.bed)
+    views[1].fill_(SENTINEL)  # f[1] holds nothing before the first step
+    L.step(p.steps)
+    st = L.sync()
+    # read the buffers before the moments: FP32 read-back converts the moments
+    # to FP64 in the population buffer the next step would write
+    raw = [v.cpu().numpy() for v in views]
+    U = L.moments()
+    ps = (planes + 63) // 64 * 64 + 1088
+    ok = True
+    for bi, b in enumerate(raw):
+        body = b[:nplanes * ps * size].reshape(nplanes, ps * size)
+        pad = body[:, planes * size:]
+        pad_ok = bool(np.all(pad == SENTINEL))
+        tail_ok = bool(np.all(b[nplanes * ps * size:] == SENTINEL))
+        if not (pad_ok and tail_ok):
+            bad = np.argwhere(pad != SENTINEL)
+            el = np.unique(bad[:, 1] // size)
+            dt = np.float64 if size == 8 else np.float32
+            vals = pad.view(dt)[bad[0, 0], el[:6]] if len(bad) else []
+            say(f"[pads {name}] buffer f[{bi}]: {len(bad)} bytes changed in the pads of planes "
+                f"{np.unique(bad[:, 0])[:8]}..., element offsets after the plane {el[:12]}..., values {vals}; "
+                f"tail ok={tail_ok}")
+        ok = ok and pad_ok and tail_ok
+    L.close()
+    say(f"[pads {name} prec={prec}] pads and tails untouched={ok} results bitwise={np.array_equal(U, Uref)} "
+        f"flags {st['flags']}")
+    assert ok
+    assert np.array_equal(U, Uref)
