@@ -1,7 +1,7 @@
 """Build libarlbm.so in-tree for gfx950 with hipcc.
 
-The kernel source is compiled twice: FP32 (contraction allowed) and FP64
-(-ffp-contract=off, so every rounding follows the written expression order).
+The kernel source is compiled twice, FP32 and FP64, both with
+-ffp-contract=off, so every rounding follows the written expression order.
 All device code is built with packed-FP32 instructions disabled.
 """
 import os
@@ -34,10 +34,13 @@ def build(verbose: bool = False) -> str:
     k64 = os.path.join(OUT, "kernels_f64.o")
     rt = os.path.join(OUT, "runtime.o")
     kern = os.path.join(SRC, "kernels.hip")
-    # FP32: hardware reciprocal / square root (about 1 ulp) instead of the
-    # correctly rounded sequences, and denormals flushed to zero
+    # FP32: hardware reciprocal / square root (about 1 ulp; the kernels name
+    # them explicitly), denormals flushed to zero, and no contraction of
+    # a*b+c, so that every kernel rounds each expression as written: the
+    # single-lattice kernels (one or two columns per lane) and the batched one
+    # then give the same bits for any band decomposition
     _run([HIPCC, *DEVICE_FLAGS, "-DARLBM_F64=0", "-fno-hip-fp32-correctly-rounded-divide-sqrt",
-          "-fgpu-flush-denormals-to-zero", "-c", kern, "-o", k32], verbose)
+          "-fgpu-flush-denormals-to-zero", "-ffp-contract=off", "-c", kern, "-o", k32], verbose)
     _run([HIPCC, *DEVICE_FLAGS, "-DARLBM_F64=1", "-ffp-contract=off", "-c", kern, "-o", k64], verbose)
     _run([HIPCC, "-std=c++17", "-O2", "-fPIC", "-Wall", "-x", "c++", "-D__HIP_PLATFORM_AMD__",
           "-I/opt/rocm/include", "-I" + INCLUDE, "-c", os.path.join(SRC, "runtime.cpp"), "-o", rt], verbose)

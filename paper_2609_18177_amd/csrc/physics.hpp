@@ -30,12 +30,25 @@ struct Phys {
     double h_dry, rho_floor, p_floor;
 };
 
+// Division and square root in the storage precision.  FP64: the IEEE
+// quotient and root (the oracle's arithmetic).  FP32: the hardware reciprocal
+// and root (about 1 ulp), named explicitly, so that every kernel and every
+// inlined copy rounds the same way.  Left to the compiler, a quotient it
+// speculates or merges (under a select, say) can fall back to the correctly
+// rounded sequence in one kernel and not in another, and a one-ulp difference
+// in the wave-speed bound then moves every cell of the next step.
+template <typename T>
+__device__ __forceinline__ T ddiv(T a, T b);
+template <>
+__device__ __forceinline__ double ddiv<double>(double a, double b) { return a / b; }
+template <>
+__device__ __forceinline__ float ddiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 template <typename T>
 __device__ __forceinline__ T dsqrt(T v);
 template <>
 __device__ __forceinline__ double dsqrt<double>(double v) { return __builtin_sqrt(v); }
 template <>
-__device__ __forceinline__ float dsqrt<float>(float v) { return __builtin_sqrtf(v); }
+__device__ __forceinline__ float dsqrt<float>(float v) { return __builtin_amdgcn_sqrtf(v); }
 
 template <typename T>
 __device__ __forceinline__ T dabs(T v) { return __builtin_fabs(v); }
@@ -72,15 +85,15 @@ __device__ __forceinline__ void primitives(const T *U, const Phys<T> &P, Prim<T>
         q.rho = U[0];
         q.E = U[D + 1];
         q.mom[0] = U[1];
-        q.vel[0] = U[1] / q.rho;
+        q.vel[0] = ddiv<T>(U[1], q.rho);
         T q2;
         if constexpr (D >= 2) {
             q.mom[1] = U[2];
-            q.vel[1] = U[2] / q.rho;
+            q.vel[1] = ddiv<T>(U[2], q.rho);
             q2 = q.vel[0] * q.vel[0] + q.vel[1] * q.vel[1];
             if constexpr (D == 3) {
                 q.mom[2] = U[3];
-                q.vel[2] = U[3] / q.rho;
+                q.vel[2] = ddiv<T>(U[3], q.rho);
                 q2 = q2 + q.vel[2] * q.vel[2];
             }
         } else {
@@ -90,24 +103,24 @@ __device__ __forceinline__ void primitives(const T *U, const Phys<T> &P, Prim<T>
             q.p = P.gm1 * (q.E - T(0.5) * q.rho * q2);
         } else {
             q.Z = U[D + 2];
-            q.Y = q.Z / q.rho;
+            q.Y = ddiv<T>(q.Z, q.rho);
             q.p = P.gm1 * ((q.E - T(0.5) * q.rho * q2) - P.qh * q.Z);
         }
         const bool pok = double(q.p) > P.p_floor, rok = double(q.rho) > P.rho_floor;
         const T pf = pok ? q.p : P.p_floor_t;
         const T rf = rok ? q.rho : P.rho_floor_t;
         if (!(pok && rok)) q.flags |= 2u;
-        q.c = dsqrt<T>(P.gamma * pf / rf);
+        q.c = dsqrt<T>(ddiv<T>(P.gamma * pf, rf));
         q.cL = q.c;
     } else if constexpr (SYS == 2) {
         const T h = U[0];
         q.rho = h;
         const bool wet = double(h) > P.h_dry;
         q.mom[0] = wet ? U[1] : T(0);
-        q.vel[0] = wet ? U[1] / h : T(0);
+        q.vel[0] = wet ? ddiv<T>(U[1], h) : T(0);
         if constexpr (D == 2) {
             q.mom[1] = wet ? U[2] : T(0);
-            q.vel[1] = wet ? U[2] / h : T(0);
+            q.vel[1] = wet ? ddiv<T>(U[2], h) : T(0);
         }
         if (double(h) < -P.h_dry) q.flags |= 2u;
         q.c = dsqrt<T>(P.g * (h > T(0) ? h : T(0)));
@@ -155,7 +168,7 @@ template <typename T>
 __device__ __forceinline__ T theta(T dm, T dp, T dx)
 {
     const T adm = dabs<T>(dm), adp = dabs<T>(dp);
-    return dabs<T>(dp - dm) / (adm + adp + dx) + adm + adp;
+    return ddiv<T>(dabs<T>(dp - dm), adm + adp + dx) + adm + adp;
 }
 
 // Adds sum_r theta^(r,dir) to nu, with L_dir evaluated at the centre state
@@ -179,12 +192,12 @@ __device__ __forceinline__ void add_theta(int dir, const Prim<T> &qc, const T *U
         // increasing order), [species,] u+c; columns rho, m_x, m_y, m_z, E[, rho Y]
         const T cs = qc.c;
         const T q2 = (qc.vel[0] * qc.vel[0] + qc.vel[1] * qc.vel[1]) + qc.vel[2] * qc.vel[2];
-        const T b1 = P.gm1 / (cs * cs);
+        const T b1 = ddiv<T>(P.gm1, cs * cs);
         const T b2 = T(0.5) * q2 * b1;
         const T un = qc.vel[dir];
         const T hb1 = T(0.5) * b1;
-        const T r0c0 = T(0.5) * (b2 + un / cs), r0cn = T(-0.5) * (b1 * un + T(1) / cs);
-        const T r3c0 = T(0.5) * (b2 - un / cs), r3cn = T(-0.5) * (b1 * un - T(1) / cs);
+        const T r0c0 = T(0.5) * (b2 + ddiv<T>(un, cs)), r0cn = T(-0.5) * (b1 * un + ddiv<T>(T(1), cs));
+        const T r3c0 = T(0.5) * (b2 - ddiv<T>(un, cs)), r3cn = T(-0.5) * (b1 * un - ddiv<T>(T(1), cs));
         T r0[3], r3[3], r1[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -229,13 +242,13 @@ __device__ __forceinline__ void add_theta(int dir, const Prim<T> &qc, const T *U
         T q2;
         if constexpr (D == 2) q2 = qc.vel[0] * qc.vel[0] + qc.vel[1] * qc.vel[1];
         else q2 = qc.vel[0] * qc.vel[0];
-        const T b1 = P.gm1 / (cs * cs);
+        const T b1 = ddiv<T>(P.gm1, cs * cs);
         const T b2 = T(0.5) * q2 * b1;
         const T un = qc.vel[dir];
-        const T r0c0 = T(0.5) * (b2 + un / cs);
-        const T r0cn = T(-0.5) * (b1 * un + T(1) / cs);
-        const T r3c0 = T(0.5) * (b2 - un / cs);
-        const T r3cn = T(-0.5) * (b1 * un - T(1) / cs);
+        const T r0c0 = T(0.5) * (b2 + ddiv<T>(un, cs));
+        const T r0cn = T(-0.5) * (b1 * un + ddiv<T>(T(1), cs));
+        const T r3c0 = T(0.5) * (b2 - ddiv<T>(un, cs));
+        const T r3cn = T(-0.5) * (b1 * un - ddiv<T>(T(1), cs));
         const T hb1 = T(0.5) * b1;
         const T r1c0 = T(1) - b2;
         if constexpr (D == 1) {
@@ -278,13 +291,13 @@ __device__ __forceinline__ void add_theta(int dir, const Prim<T> &qc, const T *U
         T q2;
         if constexpr (D == 2) q2 = qc.vel[0] * qc.vel[0] + qc.vel[1] * qc.vel[1];
         else q2 = qc.vel[0] * qc.vel[0];
-        const T b1 = P.gm1 / (cs * cs);
+        const T b1 = ddiv<T>(P.gm1, cs * cs);
         const T b2 = T(0.5) * q2 * b1;
         const T un = qc.vel[dir];
-        const T r0c0 = T(0.5) * (b2 + un / cs);
-        const T r0cn = T(-0.5) * (b1 * un + T(1) / cs);
-        const T r3c0 = T(0.5) * (b2 - un / cs);
-        const T r3cn = T(-0.5) * (b1 * un - T(1) / cs);
+        const T r0c0 = T(0.5) * (b2 + ddiv<T>(un, cs));
+        const T r0cn = T(-0.5) * (b1 * un + ddiv<T>(T(1), cs));
+        const T r3c0 = T(0.5) * (b2 - ddiv<T>(un, cs));
+        const T r3cn = T(-0.5) * (b1 * un - ddiv<T>(T(1), cs));
         const T hb1 = T(0.5) * b1;
         const T r1c0 = T(1) - b2;
         const T zac = -(P.qh * hb1);  // rho Y entry of the acoustic rows
@@ -333,10 +346,10 @@ __device__ __forceinline__ void add_theta(int dir, const Prim<T> &qc, const T *U
     } else {
         const T cs = qc.cL;
         const T un = qc.vel[dir];
-        const T l00 = (un + cs) / (T(2) * cs);
-        const T l0n = T(-1) / (T(2) * cs);
-        const T l20 = (-(un - cs)) / (T(2) * cs);
-        const T l2n = T(1) / (T(2) * cs);
+        const T l00 = ddiv<T>(un + cs, T(2) * cs);
+        const T l0n = ddiv<T>(T(-1), T(2) * cs);
+        const T l20 = ddiv<T>(-(un - cs), T(2) * cs);
+        const T l2n = ddiv<T>(T(1), T(2) * cs);
         const T an = a[1 + dir], bn = b[1 + dir];
         const T dm0 = l00 * a[0] + l0n * an;
         const T dp0 = l00 * b[0] + l0n * bn;
@@ -401,11 +414,11 @@ __device__ __forceinline__ T arrhenius_rate(const Phys<T> &P, T rho, T e_int, T 
     const bool pok = double(p) > P.p_floor, rok = double(rho) > P.rho_floor;
     const T pf = pok ? p : P.p_floor_t;
     const T rf = rok ? rho : P.rho_floor_t;
-    const T Tm = pf / rf;
-    const T e = T(arrhenius_exp(double(-(P.ti / Tm))));
+    const T Tm = ddiv<T>(pf, rf);
+    const T e = T(arrhenius_exp(double(-ddiv<T>(P.ti, Tm))));
     const T R = (P.kr * z) * e;
     if (dRdz) {
-        const T dlog = pok ? (P.ti * rf) * (P.gm1 * P.qh) / (pf * pf) : T(0);
+        const T dlog = pok ? ddiv<T>((P.ti * rf) * (P.gm1 * P.qh), pf * pf) : T(0);
         *dRdz = P.kr * e * (T(1) - z * dlog);
     }
     return R;
@@ -416,11 +429,11 @@ __device__ __forceinline__ T arrhenius_rate(const Phys<T> &P, T rho, T e_int, T 
 template <int D, typename T>
 __device__ __forceinline__ T reactive_eint(const T *U)
 {
-    const T u0 = U[1] / U[0];
-    const T u1 = D >= 2 ? U[2] / U[0] : T(0);
+    const T u0 = ddiv<T>(U[1], U[0]);
+    const T u1 = D >= 2 ? ddiv<T>(U[2], U[0]) : T(0);
     T q2 = u0 * u0 + u1 * u1;
     if constexpr (D == 3) {
-        const T u2 = U[3] / U[0];
+        const T u2 = ddiv<T>(U[3], U[0]);
         q2 = q2 + u2 * u2;
     }
     return U[D + 1] - T(0.5) * U[0] * q2;
@@ -443,7 +456,7 @@ __device__ __forceinline__ T reactive_solve(const Phys<T> &P, T rho, T e_int, T 
         if (g > T(0)) hi = z;
         else lo = z;
         const T dg = T(1) + half_dt * dR;
-        T zn = z - g / dg;
+        T zn = z - ddiv<T>(g, dg);
         if (dg > T(0) && zn == z) break;  // the Newton step no longer moves z
         if (!(dg > T(0)) || !(zn > lo && zn < hi)) zn = T(0.5) * (lo + hi);
         if (zn == z) break;

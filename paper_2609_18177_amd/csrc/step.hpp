@@ -338,7 +338,7 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
         has_bed = L.bed != nullptr;
         if (has_bed) {
             const T b = ((const T *)L.bed)[xm];
-            db = (from_right(b) - from_left(b)) / (T(2) * P.dx);
+            db = ddiv<T>(from_right(b) - from_left(b), T(2) * P.dx);
         }
     }
 
@@ -890,8 +890,8 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
             right_of(B1, br);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                dbx[v] = (br[v] - bl[v]) / two_dx;
-                dby[v] = (B2[v] - B0[v]) / two_dx;
+                dbx[v] = ddiv<T>(br[v] - bl[v], two_dx);
+                dby[v] = ddiv<T>(B2[v] - B0[v], two_dx);
             }
         }
         // equilibrium (2.20) and collision at the source nodes of row r
