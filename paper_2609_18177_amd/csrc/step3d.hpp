@@ -63,42 +63,54 @@ __device__ __forceinline__ Slab slab_of(int64_t total)
     return r;
 }
 
-// Column tiles of kTX x kTY cells marching in z.  An iteration index g maps
-// to (tile, z, offset in the tile) with the offset fastest, then z, then the
-// tile: cells a plane apart are kTX kTY iterations apart and those a row apart
-// kTX, so a cell's neighbours are fetched by the same XCD at about the same
-// time, and the working set of a tile column (a few planes of 1024 cells)
-// stays in L2 where a whole lattice plane would not.  Tiles overhanging the
-// lattice leave their outside cells idle.
+// Column tiles of TX x (1024 / TX) cells marching in z.  An iteration index
+// g maps to (tile, z, offset in the tile) with the offset fastest, then z,
+// then the tile: cells a plane apart are 1024 iterations apart and those a
+// row apart TX, so a cell's neighbours are fetched by the same XCD at about
+// the same time, and the working set of a tile column (a few planes of 1024
+// cells) stays in L2 where a whole lattice plane would not.  Tiles
+// overhanging the lattice leave their outside cells idle.  The indicator pass
+// walks the lattice padded by one cell (nx + 2 wide), where a 256-wide tile
+// would leave most of a second tile idle.  Measured (ms per 256^3 FP32 Euler
+// step): all passes 64 x 16 / 128 x 8 / 256 x 4: 1.75 / 1.70 / 1.69; collide
+// 1.30 ms at 128 x 8 and 1.23 at 256 x 4, indicator 0.31 and 0.36.
 #ifndef ARLBM_3D_TX
-#define ARLBM_3D_TX 128
+#define ARLBM_3D_TX 256
 #endif
-constexpr int kTileShift = 10, kTX = ARLBM_3D_TX, kTY = (1 << kTileShift) / kTX;
-static_assert(kTX * kTY == 1 << kTileShift, "tile size");
+#ifndef ARLBM_3D_NU_TX
+#define ARLBM_3D_NU_TX 128
+#endif
+constexpr int kTileShift = 10;
+template <int TX>
 struct Tiling {
+    static constexpr int kTY = (1 << kTileShift) / TX;
+    static_assert(TX * kTY == 1 << kTileShift, "tile size");
     int nx, ny, nz, ntx;
     int64_t total;
 };
-__device__ __forceinline__ Tiling tiling_of(int nx, int ny, int nz)
+template <int TX>
+__device__ __forceinline__ Tiling<TX> tiling_of(int nx, int ny, int nz)
 {
-    Tiling t;
+    constexpr int kTY = Tiling<TX>::kTY;
+    Tiling<TX> t;
     t.nx = nx;
     t.ny = ny;
     t.nz = nz;
-    t.ntx = (nx + kTX - 1) / kTX;
+    t.ntx = (nx + TX - 1) / TX;
     const int nty = (ny + kTY - 1) / kTY;
     t.total = ((int64_t)t.ntx * nty * nz) << kTileShift;
     return t;
 }
-__device__ __forceinline__ bool tile_cell(const Tiling &t, int64_t g, int &i, int &j, int &l)
+template <int TX>
+__device__ __forceinline__ bool tile_cell(const Tiling<TX> &t, int64_t g, int &i, int &j, int &l)
 {
     const int o = (int)(g & ((1 << kTileShift) - 1));
     const unsigned rest = (unsigned)(g >> kTileShift);
     const unsigned tile = rest / (unsigned)t.nz;
     l = (int)(rest - tile * (unsigned)t.nz);
     const unsigned ty = tile / (unsigned)t.ntx;
-    i = (int)(tile - ty * (unsigned)t.ntx) * kTX + (o & (kTX - 1));
-    j = (int)ty * kTY + (o / kTX);
+    i = (int)(tile - ty * (unsigned)t.ntx) * TX + (o & (TX - 1));
+    j = (int)ty * Tiling<TX>::kTY + (o / TX);
     return i < t.nx && j < t.ny;
 }
 
@@ -130,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k3_nu(LatticeDesc L, int64_t iter)
     T *nu_out = (T *)L.nu3;
     const int px = L.nx + 2, py = L.ny + 2;
     const int64_t npad = (int64_t)px * py * (L.nz + 2);
-    const Tiling tl = tiling_of(px, py, L.nz + 2);
+    const auto tl = tiling_of<ARLBM_3D_NU_TX>(px, py, L.nz + 2);
     const Slab sl = slab_of(tl.total);
     for (int64_t g = sl.first; g < sl.end; g += sl.step) {
         int i, j, l;
@@ -183,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void k3_omega(LatticeDesc L, int64_t iter)
     const int64_t npad = (int64_t)(L.nx + 2) * (L.ny + 2) * (L.nz + 2);
     T *w_out = (T *)L.nu3 + npad;
     const T wfix = T(L.omega_fixed);
-    const Tiling tl = tiling_of(L.nx, L.ny, L.nz);
+    const auto tl = tiling_of<ARLBM_3D_TX>(L.nx, L.ny, L.nz);
     const Slab sl = slab_of(tl.total);
     for (int64_t g = sl.first; g < sl.end; g += sl.step) {
         int i, j, l;
@@ -239,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k3_collide(LatticeDesc L, int64_t iter
     unsigned flags = 0;
     // every lane of a wave runs the same number of iterations (the reduction
     // below needs the whole wave)
-    const Tiling tl = tiling_of(L.nx, L.ny, L.nz);
+    const auto tl = tiling_of<ARLBM_3D_TX>(L.nx, L.ny, L.nz);
     const Slab sl = slab_of(tl.total);
     for (int64_t g = sl.first; g < sl.lim; g += sl.step) {
         int i = 0, j = 0, l = 0;
