@@ -73,12 +73,18 @@ __device__ __forceinline__ Slab slab_of(int64_t total)
 // walks the lattice padded by one cell (nx + 2 wide), where a 256-wide tile
 // would leave most of a second tile idle.  Measured (ms per 256^3 FP32 Euler
 // step): all passes 64 x 16 / 128 x 8 / 256 x 4: 1.75 / 1.70 / 1.69; collide
-// 1.30 ms at 128 x 8 and 1.23 at 256 x 4, indicator 0.31 and 0.36.
+// 1.30 ms at 128 x 8 and 1.23 at 256 x 4, indicator 0.31 and 0.36; with the
+// collide and relaxation passes at 256 x 4, the indicator at 128 x 8 / 64 x
+// 16: 1.645 / 1.638 (FP64 3.264 / 3.236); the relaxation no better at 128 or
+// 64 wide.
 #ifndef ARLBM_3D_TX
 #define ARLBM_3D_TX 256
 #endif
 #ifndef ARLBM_3D_NU_TX
-#define ARLBM_3D_NU_TX 128
+#define ARLBM_3D_NU_TX 64
+#endif
+#ifndef ARLBM_3D_OM_TX
+#define ARLBM_3D_OM_TX ARLBM_3D_TX
 #endif
 constexpr int kTileShift = 10;
 template <int TX>
@@ -195,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k3_omega(LatticeDesc L, int64_t iter)
     const int64_t npad = (int64_t)(L.nx + 2) * (L.ny + 2) * (L.nz + 2);
     T *w_out = (T *)L.nu3 + npad;
     const T wfix = T(L.omega_fixed);
-    const auto tl = tiling_of<ARLBM_3D_TX>(L.nx, L.ny, L.nz);
+    const auto tl = tiling_of<ARLBM_3D_OM_TX>(L.nx, L.ny, L.nz);
     const Slab sl = slab_of(tl.total);
     for (int64_t g = sl.first; g < sl.end; g += sl.step) {
         int i, j, l;
