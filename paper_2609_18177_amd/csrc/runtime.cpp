@@ -302,6 +302,17 @@ int check_state(arlbm_lattice *h, const double *U0, const double *bed)
     return ARLBM_OK;
 }
 
+// The wave-speed bound of direction dir in a slot: the max over the slot's
+// copies (non-negative doubles order like their bit patterns).
+double abar_host(const DevScalars &sc, int slot, int dir)
+{
+    unsigned long long m = 0;
+    for (int c = 0; c < kAbarCopies; ++c) m = std::max(m, sc.abar[slot][c].v[dir]);
+    double d;
+    std::memcpy(&d, &m, sizeof d);
+    return d;
+}
+
 int read_scalars(arlbm_lattice *h, DevScalars *out)
 {
     HIPCHK(h, hipMemcpyAsync(out, h->desc.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, h->stream));
@@ -342,9 +353,9 @@ int set_state_impl(arlbm_lattice *h, const double *U0, const double *bed, bool o
     int rc = read_scalars(h, &got);
     if (rc) return rc;
     h->step = 0;
-    const double ab0 = *(double *)&got.abar[0][0];
-    const double ab1 = h->cfg.dim >= 2 ? *(double *)&got.abar[0][1] : 0.0;
-    const double ab2 = h->cfg.dim == 3 ? *(double *)&got.abar[0][2] : 0.0;
+    const double ab0 = abar_host(got, 0, 0);
+    const double ab1 = h->cfg.dim >= 2 ? abar_host(got, 0, 1) : 0.0;
+    const double ab2 = h->cfg.dim == 3 ? abar_host(got, 0, 2) : 0.0;
     const double sa = (ab0 + ab1) + ab2;
     if (!(sa > 0.0)) return fail(h, ARLBM_EDEGENERATE, "sum of wave-speed bounds is zero: time step undefined");
     // Theorem 4.3: 0 < eps < (1/d)(1/CFL - 1) sum_j alpha_bar_j
@@ -576,9 +587,9 @@ extern "C" int arlbm_sync(arlbm_lattice *h, arlbm_status *st)
         const int slot = (int)(h->step % 3);
         st->t = sc.t[slot];
         st->last_dt = sc.last_dt;
-        st->abar[0] = *(double *)&sc.abar[slot][0];
-        st->abar[1] = h->cfg.dim >= 2 ? *(double *)&sc.abar[slot][1] : 0.0;
-        st->abar[2] = h->cfg.dim == 3 ? *(double *)&sc.abar[slot][2] : 0.0;
+        st->abar[0] = abar_host(sc, slot, 0);
+        st->abar[1] = h->cfg.dim >= 2 ? abar_host(sc, slot, 1) : 0.0;
+        st->abar[2] = h->cfg.dim == 3 ? abar_host(sc, slot, 2) : 0.0;
         st->step = h->step - (int64_t)sc.null_launches;
         st->flags = sc.flags;
         st->first_bad_step = sc.first_bad_step == ~0ull ? -1 : (int64_t)sc.first_bad_step;

@@ -144,14 +144,37 @@ struct Coefs {
     double dt;
 };
 
+// Wave-speed bound of direction dir in a slot: the max over the slot's
+// copies, lane l reading copy l.  Every lane of the wave takes part; the
+// result is the same in all lanes (made uniform).
+__device__ __forceinline__ double abar_of(const DevScalars *sc, int slot, int dir)
+{
+    static_assert(kAbarCopies == kWave, "one copy per lane");
+    double v = bitsd(sc->abar[slot][threadIdx.x & (kWave - 1)].v[dir]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double w = __shfl_xor(v, o, kWave);
+        v = w > v ? w : v;
+    }
+    const unsigned long long b = dbits(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return bitsd(((unsigned long long)hi << 32) | lo);
+}
+// Copy of a slot this wave maxes into.
+__device__ __forceinline__ int abar_copy()
+{
+    return (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kAbarCopies - 1));
+}
+
 template <int D, typename T>
 __device__ __forceinline__ bool step_coefs(const LatticeDesc &L, int64_t n, Coefs<T> &cf)
 {
     const DevScalars *sc = L.sc;
     const int slot = (int)(n % 3);
-    const double ab0 = bitsd(sc->abar[slot][0]);
-    const double ab1 = D >= 2 ? bitsd(sc->abar[slot][1]) : 0.0;
-    const double ab2 = D == 3 ? bitsd(sc->abar[slot][2]) : 0.0;
+    const double ab0 = abar_of(sc, slot, 0);
+    const double ab1 = D >= 2 ? abar_of(sc, slot, 1) : 0.0;
+    const double ab2 = D == 3 ? abar_of(sc, slot, 2) : 0.0;
     const double sa = D == 3 ? (ab0 + ab1) + ab2 : (D == 2 ? ab0 + ab1 : ab0);
     if (!(sa > 0.0) || !(sa < 1.0e300)) return false;
     const double dt = L.cfl * L.dx / sa;
@@ -194,17 +217,21 @@ __device__ __forceinline__ Phys<T> make_phys(const LatticeDesc &L)
     return P;
 }
 
-// Work of the lattice's first wave in a launch: advance t, record dt, clear
-// the slot that the next step will max into.
+// Work of the lattice's first wave in a launch (all its lanes): advance t,
+// record dt, clear the slot that the next step will max into (lane l clears
+// copy l).
 __device__ __forceinline__ void scalar_update(const LatticeDesc &L, int64_t n, double dt)
 {
     DevScalars *sc = L.sc;
-    sc->t[(n + 1) % 3] = sc->t[n % 3] + dt;
-    sc->last_dt = dt;
-    const int clr = (int)((n + 2) % 3);
-    sc->abar[clr][0] = 0ull;
-    sc->abar[clr][1] = 0ull;
-    sc->abar[clr][2] = 0ull;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (lane == 0) {
+        sc->t[(n + 1) % 3] = sc->t[n % 3] + dt;
+        sc->last_dt = dt;
+    }
+    AbarCopy &c = sc->abar[(n + 2) % 3][lane];
+    c.v[0] = 0ull;
+    c.v[1] = 0ull;
+    c.v[2] = 0ull;
 }
 
 // A launch whose state time has reached the stop time leaves the state
@@ -214,18 +241,23 @@ __device__ __forceinline__ bool stopped(const LatticeDesc &L, int64_t n)
 {
     return L.sc->t[n % 3] >= L.t_stop;
 }
+// (all lanes of the lattice's first wave; lane l carries and clears copy l)
 __device__ __forceinline__ void null_scalars(const LatticeDesc &L, int64_t n)
 {
     DevScalars *sc = L.sc;
-    sc->t[(n + 1) % 3] = sc->t[n % 3];
-    sc->null_launches = sc->null_launches + 1ull;
-    sc->abar[(n + 1) % 3][0] = sc->abar[n % 3][0];
-    sc->abar[(n + 1) % 3][1] = sc->abar[n % 3][1];
-    sc->abar[(n + 1) % 3][2] = sc->abar[n % 3][2];
-    const int clr = (int)((n + 2) % 3);
-    sc->abar[clr][0] = 0ull;
-    sc->abar[clr][1] = 0ull;
-    sc->abar[clr][2] = 0ull;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (lane == 0) {
+        sc->t[(n + 1) % 3] = sc->t[n % 3];
+        sc->null_launches = sc->null_launches + 1ull;
+    }
+    const AbarCopy &from = sc->abar[n % 3][lane];
+    AbarCopy &to = sc->abar[(n + 1) % 3][lane];
+    AbarCopy &clr = sc->abar[(n + 2) % 3][lane];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        to.v[d] = from.v[d];
+        clr.v[d] = 0ull;
+    }
 }
 template <typename T>
 __device__ __forceinline__ void null_copy(const LatticeDesc &L, int64_t n, int planes, int x, bool xout, int ya,
@@ -239,7 +271,7 @@ __device__ __forceinline__ void null_copy(const LatticeDesc &L, int64_t n, int p
                 const unsigned o = (unsigned)(y * L.nx + x);
                 sto(fout + (size_t)p * L.pstride, o, ldo(fin + (size_t)p * L.pstride, o));
             }
-    if (first && (threadIdx.x & 63) == 0) null_scalars(L, n);
+    if (first) null_scalars(L, n);
 }
 
 __device__ __forceinline__ void flag_degenerate(const LatticeDesc &L, int64_t n)
@@ -261,10 +293,10 @@ __device__ __forceinline__ void commit(const LatticeDesc &L, int64_t n, T s0, T 
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) fl |= __shfl_xor(fl, o, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) {
-        const int slot = (int)((n + 1) % 3);
-        atomicMax(&L.sc->abar[slot][0], dbits(m0));
-        if (dims >= 2) atomicMax(&L.sc->abar[slot][1], dbits(m1));
-        if (dims == 3) atomicMax(&L.sc->abar[slot][2], dbits(m2));
+        AbarCopy &c = L.sc->abar[(n + 1) % 3][abar_copy()];
+        atomicMax(&c.v[0], dbits(m0));
+        if (dims >= 2) atomicMax(&c.v[1], dbits(m1));
+        if (dims == 3) atomicMax(&c.v[2], dbits(m2));
         if (anyf) {
             atomicOr(&L.sc->flags, fl);
             atomicMin(&L.sc->first_bad_step, (unsigned long long)n - L.sc->null_launches);
@@ -432,7 +464,7 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
         const T sp = max_speed<SYS, T>(0, qn, P);
         if (finite_val<T>(sp)) s0 = sp;
     }
-    if (first && lane == 0) scalar_update(L, n, cf.dt);
+    if (first) scalar_update(L, n, cf.dt);
     commit<T>(L, n, s0, T(0), flags, 1);
 }
 
@@ -1112,7 +1144,7 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
             row(j, fcur);
         }
     }
-    if (first && lane == 0) scalar_update(L, n, cf.dt);
+    if (first) scalar_update(L, n, cf.dt);
     commit<T>(L, n, s0, s1, flags, 2);
 }
 
@@ -1207,9 +1239,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce_abar(LatticeDesc L, const dou
     }
     const double m0 = (double)wave_max<T>(s0), m1 = (double)wave_max<T>(s1), m2 = (double)wave_max<T>(s2);
     if ((threadIdx.x & 63) == 0) {
-        atomicMax(&L.sc->abar[slot][0], dbits(m0));
-        if (D >= 2) atomicMax(&L.sc->abar[slot][1], dbits(m1));
-        if (D == 3) atomicMax(&L.sc->abar[slot][2], dbits(m2));
+        AbarCopy &c = L.sc->abar[slot][abar_copy()];
+        atomicMax(&c.v[0], dbits(m0));
+        if (D >= 2) atomicMax(&c.v[1], dbits(m1));
+        if (D == 3) atomicMax(&c.v[2], dbits(m2));
     }
 }
 
@@ -1221,9 +1254,9 @@ __global__ __launch_bounds__(kBlock) void k_init(LatticeDesc L, const double *U0
     constexpr int M = SysInfo<SYS, D>::M, Q = SysInfo<SYS, D>::Q;
     const Phys<T> P = make_phys<T>(L);
     // coefficients of the initial state, same formulas as a step
-    const double ab0 = bitsd(L.sc->abar[slot_in][0]);
-    const double ab1 = D >= 2 ? bitsd(L.sc->abar[slot_in][1]) : 0.0;
-    const double ab2 = D == 3 ? bitsd(L.sc->abar[slot_in][2]) : 0.0;
+    const double ab0 = abar_of(L.sc, slot_in, 0);
+    const double ab1 = D >= 2 ? abar_of(L.sc, slot_in, 1) : 0.0;
+    const double ab2 = D == 3 ? abar_of(L.sc, slot_in, 2) : 0.0;
     const double sa = D == 3 ? (ab0 + ab1) + ab2 : (D == 2 ? ab0 + ab1 : ab0);
     const double dt = L.cfl * L.dx / sa;
     const double lam = L.dx / dt;
@@ -1279,9 +1312,10 @@ __global__ __launch_bounds__(kBlock) void k_init(LatticeDesc L, const double *U0
     }
     const double m0 = (double)wave_max<T>(s0), m1 = (double)wave_max<T>(s1), m2 = (double)wave_max<T>(s2);
     if ((threadIdx.x & 63) == 0) {
-        atomicMax(&L.sc->abar[0][0], dbits(m0));
-        if (D >= 2) atomicMax(&L.sc->abar[0][1], dbits(m1));
-        if (D == 3) atomicMax(&L.sc->abar[0][2], dbits(m2));
+        AbarCopy &c = L.sc->abar[0][abar_copy()];
+        atomicMax(&c.v[0], dbits(m0));
+        if (D >= 2) atomicMax(&c.v[1], dbits(m1));
+        if (D == 3) atomicMax(&c.v[2], dbits(m2));
     }
 }
 

@@ -231,6 +231,7 @@ __global__ __launch_bounds__(kBlock) void k3_collide(LatticeDesc L, int64_t iter
     constexpr int D = 3, M = SysInfo<SYS, 3>::M, Q = 7;
     const int64_t n = iter - L.iter0;
     const bool first_thread = blockIdx.x == 0 && threadIdx.x == 0;
+    const bool first_wave = blockIdx.x == 0 && threadIdx.x < kWave;
     const T *fin = (const T *)L.f[n & 1];
     T *fout = (T *)L.f[(n + 1) & 1];
     const int64_t ps = L.pstride;
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k3_collide(LatticeDesc L, int64_t iter
             for (int p = 0; p < Q * M; ++p) fout[(int64_t)p * ps + c] = fin[(int64_t)p * ps + c];
             for (int p = 0; p < M; ++p) uout[(int64_t)p * ps + c] = u[(int64_t)p * ps + c];
         }
-        if (first_thread) null_scalars(L, n);
+        if (first_wave) null_scalars(L, n);
         return;
     }
     Coefs<T> cf;
@@ -367,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void k3_collide(LatticeDesc L, int64_t iter
             }
         }
     }
-    if (first_thread) scalar_update(L, n, cf.dt);
+    if (first_wave) scalar_update(L, n, cf.dt);
     commit<T>(L, n, smax[0], smax[1], flags, 3, smax[2]);
 }
 
