@@ -79,7 +79,7 @@ struct LatticeDesc {
     int32_t omega_on;     // omega export plane present (else omega is null and never written)
     int32_t cpl;          // 2D: columns per lane of the step's strips (1, or 2 when nx is even)
     int32_t buf;          // 2D: population buffers below 4 GiB, addressed by buffer resources
-    int32_t pad_;
+    int32_t abar_n;       // copies of each wave-speed slot in use: a power of two <= kAbarCopies, fixed per lattice
     double dx, cfl, eps, gamma, g, adv[3], h_dry, rho_floor, p_floor, omega_fixed;
     double q_heat, k_rate, t_act;  // reactive Euler: heat release, rate constant, activation temperature
     void *nu3;                     // 3D: padded indicator (nx+2)(ny+2)(nz+2), then omega of the cells

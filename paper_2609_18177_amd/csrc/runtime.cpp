@@ -440,6 +440,15 @@ extern "C" int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, 
 #endif
     d.buf = cfg->dim == 2 && h->sz.f_bytes <= ARLBM_BUF_MAX_BYTES ? 1 : 0;
     d.ncols = (int32_t)((cfg->nx + strip_out_w(d.cpl) - 1) / strip_out_w(d.cpl));
+    // copies of each wave-speed slot: a 1D step launches one wave per strip,
+    // and about 8 waves per copy keep its atomics from queueing while its
+    // readers (on the critical path of a step of a few microseconds) load
+    // fewer lines; 2D and 3D steps launch about a thousand waves or more
+    d.abar_n = kAbarCopies;
+    if (cfg->dim == 1) {
+        d.abar_n = 1;
+        while (d.abar_n < kAbarCopies && d.abar_n * 8 < d.ncols) d.abar_n *= 2;
+    }
     d.band_h = cfg->dim == 2 ? choose_band(cfg->ny, d.ncols, resident_waves(cfg->precision, d.variant, d.cpl),
                                            4 * (int64_t)num_cus())
                              : 1;

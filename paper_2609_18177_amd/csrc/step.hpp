@@ -144,13 +144,19 @@ struct Coefs {
     double dt;
 };
 
-// Wave-speed bound of direction dir in a slot: the max over the slot's
-// copies, lane l reading copy l.  Every lane of the wave takes part; the
-// result is the same in all lanes (made uniform).
-__device__ __forceinline__ double abar_of(const DevScalars *sc, int slot, int dir)
+// Mask of the copy index: abar_n - 1, kept inside the slot's kAbarCopies
+// copies whatever the descriptor holds.
+__device__ __forceinline__ int abar_mask(const LatticeDesc &L)
+{
+    return (L.abar_n - 1) & (kAbarCopies - 1);
+}
+// Wave-speed bound of direction dir in a slot: the max over the lattice's
+// L.abar_n copies, lane l reading copy l mod abar_n.  Every lane of the wave
+// takes part; the result is the same in all lanes (made uniform).
+__device__ __forceinline__ double abar_of(const LatticeDesc &L, int slot, int dir)
 {
     static_assert(kAbarCopies == kWave, "one copy per lane");
-    double v = bitsd(sc->abar[slot][threadIdx.x & (kWave - 1)].v[dir]);
+    double v = bitsd(L.sc->abar[slot][threadIdx.x & abar_mask(L)].v[dir]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         const double w = __shfl_xor(v, o, kWave);
@@ -162,9 +168,9 @@ __device__ __forceinline__ double abar_of(const DevScalars *sc, int slot, int di
     return bitsd(((unsigned long long)hi << 32) | lo);
 }
 // Copy of a slot this wave maxes into.
-__device__ __forceinline__ int abar_copy()
+__device__ __forceinline__ int abar_copy(const LatticeDesc &L)
 {
-    return (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kAbarCopies - 1));
+    return (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & abar_mask(L));
 }
 
 template <int D, typename T>
@@ -172,9 +178,9 @@ __device__ __forceinline__ bool step_coefs(const LatticeDesc &L, int64_t n, Coef
 {
     const DevScalars *sc = L.sc;
     const int slot = (int)(n % 3);
-    const double ab0 = abar_of(sc, slot, 0);
-    const double ab1 = D >= 2 ? abar_of(sc, slot, 1) : 0.0;
-    const double ab2 = D == 3 ? abar_of(sc, slot, 2) : 0.0;
+    const double ab0 = abar_of(L, slot, 0);
+    const double ab1 = D >= 2 ? abar_of(L, slot, 1) : 0.0;
+    const double ab2 = D == 3 ? abar_of(L, slot, 2) : 0.0;
     const double sa = D == 3 ? (ab0 + ab1) + ab2 : (D == 2 ? ab0 + ab1 : ab0);
     if (!(sa > 0.0) || !(sa < 1.0e300)) return false;
     const double dt = L.cfl * L.dx / sa;
@@ -228,10 +234,12 @@ __device__ __forceinline__ void scalar_update(const LatticeDesc &L, int64_t n, d
         sc->t[(n + 1) % 3] = sc->t[n % 3] + dt;
         sc->last_dt = dt;
     }
-    AbarCopy &c = sc->abar[(n + 2) % 3][lane];
-    c.v[0] = 0ull;
-    c.v[1] = 0ull;
-    c.v[2] = 0ull;
+    if (lane <= abar_mask(L)) {
+        AbarCopy &c = sc->abar[(n + 2) % 3][lane];
+        c.v[0] = 0ull;
+        c.v[1] = 0ull;
+        c.v[2] = 0ull;
+    }
 }
 
 // A launch whose state time has reached the stop time leaves the state
@@ -250,13 +258,15 @@ __device__ __forceinline__ void null_scalars(const LatticeDesc &L, int64_t n)
         sc->t[(n + 1) % 3] = sc->t[n % 3];
         sc->null_launches = sc->null_launches + 1ull;
     }
-    const AbarCopy &from = sc->abar[n % 3][lane];
-    AbarCopy &to = sc->abar[(n + 1) % 3][lane];
-    AbarCopy &clr = sc->abar[(n + 2) % 3][lane];
+    if (lane <= abar_mask(L)) {
+        const AbarCopy &from = sc->abar[n % 3][lane];
+        AbarCopy &to = sc->abar[(n + 1) % 3][lane];
+        AbarCopy &clr = sc->abar[(n + 2) % 3][lane];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        to.v[d] = from.v[d];
-        clr.v[d] = 0ull;
+        for (int d = 0; d < 3; ++d) {
+            to.v[d] = from.v[d];
+            clr.v[d] = 0ull;
+        }
     }
 }
 template <typename T>
@@ -293,7 +303,7 @@ __device__ __forceinline__ void commit(const LatticeDesc &L, int64_t n, T s0, T 
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) fl |= __shfl_xor(fl, o, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) {
-        AbarCopy &c = L.sc->abar[(n + 1) % 3][abar_copy()];
+        AbarCopy &c = L.sc->abar[(n + 1) % 3][abar_copy(L)];
         atomicMax(&c.v[0], dbits(m0));
         if (dims >= 2) atomicMax(&c.v[1], dbits(m1));
         if (dims == 3) atomicMax(&c.v[2], dbits(m2));
@@ -1239,7 +1249,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_abar(LatticeDesc L, const dou
     }
     const double m0 = (double)wave_max<T>(s0), m1 = (double)wave_max<T>(s1), m2 = (double)wave_max<T>(s2);
     if ((threadIdx.x & 63) == 0) {
-        AbarCopy &c = L.sc->abar[slot][abar_copy()];
+        AbarCopy &c = L.sc->abar[slot][abar_copy(L)];
         atomicMax(&c.v[0], dbits(m0));
         if (D >= 2) atomicMax(&c.v[1], dbits(m1));
         if (D == 3) atomicMax(&c.v[2], dbits(m2));
@@ -1254,9 +1264,9 @@ __global__ __launch_bounds__(kBlock) void k_init(LatticeDesc L, const double *U0
     constexpr int M = SysInfo<SYS, D>::M, Q = SysInfo<SYS, D>::Q;
     const Phys<T> P = make_phys<T>(L);
     // coefficients of the initial state, same formulas as a step
-    const double ab0 = abar_of(L.sc, slot_in, 0);
-    const double ab1 = D >= 2 ? abar_of(L.sc, slot_in, 1) : 0.0;
-    const double ab2 = D == 3 ? abar_of(L.sc, slot_in, 2) : 0.0;
+    const double ab0 = abar_of(L, slot_in, 0);
+    const double ab1 = D >= 2 ? abar_of(L, slot_in, 1) : 0.0;
+    const double ab2 = D == 3 ? abar_of(L, slot_in, 2) : 0.0;
     const double sa = D == 3 ? (ab0 + ab1) + ab2 : (D == 2 ? ab0 + ab1 : ab0);
     const double dt = L.cfl * L.dx / sa;
     const double lam = L.dx / dt;
@@ -1312,7 +1322,7 @@ __global__ __launch_bounds__(kBlock) void k_init(LatticeDesc L, const double *U0
     }
     const double m0 = (double)wave_max<T>(s0), m1 = (double)wave_max<T>(s1), m2 = (double)wave_max<T>(s2);
     if ((threadIdx.x & 63) == 0) {
-        AbarCopy &c = L.sc->abar[0][abar_copy()];
+        AbarCopy &c = L.sc->abar[0][abar_copy(L)];
         atomicMax(&c.v[0], dbits(m0));
         if (D >= 2) atomicMax(&c.v[1], dbits(m1));
         if (D == 3) atomicMax(&c.v[2], dbits(m2));
