@@ -11,7 +11,8 @@ Default run (one JSON line on stdout, progress on stderr):
 * beside it: the FP64 plain path on the same inputs (and its FP32-vs-FP64
   error), 2D shallow water 4096 x 4096 with the bed source (FP32), 1D Euler
   N=4096 solve latency, the serving mix (continuous batching, p50/p99
-  latency), and the FP64 CPU oracle timed on a bounded sample.
+  latency), the same arrivals solved one at a time on the plain path (FP64
+  and FP32), and the FP64 CPU oracle timed on a bounded sample.
 
 ``--only NAME`` runs one workload (for profilers); ``--copy-calibration``
 times a plain device copy of known size (HBM counter calibration).
@@ -42,6 +43,15 @@ ALG_BYTES = {("euler2d", 4): 160, ("euler2d", 8): 320, ("swe2d", 4): 124, ("swe2
 KERNEL_SOURCES = ["paper_2609_18177_amd/csrc/step.hpp", "paper_2609_18177_amd/csrc/physics.hpp",
                   "paper_2609_18177_amd/csrc/step3d.hpp",
                   "paper_2609_18177_amd/csrc/kernels.hip", "paper_2609_18177_amd/build.py"]
+
+
+def alg_bytes_per_lup(p, size):
+    """One read and one write of the Q*m populations (Q = 2d+1; m = 1 for
+    advection, d+2 for Euler, d+1 for shallow water, d+3 for reactive Euler),
+    plus the bed plane's read when the problem has a bed."""
+    q = 2 * p.dim + 1
+    m = {W.ADVECTION: 1, W.EULER: p.dim + 2, W.SWE: p.dim + 1, W.REACTIVE: p.dim + 3}[p.system]
+    return 2 * q * m * size + (size if p.bed is not None else 0)
 
 
 def log(*a):
@@ -214,6 +224,7 @@ def run_serving(torch, args, n_requests, rate_hz, fp64_check, tag="serving", bud
     lups = 0
     by_id = {r.server_id: r for r in reqs}
     bad = 0
+    nbytes = 0
     for rid, c in results.items():
         r = by_id[rid]
         if c["status"] != 0:
@@ -223,9 +234,11 @@ def run_serving(torch, args, n_requests, rate_hz, fp64_check, tag="serving", bud
         # library's steady clock both read CLOCK_MONOTONIC
         lat.append(c["done_s"] - (start + r.arrival_s))
         lups += probs[r.rid].cells * r.steps
+        nbytes += probs[r.rid].cells * r.steps * alg_bytes_per_lup(probs[r.rid], 4)
     lat = np.array(lat) * 1e3
     span = max(reqs[-1].arrival_s, 1e-9)
     out = {"requests": len(reqs), "failed": bad, "wall_s": wall, "glups": lups / wall / 1e9,
+           "alg_gbs_whole_job": nbytes / wall / 1e9,
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "iterations": iters, "peak_resident_bytes": int(peak_mem), "offered_lups": int(lups),
            "offered_glups_over_arrivals": lups / span / 1e9, "arrival_span_s": span,
@@ -244,6 +257,43 @@ def run_serving(torch, args, n_requests, rate_hz, fp64_check, tag="serving", bud
     out["fp32_batched_vs_fp64_plain_rel_l1"] = {"n": len(errs), "max": max(errs) if errs else None,
                                                 "median": float(np.median(errs)) if errs else None}
     srv.close()
+    log(f"[{tag}] {out}")
+    return out
+
+
+def run_plain(torch, args, n_requests, rate_hz, precision, tag):
+    """The same arrival stream as run_serving, solved one request at a time
+    in arrival order on the plain single-lattice path (no batching, no
+    admission: a request waits until the one before it has been read back).
+    Latency = moments read back - arrival, as for the server."""
+    reqs = W.serving_requests(n_requests, rate_hz=rate_hz, seed=0)
+    probs = [r.problem() for r in reqs]
+    cfgs = [A.config_from(p, precision=precision) for p in probs]
+    log(f"[{tag}] {len(reqs)} requests, one at a time")
+    lat, lups, nbytes, bad = [], 0, 0, 0
+    start = time.perf_counter()
+    for r, p, cfg in zip(reqs, probs, cfgs):
+        wait = r.arrival_s - (time.perf_counter() - start)
+        if wait > 0:
+            time.sleep(wait)
+        L = A.Lattice(cfg, owner="torch")
+        L.set_state(p.U0, p.bed)
+        L.step(r.steps)
+        st = L.sync(check=False)
+        L.moments()
+        L.close()
+        if st["rc"] not in (0, A.EPOSITIVITY):
+            bad += 1
+            continue
+        lat.append(time.perf_counter() - (start + r.arrival_s))
+        lups += p.cells * r.steps
+        nbytes += p.cells * r.steps * alg_bytes_per_lup(p, 8 if precision == A.F64 else 4)
+    wall = time.perf_counter() - start
+    lat = np.array(lat) * 1e3
+    out = {"requests": len(reqs), "failed": bad, "wall_s": wall, "glups": lups / wall / 1e9,
+           "alg_gbs_whole_job": nbytes / wall / 1e9,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "precision": "f64" if precision == A.F64 else "f32", "rate_hz": rate_hz}
     log(f"[{tag}] {out}")
     return out
 
@@ -303,6 +353,7 @@ def main():
     ap.add_argument("--latency-solves", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -365,6 +416,16 @@ def main():
         # admitted on arrival
         extra["serving_unlimited_budget"] = run_serving(torch, args, args.requests, args.rate, 4,
                                                         tag="serving-unlimited", budget_gib=args.unlimited_gib)
+        if not args.no_plain:
+            # the metric's comparison: the same arrivals on the plain path,
+            # FP64 and FP32, one solve at a time (the FP32 run isolates what
+            # the batched server gains from batching alone)
+            extra["plain_fp64_sequential"] = run_plain(torch, args, args.requests, args.rate, A.F64,
+                                                       "plain-f64")
+            extra["plain_fp32_sequential"] = run_plain(torch, args, args.requests, args.rate, A.F32,
+                                                       "plain-f32")
+            extra["plain_fp64_sequential_low_rate"] = run_plain(torch, args, args.low_requests, args.low_rate,
+                                                                A.F64, "plain-f64-low")
     cpu = None if args.no_cpu else run_cpu_baseline(args)
     line = {
         "metric": METRIC, "value": glups, "unit": "GLUPS", "n_gpus": 1, "steps": args.steps,
