@@ -337,7 +337,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--only", choices=["euler2d_f32", "euler2d_f64", "swe2d_f32", "euler3d_f32"], default=None)
+    ap.add_argument("--only", choices=["euler2d_f32", "euler2d_f64", "swe2d_f32", "euler3d_f32", "serving"],
+                    default=None)
     ap.add_argument("--steps3d", type=int, default=100)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--swe-steps", type=int, default=2000)
@@ -377,6 +378,10 @@ def main():
     if args.only == "euler3d_f32":
         r = run_euler3d(torch, args, steps=args.steps)
         log(f"[only] euler3d_f32 {r}")
+        return
+    if args.only == "serving":
+        r = run_serving(torch, args, args.requests, args.rate, 0)
+        log(f"[only] serving {r}")
         return
     if args.only == "euler2d_f64":
         p = W.euler_seeded_2d(0, n=2048, steps=1000)

@@ -507,15 +507,8 @@ extern "C" int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, 
     }
     if (cfg->dim == 3)
         d.nu3 = (char *)d.u[1] + (size_t)h->sz.m * d.pstride * (cfg->precision == ARLBM_F64 ? 8 : 4);
-    // per-block conservation partials of up to 6 fields (3D reactive Euler)
-    hipError_t err = hipMalloc((void **)&h->d_partial, sizeof(double) * kConsBlocks * 6);
     // without an omega plane the kernels store no omega (omega_on = 0)
     d.omega_on = d.omega ? 1 : 0;
-    if (err != hipSuccess) {
-        free_owned(h);
-        delete h;
-        return fail(nullptr, ARLBM_ENOMEM, "device allocation failed");
-    }
     *out = h;
     return ARLBM_OK;
 }
@@ -609,8 +602,10 @@ extern "C" int arlbm_sync(arlbm_lattice *h, arlbm_status *st)
     return ARLBM_OK;
 }
 
-// Copy m strided device planes (stride pstride) to dense host FP64 planes.
-static int read_planes(arlbm_lattice *h, const void *src, int m, double *out)
+// Enqueue the copy of m strided device planes (stride pstride) to dense host
+// FP64 planes (FP32 data through the population buffer the step does not
+// read next).
+static int read_planes_async(arlbm_lattice *h, const void *src, int m, double *out)
 {
     const int64_t plane = h->desc.plane, ps = h->desc.pstride;
     if (is_f64(h)) {
@@ -621,6 +616,13 @@ static int read_planes(arlbm_lattice *h, const void *src, int m, double *out)
         HIPCHK(h, f32::to_double(src, stage, plane, ps, m, h->stream));
         HIPCHK(h, hipMemcpyAsync(out, stage, sizeof(double) * plane * m, hipMemcpyDeviceToHost, h->stream));
     }
+    return ARLBM_OK;
+}
+
+static int read_planes(arlbm_lattice *h, const void *src, int m, double *out)
+{
+    int rc = read_planes_async(h, src, m, out);
+    if (rc) return rc;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return ARLBM_OK;
 }
@@ -678,6 +680,9 @@ extern "C" int arlbm_conservation(arlbm_lattice *h, double *sums)
     int rc = form_moments(h);
     if (rc) return rc;
     const void *u = h->desc.u[h->step & 1];
+    // per-block partials of up to 6 fields (3D reactive Euler), allocated on
+    // the first request, so that a lattice that never asks allocates nothing
+    if (!h->d_partial) HIPCHK(h, hipMalloc((void **)&h->d_partial, sizeof(double) * kConsBlocks * 6));
     hipError_t e = is_f64(h) ? f64::conservation(u, h->desc.plane, h->desc.pstride, m, h->d_partial, kConsBlocks,
                                                  h->stream)
                              : f32::conservation(u, h->desc.plane, h->desc.pstride, m, h->d_partial, kConsBlocks,
@@ -793,6 +798,18 @@ extern "C" int arlbm_step_kernel_vgprs(int32_t precision, int32_t system, int32_
 // ------------------------------------------------------------------------
 // Server
 // ------------------------------------------------------------------------
+//
+// Everything a served lattice needs runs on the server's one stream, in
+// order: its upload and initialisation, the batched steps, its read-back.
+// Device memory therefore never needs a synchronisation before reuse: a
+// block released by a retiring lattice is written by a later admission only
+// after the read-back that precedes it in the stream.  Uploads and
+// read-backs go through pinned host blocks, and each iteration enqueues the
+// retirements, the admissions and the table upload before its batched
+// launch and finishes them (result copies, admission checks) after it, so
+// the host work overlaps the launch instead of leaving the GPU idle.  Served
+// lattices take their buffers from a pool of device blocks in size classes:
+// once the pool is warm, serving calls neither hipMalloc nor hipFree.
 
 namespace {
 struct Pending {
@@ -809,10 +826,103 @@ struct Resident {
     int64_t nsteps, iter0;
     double submit_s, admit_s;
     size_t bytes;
+    void *dev;       // the lattice's device block (pool)
+    size_t dev_cls;  // its size class
 };
 struct Done {
     arlbm_completion c;
     std::vector<double> U;
+};
+// An admission or a retirement whose transfers are in the stream, finished
+// after the iteration's launch.
+struct Staged {
+    bool retiring;
+    uint64_t id;
+    arlbm_lattice *lat;
+    int64_t nsteps;
+    double submit_s, admit_s;
+    void *host;  // pinned block: scalars [, scalars out], planes
+    size_t host_cls;
+    hipEvent_t ev;
+};
+
+// Size classes a quarter octave apart (a block is at most 25% larger than
+// asked), at least 64 KiB.
+size_t size_class(size_t n)
+{
+    if (n <= ((size_t)1 << 16)) return (size_t)1 << 16;
+    const int lg = 63 - __builtin_clzll((unsigned long long)n);
+    const size_t q = (size_t)1 << (lg - 2);
+    return (n + q - 1) / q * q;
+}
+
+// Free lists of device or pinned host blocks per size class.  Free blocks are
+// given back (largest first) when the blocks held would exceed cap.  A free
+// device block may still be read by work queued before its release (a
+// retiring lattice's read-back), so giving one back first waits for the
+// stream; a pinned block is released only after its transfers completed.
+struct BlockPool {
+    bool pinned = false;
+    hipStream_t stream = nullptr;
+    size_t cap = 0;
+    size_t free_bytes = 0, used_bytes = 0;
+    std::vector<std::pair<size_t, void *>> free_blocks;  // (class, pointer)
+
+    void give_back(void *p)
+    {
+        if (pinned) {
+            (void)hipHostFree(p);
+        } else {
+            (void)hipStreamSynchronize(stream);
+            (void)hipFree(p);
+        }
+    }
+    void drop_largest()
+    {
+        auto it = std::max_element(free_blocks.begin(), free_blocks.end(),
+                                   [](const auto &a, const auto &b) { return a.first < b.first; });
+        free_bytes -= it->first;
+        give_back(it->second);
+        free_blocks.erase(it);
+    }
+    void *acquire(size_t n, size_t *cls_out)
+    {
+        const size_t cls = size_class(n);
+        for (size_t i = 0; i < free_blocks.size(); ++i) {
+            if (free_blocks[i].first != cls) continue;
+            void *p = free_blocks[i].second;
+            free_blocks[i] = free_blocks.back();
+            free_blocks.pop_back();
+            free_bytes -= cls;
+            used_bytes += cls;
+            *cls_out = cls;
+            return p;
+        }
+        while (!free_blocks.empty() && used_bytes + free_bytes + cls > cap) drop_largest();
+        void *p = nullptr;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            const hipError_t e = pinned ? hipHostMalloc(&p, cls, hipHostMallocDefault) : hipMalloc(&p, cls);
+            if (e == hipSuccess) break;
+            p = nullptr;
+            (void)hipGetLastError();
+            while (!free_blocks.empty()) drop_largest();
+        }
+        if (!p) return nullptr;
+        used_bytes += cls;
+        *cls_out = cls;
+        return p;
+    }
+    void release(void *p, size_t cls)
+    {
+        used_bytes -= cls;
+        free_blocks.emplace_back(cls, p);
+        free_bytes += cls;
+        while (!free_blocks.empty() && used_bytes + free_bytes > cap) drop_largest();
+    }
+    void clear()
+    {
+        while (!free_blocks.empty()) drop_largest();
+    }
 };
 }  // namespace
 
@@ -824,11 +934,20 @@ struct arlbm_server {
     int64_t iter = 0;
     std::deque<Pending> queue;
     std::vector<Resident> resident;
+    std::vector<Staged> staged;
     std::deque<Done> done;
     std::vector<Done> handed;  // results returned by the last poll
+    BlockPool dev, pin;
     LatticeDesc *d_descs = nullptr;
     WorkItem *d_items = nullptr;
     size_t cap_descs = 0, cap_items = 0;
+    // pinned host copies of the work table, two sets used in turn; a set is
+    // rewritten only after the upload that read it (its event) has completed
+    LatticeDesc *h_descs[2] = {nullptr, nullptr};
+    WorkItem *h_items[2] = {nullptr, nullptr};
+    size_t hcap_descs[2] = {0, 0}, hcap_items[2] = {0, 0};
+    hipEvent_t table_ev[2] = {nullptr, nullptr};
+    int table_set = 0;
     int32_t nitems = 0;
     bool dirty = true;
     std::string err;
@@ -841,6 +960,40 @@ int sfail(arlbm_server *s, int code, const std::string &msg)
     if (s) s->err = msg;
     g_thread_err = msg;
     return code;
+}
+
+// Byte offsets of a lattice's buffers inside its device block, in the order
+// f[0], f[1], u[0], u[1], bed, scalars (every size is a multiple of 256).
+arlbm_buffers carve(void *blk, const arlbm_sizes &sz, bool has_bed)
+{
+    char *b = (char *)blk;
+    arlbm_buffers r{};
+    r.f[0] = b;
+    r.f[1] = b + sz.f_bytes;
+    r.u[0] = b + 2 * sz.f_bytes;
+    r.u[1] = b + 2 * sz.f_bytes + sz.u_bytes;
+    r.bed = has_bed ? b + 2 * sz.f_bytes + 2 * sz.u_bytes : nullptr;
+    r.scalars = b + 2 * sz.f_bytes + 2 * sz.u_bytes + sz.bed_bytes;
+    r.omega = nullptr;
+    return r;
+}
+
+// A served lattice's handle: its buffers belong to the server's pool and
+// no kernel touches them after this point in the stream, so nothing waits.
+void drop_handle(arlbm_lattice *h)
+{
+    free_owned(h);
+    delete h;
+}
+
+void push_failed(arlbm_server *s, uint64_t id, int rc, double submit_s)
+{
+    Done d{};
+    d.c.id = id;
+    d.c.status = rc;
+    d.c.submit_s = submit_s;
+    d.c.done_s = now_s();
+    s->done.push_back(std::move(d));
 }
 
 // Band height of the served 2D lattices, common to all of them: as tall as
@@ -877,28 +1030,269 @@ int rebuild_table(arlbm_server *s)
             for (int c = 0; c < d.ncols; ++c) items.push_back({(int32_t)i, c, (int32_t)b, (b == 0 && c == 0) ? 1 : 0});
     }
     hipError_t e;
+    // device tables grow by reallocation, after the launches that still read
+    // the old ones
+    if (descs.size() > s->cap_descs || items.size() > s->cap_items) {
+        e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, hipGetErrorString(e));
+    }
     if (descs.size() > s->cap_descs) {
         if (s->d_descs) (void)hipFree(s->d_descs);
+        s->d_descs = nullptr;
         s->cap_descs = std::max<size_t>(descs.size() * 2, 64);
         e = hipMalloc((void **)&s->d_descs, sizeof(LatticeDesc) * s->cap_descs);
         if (e != hipSuccess) return sfail(s, ARLBM_ENOMEM, "descriptor table allocation failed");
     }
     if (items.size() > s->cap_items) {
         if (s->d_items) (void)hipFree(s->d_items);
+        s->d_items = nullptr;
         s->cap_items = std::max<size_t>(items.size() * 2, 4096);
         e = hipMalloc((void **)&s->d_items, sizeof(WorkItem) * s->cap_items);
         if (e != hipSuccess) return sfail(s, ARLBM_ENOMEM, "work table allocation failed");
     }
-    // the stream is idle here (admission and retirement synchronise), so the
-    // synchronous copies cannot overtake a launch that still reads the table
     if (!descs.empty()) {
-        e = hipMemcpy(s->d_descs, descs.data(), sizeof(LatticeDesc) * descs.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(s->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice);
+        // the upload is ordered after the launches that read the previous
+        // table; its source, a pinned set, is rewritten two rebuilds later,
+        // after its own upload has completed
+        const int k = s->table_set;
+        s->table_set ^= 1;
+        if (!s->table_ev[k]) {
+            e = hipEventCreateWithFlags(&s->table_ev[k], hipEventDisableTiming);
+            if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("event: ") + hipGetErrorString(e));
+        } else {
+            e = hipEventSynchronize(s->table_ev[k]);
+            if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("table event: ") + hipGetErrorString(e));
+        }
+        if (descs.size() > s->hcap_descs[k]) {
+            if (s->h_descs[k]) (void)hipHostFree(s->h_descs[k]);
+            s->h_descs[k] = nullptr;
+            s->hcap_descs[k] = s->cap_descs;
+            e = hipHostMalloc((void **)&s->h_descs[k], sizeof(LatticeDesc) * s->hcap_descs[k], hipHostMallocDefault);
+            if (e != hipSuccess) {
+                s->hcap_descs[k] = 0;
+                return sfail(s, ARLBM_ENOMEM, "pinned descriptor table allocation failed");
+            }
+        }
+        if (items.size() > s->hcap_items[k]) {
+            if (s->h_items[k]) (void)hipHostFree(s->h_items[k]);
+            s->h_items[k] = nullptr;
+            s->hcap_items[k] = s->cap_items;
+            e = hipHostMalloc((void **)&s->h_items[k], sizeof(WorkItem) * s->hcap_items[k], hipHostMallocDefault);
+            if (e != hipSuccess) {
+                s->hcap_items[k] = 0;
+                return sfail(s, ARLBM_ENOMEM, "pinned work table allocation failed");
+            }
+        }
+        std::memcpy(s->h_descs[k], descs.data(), sizeof(LatticeDesc) * descs.size());
+        if (!items.empty()) std::memcpy(s->h_items[k], items.data(), sizeof(WorkItem) * items.size());
+        e = hipMemcpyAsync(s->d_descs, s->h_descs[k], sizeof(LatticeDesc) * descs.size(), hipMemcpyHostToDevice,
+                           s->stream);
+        if (e == hipSuccess && !items.empty())
+            e = hipMemcpyAsync(s->d_items, s->h_items[k], sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice,
+                               s->stream);
+        if (e == hipSuccess) e = hipEventRecord(s->table_ev[k], s->stream);
         if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("table upload: ") + hipGetErrorString(e));
     }
     s->nitems = (int32_t)items.size();
     s->dirty = false;
     return ARLBM_OK;
+}
+
+// Pinned staging layout of an admission: initial scalars, scalars read back
+// after the initialisation, the U0 planes, the bed plane.
+struct AdmitLayout {
+    size_t sc_in, sc_out, u0, bed, total;
+};
+AdmitLayout admit_layout(const arlbm_sizes &sz, int64_t plane, bool has_bed)
+{
+    AdmitLayout l;
+    l.sc_in = 0;
+    l.sc_out = align_up(sizeof(DevScalars));
+    l.u0 = l.sc_out + align_up(sizeof(DevScalars));
+    l.bed = l.u0 + align_up(sizeof(double) * sz.m * plane);
+    l.total = l.bed + (has_bed ? sizeof(double) * plane : 0);
+    return l;
+}
+
+// Admission: a device block from the pool, the handle, the host checks of the
+// initial state, then the upload and initialisation enqueued (as set_state
+// does, without its wait); the wave-speed checks follow in finish_staged.
+void admit_enqueue(arlbm_server *s, Pending &p)
+{
+    arlbm_sizes sz;
+    fill_sizes(&p.cfg, &sz);
+    const bool has_bed = p.cfg.has_bed != 0;
+    size_t dcls = 0;
+    void *blk = s->dev.acquire(sz.total_bytes, &dcls);
+    if (!blk) {
+        g_thread_err = "device allocation failed";
+        push_failed(s, p.id, ARLBM_ENOMEM, p.submit_s);
+        return;
+    }
+    const arlbm_buffers b = carve(blk, sz, has_bed);
+    arlbm_lattice *lat = nullptr;
+    int rc = arlbm_create(&p.cfg, &b, s->stream, &lat);
+    if (rc == ARLBM_OK) rc = check_state(lat, p.U0.data(), has_bed ? p.bed.data() : nullptr);
+    const int64_t plane = (int64_t)p.cfg.nx * p.cfg.ny * p.cfg.nz;
+    const AdmitLayout L = admit_layout(sz, plane, has_bed);
+    size_t hcls = 0;
+    char *host = nullptr;
+    if (rc == ARLBM_OK) {
+        host = (char *)s->pin.acquire(L.total, &hcls);
+        if (!host) rc = fail(lat, ARLBM_ENOMEM, "pinned staging allocation failed");
+    }
+    hipEvent_t ev = nullptr;
+    if (rc == ARLBM_OK) {
+        DevScalars init{};
+        init.t[0] = 0.0;
+        init.first_bad_step = ~0ull;
+        std::memcpy(host + L.sc_in, &init, sizeof init);
+        std::memcpy(host + L.u0, p.U0.data(), sizeof(double) * sz.m * plane);
+        if (has_bed) std::memcpy(host + L.bed, p.bed.data(), sizeof(double) * plane);
+        double *U0d = (double *)lat->desc.f[1];
+        double *bedd = has_bed ? U0d + (size_t)sz.m * plane : nullptr;
+        hipError_t e = hipMemcpyAsync(U0d, host + L.u0, sizeof(double) * sz.m * plane, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess && has_bed)
+            e = hipMemcpyAsync(bedd, host + L.bed, sizeof(double) * plane, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(lat->desc.sc, host + L.sc_in, sizeof(DevScalars), hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = L_reduce(lat, U0d, 2);
+        if (e == hipSuccess) e = L_init(lat, U0d, bedd, 2);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(host + L.sc_out, lat->desc.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(ev, s->stream);
+        if (e != hipSuccess) {
+            rc = hip_fail(lat, e, "admission upload");
+            // a transfer may be in the stream: wait before the blocks return
+            (void)hipStreamSynchronize(s->stream);
+            if (ev) (void)hipEventDestroy(ev);
+        }
+    }
+    if (rc != ARLBM_OK) {
+        if (host) s->pin.release(host, hcls);
+        if (lat) drop_handle(lat);
+        s->dev.release(blk, dcls);
+        push_failed(s, p.id, rc, p.submit_s);
+        return;
+    }
+    lat->step = 0;
+    lat->busy = true;
+    const double t_admit = now_s();
+    s->resident.push_back({p.id, lat, p.nsteps, s->iter, p.submit_s, t_admit, p.bytes, blk, dcls});
+    s->staged.push_back({false, p.id, lat, p.nsteps, p.submit_s, t_admit, host, hcls, ev});
+    s->in_use += p.bytes;
+    s->dirty = true;
+}
+
+// Retirement: the moments and scalars of the final state enqueued into a
+// pinned block; the device block goes back to the pool at once (stream order
+// keeps it intact until the read-back has run).
+int retire_enqueue(arlbm_server *s, const Resident &r)
+{
+    arlbm_lattice *h = r.lat;
+    h->step = r.nsteps;  // the batched launches advanced it
+    h->busy = false;
+    const size_t o_u = align_up(sizeof(DevScalars));
+    const size_t nU = (size_t)h->sz.m * h->desc.plane;
+    size_t hcls = 0;
+    char *host = (char *)s->pin.acquire(o_u + sizeof(double) * nU, &hcls);
+    int rc = host ? ARLBM_OK : fail(h, ARLBM_ENOMEM, "pinned staging allocation failed");
+    hipEvent_t ev = nullptr;
+    if (rc == ARLBM_OK) rc = form_moments(h);
+    if (rc == ARLBM_OK) rc = read_planes_async(h, h->desc.u[h->step & 1], h->sz.m, (double *)(host + o_u));
+    if (rc == ARLBM_OK) {
+        hipError_t e = hipMemcpyAsync(host, h->desc.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(ev, s->stream);
+        if (e != hipSuccess) {
+            rc = hip_fail(h, e, "read-back");
+            if (ev) (void)hipEventDestroy(ev);
+        }
+    }
+    if (rc != ARLBM_OK) {
+        (void)hipStreamSynchronize(s->stream);
+        if (host) s->pin.release(host, hcls);
+        drop_handle(h);
+        s->dev.release(r.dev, r.dev_cls);
+        s->in_use -= r.bytes;
+        push_failed(s, r.id, rc, r.submit_s);
+        return rc;
+    }
+    s->staged.push_back({true, r.id, h, r.nsteps, r.submit_s, r.admit_s, host, hcls, ev});
+    s->dev.release(r.dev, r.dev_cls);
+    s->in_use -= r.bytes;
+    return ARLBM_OK;
+}
+
+// Finish what admissions and retirements enqueued before the launch: copy
+// results out of their pinned blocks and check the admitted lattices'
+// wave-speed bounds (Theorem 4.3's bound on eps, a nonzero sum), as
+// set_state does.  An admitted lattice that fails leaves the mix with its
+// error; its one launched step touched only its own buffers.
+int finish_staged(arlbm_server *s)
+{
+    int first_err = ARLBM_OK;
+    for (Staged &g : s->staged) {
+        hipError_t e = hipEventSynchronize(g.ev);
+        (void)hipEventDestroy(g.ev);
+        if (e != hipSuccess && first_err == ARLBM_OK)
+            first_err = sfail(s, ARLBM_EDEVICE, std::string("staged transfer: ") + hipGetErrorString(e));
+        arlbm_lattice *h = g.lat;
+        if (g.retiring) {
+            DevScalars sc;
+            std::memcpy(&sc, g.host, sizeof sc);
+            Done d{};
+            d.c.id = g.id;
+            d.c.steps = g.nsteps;
+            d.c.submit_s = g.submit_s;
+            d.c.admit_s = g.admit_s;
+            d.c.t = sc.t[g.nsteps % 3];
+            d.c.flags = sc.flags;
+            int rc = e != hipSuccess ? ARLBM_EDEVICE : ARLBM_OK;
+            if (rc == ARLBM_OK && (sc.flags & ARLBM_FLAG_NONFINITE)) rc = ARLBM_ENONFINITE;
+            if (rc == ARLBM_OK && (sc.flags & ARLBM_FLAG_DEGENERATE)) rc = ARLBM_EDEGENERATE;
+            // the positivity flag is advisory: the moments are still the result
+            if (rc == ARLBM_OK) {
+                const double *U = (const double *)((const char *)g.host + align_up(sizeof(DevScalars)));
+                d.U.assign(U, U + (size_t)h->sz.m * h->desc.plane);
+            }
+            d.c.status = rc;
+            d.c.done_s = now_s();
+            s->done.push_back(std::move(d));
+            drop_handle(h);
+        } else {
+            arlbm_sizes sz = h->sz;
+            const AdmitLayout L = admit_layout(sz, h->desc.plane, h->cfg.has_bed != 0);
+            DevScalars got;
+            std::memcpy(&got, (const char *)g.host + L.sc_out, sizeof got);
+            const double ab0 = abar_host(got, 0, 0);
+            const double ab1 = h->cfg.dim >= 2 ? abar_host(got, 0, 1) : 0.0;
+            const double ab2 = h->cfg.dim == 3 ? abar_host(got, 0, 2) : 0.0;
+            const double sa = (ab0 + ab1) + ab2;
+            int rc = e != hipSuccess ? ARLBM_EDEVICE : ARLBM_OK;
+            if (rc == ARLBM_OK && !(sa > 0.0))
+                rc = fail(h, ARLBM_EDEGENERATE, "sum of wave-speed bounds is zero: time step undefined");
+            const double bound = (1.0 / h->cfg.dim) * (1.0 / h->cfg.cfl - 1.0) * sa;
+            if (rc == ARLBM_OK && !(h->cfg.eps < bound))
+                rc = fail(h, ARLBM_EINVAL, "eps exceeds the stability bound of Theorem 4.3");
+            if (rc != ARLBM_OK) {
+                for (size_t i = 0; i < s->resident.size(); ++i) {
+                    if (s->resident[i].lat != h) continue;
+                    s->dev.release(s->resident[i].dev, s->resident[i].dev_cls);
+                    s->in_use -= s->resident[i].bytes;
+                    s->resident.erase(s->resident.begin() + i);
+                    break;
+                }
+                s->dirty = true;
+                push_failed(s, g.id, rc, g.submit_s);
+                drop_handle(h);
+            }
+        }
+        s->pin.release(g.host, g.host_cls);
+    }
+    s->staged.clear();
+    return first_err;
 }
 
 }  // namespace
@@ -911,6 +1305,13 @@ extern "C" int arlbm_server_create(size_t budget, int32_t precision, void *strea
     s->budget = budget;
     s->precision = precision;
     s->stream = (hipStream_t)stream;
+    // device blocks held (in use or free): at most 1.5 times the budget;
+    // free pinned staging blocks: at most 1 GiB
+    s->dev.cap = budget + budget / 2;
+    s->dev.stream = s->stream;
+    s->pin.stream = s->stream;
+    s->pin.pinned = true;
+    s->pin.cap = (size_t)1 << 30;
     *out = s;
     return ARLBM_OK;
 }
@@ -944,31 +1345,13 @@ extern "C" int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, con
 extern "C" int arlbm_server_iterate(arlbm_server *s, int32_t *n_res, int32_t *n_queued)
 {
     if (!s) return sfail(nullptr, ARLBM_EINVAL, "server is NULL");
-    // retire lattices whose steps are complete
+    // retire lattices whose steps are complete (read-backs enqueued)
     for (size_t i = 0; i < s->resident.size();) {
-        Resident &r = s->resident[i];
+        const Resident r = s->resident[i];
         if (s->iter - r.iter0 >= r.nsteps) {
-            Done d{};
-            d.c.id = r.id;
-            d.c.steps = r.nsteps;
-            d.c.submit_s = r.submit_s;
-            d.c.admit_s = r.admit_s;
-            d.U.resize((size_t)r.lat->sz.m * r.lat->desc.plane);
-            r.lat->step = r.nsteps;  // the batched launches advanced it
-            r.lat->busy = false;
-            arlbm_status st{};
-            int rc = arlbm_sync(r.lat, &st);
-            d.c.t = st.t;
-            d.c.flags = st.flags;
-            if (rc == ARLBM_EPOSITIVITY) rc = ARLBM_OK;  // advisory: the moments are still the result
-            if (rc == ARLBM_OK) rc = arlbm_read_moments(r.lat, d.U.data());
-            d.c.status = rc;
-            d.c.done_s = now_s();
-            s->done.push_back(std::move(d));
-            s->in_use -= r.bytes;
-            arlbm_destroy(r.lat);
             s->resident.erase(s->resident.begin() + i);
             s->dirty = true;
+            (void)retire_enqueue(s, r);  // a failure is reported in its completion
         } else {
             ++i;
         }
@@ -977,27 +1360,9 @@ extern "C" int arlbm_server_iterate(arlbm_server *s, int32_t *n_res, int32_t *n_
     while (!s->queue.empty() && s->in_use + s->queue.front().bytes <= s->budget) {
         Pending p = std::move(s->queue.front());
         s->queue.pop_front();
-        arlbm_lattice *lat = nullptr;
-        int rc = arlbm_create(&p.cfg, nullptr, s->stream, &lat);
-        if (rc == ARLBM_OK) rc = arlbm_set_state(lat, p.U0.data(), p.cfg.has_bed ? p.bed.data() : nullptr, 0.0);
-        if (rc != ARLBM_OK) {
-            Done d{};
-            d.c.id = p.id;
-            d.c.status = rc;
-            d.c.submit_s = p.submit_s;
-            d.c.done_s = now_s();
-            s->done.push_back(std::move(d));
-            if (lat) arlbm_destroy(lat);
-            continue;
-        }
-        lat->busy = true;
-        s->resident.push_back({p.id, lat, p.nsteps, s->iter, p.submit_s, now_s(), p.bytes});
-        s->in_use += p.bytes;
-        s->dirty = true;
+        admit_enqueue(s, p);
     }
     if (s->dirty) {
-        hipError_t e = hipStreamSynchronize(s->stream);
-        if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, hipGetErrorString(e));
         int rc = rebuild_table(s);
         if (rc) return rc;
     }
@@ -1020,6 +1385,9 @@ extern "C" int arlbm_server_iterate(arlbm_server *s, int32_t *n_res, int32_t *n_
         }
         ++s->iter;
     }
+    // result copies and admission checks, while the launch runs
+    int rc = finish_staged(s);
+    if (rc) return rc;
     if (n_res) *n_res = (int32_t)s->resident.size();
     if (n_queued) *n_queued = (int32_t)s->queue.size();
     return ARLBM_OK;
@@ -1056,9 +1424,20 @@ extern "C" int arlbm_server_destroy(arlbm_server *s)
 {
     if (!s) return ARLBM_OK;
     (void)hipStreamSynchronize(s->stream);
-    for (auto &r : s->resident) arlbm_destroy(r.lat);
+    (void)finish_staged(s);
+    for (auto &r : s->resident) {
+        drop_handle(r.lat);
+        s->dev.release(r.dev, r.dev_cls);
+    }
+    s->dev.clear();
+    s->pin.clear();
     if (s->d_descs) (void)hipFree(s->d_descs);
     if (s->d_items) (void)hipFree(s->d_items);
+    for (int k = 0; k < 2; ++k) {
+        if (s->h_descs[k]) (void)hipHostFree(s->h_descs[k]);
+        if (s->h_items[k]) (void)hipHostFree(s->h_items[k]);
+        if (s->table_ev[k]) (void)hipEventDestroy(s->table_ev[k]);
+    }
     delete s;
     return ARLBM_OK;
 }
