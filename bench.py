@@ -209,7 +209,7 @@ def run_serving(torch, args, n_requests, rate_hz, fp64_check, tag="serving", bud
             reqs[nxt].server_id = srv.submit(cfgs[nxt], p.U0, p.bed, reqs[nxt].steps)
             nxt += 1
         ti = time.perf_counter()
-        resident, queued = srv.iterate()
+        resident, queued = srv.iterate(args.launches_per_iterate)
         if resident:
             busy += time.perf_counter() - ti
         iters += 1
@@ -242,7 +242,8 @@ def run_serving(torch, args, n_requests, rate_hz, fp64_check, tag="serving", bud
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "iterations": iters, "peak_resident_bytes": int(peak_mem), "offered_lups": int(lups),
            "offered_glups_over_arrivals": lups / span / 1e9, "arrival_span_s": span,
-           "iterate_time_fraction_with_work": busy / wall, "rate_hz": rate_hz, "budget_gib": budget_gib}
+           "iterate_time_fraction_with_work": busy / wall, "rate_hz": rate_hz, "budget_gib": budget_gib,
+           "launches_per_iterate": args.launches_per_iterate}
     # FP32 (batched) against the FP64 plain path on a subsample of requests
     errs = []
     for r in reqs[:fp64_check]:
@@ -349,6 +350,9 @@ def main():
     # that admission never waits for memory
     ap.add_argument("--unlimited-gib", type=float, default=192.0)
     ap.add_argument("--fp64-check", type=int, default=12)
+    # batched launches per server iteration at most (capped by the resident
+    # lattices' remaining steps): the host loop keeps that much work queued
+    ap.add_argument("--launches-per-iterate", type=int, default=32)
     ap.add_argument("--low-requests", type=int, default=64)
     ap.add_argument("--low-rate", type=float, default=8.0)
     ap.add_argument("--latency-solves", type=int, default=20)

@@ -250,6 +250,15 @@ int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, const double *
  * after the iteration (either may be NULL). */
 int arlbm_server_iterate(arlbm_server *s, int32_t *resident, int32_t *queued);
 
+/* As arlbm_server_iterate, with up to max_launches (>= 1) batched launches
+ * after the admissions, fewer where a resident lattice would otherwise pass
+ * its step count: retirements and results are those of one launch per call,
+ * while the host keeps more work queued on the GPU (requests submitted
+ * meanwhile wait for the next call).  *launched (may be NULL) receives the
+ * launches made.  EINVAL if max_launches < 1. */
+int arlbm_server_iterate_n(arlbm_server *s, int32_t max_launches, int32_t *resident,
+                           int32_t *queued, int32_t *launched);
+
 /* Pop up to max finished requests into out; *n receives the count. */
 int arlbm_server_poll(arlbm_server *s, arlbm_completion *out, int32_t max, int32_t *n);
 

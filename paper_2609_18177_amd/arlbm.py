@@ -104,6 +104,8 @@ def lib():
             "arlbm_server_create": ([C.c_size_t, C.c_int32, vp, C.POINTER(vp)], C.c_int),
             "arlbm_server_submit": ([vp, C.POINTER(Config), dp, dp, C.c_int64, C.POINTER(C.c_uint64)], C.c_int),
             "arlbm_server_iterate": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+            "arlbm_server_iterate_n": ([vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_int32)], C.c_int),
             "arlbm_server_poll": ([vp, C.POINTER(Completion), C.c_int32, C.POINTER(C.c_int32)], C.c_int),
             "arlbm_server_memory": ([vp, C.POINTER(C.c_size_t)], C.c_int),
             "arlbm_server_destroy": ([vp], C.c_int),
@@ -310,9 +312,14 @@ class Server:
         _check(lib().arlbm_server_submit(self._h, C.byref(cfg), _dptr(U0), _dptr(bed), int(nsteps), C.byref(rid)))
         return rid.value
 
-    def iterate(self):
+    def iterate(self, max_launches: int = 1):
+        """Admit, launch (up to max_launches batched steps, never past a
+        resident lattice's step count), retire; returns (resident, queued)."""
         r, q = C.c_int32(), C.c_int32()
-        _check(lib().arlbm_server_iterate(self._h, C.byref(r), C.byref(q)))
+        if max_launches == 1:
+            _check(lib().arlbm_server_iterate(self._h, C.byref(r), C.byref(q)))
+        else:
+            _check(lib().arlbm_server_iterate_n(self._h, int(max_launches), C.byref(r), C.byref(q), None))
         return r.value, q.value
 
     def poll(self, max_items: int = 64):

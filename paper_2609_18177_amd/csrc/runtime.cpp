@@ -1344,7 +1344,15 @@ extern "C" int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, con
 
 extern "C" int arlbm_server_iterate(arlbm_server *s, int32_t *n_res, int32_t *n_queued)
 {
+    return arlbm_server_iterate_n(s, 1, n_res, n_queued, nullptr);
+}
+
+extern "C" int arlbm_server_iterate_n(arlbm_server *s, int32_t max_launches, int32_t *n_res, int32_t *n_queued,
+                                      int32_t *n_launched)
+{
     if (!s) return sfail(nullptr, ARLBM_EINVAL, "server is NULL");
+    if (max_launches < 1) return sfail(s, ARLBM_EINVAL, "max_launches must be >= 1");
+    if (n_launched) *n_launched = 0;
     // retire lattices whose steps are complete (read-backs enqueued)
     for (size_t i = 0; i < s->resident.size();) {
         const Resident r = s->resident[i];
@@ -1366,7 +1374,13 @@ extern "C" int arlbm_server_iterate(arlbm_server *s, int32_t *n_res, int32_t *n_
         int rc = rebuild_table(s);
         if (rc) return rc;
     }
-    if (!s->resident.empty()) {
+    // launches this call: as many as asked, but no resident lattice past its
+    // step count, so retirements fall on the same iteration as one launch
+    // per call would give
+    int64_t nl = s->resident.empty() ? 0 : max_launches;
+    for (const Resident &r : s->resident) nl = std::min<int64_t>(nl, r.nsteps - (s->iter - r.iter0));
+    if (!s->resident.empty() && nl < 1) nl = 1;
+    for (int64_t l = 0; l < nl; ++l) {
         hipError_t e = hipSuccess;
         if (s->nitems > 0)
             e = s->precision == ARLBM_F64 ? f64::step_batched(s->d_descs, s->d_items, s->nitems, s->iter, s->stream)
@@ -1384,6 +1398,7 @@ extern "C" int arlbm_server_iterate(arlbm_server *s, int32_t *n_res, int32_t *n_
             if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("3D step launch: ") + hipGetErrorString(e));
         }
         ++s->iter;
+        if (n_launched) ++*n_launched;
     }
     // result copies and admission checks, while the launch runs
     int rc = finish_staged(s);

@@ -247,7 +247,7 @@ def _requests():
             W.swe_bed_2d(6, n=77, steps=200), W.euler_seeded_2d(7, n=64, steps=30)]
 
 
-def _serve(probs, budget, precision=A.F32, one_at_a_time=False):
+def _serve(probs, budget, precision=A.F32, one_at_a_time=False, max_launches=1):
     srv = A.Server(budget, precision)
     ids, res, peak = [], {}, 0
     pending = list(probs)
@@ -255,7 +255,7 @@ def _serve(probs, budget, precision=A.F32, one_at_a_time=False):
         if pending and (not one_at_a_time or len(res) == len(ids)):
             p = pending.pop(0)
             ids.append(srv.submit(A.config_from(p, precision=precision), p.U0, p.bed, p.steps))
-        srv.iterate()
+        srv.iterate(max_launches)
         peak = max(peak, srv.memory())
         for c in srv.poll(16):
             res[c["id"]] = c
@@ -275,6 +275,25 @@ def test_serving_alone_equals_mix_bitwise():
         assert np.array_equal(a["U"], b["U"]), p.name
         assert a["t"] == b["t"]
     say(f"[serving] {len(probs)} requests, alone == mix bitwise, peak resident {peak} bytes")
+
+
+def test_serving_several_launches_per_iterate_bitwise():
+    """Up to 7 launches per call (capped at each lattice's remaining steps)
+    give the results, step counts and times of one launch per call, with a
+    budget that makes requests wait for retirements."""
+    require_gpu()
+    probs = _requests()
+    sizes = [A.query_sizes(A.config_from(p, precision=A.F32)).total_bytes for p in probs]
+    budget = max(sizes) + min(sizes)
+    one, _ = _serve(probs, budget)
+    many, peak = _serve(probs, budget, max_launches=7)
+    assert peak <= budget
+    for p, a, b in zip(probs, one, many):
+        assert a["status"] == 0 and b["status"] == 0
+        assert b["steps"] == p.steps
+        assert np.array_equal(a["U"], b["U"]), p.name
+        assert a["t"] == b["t"]
+    say(f"[serving] {len(probs)} requests, 7 launches per iterate == 1, bitwise")
 
 
 def test_serving_fp64_matches_oracle_and_fp32_is_close():
