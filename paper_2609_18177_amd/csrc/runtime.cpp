@@ -15,7 +15,9 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "arlbm.h"
@@ -812,10 +814,50 @@ extern "C" int arlbm_step_kernel_vgprs(int32_t precision, int32_t system, int32_
 // once the pool is warm, serving calls neither hipMalloc nor hipFree.
 
 namespace {
+// Host arrays the server keeps (queued initial states, results): left
+// uninitialised when allocated, since a parallel copy fills them at once.
+struct HostArray {
+    std::unique_ptr<double[]> p;
+    size_t n = 0;
+    void alloc(size_t count)
+    {
+        p.reset(count ? new double[count] : nullptr);
+        n = count;
+    }
+    double *data() { return p.get(); }
+    const double *data() const { return p.get(); }
+    size_t size() const { return n; }
+};
+
+// memcpy of large host arrays over several threads: a fresh destination
+// faults its pages in on first touch, and those faults proceed in parallel
+// (measured on 32 MB: 21 ms on one thread, 4 ms on eight).
+void par_copy(void *dst, const void *src, size_t bytes)
+{
+    constexpr size_t kPerThread = (size_t)4 << 20;
+    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>({(size_t)8, hw, bytes / kPerThread});
+    if (nt < 2) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    const size_t chunk = (bytes / nt + 4095) / 4096 * 4096;
+    std::vector<std::thread> th;
+    th.reserve(nt - 1);
+    for (size_t t = 1; t < nt; ++t) {
+        const size_t a = t * chunk;
+        if (a >= bytes) break;
+        const size_t len = std::min(chunk, bytes - a);
+        th.emplace_back([=] { std::memcpy((char *)dst + a, (const char *)src + a, len); });
+    }
+    std::memcpy(dst, src, std::min(chunk, bytes));
+    for (auto &x : th) x.join();
+}
+
 struct Pending {
     uint64_t id;
     arlbm_config cfg;
-    std::vector<double> U0, bed;
+    HostArray U0, bed;
     int64_t nsteps;
     double submit_s;
     size_t bytes;
@@ -831,7 +873,7 @@ struct Resident {
 };
 struct Done {
     arlbm_completion c;
-    std::vector<double> U;
+    HostArray U;
 };
 // An admission or a retirement whose transfers are in the stream, finished
 // after the iteration's launch.
@@ -1147,8 +1189,8 @@ void admit_enqueue(arlbm_server *s, Pending &p)
         init.t[0] = 0.0;
         init.first_bad_step = ~0ull;
         std::memcpy(host + L.sc_in, &init, sizeof init);
-        std::memcpy(host + L.u0, p.U0.data(), sizeof(double) * sz.m * plane);
-        if (has_bed) std::memcpy(host + L.bed, p.bed.data(), sizeof(double) * plane);
+        par_copy(host + L.u0, p.U0.data(), sizeof(double) * sz.m * plane);
+        if (has_bed) par_copy(host + L.bed, p.bed.data(), sizeof(double) * plane);
         double *U0d = (double *)lat->desc.f[1];
         double *bedd = has_bed ? U0d + (size_t)sz.m * plane : nullptr;
         hipError_t e = hipMemcpyAsync(U0d, host + L.u0, sizeof(double) * sz.m * plane, hipMemcpyHostToDevice, s->stream);
@@ -1255,7 +1297,8 @@ int finish_staged(arlbm_server *s)
             // the positivity flag is advisory: the moments are still the result
             if (rc == ARLBM_OK) {
                 const double *U = (const double *)((const char *)g.host + align_up(sizeof(DevScalars)));
-                d.U.assign(U, U + (size_t)h->sz.m * h->desc.plane);
+                d.U.alloc((size_t)h->sz.m * h->desc.plane);
+                par_copy(d.U.data(), U, sizeof(double) * d.U.size());
             }
             d.c.status = rc;
             d.c.done_s = now_s();
@@ -1332,8 +1375,12 @@ extern "C" int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, con
     p.id = s->next_id++;
     p.cfg = c;
     const size_t plane = (size_t)c.nx * c.ny * c.nz;
-    p.U0.assign(U0, U0 + (size_t)sz.m * plane);
-    if (c.has_bed) p.bed.assign(bed, bed + plane);
+    p.U0.alloc((size_t)sz.m * plane);
+    par_copy(p.U0.data(), U0, sizeof(double) * p.U0.size());
+    if (c.has_bed) {
+        p.bed.alloc(plane);
+        par_copy(p.bed.data(), bed, sizeof(double) * plane);
+    }
     p.nsteps = nsteps;
     p.submit_s = now_s();
     p.bytes = sz.total_bytes;
