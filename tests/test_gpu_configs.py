@@ -296,6 +296,44 @@ def test_serving_several_launches_per_iterate_bitwise():
     say(f"[serving] {len(probs)} requests, 7 launches per iterate == 1, bitwise")
 
 
+def test_serving_failed_admissions_leave_the_mix_intact():
+    """Requests that fail the checks set_state makes after the initialisation
+    (an all-dry shallow-water state: zero wave-speed bounds; an eps above the
+    bound of Theorem 4.3) complete with that error, and the requests served
+    beside them give the bits they give alone."""
+    require_gpu()
+    import dataclasses
+    probs = _requests()
+    alone, _ = _serve(probs, 1 << 30, one_at_a_time=True)
+    base = W.swe_bed_2d(5, n=100, steps=90)
+    dry = dataclasses.replace(base, U0=np.zeros_like(base.U0))
+    stiff = W.euler_seeded_2d(4, n=130, steps=120)
+    srv = A.Server(1 << 30, A.F32)
+    ids = []
+    for i, p in enumerate(probs):
+        ids.append(srv.submit(A.config_from(p, precision=A.F32), p.U0, p.bed, p.steps))
+        if i == 1:
+            bad_dry = srv.submit(A.config_from(dry, precision=A.F32), dry.U0, dry.bed, dry.steps)
+            cfg = A.config_from(stiff, precision=A.F32)
+            cfg.eps = 1e3
+            bad_eps = srv.submit(cfg, stiff.U0, stiff.bed, stiff.steps)
+    res = {}
+    while len(res) < len(probs) + 2:
+        srv.iterate(4)
+        for c in srv.poll(16):
+            res[c["id"]] = c
+    assert srv.memory() == 0
+    srv.close()
+    assert res[bad_dry]["status"] == A.EDEGENERATE and res[bad_dry]["U"] is None
+    assert res[bad_eps]["status"] == A.EINVAL and res[bad_eps]["U"] is None
+    for p, a, i in zip(probs, alone, ids):
+        b = res[i]
+        assert b["status"] == 0 and b["steps"] == p.steps
+        assert np.array_equal(a["U"], b["U"]), p.name
+        assert a["t"] == b["t"]
+    say(f"[serving] degenerate and eps-bound admissions fail cleanly; {len(probs)} others bitwise as alone")
+
+
 def test_serving_fp64_matches_oracle_and_fp32_is_close():
     require_gpu()
     probs = _requests()
