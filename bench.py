@@ -312,9 +312,16 @@ def run_cpu_baseline(args):
     dt = time.perf_counter() - t0
     glups = p.cells * args.cpu_steps / dt / 1e9
     log(f"[cpu] oracle {args.cpu_steps} steps of 2048^2 in {dt:.1f}s: {glups * 1e3:.2f} MLUPS")
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": glups, "unit": "GLUPS", "cores": 1, "kind": "oracle",
             "sample": f"{args.cpu_steps} steps of the 2048x2048 2D Euler lattice (seed 0), FP64, "
-                      f"single-threaded C oracle, {dt:.1f} s"}
+                      f"single-threaded C oracle, {dt:.1f} s",
+            "host_cpu": model, "host_logical_cpus": os.cpu_count()}
 
 
 def copy_calibration(torch, args):
