@@ -16,6 +16,7 @@
 #include <cstring>
 #include <deque>
 #include <memory>
+#include <new>
 #include <string>
 #include <thread>
 #include <vector>
@@ -819,10 +820,11 @@ namespace {
 struct HostArray {
     std::unique_ptr<double[]> p;
     size_t n = 0;
-    void alloc(size_t count)
+    bool alloc(size_t count)  // false when the memory is not there
     {
-        p.reset(count ? new double[count] : nullptr);
-        n = count;
+        p.reset(count ? new (std::nothrow) double[count] : nullptr);
+        n = p ? count : 0;
+        return p || count == 0;
     }
     double *data() { return p.get(); }
     const double *data() const { return p.get(); }
@@ -837,20 +839,27 @@ void par_copy(void *dst, const void *src, size_t bytes)
     constexpr size_t kPerThread = (size_t)4 << 20;
     const size_t hw = std::max(1u, std::thread::hardware_concurrency());
     const size_t nt = std::min<size_t>({(size_t)8, hw, bytes / kPerThread});
+    if (bytes == 0) return;
     if (nt < 2) {
         std::memcpy(dst, src, bytes);
         return;
     }
-    const size_t chunk = (bytes / nt + 4095) / 4096 * 4096;
+    const size_t chunk = (bytes / nt + 4095) / 4096 * 4096;  // nt * chunk >= bytes
     std::vector<std::thread> th;
-    th.reserve(nt - 1);
-    for (size_t t = 1; t < nt; ++t) {
-        const size_t a = t * chunk;
-        if (a >= bytes) break;
-        const size_t len = std::min(chunk, bytes - a);
-        th.emplace_back([=] { std::memcpy((char *)dst + a, (const char *)src + a, len); });
+    size_t started = 0;  // chunks 1 .. started run on threads of their own
+    try {
+        th.reserve(nt - 1);
+        for (size_t t = 1; t < nt && t * chunk < bytes; ++t) {
+            const size_t a = t * chunk, len = std::min(chunk, bytes - a);
+            th.emplace_back([=] { std::memcpy((char *)dst + a, (const char *)src + a, len); });
+            started = t;
+        }
+    } catch (...) {
+        // no thread for the remaining chunks: copied below
     }
     std::memcpy(dst, src, std::min(chunk, bytes));
+    const size_t rest = (started + 1) * chunk;
+    if (rest < bytes) std::memcpy((char *)dst + rest, (const char *)src + rest, bytes - rest);
     for (auto &x : th) x.join();
 }
 
@@ -1297,8 +1306,8 @@ int finish_staged(arlbm_server *s)
             // the positivity flag is advisory: the moments are still the result
             if (rc == ARLBM_OK) {
                 const double *U = (const double *)((const char *)g.host + align_up(sizeof(DevScalars)));
-                d.U.alloc((size_t)h->sz.m * h->desc.plane);
-                par_copy(d.U.data(), U, sizeof(double) * d.U.size());
+                if (d.U.alloc((size_t)h->sz.m * h->desc.plane)) par_copy(d.U.data(), U, sizeof(double) * d.U.size());
+                else rc = ARLBM_ENOMEM;
             }
             d.c.status = rc;
             d.c.done_s = now_s();
@@ -1375,12 +1384,10 @@ extern "C" int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, con
     p.id = s->next_id++;
     p.cfg = c;
     const size_t plane = (size_t)c.nx * c.ny * c.nz;
-    p.U0.alloc((size_t)sz.m * plane);
+    if (!p.U0.alloc((size_t)sz.m * plane) || (c.has_bed && !p.bed.alloc(plane)))
+        return sfail(s, ARLBM_ENOMEM, "host memory for the queued state");
     par_copy(p.U0.data(), U0, sizeof(double) * p.U0.size());
-    if (c.has_bed) {
-        p.bed.alloc(plane);
-        par_copy(p.bed.data(), bed, sizeof(double) * plane);
-    }
+    if (c.has_bed) par_copy(p.bed.data(), bed, sizeof(double) * plane);
     p.nsteps = nsteps;
     p.submit_s = now_s();
     p.bytes = sz.total_bytes;
