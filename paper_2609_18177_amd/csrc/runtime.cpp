@@ -1280,7 +1280,8 @@ int retire_enqueue(arlbm_server *s, const Resident &r)
 // results out of their pinned blocks and check the admitted lattices'
 // wave-speed bounds (Theorem 4.3's bound on eps, a nonzero sum), as
 // set_state does.  An admitted lattice that fails leaves the mix with its
-// error; its one launched step touched only its own buffers.
+// error; the steps launched with it (as many as the call's launches) touched
+// only its own buffers.
 int finish_staged(arlbm_server *s)
 {
     int first_err = ARLBM_OK;
