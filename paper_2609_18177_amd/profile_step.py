@@ -11,12 +11,14 @@ mode (the launch configuration bench.py times):
 
 Writes ``profiles/<workload>_pmc.json`` (HBM bytes per launch, keyed to a
 hash of the kernel sources) and ``profiles/<workload>_rocprof.md`` (the
-figures and the commands).  Usage, on a GPU machine, from the repository
+figures and the commands).  ``--workload serving`` runs only a kernel trace
+of the serving mix and writes ``profiles/serving_mix_f32_rocprof.md``.  Usage, on a GPU machine, from the repository
 root::
 
     python -m paper_2609_18177_amd.profile_step --workload euler2d_f32 --raw gpurun_out/prof
 """
 import argparse
+import ast
 import csv
 import collections
 import json
@@ -71,15 +73,63 @@ def kernel_stats(csv_path, name_part):
     return None
 
 
+def serving_profile(args, raw):
+    """Kernel trace of the default serving mix (bench.py --only serving):
+    time per kernel, and how much of the run the GPU spent in kernels.  The
+    batched kernel's work differs from launch to launch (the resident mix
+    changes), so no per-launch counters are taken."""
+    prog = ["bench.py", "--only", "serving"]
+    d, cmd = rocprof(["--kernel-trace", "--stats"], raw, "serving_trace", prog, 300)
+    with open(os.path.join(raw, "serving_trace.log")) as f:
+        line = [ln for ln in f if "[only] serving " in ln][-1]
+    res = ast.literal_eval(line.split("[only] serving ", 1)[1].strip())
+    starts, ends = [], []
+    with open(os.path.join(d, "run_kernel_trace.csv")) as f:
+        for r in csv.DictReader(f):
+            starts.append(int(r["Start_Timestamp"]))
+            ends.append(int(r["End_Timestamp"]))
+    span_s = (max(ends) - min(starts)) / 1e9
+    busy_s = sum(e - b for b, e in zip(starts, ends)) / 1e9
+    rows = []
+    with open(os.path.join(d, "run_kernel_stats.csv")) as f:
+        for r in csv.DictReader(f):
+            rows.append((r["Name"].split("(")[0].replace("void ", ""), int(r["Calls"]), float(r["TotalDurationNs"]),
+                         float(r["AverageNs"])))
+    rows.sort(key=lambda x: -x[2])
+    pdir = os.path.abspath(args.profiles_dir)
+    os.makedirs(pdir, exist_ok=True)
+    with open(os.path.join(pdir, "serving_mix_f32_rocprof.md"), "w") as f:
+        f.write("# rocprofv3 summary: k_step_batched<float>, workload serving_mix_f32\n\n")
+        f.write("Made by `python -m paper_2609_18177_amd.profile_step --workload serving` (kernel source hash "
+                f"{bench.kernel_source_hash()}); the pass it ran:\n\n    {cmd}\n\n")
+        f.write("512 requests (Poisson arrivals at 200/s; 1D Euler, 2D Euler and shallow water) admitted by a 4 GiB "
+                "budget, served by the batched FP32 kernel.\n\n")
+        f.write("| quantity | value |\n|---|---|\n")
+        f.write(f"| requests served / failed | {res['requests']} / {res['failed']} |\n")
+        f.write(f"| serving wall time (bench) | {res['wall_s']:.2f} s |\n")
+        f.write(f"| throughput (bench) | {res['glups']:.2f} GLUPS |\n")
+        f.write(f"| latency p50 / p99 (bench) | {res['p50_ms'] / 1e3:.2f} / {res['p99_ms'] / 1e3:.2f} s |\n")
+        f.write(f"| batched launches per server call at most | {res.get('launches_per_iterate', 1)} |\n")
+        f.write(f"| first kernel start to last kernel end | {span_s:.2f} s |\n")
+        f.write(f"| time in kernels (all kinds) | {busy_s:.2f} s ({100 * busy_s / span_s:.1f}% of the span) |\n")
+        f.write("\n| kernel | calls | total (s) | average (us) |\n|---|---|---|---|\n")
+        for name, calls, tot, avg in rows[:8]:
+            f.write(f"| {name} | {calls} | {tot / 1e9:.3f} | {avg / 1e3:.1f} |\n")
+    print(json.dumps({"span_s": span_s, "busy_s": busy_s, "bench": res}, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=sorted(KERNELS), default="euler2d_f32")
+    ap.add_argument("--workload", choices=sorted(KERNELS) + ["serving"], default="euler2d_f32")
     ap.add_argument("--raw", default="gpurun_out/prof")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--profiles-dir", default=os.path.join(ROOT, "profiles"))
     args = ap.parse_args()
     raw = os.path.abspath(args.raw)
     os.makedirs(raw, exist_ok=True)
+    if args.workload == "serving":
+        serving_profile(args, raw)
+        return
     prog = ["bench.py", "--only", args.workload, "--steps", str(args.steps), "--warmup", "10"]
     kname = KERNELS[args.workload]
     d, cmd_trace = rocprof(["--kernel-trace", "--stats"], raw, "trace", prog, 300)
