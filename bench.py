@@ -185,6 +185,33 @@ def run_latency_1d(torch, args):
     return out
 
 
+def run_latency_advection(torch, args):
+    """Solve latency of the advection configuration (N=256, sin 2 pi x,
+    periodic, CFL 0.5, 512 steps to t=1), FP64 as configured: set_state ->
+    steps -> read_moments; with the relative L2 error against the exact
+    solution (the initial profile after one period)."""
+    p = W.advection_sine(n=256, steps=512)
+    L = A.Lattice(A.config_from(p, precision=A.F64), owner="torch")
+    lat = []
+    U = None
+    for i in range(args.latency_solves + 2):
+        t0 = time.perf_counter()
+        L.set_state(p.U0)
+        L.step(p.steps)
+        U = L.moments()
+        dt = time.perf_counter() - t0
+        if i >= 2:
+            lat.append(dt)
+    st = L.sync(check=False)
+    L.close()
+    lat = np.array(lat) * 1e3
+    err = float(np.linalg.norm(U.ravel() - p.U0.ravel()) / np.linalg.norm(p.U0.ravel()))
+    out = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)), "t": st["t"],
+           "rel_l2_vs_exact": err}
+    log(f"[latency] advection N=256, 512 steps, FP64: {out}")
+    return out
+
+
 def run_serving(torch, args, n_requests, rate_hz, fp64_check, tag="serving", budget_gib=None):
     """Continuous batching: Poisson arrivals admitted by HBM budget into the
     batched FP32 kernel; latency = result read back - arrival."""
@@ -422,6 +449,7 @@ def main():
                                "mass_drift_rel": sw["mass_drift_rel"], "flags": sw["flags"]}
     extra["euler3d_256_f32"] = run_euler3d(torch, args)
     extra["euler1d_4096_latency"] = run_latency_1d(torch, args)
+    extra["advection_256_latency_f64"] = run_latency_advection(torch, args)
     if not args.no_serving:
         extra["serving"] = run_serving(torch, args, args.requests, args.rate, args.fp64_check)
         # the default mix offers several times the capacity, so its latency is
