@@ -142,7 +142,7 @@ def test_conservation_sums_3d(system):
     G.close()
 
 
-def _serve(probs, precision, one_at_a_time):
+def _serve(probs, precision, one_at_a_time, max_launches=1):
     srv = A.Server(1 << 30, precision)
     ids, res = [], {}
     pending = list(probs)
@@ -150,7 +150,7 @@ def _serve(probs, precision, one_at_a_time):
         if pending and (not one_at_a_time or len(res) == len(ids)):
             p = pending.pop(0)
             ids.append(srv.submit(A.config_from(p, precision=precision), p.U0, p.bed, p.steps))
-        srv.iterate()
+        srv.iterate(max_launches)
         for c in srv.poll(16):
             res[c["id"]] = c
     srv.close()
@@ -168,9 +168,12 @@ def test_3d_in_serving_mix():
              W.euler_seeded_2d(2, n=90, steps=30),
              dataclasses.replace(W.advection_sine_3d(n=16), steps=15)]
     mix, alone = _serve(probs, A.F32, False), _serve(probs, A.F32, True)
-    for p, a, b in zip(probs, alone, mix):
-        assert a["status"] == 0 and b["status"] == 0, p.name
+    # several launches per call: the 3D passes run after each batched launch
+    many = _serve(probs, A.F32, False, max_launches=5)
+    for p, a, b, c in zip(probs, alone, mix, many):
+        assert a["status"] == 0 and b["status"] == 0 and c["status"] == 0, p.name
         assert np.array_equal(a["U"], b["U"]), p.name
+        assert np.array_equal(a["U"], c["U"]) and a["t"] == c["t"] and c["steps"] == p.steps, p.name
         if p.dim == 3:
             G = gpu_lattice(p, A.F32)
             G.step(p.steps)
@@ -184,4 +187,4 @@ def test_3d_in_serving_mix():
         assert r["status"] == 0 and r["steps"] == p.steps, p.name
         assert np.array_equal(r["U"].reshape(Lo.moments().shape), Lo.moments()), p.name
         assert r["t"] == Lo.t, p.name
-    say("[3d serving] alone == mix == single (FP32); FP64 served == oracle, 3D and 1D/2D")
+    say("[3d serving] alone == mix == 5 launches per call == single (FP32); FP64 served == oracle, 3D and 1D/2D")
