@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define ARLBM_ABI_VERSION 3
+#define ARLBM_ABI_VERSION 4
 
 /* Systems, boundary conditions, precisions, relaxation modes. */
 enum { ARLBM_ADVECTION = 0, ARLBM_EULER = 1, ARLBM_SWE = 2, ARLBM_REACTIVE = 3 };
@@ -222,7 +222,10 @@ typedef struct arlbm_completion {
     int32_t status;       /* 0 or an ARLBM_E* code (EPOSITIVITY is reported in
                              flags, with status 0)                             */
     uint32_t flags;       /* ARLBM_FLAG_* bits seen during the run              */
-    int64_t steps;        /* steps taken                                        */
+    int64_t steps;        /* steps taken in the server (fewer than asked when a
+                             non-finite or degenerate state retired it early)  */
+    int64_t first_bad_step; /* the lattice's first step whose result set a flag,
+                             or -1                                             */
     double t;             /* simulated time reached                             */
     double submit_s;      /* host clock (seconds) at submit                     */
     double admit_s;       /* host clock when its lattice became resident        */
@@ -232,17 +235,35 @@ typedef struct arlbm_completion {
     int64_t u_count;      /* number of doubles in U                             */
 } arlbm_completion;
 
-/* Create a server whose resident lattices never exceed hbm_budget bytes of
- * device memory.  precision must be ARLBM_F32 or ARLBM_F64. */
+/* Create a server whose lattices never hold more than hbm_budget bytes of
+ * device memory: each resident lattice takes one block of the server's pool,
+ * sized to a class at most 25% above its buffers (arlbm_sizes.total_bytes),
+ * and the blocks the pool keeps, in use or free for reuse, never exceed the
+ * budget together.  The work table of the batched launch (about 0.3 KB per
+ * resident lattice plus 16 bytes per segment) is outside the budget.
+ * precision must be ARLBM_F32 or ARLBM_F64. */
 int arlbm_server_create(size_t hbm_budget, int32_t precision, void *stream,
                         arlbm_server **out);
 
 /* Queue a request: a configuration, host FP64 initial planes (and bed) copied
- * at submit time, and a step count.  EBUDGET if it can never fit the budget.
- * 1D and 2D lattices advance in the iteration's batched launch; a 3D lattice
- * runs its three passes as launches of its own after it, on the same stream. */
+ * at submit time, and a step count (>= 1, else EINVAL).  EBUDGET if its block
+ * can never fit the budget.  1D and 2D lattices advance in the iteration's
+ * batched launch; a 3D lattice, or a 2D one whose population buffer spans
+ * 4 GiB or more, runs its step as launches of its own after it, on the same
+ * stream.  A lattice whose state becomes non-finite (or whose wave-speed
+ * bounds sum to zero) is retired at a later call, before its step count,
+ * and completes with ENONFINITE (EDEGENERATE); the others are unaffected. */
 int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, const double *U0,
                         const double *bed, int64_t nsteps, uint64_t *id);
+
+/* Queue a request that resumes a saved lattice: blob holds bytes written by
+ * arlbm_save_state for a lattice of configuration cfg in the server's
+ * precision (copied at submit time); the lattice takes nsteps (>= 1) more
+ * steps from the saved step and time, exactly as the saved lattice would have
+ * on its own.  EINVAL if the blob does not match cfg (header, sizes), or if
+ * cfg has a bed; EBUDGET as for submit. */
+int arlbm_server_submit_state(arlbm_server *s, const arlbm_config *cfg, const void *blob,
+                              size_t bytes, int64_t nsteps, uint64_t *id);
 
 /* One serving iteration: admit queued requests while the budget allows, run
  * one batched step for every resident lattice, and retire finished ones
@@ -262,14 +283,33 @@ int arlbm_server_iterate_n(arlbm_server *s, int32_t max_launches, int32_t *resid
 /* Pop up to max finished requests into out; *n receives the count. */
 int arlbm_server_poll(arlbm_server *s, arlbm_completion *out, int32_t max, int32_t *n);
 
-/* Bytes of device memory held by resident lattices. */
+/* Bytes of device memory charged to resident lattices (their blocks). */
 int arlbm_server_memory(arlbm_server *s, size_t *bytes_in_use);
+
+/* Bytes of device memory the server's pool holds for lattices: blocks in use
+ * and free blocks kept for reuse (never above the budget). */
+int arlbm_server_pool_bytes(arlbm_server *s, size_t *bytes_held);
 
 int arlbm_server_destroy(arlbm_server *s);
 
 /* ------------------------------------------------------------------------ */
 /* Diagnostics                                                               */
 /* ------------------------------------------------------------------------ */
+
+/* The batched launch's schedule for lattices of configurations cfgs[0..n-1]
+ * served together (3D lattices, which run launches of their own, take no
+ * part), dealt to at most `waves` waves, computed on the host as the server
+ * computes it (no GPU needed).  On return *nwaves waves and *nsegs segments;
+ * wave w runs segments wave_start[w] .. wave_start[w+1]-1 (wave_start has
+ * *nwaves + 1 entries), and segment k is segs[4k .. 4k+3] = (lattice index,
+ * strip, first row, end row) for a 2D lattice, (lattice index, first strip,
+ * 0, end strip) for a 1D one.  Strips are 58 output columns, or 120 where
+ * the lattice runs two columns per lane.  EINVAL on a bad configuration or
+ * when the output arrays (max_waves + 1 and 4 max_segs entries) are too
+ * small (the counts are still set). */
+int arlbm_plan_schedule(const arlbm_config *cfgs, int32_t n, int32_t waves, int32_t *wave_start,
+                        int32_t max_waves, int32_t *segs, int32_t max_segs, int32_t *nwaves,
+                        int32_t *nsegs);
 
 /* Vector registers per lane of the fused step kernel for a precision, system
  * and dimension (from the code object; in 2D the kernel that a lattice of

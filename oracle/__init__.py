@@ -30,16 +30,18 @@ class OraCfg(C.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    """Load the oracle library, building it first only if it is absent."""
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_build.LIB):
+def lib(parallel: bool = False):
+    """Load the oracle library, building it first only if it is absent.
+    parallel=True: the OpenMP build (same arithmetic, same bits, rows of a
+    lattice spread over the host's cores; OMP_NUM_THREADS sets the count)."""
+    if parallel not in _libs:
+        path = _build.LIB_OMP if parallel else _build.LIB
+        if not os.path.exists(path):
             _build.build()
-        L = C.CDLL(_build.LIB)
+        L = C.CDLL(path)
         dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
         vp = C.c_void_p
         L.ora_num_fields.argtypes = [C.c_int, C.c_int]
@@ -71,10 +73,8 @@ def lib():
         L.ora_equilibrium.argtypes = [C.POINTER(OraCfg), dp, dp, C.c_double, dp]
         L.ora_source.argtypes = [C.POINTER(OraCfg), dp, dp, dp]
         L.ora_moment_update.argtypes = [C.POINTER(OraCfg), dp, dp, C.c_double, dp]
-        L.ora_arrhenius_exp.argtypes = [C.c_double]
-        L.ora_arrhenius_exp.restype = C.c_double
-        _lib = L
-    return _lib
+        _libs[parallel] = L
+    return _libs[parallel]
 
 
 def num_fields(system, dim):
@@ -107,20 +107,21 @@ def make_cfg(system, dim, nx, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=(PERIODIC
 class Lattice:
     """One oracle lattice: ``U0`` has shape (m, nx), (m, ny, nx) or (m, nz, ny, nx)."""
 
-    def __init__(self, cfg: OraCfg):
+    def __init__(self, cfg: OraCfg, parallel: bool = False):
         self.cfg = cfg
+        self._lib = lib(parallel)
         self.d = cfg.dim
         self.m = num_fields(cfg.system, cfg.dim)
         self.Q = 2 * self.d + 1
         self.nx, self.ny, self.nz = cfg.nx, cfg.ny, cfg.nz
-        self._h = lib().ora_create(C.byref(cfg))
+        self._h = self._lib.ora_create(C.byref(cfg))
         if not self._h:
             raise ValueError("oracle rejected the configuration")
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().ora_destroy(h)
+            self._lib.ora_destroy(h)
             self._h = None
 
     def _shape(self, lead):
@@ -135,66 +136,66 @@ class Lattice:
             bed = np.ascontiguousarray(bed, dtype=np.float64)
             self._bed = bed
             bp = bed.ctypes.data_as(C.c_void_p)
-        rc = lib().ora_init(self._h, U0, bp, float(t0))
+        rc = self._lib.ora_init(self._h, U0, bp, float(t0))
         if rc != 0:
             raise RuntimeError(f"ora_init failed: {rc}")
         return self
 
     def run(self, nsteps, t_final=0.0):
-        n = lib().ora_run(self._h, int(nsteps), float(t_final))
+        n = self._lib.ora_run(self._h, int(nsteps), float(t_final))
         if n < 0:
             raise RuntimeError(f"ora_run failed: {n}")
         return n
 
     def moments(self):
         out = np.empty(self._shape(self.m))
-        lib().ora_moments(self._h, out)
+        self._lib.ora_moments(self._h, out)
         return out
 
     def f(self):
         out = np.empty((self.Q,) + self._shape(self.m))
-        lib().ora_get_f(self._h, out)
+        self._lib.ora_get_f(self._h, out)
         return out
 
     def set_f(self, f):
-        lib().ora_set_f(self._h, np.ascontiguousarray(f, dtype=np.float64))
+        self._lib.ora_set_f(self._h, np.ascontiguousarray(f, dtype=np.float64))
 
     def last_omega(self):
         out = np.empty(self._shape(1)[1:])
-        lib().ora_last_omega(self._h, out)
+        self._lib.ora_last_omega(self._h, out)
         return out
 
     def omega_field(self):
         out = np.empty(self._shape(1)[1:])
-        lib().ora_omega_field(self._h, out)
+        self._lib.ora_omega_field(self._h, out)
         return out
 
     def nu_field(self):
         out = np.empty(self._shape(1)[1:])
-        lib().ora_nu_field(self._h, out)
+        self._lib.ora_nu_field(self._h, out)
         return out
 
     def alpha_bar(self):
         out = np.zeros(3)
-        lib().ora_alpha_bar(self._h, out)
+        self._lib.ora_alpha_bar(self._h, out)
         return out[: self.d]
 
     @property
     def t(self):
-        return lib().ora_time(self._h)
+        return self._lib.ora_time(self._h)
 
     @property
     def steps(self):
-        return lib().ora_steps(self._h)
+        return self._lib.ora_steps(self._h)
 
     @property
     def flags(self):
-        return lib().ora_flags(self._h)
+        return self._lib.ora_flags(self._h)
 
     def last_scalars(self):
         ab = np.zeros(3)
         dt = C.c_double()
-        lib().ora_last_scalars(self._h, ab, C.byref(dt))
+        self._lib.ora_last_scalars(self._h, ab, C.byref(dt))
         return ab[: self.d], dt.value
 
 
@@ -248,7 +249,3 @@ def moment_update(cfg, sumF, half_dt, db=(0.0, 0.0)):
     lib().ora_moment_update(C.byref(cfg), np.ascontiguousarray(sumF, dtype=np.float64),
                             np.ascontiguousarray(db, dtype=np.float64), float(half_dt), out)
     return out
-
-
-def arrhenius_exp(x):
-    return lib().ora_arrhenius_exp(float(x))

@@ -33,15 +33,16 @@
  *     in (rho, m, E') plus the passively advected rho Y, so L = L' T where
  *     L' holds the Euler rows (zero in the rho Y column) and the species row
  *     (-Y, 0, .., 0, 1), and T maps U to (rho, m, E - q rho Y, rho Y);
- *   - reactive Euler: (2.8) reduces to one scalar equation for rho Y, solved
- *     by a safeguarded Newton iteration on the bracket [min(0,B), max(0,B)]
- *     with B = sum_k F_k of rho Y (the sink R >= 0 for rho Y >= 0 puts the
- *     root there), stopped when a Newton step no longer changes rho Y (or a
- *     bisection lands on the current point) or after 40 iterations;
- *   - the Arrhenius exponential is evaluated by one fixed algorithm (Cody-Waite
- *     reduction by ln 2, degree-13 Taylor polynomial, scaling by 2^k), written
- *     out here and, independently, in the GPU library, so that the FP64 paths
- *     can agree bit for bit; it is pinned against the C library's exp.
+ *   - reactive Euler: (2.8) reduces to one scalar equation for rho Y whose
+ *     root lies in [min(0,B), max(0,B)], B = sum_k F_k of rho Y (the sink
+ *     R >= 0 for rho Y >= 0 puts it there); the oracle brackets it by the
+ *     Illinois variant of regula falsi until the bracket is two adjacent
+ *     doubles, and the Arrhenius factor uses the C library's exp.
+ *
+ * Built once single-threaded (the reference timing and every test) and once
+ * with OpenMP over rows (the benchmark's all-core timing): every cell's
+ * arithmetic is the same in both and the only reduction is a maximum, so the
+ * two builds give the same bits.
  */
 #include "arlbm_oracle.h"
 
@@ -87,37 +88,6 @@ typedef struct {
     double cL;                           /* SWE: speed used in L      */
     double Z, Y;                         /* reactive: rho Y and Y     */
 } prim_t;
-
-/* exp(x) for the Arrhenius factor.  Cody-Waite argument reduction
- * x = k ln2 + r, |r| <= ln2/2, with ln2 split into a head with trailing zero
- * bits (k * head is exact) and a tail; exp(r) by its Taylor series to degree
- * 13 (truncation below 5e-18 for |r| <= ln2/2) in Horner form; then 2^k. */
-double ora_arrhenius_exp(double x)
-{
-    const double inv_ln2 = 1.44269504088896338700e+00;
-    const double ln2_hi = 6.93147180369123816490e-01;
-    const double ln2_lo = 1.90821492927058770002e-10;
-    if (x != x) return x;
-    if (x < -746.0) return 0.0;
-    if (x > 710.0) return HUGE_VAL;
-    double k = nearbyint(x * inv_ln2);
-    double r = (x - k * ln2_hi) - k * ln2_lo;
-    double p = 1.0 / 6227020800.0;      /* 1/13! */
-    p = p * r + 1.0 / 479001600.0;      /* 1/12! */
-    p = p * r + 1.0 / 39916800.0;       /* 1/11! */
-    p = p * r + 1.0 / 3628800.0;        /* 1/10! */
-    p = p * r + 1.0 / 362880.0;         /* 1/9!  */
-    p = p * r + 1.0 / 40320.0;          /* 1/8!  */
-    p = p * r + 1.0 / 5040.0;           /* 1/7!  */
-    p = p * r + 1.0 / 720.0;            /* 1/6!  */
-    p = p * r + 1.0 / 120.0;            /* 1/5!  */
-    p = p * r + 1.0 / 24.0;             /* 1/4!  */
-    p = p * r + 1.0 / 6.0;              /* 1/3!  */
-    p = p * r + 0.5;                    /* 1/2!  */
-    p = p * r + 1.0;
-    p = p * r + 1.0;
-    return ldexp(p, (int)k);
-}
 
 static void primitives(const ora_cfg *c, const double *U, prim_t *P, int32_t *flags)
 {
@@ -266,22 +236,15 @@ void ora_left_eigvecs(const ora_cfg *c, int dir, const double *U, double *L)
  * T = p / rho (Section 5.4). */
 static int has_bed(const ora_cfg *c) { return c->system == ORA_SWE && c->has_bed; }
 
-/* The Arrhenius rate R at rho Y = z, with rho, (E - rho |u|^2/2) fixed; and
- * its derivative dR/dz (p depends on z through -q z). */
-static double arrhenius(const ora_cfg *c, double rho, double e_int, double z, double *dRdz)
+/* The Arrhenius rate R at rho Y = z, with rho and (E - rho |u|^2/2) fixed
+ * (p depends on z through -q z). */
+static double arrhenius(const ora_cfg *c, double rho, double e_int, double z)
 {
     double p = (c->gamma - 1.0) * (e_int - c->q_heat * z);
     double pf = p > c->p_floor ? p : c->p_floor;
     double rf = rho > c->rho_floor ? rho : c->rho_floor;
     double T = pf / rf;
-    double e = ora_arrhenius_exp(-(c->t_act / T));
-    double R = (c->k_rate * z) * e;
-    if (dRdz) {
-        /* d/dz exp(-T_i rho / p) = exp(..) * (-T_i rho (gamma-1) q / p^2) */
-        double dlog = p > c->p_floor ? (c->t_act * rf) * ((c->gamma - 1.0) * c->q_heat) / (pf * pf) : 0.0;
-        *dRdz = c->k_rate * e * (1.0 - z * dlog);
-    }
-    return R;
+    return (c->k_rate * z) * exp(-(c->t_act / T));
 }
 
 static void reactive_parts(const ora_cfg *c, const double *U, double *rho, double *e_int)
@@ -303,13 +266,51 @@ void ora_source(const ora_cfg *c, const double *U, const double *db, double *S)
     if (c->system == ORA_REACTIVE) {
         double rho, e_int;
         reactive_parts(c, U, &rho, &e_int);
-        S[m - 1] = -arrhenius(c, rho, e_int, U[m - 1], NULL);
+        S[m - 1] = -arrhenius(c, rho, e_int, U[m - 1]);
     }
 }
 
 static void source(const ora_cfg *c, const double *U, const double *db, double *S)
 {
     ora_source(c, U, db, S);
+}
+
+/* Root of g(z) = (z - B) + (dt/2) R(z), the rho Y component of (2.8), in
+ * the bracket [min(0,B), max(0,B)] (g <= 0 at its low end, >= 0 at its high
+ * end for R >= 0).  Illinois variant of regula falsi: the secant point of the
+ * bracket, with the function value kept at an end that stays twice in a row
+ * halved; a bisection when the secant point does not fall strictly inside.
+ * Stops at an exact zero or when the bracket is two adjacent doubles, and
+ * returns the end with the smaller residual. */
+static double reactive_root(const ora_cfg *c, double rho, double e_int, double B, double half_dt)
+{
+    double a = B < 0.0 ? B : 0.0, b = B < 0.0 ? 0.0 : B;
+    double ga = (a - B) + half_dt * arrhenius(c, rho, e_int, a);
+    double gb = (b - B) + half_dt * arrhenius(c, rho, e_int, b);
+    if (ga == 0.0) return a;
+    if (gb == 0.0) return b;
+    int kept = 0; /* -1: a was kept by the last step, +1: b */
+    for (int it = 0; it < 2000; ++it) {
+        double z = b - gb * (b - a) / (gb - ga);
+        if (!(z > a && z < b)) z = a + 0.5 * (b - a);
+        if (!(z > a && z < b)) break; /* a and b are adjacent doubles */
+        double gz = (z - B) + half_dt * arrhenius(c, rho, e_int, z);
+        if (gz == 0.0) return z;
+        if ((gz < 0.0) == (ga < 0.0)) {
+            a = z;
+            ga = gz;
+            if (kept == 1) gb *= 0.5;
+            kept = 1;
+        } else {
+            b = z;
+            gb = gz;
+            if (kept == -1) ga *= 0.5;
+            kept = -1;
+        }
+    }
+    double ra = fabs((a - B) + half_dt * arrhenius(c, rho, e_int, a));
+    double rb = fabs((b - B) + half_dt * arrhenius(c, rho, e_int, b));
+    return ra <= rb ? a : b;
 }
 
 /* (2.8): U = sumF + (dt/2) S(U).  Bed source: S_h = 0 and S depends on h
@@ -328,22 +329,7 @@ void ora_moment_update(const ora_cfg *c, const double *sumF, const double *db, d
     if (c->system == ORA_REACTIVE) {
         double rho, e_int;
         reactive_parts(c, sumF, &rho, &e_int);
-        double B = sumF[m - 1];
-        double lo = B < 0.0 ? B : 0.0, hi = B < 0.0 ? 0.0 : B;
-        double z = B;
-        for (int it = 0; it < 40; ++it) {
-            double dR;
-            double g = (z - B) + half_dt * arrhenius(c, rho, e_int, z, &dR);
-            if (g == 0.0) break;
-            if (g > 0.0) hi = z; else lo = z;
-            double dg = 1.0 + half_dt * dR;
-            double zn = z - g / dg;
-            if (dg > 0.0 && zn == z) break; /* the Newton step no longer moves z */
-            if (!(dg > 0.0) || !(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
-            if (zn == z) break;
-            z = zn;
-        }
-        U[m - 1] = z;
+        U[m - 1] = reactive_root(c, rho, e_int, sumF[m - 1], half_dt);
     }
 }
 
@@ -518,6 +504,7 @@ void ora_destroy(ora_lattice *L)
 static void fill_moments(ora_lattice *L)
 {
     int d = L->d, m = L->m, nx = L->nx, ny = L->ny, nz = L->nz;
+#pragma omp parallel for collapse(2) schedule(static)
     for (int l = 0; l < nz; ++l)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i)
@@ -572,12 +559,13 @@ static void load_U(const ora_lattice *L, int i, int j, int l, double *U)
 /* Wave-speed bounds alpha_bar_j (2.19): global max over interior cells. */
 static void alpha_bar(const ora_lattice *L, double *abar)
 {
-    double U[ORA_MMAX];
     for (int dir = 0; dir < L->d; ++dir) {
         double mx = 0.0;
+#pragma omp parallel for collapse(2) reduction(max : mx) schedule(static)
         for (int l = 0; l < L->nz; ++l)
             for (int j = 0; j < L->ny; ++j)
                 for (int i = 0; i < L->nx; ++i) {
+                    double U[ORA_MMAX];
                     load_U(L, i, j, l, U);
                     double s = ora_max_speed(&L->c, dir, U);
                     if (s > mx) mx = s;
@@ -590,11 +578,12 @@ static void alpha_bar(const ora_lattice *L, double *abar)
 static void compute_nu(ora_lattice *L)
 {
     int d = L->d, m = L->m;
-    double Uz[ORA_MMAX], Um[ORA_MMAX], Upl[ORA_MMAX], Lm[ORA_MMAX * ORA_MMAX];
-    double dm[ORA_MMAX], dp[ORA_MMAX], dU[ORA_MMAX];
+#pragma omp parallel for collapse(2) schedule(static)
     for (int l = -gz(L, 1); l < L->nz + gz(L, 1); ++l)
         for (int j = -gy(L, 1); j < L->ny + gy(L, 1); ++j)
             for (int i = -1; i < L->nx + 1; ++i) {
+                double Uz[ORA_MMAX], Um[ORA_MMAX], Upl[ORA_MMAX], Lm[ORA_MMAX * ORA_MMAX];
+                double dm[ORA_MMAX], dp[ORA_MMAX], dU[ORA_MMAX];
                 load_U(L, i, j, l, Uz);
                 double nu = 0.0;
                 for (int dir = 0; dir < d; ++dir) {
@@ -632,6 +621,7 @@ static void compute_omega(ora_lattice *L)
 {
     int d = L->d;
     int zr = d == 3 ? 1 : 0, yr = d >= 2 ? 1 : 0;
+#pragma omp parallel for collapse(2) schedule(static)
     for (int l = 0; l < L->nz; ++l)
         for (int j = 0; j < L->ny; ++j)
             for (int i = 0; i < L->nx; ++i) {
@@ -689,10 +679,11 @@ int ora_init(ora_lattice *L, const double *U0, const double *bed, double t0)
     double dt = L->c.cfl * L->dx / sa;
     double lambda = L->dx / dt;
     for (int j = 0; j < L->d; ++j) alpha[j] = abar[j] + L->c.eps;
-    double U[ORA_MMAX], feq[7 * ORA_MMAX];
+#pragma omp parallel for collapse(2) schedule(static)
     for (int l = 0; l < L->nz; ++l)
         for (int j = 0; j < L->ny; ++j)
             for (int i = 0; i < L->nx; ++i) {
+                double U[ORA_MMAX], feq[7 * ORA_MMAX];
                 load_U(L, i, j, l, U);
                 ora_equilibrium(&L->c, U, alpha, lambda, feq);
                 for (int k = 0; k < L->Q; ++k)
@@ -727,11 +718,12 @@ static int one_step(ora_lattice *L)
     compute_omega(L);
 
     /* collision at every interior source node */
-    double U[ORA_MMAX], feq[7 * ORA_MMAX], S[ORA_MMAX], db[2] = {0, 0};
     int bsrc = has_bed(cf);
+#pragma omp parallel for collapse(2) schedule(static)
     for (int l = 0; l < nz; ++l)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
+                double U[ORA_MMAX], feq[7 * ORA_MMAX], S[ORA_MMAX], db[2] = {0, 0};
                 load_U(L, i, j, l, U);
                 equilibrium_ab(cf, U, a, b, feq);
                 if (bsrc)
@@ -772,10 +764,11 @@ static int one_step(ora_lattice *L)
 
     /* pull streaming F_k(x) = f*_k(x - e_k), implicit moments (2.8), and the
      * second half source f_k = F_k + dt/2 s_k(U^{n+1}) */
-    double Fk[7 * ORA_MMAX], sumF[ORA_MMAX], Un[ORA_MMAX];
+#pragma omp parallel for collapse(2) schedule(static)
     for (int l = 0; l < nz; ++l)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
+                double Fk[7 * ORA_MMAX], sumF[ORA_MMAX], Un[ORA_MMAX], S[ORA_MMAX], db[2] = {0, 0};
                 for (int c = 0; c < m; ++c) sumF[c] = 0.0;
                 for (int k = 0; k < Q; ++k) {
                     int ex, ey, ez;

@@ -100,8 +100,6 @@ void ora_source(const ora_cfg *c, const double *U, const double *db, double *S);
 /* Implicit moment update (2.8) of one cell: U = sumF + (dt/2) S(U). */
 void ora_moment_update(const ora_cfg *c, const double *sumF, const double *db, double half_dt,
                        double *U);
-/* The exponential used by the Arrhenius rate (see the source file). */
-double ora_arrhenius_exp(double x);
 /* Lax-Friedrichs-type equilibrium coefficients a_k, b_kj of eq. (2.20)
  * written in the general form (2.5): b is Q x d row-major. */
 void ora_lf_coeffs(int dim, const double *alpha, double lambda, double *a,

@@ -21,7 +21,7 @@ ADVECTION, EULER, SWE, REACTIVE = 0, 1, 2, 3
 PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
 F32, F64 = 0, 1
 OMEGA_ADAPTIVE, OMEGA_FIXED = 0, 1
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EPOSITIVITY, EDEGENERATE, EBUSY, EBUDGET = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
@@ -68,7 +68,7 @@ class Status(C.Structure):
 
 class Completion(C.Structure):
     _fields_ = [("id", C.c_uint64), ("status", C.c_int32), ("flags", C.c_uint32), ("steps", C.c_int64),
-                ("t", C.c_double), ("submit_s", C.c_double), ("admit_s", C.c_double), ("done_s", C.c_double),
+                ("first_bad_step", C.c_int64), ("t", C.c_double), ("submit_s", C.c_double), ("admit_s", C.c_double), ("done_s", C.c_double),
                 ("U", C.POINTER(C.c_double)), ("u_count", C.c_int64)]
 
 
@@ -103,13 +103,19 @@ def lib():
             "arlbm_last_error": ([vp], C.c_char_p),
             "arlbm_server_create": ([C.c_size_t, C.c_int32, vp, C.POINTER(vp)], C.c_int),
             "arlbm_server_submit": ([vp, C.POINTER(Config), dp, dp, C.c_int64, C.POINTER(C.c_uint64)], C.c_int),
+            "arlbm_server_submit_state": ([vp, C.POINTER(Config), vp, C.c_size_t, C.c_int64,
+                                           C.POINTER(C.c_uint64)], C.c_int),
             "arlbm_server_iterate": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
             "arlbm_server_iterate_n": ([vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                         C.POINTER(C.c_int32)], C.c_int),
             "arlbm_server_poll": ([vp, C.POINTER(Completion), C.c_int32, C.POINTER(C.c_int32)], C.c_int),
             "arlbm_server_memory": ([vp, C.POINTER(C.c_size_t)], C.c_int),
+            "arlbm_server_pool_bytes": ([vp, C.POINTER(C.c_size_t)], C.c_int),
             "arlbm_server_destroy": ([vp], C.c_int),
             "arlbm_step_kernel_vgprs": ([C.c_int32, C.c_int32, C.c_int32], C.c_int),
+            "arlbm_plan_schedule": ([C.POINTER(Config), C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                                     C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32)], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -312,6 +318,13 @@ class Server:
         _check(lib().arlbm_server_submit(self._h, C.byref(cfg), _dptr(U0), _dptr(bed), int(nsteps), C.byref(rid)))
         return rid.value
 
+    def submit_state(self, cfg: Config, blob: bytes, nsteps: int) -> int:
+        """Queue a request that resumes a state saved by Lattice.save_state."""
+        buf = C.create_string_buffer(blob, len(blob))
+        rid = C.c_uint64()
+        _check(lib().arlbm_server_submit_state(self._h, C.byref(cfg), buf, len(blob), int(nsteps), C.byref(rid)))
+        return rid.value
+
     def iterate(self, max_launches: int = 1):
         """Admit, launch (up to max_launches batched steps, never past a
         resident lattice's step count), retire; returns (resident, queued)."""
@@ -330,14 +343,22 @@ class Server:
         for i in range(n.value):
             c = arr[i]
             U = np.ctypeslib.as_array(c.U, shape=(c.u_count,)).copy() if c.status == OK and c.u_count else None
-            out.append({"id": c.id, "status": c.status, "flags": c.flags, "steps": c.steps, "t": c.t,
+            out.append({"id": c.id, "status": c.status, "flags": c.flags, "steps": c.steps,
+                        "first_bad_step": c.first_bad_step, "t": c.t,
                         "submit_s": c.submit_s,
                         "admit_s": c.admit_s, "done_s": c.done_s, "U": U})
         return out
 
     def memory(self) -> int:
+        """Device bytes charged to resident lattices."""
         b = C.c_size_t()
         _check(lib().arlbm_server_memory(self._h, C.byref(b)))
+        return b.value
+
+    def pool_bytes(self) -> int:
+        """Device bytes the pool holds for lattices (in use and free)."""
+        b = C.c_size_t()
+        _check(lib().arlbm_server_pool_bytes(self._h, C.byref(b)))
         return b.value
 
     def close(self):
@@ -355,3 +376,19 @@ class Server:
 
 def step_kernel_vgprs(precision: int, system: int, dim: int) -> int:
     return lib().arlbm_step_kernel_vgprs(precision, system, dim)
+
+
+def plan_schedule(cfgs, waves: int):
+    """The batched launch's schedule for these configurations (host only):
+    (wave_start array of nwaves + 1 entries, segments as an (nsegs, 4) array
+    of (lattice, strip, first row, end row) or (lattice, first strip, 0, end
+    strip) for 1D)."""
+    arr = (Config * max(len(cfgs), 1))(*cfgs)
+    nw, ns = C.c_int32(), C.c_int32()
+    lib().arlbm_plan_schedule(arr, len(cfgs), int(waves), None, 0, None, 0, C.byref(nw), C.byref(ns))
+    ws = np.zeros(nw.value + 1, dtype=np.int32)
+    sg = np.zeros(4 * max(ns.value, 1), dtype=np.int32)
+    _check(lib().arlbm_plan_schedule(arr, len(cfgs), int(waves), ws.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     nw.value, sg.ctypes.data_as(C.POINTER(C.c_int32)), ns.value,
+                                     C.byref(nw), C.byref(ns)))
+    return ws, sg[:4 * ns.value].reshape(-1, 4)

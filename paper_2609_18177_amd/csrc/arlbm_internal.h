@@ -85,18 +85,20 @@ struct LatticeDesc {
     void *nu3;                     // 3D: padded indicator (nx+2)(ny+2)(nz+2), then omega of the cells
 };
 
-// One wave's work item in a batched launch.
-struct WorkItem {
+// One segment of a wave's work in a batched launch.  2D: rows y0 .. y1-1 of
+// strip col.  1D: strips col .. y1-1 (y0 unused).  The segment that holds
+// the lattice's first cell (col 0, row 0) also updates its scalars.
+struct Segment {
     int32_t lattice;
     int32_t col;
-    int32_t band;
-    int32_t first;  // 1 for the item that updates the lattice's scalars
+    int32_t y0;
+    int32_t y1;
 };
 
 }  // namespace arlbm
 
 // Host-side launchers, implemented once per precision (kernels.hip is
-// compiled twice: FP32 with contraction, FP64 without).
+// compiled twice, FP32 and FP64, both without contraction).
 #define ARLBM_DECLARE_LAUNCHERS(NS)                                                                    \
     namespace arlbm {                                                                                  \
     namespace NS {                                                                                     \
@@ -104,8 +106,8 @@ struct WorkItem {
     hipError_t init(const LatticeDesc &h, const double *U0, const double *bed64, int slot_in,         \
                     hipStream_t s);                                                                    \
     hipError_t step_single(const LatticeDesc &h, int64_t iter, hipStream_t s);                        \
-    hipError_t step_batched(const LatticeDesc *d_descs, const WorkItem *d_items, int32_t nitems,      \
-                            int64_t iter, hipStream_t s);                                              \
+    hipError_t step_batched(const LatticeDesc *d_descs, const int32_t *d_wave_start,                  \
+                            const Segment *d_segs, int32_t nwaves, int64_t iter, hipStream_t s);       \
     hipError_t conservation(const void *u, int64_t plane, int64_t pstride, int m, double *partial,    \
                             int nblocks, hipStream_t s);                                               \
     hipError_t moments(const void *f, void *u, int64_t plane, int64_t pstride, int m, int q,          \
@@ -119,3 +121,8 @@ struct WorkItem {
 
 ARLBM_DECLARE_LAUNCHERS(f32)
 ARLBM_DECLARE_LAUNCHERS(f64)
+
+namespace arlbm {
+// out[i] = descs[i].sc->flags for i < n (either precision: the scalars are FP64).
+hipError_t gather_flags_launch(const LatticeDesc *descs, int32_t n, unsigned *out, hipStream_t s);
+}  // namespace arlbm

@@ -1,10 +1,18 @@
 // Kernel instantiations and launchers for one storage precision.  Built twice
-// by the package's build step: -DARLBM_F64=0 (float, contraction allowed) and
-// -DARLBM_F64=1 (double, -ffp-contract=off so every rounding matches the
-// written expression order).
+// by the package's build step, -DARLBM_F64=0 (float) and -DARLBM_F64=1
+// (double), both with -ffp-contract=off so every rounding follows the written
+// expression order.
 #include "arlbm_internal.h"
 #include "step.hpp"
 #include "step3d.hpp"
+
+namespace arlbm {
+static int cell_grid_flags(int64_t n)
+{
+    int64_t b = (n + kBlock - 1) / kBlock;
+    return (int)(b > 64 ? 64 : (b < 1 ? 1 : b));
+}
+}  // namespace arlbm
 
 #if ARLBM_F64
 #define ARLBM_NS f64
@@ -129,11 +137,11 @@ hipError_t step_single(const LatticeDesc &h, int64_t iter, hipStream_t s)
 #undef C_
 }
 
-hipError_t step_batched(const LatticeDesc *d_descs, const WorkItem *d_items, int32_t nitems, int64_t iter,
-                        hipStream_t s)
+hipError_t step_batched(const LatticeDesc *d_descs, const int32_t *d_wave_start, const Segment *d_segs,
+                        int32_t nwaves, int64_t iter, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_step_batched<real>), dim3(grid_for(nitems, kWavesPerBlock)), dim3(kBlock), 0, s,
-                       d_descs, d_items, nitems, iter);
+    hipLaunchKernelGGL((k_step_batched<real>), dim3(grid_for(nwaves, kWavesPerBlock)), dim3(kBlock), 0, s,
+                       d_descs, d_wave_start, d_segs, nwaves, iter);
     return hipGetLastError();
 }
 
@@ -205,4 +213,17 @@ int step_kernel_vgprs(int variant, int cpl)
 }
 
 }  // namespace ARLBM_NS
+
+#if !ARLBM_F64
+__global__ __launch_bounds__(kBlock) void k_gather_flags(const LatticeDesc *descs, int32_t n, unsigned *out)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = descs[i].sc->flags;
+}
+
+hipError_t gather_flags_launch(const LatticeDesc *descs, int32_t n, unsigned *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_flags, dim3(cell_grid_flags(n)), dim3(kBlock), 0, s, descs, n, out);
+    return hipGetLastError();
+}
+#endif
 }  // namespace arlbm

@@ -867,14 +867,19 @@ struct Pending {
     uint64_t id;
     arlbm_config cfg;
     HostArray U0, bed;
+    std::unique_ptr<char[]> blob;  // a saved state to resume instead of U0 (and its step)
+    size_t blob_bytes = 0;
+    int64_t step0 = 0;
     int64_t nsteps;
     double submit_s;
-    size_t bytes;
+    size_t bytes;  // device memory charged: the size class of the lattice's block
 };
 struct Resident {
     uint64_t id;
     arlbm_lattice *lat;
-    int64_t nsteps, iter0;
+    int64_t iter0;     // the lattice's step index is iter - iter0 (iter0 = admission - step0)
+    int64_t admit_it;  // server iteration at admission
+    int64_t end_it;    // iteration at which it has taken its steps
     double submit_s, admit_s;
     size_t bytes;
     void *dev;       // the lattice's device block (pool)
@@ -887,10 +892,10 @@ struct Done {
 // An admission or a retirement whose transfers are in the stream, finished
 // after the iteration's launch.
 struct Staged {
-    bool retiring;
+    enum Kind { ADMIT, ADMIT_STATE, RETIRE } kind;
     uint64_t id;
     arlbm_lattice *lat;
-    int64_t nsteps;
+    int64_t steps;  // retirement: steps taken in the server
     double submit_s, admit_s;
     void *host;  // pinned block: scalars [, scalars out], planes
     size_t host_cls;
@@ -989,17 +994,32 @@ struct arlbm_server {
     std::deque<Done> done;
     std::vector<Done> handed;  // results returned by the last poll
     BlockPool dev, pin;
-    LatticeDesc *d_descs = nullptr;
-    WorkItem *d_items = nullptr;
-    size_t cap_descs = 0, cap_items = 0;
-    // pinned host copies of the work table, two sets used in turn; a set is
+    // device work table: descriptors, then the schedule (the first segment
+    // of each wave, nwaves + 1 entries, then the segments); one allocation
+    char *d_table = nullptr;
+    size_t cap_table = 0;
+    // pinned host copies of the work table, two used in turn; one is
     // rewritten only after the upload that read it (its event) has completed
-    LatticeDesc *h_descs[2] = {nullptr, nullptr};
-    WorkItem *h_items[2] = {nullptr, nullptr};
-    size_t hcap_descs[2] = {0, 0}, hcap_items[2] = {0, 0};
+    char *h_table[2] = {nullptr, nullptr};
+    size_t hcap_table[2] = {0, 0};
     hipEvent_t table_ev[2] = {nullptr, nullptr};
     int table_set = 0;
-    int32_t nitems = 0;
+    int32_t nwaves = 0;
+    size_t off_start = 0, off_segs = 0;  // byte offsets in the table
+    // flag words of the residents gathered after each call's launches (two
+    // in turn), read by a later call once their copy has completed: a
+    // lattice that became non-finite or degenerate retires early
+    unsigned *d_flags = nullptr;
+    size_t cap_flags = 0;
+    struct FlagGather {
+        unsigned *host = nullptr;  // pinned
+        size_t cap = 0;
+        std::vector<uint64_t> ids;  // resident ids in gather order
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+    } gather[2];
+    int gather_next = 0;
+    std::vector<uint64_t> failing;  // residents seen with a fatal flag
     bool dirty = true;
     std::string err;
 };
@@ -1047,63 +1067,140 @@ void push_failed(arlbm_server *s, uint64_t id, int rc, double submit_s)
     s->done.push_back(std::move(d));
 }
 
-// Band height of the served 2D lattices, common to all of them: as tall as
-// keeps the launch at about ARLBM_SERVER_WAVES waves per SIMD from the 2D
-// lattices (each band pays five warm-up rows; one band height for all keeps
-// the waves' work even), at least 8 rows.  Measured on the default serving
-// mix (GLUPS): each lattice's own bands 16.6; 2 waves per SIMD 12.9, 8 16.1,
-// 32 17.4, 64 16.3, 128 16.4.  0 keeps each lattice's own bands.
-#ifndef ARLBM_SERVER_WAVES
-#define ARLBM_SERVER_WAVES 32
-#endif
+// Served lattices that the batched kernel does not step: 3D lattices (three
+// passes over the whole lattice, the indicator needing every neighbour's
+// moments first) and 2D lattices whose population buffer spans 4 GiB or more
+// (the batched kernel addresses planes through 32-bit buffer offsets).
+bool own_launch(const LatticeDesc &d) { return d.variant >= V_ADV3 || (d.variant >= V_ADV2 && !d.buf); }
+
+// Static schedule of the batched launch.  The work of every resident 1D and
+// 2D lattice is cut into items and dealt to at most batched_waves() waves
+// (one per SIMD) so that each wave's work is about equal.
+//
+// Cost model, in population values a wave moves: a 2D item of h rows of one
+// strip costs (h + 6) rows of 64 V lanes by Q m values (the march reads 3
+// rows of moments beyond each end and collides one row beyond each end); a
+// 1D strip costs 64 Q m values plus a latency share of one 1280-value row,
+// and a run of 1D strips two strips more.
+//
+// Every lattice gets one band height, as tall as the common per-wave budget
+// B allows ((h + 6) unit <= B), and its items are its bands taken in order,
+// each band's strips left to right; the items are then dealt in that order,
+// as many consecutive items per wave as fit in B.  A large lattice thus gets
+// one band of one strip per wave, its waves laid out as the single-lattice
+// kernel lays them out: consecutive waves (which the step kernels deal to
+// one XCD) hold neighbouring strips of the same rows, so a wave's halo
+// columns are in its neighbours' L2 and the concurrent reads of one XCD
+// cover whole plane rows.  (Cutting each strip into row ranges instead put
+// the waves of one XCD at scattered rows of a few strips and ran the 2048^2
+// Euler lattice 51% slower than the single-lattice kernel.)  Small lattices
+// share waves.  B starts at the total cost over the waves and grows until
+// the deal needs no more waves than there are.
+constexpr int kWarmRows2d = 6, kWarmStrips1d = 2, kMinRows2d = 8;
+constexpr int64_t kStrip1dLatency = 1280;
+
+int64_t batched_waves() { return 4 * (int64_t)num_cus(); }  // one wave per SIMD
+
+struct SchedLattice {
+    int32_t lattice;
+    bool one_d;
+    int32_t ncols;  // strips
+    int64_t ny;     // 2D rows
+    int64_t unit;   // cost per row (2D) or per strip (1D)
+};
+
+int64_t build_schedule(const std::vector<SchedLattice> &lats, int64_t W, std::vector<int32_t> &start,
+                       std::vector<Segment> &segs)
+{
+    double total = 0.0;
+    for (const SchedLattice &l : lats)
+        total += l.one_d ? (double)(l.ncols + kWarmStrips1d) * (double)l.unit
+                         : (double)l.ncols * (double)(l.ny + kWarmRows2d) * (double)l.unit;
+    double B = total / (double)W;
+    for (int attempt = 0;; ++attempt) {
+        start.assign(1, 0);
+        segs.clear();
+        double rem = B;
+        auto put = [&](const Segment &g, double cost) {
+            // a new wave when this item does not fit the current one's budget
+            if ((int32_t)segs.size() > start.back() && cost > rem) {
+                start.push_back((int32_t)segs.size());
+                rem = B;
+            }
+            segs.push_back(g);
+            rem -= cost;
+        };
+        for (const SchedLattice &l : lats) {
+            if (l.one_d) {
+                // runs of strips of at most the budget
+                int64_t per = (int64_t)(B / (double)l.unit) - kWarmStrips1d;
+                per = std::max<int64_t>(1, per);
+                for (int64_t c = 0; c < l.ncols; c += per) {
+                    const int64_t e = std::min<int64_t>(l.ncols, c + per);
+                    put({l.lattice, (int32_t)c, 0, (int32_t)e}, (double)(e - c + kWarmStrips1d) * (double)l.unit);
+                }
+            } else {
+                int64_t h = (int64_t)(B / (double)l.unit) - kWarmRows2d;
+                h = std::min<int64_t>(l.ny, std::max<int64_t>(kMinRows2d, h));
+                const int64_t nb = (l.ny + h - 1) / h;
+                h = (l.ny + nb - 1) / nb;  // even bands
+                for (int64_t b = 0; b < nb; ++b) {
+                    const int64_t y0 = b * h, y1 = std::min<int64_t>(l.ny, y0 + h);
+                    for (int32_t c = 0; c < l.ncols; ++c)
+                        put({l.lattice, c, (int32_t)y0, (int32_t)y1}, (double)(y1 - y0 + kWarmRows2d) * (double)l.unit);
+                }
+            }
+        }
+        if ((int32_t)segs.size() > start.back()) start.push_back((int32_t)segs.size());
+        const int64_t nw = (int64_t)start.size() - 1;
+        if (nw <= W || attempt >= 60) return nw;
+        B *= 1.02;
+    }
+}
+
+// A schedule item of lattice i from its descriptor (1D and 2D lattices the
+// batched kernel steps).
+SchedLattice sched_lattice(int32_t i, const LatticeDesc &d)
+{
+    const int m = num_fields(d.variant % 4, d.variant / 4 + 1);
+    if (d.variant >= V_ADV2) return {i, false, d.ncols, d.ny, (int64_t)kWave * d.cpl * 5 * m};
+    return {i, true, d.ncols, 1, (int64_t)kWave * 3 * m + kStrip1dLatency};
+}
+
 int rebuild_table(arlbm_server *s)
 {
     std::vector<LatticeDesc> descs;
-    std::vector<WorkItem> items;
-    int64_t strip_rows = 0;
-    for (const Resident &r : s->resident) {
-        const LatticeDesc &d = r.lat->desc;
-        if (d.variant >= V_ADV2 && d.variant < V_ADV3) strip_rows += (d.nx + kOutW - 1) / kOutW * d.ny;
-    }
-    const int64_t target = 4 * (int64_t)num_cus() * std::max(ARLBM_SERVER_WAVES, 1);
-    const int64_t band = ARLBM_SERVER_WAVES > 0 ? std::max<int64_t>(8, strip_rows / target) : 0;
+    std::vector<SchedLattice> lats;
     for (size_t i = 0; i < s->resident.size(); ++i) {
         LatticeDesc d = s->resident[i].lat->desc;
         d.iter0 = s->resident[i].iter0;
-        // the batched kernel runs every strip with one column per lane
-        d.cpl = 1;
-        d.ncols = (int32_t)((d.nx + kOutW - 1) / kOutW);
-        if (band > 0 && d.variant >= V_ADV2 && d.variant < V_ADV3) d.band_h = (int32_t)std::min<int64_t>(band, d.ny);
         descs.push_back(d);
-        if (d.variant >= V_ADV3) continue;  // 3D lattices run their own passes
-        const int64_t nb = d.variant >= V_ADV2 ? (d.ny + d.band_h - 1) / d.band_h : 1;
-        for (int64_t b = 0; b < nb; ++b)
-            for (int c = 0; c < d.ncols; ++c) items.push_back({(int32_t)i, c, (int32_t)b, (b == 0 && c == 0) ? 1 : 0});
+        if (!own_launch(d)) lats.push_back(sched_lattice((int32_t)i, d));
     }
+    std::vector<int32_t> start;
+    std::vector<Segment> segs;
+    const int64_t nw = lats.empty() ? 0 : build_schedule(lats, batched_waves(), start, segs);
+    s->off_start = align_up(sizeof(LatticeDesc) * descs.size());
+    s->off_segs = s->off_start + align_up(sizeof(int32_t) * start.size());
+    const size_t bytes = s->off_segs + sizeof(Segment) * segs.size();
     hipError_t e;
-    // device tables grow by reallocation, after the launches that still read
-    // the old ones
-    if (descs.size() > s->cap_descs || items.size() > s->cap_items) {
+    // the device table grows by reallocation, after the launches that still
+    // read the old one
+    if (bytes > s->cap_table) {
         e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, hipGetErrorString(e));
-    }
-    if (descs.size() > s->cap_descs) {
-        if (s->d_descs) (void)hipFree(s->d_descs);
-        s->d_descs = nullptr;
-        s->cap_descs = std::max<size_t>(descs.size() * 2, 64);
-        e = hipMalloc((void **)&s->d_descs, sizeof(LatticeDesc) * s->cap_descs);
-        if (e != hipSuccess) return sfail(s, ARLBM_ENOMEM, "descriptor table allocation failed");
-    }
-    if (items.size() > s->cap_items) {
-        if (s->d_items) (void)hipFree(s->d_items);
-        s->d_items = nullptr;
-        s->cap_items = std::max<size_t>(items.size() * 2, 4096);
-        e = hipMalloc((void **)&s->d_items, sizeof(WorkItem) * s->cap_items);
-        if (e != hipSuccess) return sfail(s, ARLBM_ENOMEM, "work table allocation failed");
+        if (s->d_table) (void)hipFree(s->d_table);
+        s->d_table = nullptr;
+        s->cap_table = std::max<size_t>(bytes * 2, (size_t)1 << 16);
+        e = hipMalloc((void **)&s->d_table, s->cap_table);
+        if (e != hipSuccess) {
+            s->cap_table = 0;
+            return sfail(s, ARLBM_ENOMEM, "work table allocation failed");
+        }
     }
     if (!descs.empty()) {
         // the upload is ordered after the launches that read the previous
-        // table; its source, a pinned set, is rewritten two rebuilds later,
+        // table; its source, a pinned copy, is rewritten two rebuilds later,
         // after its own upload has completed
         const int k = s->table_set;
         s->table_set ^= 1;
@@ -1114,37 +1211,25 @@ int rebuild_table(arlbm_server *s)
             e = hipEventSynchronize(s->table_ev[k]);
             if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("table event: ") + hipGetErrorString(e));
         }
-        if (descs.size() > s->hcap_descs[k]) {
-            if (s->h_descs[k]) (void)hipHostFree(s->h_descs[k]);
-            s->h_descs[k] = nullptr;
-            s->hcap_descs[k] = s->cap_descs;
-            e = hipHostMalloc((void **)&s->h_descs[k], sizeof(LatticeDesc) * s->hcap_descs[k], hipHostMallocDefault);
+        if (bytes > s->hcap_table[k]) {
+            if (s->h_table[k]) (void)hipHostFree(s->h_table[k]);
+            s->h_table[k] = nullptr;
+            s->hcap_table[k] = s->cap_table;
+            e = hipHostMalloc((void **)&s->h_table[k], s->hcap_table[k], hipHostMallocDefault);
             if (e != hipSuccess) {
-                s->hcap_descs[k] = 0;
-                return sfail(s, ARLBM_ENOMEM, "pinned descriptor table allocation failed");
-            }
-        }
-        if (items.size() > s->hcap_items[k]) {
-            if (s->h_items[k]) (void)hipHostFree(s->h_items[k]);
-            s->h_items[k] = nullptr;
-            s->hcap_items[k] = s->cap_items;
-            e = hipHostMalloc((void **)&s->h_items[k], sizeof(WorkItem) * s->hcap_items[k], hipHostMallocDefault);
-            if (e != hipSuccess) {
-                s->hcap_items[k] = 0;
+                s->hcap_table[k] = 0;
                 return sfail(s, ARLBM_ENOMEM, "pinned work table allocation failed");
             }
         }
-        std::memcpy(s->h_descs[k], descs.data(), sizeof(LatticeDesc) * descs.size());
-        if (!items.empty()) std::memcpy(s->h_items[k], items.data(), sizeof(WorkItem) * items.size());
-        e = hipMemcpyAsync(s->d_descs, s->h_descs[k], sizeof(LatticeDesc) * descs.size(), hipMemcpyHostToDevice,
-                           s->stream);
-        if (e == hipSuccess && !items.empty())
-            e = hipMemcpyAsync(s->d_items, s->h_items[k], sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice,
-                               s->stream);
+        char *h = s->h_table[k];
+        std::memcpy(h, descs.data(), sizeof(LatticeDesc) * descs.size());
+        if (!start.empty()) std::memcpy(h + s->off_start, start.data(), sizeof(int32_t) * start.size());
+        if (!segs.empty()) std::memcpy(h + s->off_segs, segs.data(), sizeof(Segment) * segs.size());
+        e = hipMemcpyAsync(s->d_table, h, bytes, hipMemcpyHostToDevice, s->stream);
         if (e == hipSuccess) e = hipEventRecord(s->table_ev[k], s->stream);
         if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("table upload: ") + hipGetErrorString(e));
     }
-    s->nitems = (int32_t)items.size();
+    s->nwaves = (int32_t)nw;
     s->dirty = false;
     return ARLBM_OK;
 }
@@ -1165,14 +1250,35 @@ AdmitLayout admit_layout(const arlbm_sizes &sz, int64_t plane, bool has_bed)
     return l;
 }
 
+// A saved state (arlbm_save_state): header, the f planes, the moment planes,
+// the device scalars.
+namespace {
+struct StateView {
+    const StateHeader *hd;
+    const char *f, *u, *sc;
+};
+StateView state_view(const char *blob)
+{
+    StateView v;
+    v.hd = (const StateHeader *)blob;
+    v.f = blob + sizeof(StateHeader);
+    v.u = v.f + v.hd->f_bytes;
+    v.sc = v.u + v.hd->u_bytes;
+    return v;
+}
+}  // namespace
+
 // Admission: a device block from the pool, the handle, the host checks of the
 // initial state, then the upload and initialisation enqueued (as set_state
-// does, without its wait); the wave-speed checks follow in finish_staged.
+// does, without its wait); the wave-speed checks follow in finish_staged.  A
+// resumed state is uploaded as saved (populations, moments, scalars) and
+// continues from its step and time.
 void admit_enqueue(arlbm_server *s, Pending &p)
 {
     arlbm_sizes sz;
     fill_sizes(&p.cfg, &sz);
     const bool has_bed = p.cfg.has_bed != 0;
+    const bool resume = p.blob != nullptr;
     size_t dcls = 0;
     void *blk = s->dev.acquire(sz.total_bytes, &dcls);
     if (!blk) {
@@ -1183,34 +1289,49 @@ void admit_enqueue(arlbm_server *s, Pending &p)
     const arlbm_buffers b = carve(blk, sz, has_bed);
     arlbm_lattice *lat = nullptr;
     int rc = arlbm_create(&p.cfg, &b, s->stream, &lat);
-    if (rc == ARLBM_OK) rc = check_state(lat, p.U0.data(), has_bed ? p.bed.data() : nullptr);
+    if (rc == ARLBM_OK && !resume) rc = check_state(lat, p.U0.data(), has_bed ? p.bed.data() : nullptr);
     const int64_t plane = (int64_t)p.cfg.nx * p.cfg.ny * p.cfg.nz;
     const AdmitLayout L = admit_layout(sz, plane, has_bed);
+    const size_t host_bytes = resume ? p.blob_bytes : L.total;
     size_t hcls = 0;
     char *host = nullptr;
     if (rc == ARLBM_OK) {
-        host = (char *)s->pin.acquire(L.total, &hcls);
+        host = (char *)s->pin.acquire(host_bytes, &hcls);
         if (!host) rc = fail(lat, ARLBM_ENOMEM, "pinned staging allocation failed");
     }
     hipEvent_t ev = nullptr;
     if (rc == ARLBM_OK) {
-        DevScalars init{};
-        init.t[0] = 0.0;
-        init.first_bad_step = ~0ull;
-        std::memcpy(host + L.sc_in, &init, sizeof init);
-        par_copy(host + L.u0, p.U0.data(), sizeof(double) * sz.m * plane);
-        if (has_bed) par_copy(host + L.bed, p.bed.data(), sizeof(double) * plane);
-        double *U0d = (double *)lat->desc.f[1];
-        double *bedd = has_bed ? U0d + (size_t)sz.m * plane : nullptr;
-        hipError_t e = hipMemcpyAsync(U0d, host + L.u0, sizeof(double) * sz.m * plane, hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess && has_bed)
-            e = hipMemcpyAsync(bedd, host + L.bed, sizeof(double) * plane, hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(lat->desc.sc, host + L.sc_in, sizeof(DevScalars), hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess) e = L_reduce(lat, U0d, 2);
-        if (e == hipSuccess) e = L_init(lat, U0d, bedd, 2);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(host + L.sc_out, lat->desc.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s->stream);
+        hipError_t e = hipSuccess;
+        if (resume) {
+            par_copy(host, p.blob.get(), p.blob_bytes);
+            const StateView v = state_view(host);
+            const int par = (int)(p.step0 & 1);
+            e = hipMemcpyAsync(lat->desc.f[par], v.f, sz.f_bytes, hipMemcpyHostToDevice, s->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(lat->desc.u[par], v.u, sz.u_bytes, hipMemcpyHostToDevice, s->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(lat->desc.sc, v.sc, sizeof(DevScalars), hipMemcpyHostToDevice, s->stream);
+        } else {
+            DevScalars init{};
+            init.t[0] = 0.0;
+            init.first_bad_step = ~0ull;
+            std::memcpy(host + L.sc_in, &init, sizeof init);
+            par_copy(host + L.u0, p.U0.data(), sizeof(double) * sz.m * plane);
+            if (has_bed) par_copy(host + L.bed, p.bed.data(), sizeof(double) * plane);
+            double *U0d = (double *)lat->desc.f[1];
+            double *bedd = has_bed ? U0d + (size_t)sz.m * plane : nullptr;
+            e = hipMemcpyAsync(U0d, host + L.u0, sizeof(double) * sz.m * plane, hipMemcpyHostToDevice, s->stream);
+            if (e == hipSuccess && has_bed)
+                e = hipMemcpyAsync(bedd, host + L.bed, sizeof(double) * plane, hipMemcpyHostToDevice, s->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(lat->desc.sc, host + L.sc_in, sizeof(DevScalars), hipMemcpyHostToDevice,
+                                   s->stream);
+            if (e == hipSuccess) e = L_reduce(lat, U0d, 2);
+            if (e == hipSuccess) e = L_init(lat, U0d, bedd, 2);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(host + L.sc_out, lat->desc.sc, sizeof(DevScalars), hipMemcpyDeviceToHost,
+                                   s->stream);
+        }
         if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventRecord(ev, s->stream);
         if (e != hipSuccess) {
@@ -1227,23 +1348,26 @@ void admit_enqueue(arlbm_server *s, Pending &p)
         push_failed(s, p.id, rc, p.submit_s);
         return;
     }
-    lat->step = 0;
+    lat->step = p.step0;
     lat->busy = true;
     const double t_admit = now_s();
-    s->resident.push_back({p.id, lat, p.nsteps, s->iter, p.submit_s, t_admit, p.bytes, blk, dcls});
-    s->staged.push_back({false, p.id, lat, p.nsteps, p.submit_s, t_admit, host, hcls, ev});
+    s->resident.push_back({p.id, lat, s->iter - p.step0, s->iter, s->iter + p.nsteps, p.submit_s, t_admit, p.bytes,
+                           blk, dcls});
+    s->staged.push_back({resume ? Staged::ADMIT_STATE : Staged::ADMIT, p.id, lat, 0, p.submit_s, t_admit, host,
+                         hcls, ev});
     s->in_use += p.bytes;
     s->dirty = true;
 }
 
-// Retirement: the moments and scalars of the final state enqueued into a
+// Retirement: the moments and scalars of the lattice's state enqueued into a
 // pinned block; the device block goes back to the pool at once (stream order
 // keeps it intact until the read-back has run).
 int retire_enqueue(arlbm_server *s, const Resident &r)
 {
     arlbm_lattice *h = r.lat;
-    h->step = r.nsteps;  // the batched launches advanced it
+    h->step = s->iter - r.iter0;  // the batched launches advanced it
     h->busy = false;
+    const int64_t steps = s->iter - r.admit_it;
     const size_t o_u = align_up(sizeof(DevScalars));
     const size_t nU = (size_t)h->sz.m * h->desc.plane;
     size_t hcls = 0;
@@ -1270,7 +1394,7 @@ int retire_enqueue(arlbm_server *s, const Resident &r)
         push_failed(s, r.id, rc, r.submit_s);
         return rc;
     }
-    s->staged.push_back({true, r.id, h, r.nsteps, r.submit_s, r.admit_s, host, hcls, ev});
+    s->staged.push_back({Staged::RETIRE, r.id, h, steps, r.submit_s, r.admit_s, host, hcls, ev});
     s->dev.release(r.dev, r.dev_cls);
     s->in_use -= r.bytes;
     return ARLBM_OK;
@@ -1291,16 +1415,17 @@ int finish_staged(arlbm_server *s)
         if (e != hipSuccess && first_err == ARLBM_OK)
             first_err = sfail(s, ARLBM_EDEVICE, std::string("staged transfer: ") + hipGetErrorString(e));
         arlbm_lattice *h = g.lat;
-        if (g.retiring) {
+        if (g.kind == Staged::RETIRE) {
             DevScalars sc;
             std::memcpy(&sc, g.host, sizeof sc);
             Done d{};
             d.c.id = g.id;
-            d.c.steps = g.nsteps;
+            d.c.steps = g.steps;
             d.c.submit_s = g.submit_s;
             d.c.admit_s = g.admit_s;
-            d.c.t = sc.t[g.nsteps % 3];
+            d.c.t = sc.t[h->step % 3];
             d.c.flags = sc.flags;
+            d.c.first_bad_step = sc.first_bad_step == ~0ull ? -1 : (int64_t)sc.first_bad_step;
             int rc = e != hipSuccess ? ARLBM_EDEVICE : ARLBM_OK;
             if (rc == ARLBM_OK && (sc.flags & ARLBM_FLAG_NONFINITE)) rc = ARLBM_ENONFINITE;
             if (rc == ARLBM_OK && (sc.flags & ARLBM_FLAG_DEGENERATE)) rc = ARLBM_EDEGENERATE;
@@ -1314,7 +1439,7 @@ int finish_staged(arlbm_server *s)
             d.c.done_s = now_s();
             s->done.push_back(std::move(d));
             drop_handle(h);
-        } else {
+        } else if (g.kind == Staged::ADMIT) {
             arlbm_sizes sz = h->sz;
             const AdmitLayout L = admit_layout(sz, h->desc.plane, h->cfg.has_bed != 0);
             DevScalars got;
@@ -1348,19 +1473,90 @@ int finish_staged(arlbm_server *s)
     return first_err;
 }
 
+// Ids of residents whose gathered flags show a non-finite or degenerate
+// state, from every gather whose copy has completed (never waits).
+void take_gathers(arlbm_server *s)
+{
+    for (auto &g : s->gather) {
+        if (!g.pending || hipEventQuery(g.ev) != hipSuccess) continue;
+        for (size_t i = 0; i < g.ids.size(); ++i)
+            if (g.host[i] & (ARLBM_FLAG_NONFINITE | ARLBM_FLAG_DEGENERATE)) s->failing.push_back(g.ids[i]);
+        g.pending = false;
+    }
+}
+
+// Enqueue the gather of the residents' flag words (after the launches, with
+// the table the launches read), unless both gathers are still in flight.
+int gather_flags(arlbm_server *s)
+{
+    const size_t n = s->resident.size();
+    if (n == 0) return ARLBM_OK;
+    auto &g = s->gather[s->gather_next];
+    if (g.pending) return ARLBM_OK;
+    hipError_t e = hipSuccess;
+    if (n > s->cap_flags) {
+        if (s->d_flags) {
+            e = hipStreamSynchronize(s->stream);
+            (void)hipFree(s->d_flags);
+        }
+        s->d_flags = nullptr;
+        s->cap_flags = std::max<size_t>(2 * n, 256);
+        if (e == hipSuccess) e = hipMalloc((void **)&s->d_flags, sizeof(unsigned) * s->cap_flags);
+        if (e != hipSuccess) {
+            s->cap_flags = 0;
+            return sfail(s, ARLBM_ENOMEM, "flag gather allocation failed");
+        }
+    }
+    if (n > g.cap) {
+        if (g.host) (void)hipHostFree(g.host);
+        g.host = nullptr;
+        g.cap = s->cap_flags;
+        e = hipHostMalloc((void **)&g.host, sizeof(unsigned) * g.cap, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            g.cap = 0;
+            return sfail(s, ARLBM_ENOMEM, "pinned flag gather allocation failed");
+        }
+    }
+    if (!g.ev) {
+        e = hipEventCreateWithFlags(&g.ev, hipEventDisableTiming);
+        if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("event: ") + hipGetErrorString(e));
+    }
+    e = gather_flags_launch((const LatticeDesc *)s->d_table, (int32_t)n, s->d_flags, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g.host, s->d_flags, sizeof(unsigned) * n, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(g.ev, s->stream);
+    if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("flag gather: ") + hipGetErrorString(e));
+    g.ids.clear();
+    for (const Resident &r : s->resident) g.ids.push_back(r.id);
+    g.pending = true;
+    s->gather_next ^= 1;
+    return ARLBM_OK;
+}
+
+// Queue a request after the checks common to both submit calls.
+int queue_request(arlbm_server *s, Pending &&p, uint64_t *id)
+{
+    p.id = s->next_id++;
+    p.submit_s = now_s();
+    s->queue.push_back(std::move(p));
+    if (id) *id = s->queue.back().id;
+    return ARLBM_OK;
+}
+
 }  // namespace
 
 extern "C" int arlbm_server_create(size_t budget, int32_t precision, void *stream, arlbm_server **out)
 {
     if (!out) return sfail(nullptr, ARLBM_EINVAL, "out is NULL");
     if (precision != ARLBM_F32 && precision != ARLBM_F64) return sfail(nullptr, ARLBM_EINVAL, "bad precision");
-    arlbm_server *s = new arlbm_server();
+    arlbm_server *s = new (std::nothrow) arlbm_server();
+    if (!s) return sfail(nullptr, ARLBM_ENOMEM, "host memory for the server");
     s->budget = budget;
     s->precision = precision;
     s->stream = (hipStream_t)stream;
-    // device blocks held (in use or free): at most 1.5 times the budget;
+    // device blocks held for lattices (in use or free): at most the budget;
     // free pinned staging blocks: at most 1 GiB
-    s->dev.cap = budget + budget / 2;
+    s->dev.cap = budget;
     s->dev.stream = s->stream;
     s->pin.stream = s->stream;
     s->pin.pinned = true;
@@ -1372,7 +1568,8 @@ extern "C" int arlbm_server_create(size_t budget, int32_t precision, void *strea
 extern "C" int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, const double *U0, const double *bed,
                                    int64_t nsteps, uint64_t *id)
 {
-    if (!s || !cfg || !U0 || nsteps < 0) return sfail(s, ARLBM_EINVAL, "bad argument");
+    if (!s || !cfg || !U0) return sfail(s, ARLBM_EINVAL, "bad argument");
+    if (nsteps < 1) return sfail(s, ARLBM_EINVAL, "nsteps must be >= 1");
     arlbm_config c = *cfg;
     c.precision = s->precision;
     std::string e = check_config(&c);
@@ -1380,9 +1577,9 @@ extern "C" int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, con
     if (c.has_bed && !bed) return sfail(s, ARLBM_EINVAL, "bed is NULL");
     arlbm_sizes sz;
     fill_sizes(&c, &sz);
-    if (sz.total_bytes > s->budget) return sfail(s, ARLBM_EBUDGET, "request can never fit the HBM budget");
     Pending p;
-    p.id = s->next_id++;
+    p.bytes = size_class(sz.total_bytes);
+    if (p.bytes > s->budget) return sfail(s, ARLBM_EBUDGET, "request can never fit the HBM budget");
     p.cfg = c;
     const size_t plane = (size_t)c.nx * c.ny * c.nz;
     if (!p.U0.alloc((size_t)sz.m * plane) || (c.has_bed && !p.bed.alloc(plane)))
@@ -1390,11 +1587,40 @@ extern "C" int arlbm_server_submit(arlbm_server *s, const arlbm_config *cfg, con
     par_copy(p.U0.data(), U0, sizeof(double) * p.U0.size());
     if (c.has_bed) par_copy(p.bed.data(), bed, sizeof(double) * plane);
     p.nsteps = nsteps;
-    p.submit_s = now_s();
-    p.bytes = sz.total_bytes;
-    s->queue.push_back(std::move(p));
-    if (id) *id = s->queue.back().id;
-    return ARLBM_OK;
+    return queue_request(s, std::move(p), id);
+}
+
+extern "C" int arlbm_server_submit_state(arlbm_server *s, const arlbm_config *cfg, const void *blob, size_t bytes,
+                                         int64_t nsteps, uint64_t *id)
+{
+    if (!s || !cfg || !blob) return sfail(s, ARLBM_EINVAL, "bad argument");
+    if (nsteps < 1) return sfail(s, ARLBM_EINVAL, "nsteps must be >= 1");
+    arlbm_config c = *cfg;
+    c.precision = s->precision;
+    std::string e = check_config(&c);
+    if (!e.empty()) return sfail(s, ARLBM_EINVAL, e);
+    if (c.has_bed) return sfail(s, ARLBM_EINVAL, "a lattice with a bed cannot be resumed in the server");
+    arlbm_sizes sz;
+    fill_sizes(&c, &sz);
+    const size_t need = sizeof(StateHeader) + sz.f_bytes + sz.u_bytes + sizeof(DevScalars);
+    if (bytes < need) return sfail(s, ARLBM_EINVAL, "state blob too small");
+    StateHeader hd;
+    std::memcpy(&hd, blob, sizeof hd);
+    if (hd.magic != kMagic || hd.precision != c.precision || hd.variant != variant_of(c.system, c.dim) ||
+        hd.nx != c.nx || hd.ny != c.ny || hd.nz != c.nz || hd.f_bytes != sz.f_bytes || hd.u_bytes != sz.u_bytes ||
+        hd.step < 0)
+        return sfail(s, ARLBM_EINVAL, "state blob does not match the configuration");
+    Pending p;
+    p.bytes = size_class(sz.total_bytes);
+    if (p.bytes > s->budget) return sfail(s, ARLBM_EBUDGET, "request can never fit the HBM budget");
+    p.cfg = c;
+    p.blob.reset(new (std::nothrow) char[need]);
+    if (!p.blob) return sfail(s, ARLBM_ENOMEM, "host memory for the queued state");
+    par_copy(p.blob.get(), blob, need);
+    p.blob_bytes = need;
+    p.step0 = hd.step;
+    p.nsteps = nsteps;
+    return queue_request(s, std::move(p), id);
 }
 
 extern "C" int arlbm_server_iterate(arlbm_server *s, int32_t *n_res, int32_t *n_queued)
@@ -1408,10 +1634,13 @@ extern "C" int arlbm_server_iterate_n(arlbm_server *s, int32_t max_launches, int
     if (!s) return sfail(nullptr, ARLBM_EINVAL, "server is NULL");
     if (max_launches < 1) return sfail(s, ARLBM_EINVAL, "max_launches must be >= 1");
     if (n_launched) *n_launched = 0;
-    // retire lattices whose steps are complete (read-backs enqueued)
+    take_gathers(s);
+    // retire lattices whose steps are complete, or whose state became
+    // non-finite or degenerate (read-backs enqueued)
     for (size_t i = 0; i < s->resident.size();) {
         const Resident r = s->resident[i];
-        if (s->iter - r.iter0 >= r.nsteps) {
+        const bool failing = std::find(s->failing.begin(), s->failing.end(), r.id) != s->failing.end();
+        if (s->iter >= r.end_it || failing) {
             s->resident.erase(s->resident.begin() + i);
             s->dirty = true;
             (void)retire_enqueue(s, r);  // a failure is reported in its completion
@@ -1419,6 +1648,7 @@ extern "C" int arlbm_server_iterate_n(arlbm_server *s, int32_t max_launches, int
             ++i;
         }
     }
+    s->failing.clear();
     // admit queued requests in arrival order while the budget allows
     while (!s->queue.empty() && s->in_use + s->queue.front().bytes <= s->budget) {
         Pending p = std::move(s->queue.front());
@@ -1431,29 +1661,36 @@ extern "C" int arlbm_server_iterate_n(arlbm_server *s, int32_t max_launches, int
     }
     // launches this call: as many as asked, but no resident lattice past its
     // step count, so retirements fall on the same iteration as one launch
-    // per call would give
+    // per call would give (every resident has a step left: finished lattices
+    // retired above, and a request asks for at least one step)
     int64_t nl = s->resident.empty() ? 0 : max_launches;
-    for (const Resident &r : s->resident) nl = std::min<int64_t>(nl, r.nsteps - (s->iter - r.iter0));
-    if (!s->resident.empty() && nl < 1) nl = 1;
+    for (const Resident &r : s->resident) nl = std::min<int64_t>(nl, r.end_it - s->iter);
     for (int64_t l = 0; l < nl; ++l) {
         hipError_t e = hipSuccess;
-        if (s->nitems > 0)
-            e = s->precision == ARLBM_F64 ? f64::step_batched(s->d_descs, s->d_items, s->nitems, s->iter, s->stream)
-                                          : f32::step_batched(s->d_descs, s->d_items, s->nitems, s->iter, s->stream);
+        if (s->nwaves > 0) {
+            const LatticeDesc *dd = (const LatticeDesc *)s->d_table;
+            const int32_t *ds = (const int32_t *)(s->d_table + s->off_start);
+            const Segment *dg = (const Segment *)(s->d_table + s->off_segs);
+            e = s->precision == ARLBM_F64 ? f64::step_batched(dd, ds, dg, s->nwaves, s->iter, s->stream)
+                                          : f32::step_batched(dd, ds, dg, s->nwaves, s->iter, s->stream);
+        }
         if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("batched launch: ") + hipGetErrorString(e));
-        // a 3D lattice's step is three passes over the whole lattice (the
-        // indicator needs every neighbour's moments first), launched on the
-        // same stream after the batched step
+        // lattices outside the batched kernel (3D; 2D beyond 4 GiB of
+        // populations) run their own step after it, on the same stream
         for (const Resident &r : s->resident) {
-            if (r.lat->desc.variant < V_ADV3) continue;
+            if (!own_launch(r.lat->desc)) continue;
             LatticeDesc d = r.lat->desc;
             d.iter0 = r.iter0;
             e = s->precision == ARLBM_F64 ? f64::step_single(d, s->iter, s->stream)
                                           : f32::step_single(d, s->iter, s->stream);
-            if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("3D step launch: ") + hipGetErrorString(e));
+            if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
         }
         ++s->iter;
         if (n_launched) ++*n_launched;
+    }
+    if (nl > 0) {
+        int rc = gather_flags(s);
+        if (rc) return rc;
     }
     // result copies and admission checks, while the launch runs
     int rc = finish_staged(s);
@@ -1490,6 +1727,13 @@ extern "C" int arlbm_server_memory(arlbm_server *s, size_t *bytes)
     return ARLBM_OK;
 }
 
+extern "C" int arlbm_server_pool_bytes(arlbm_server *s, size_t *bytes)
+{
+    if (!s || !bytes) return sfail(s, ARLBM_EINVAL, "bad argument");
+    *bytes = s->dev.used_bytes + s->dev.free_bytes;
+    return ARLBM_OK;
+}
+
 extern "C" int arlbm_server_destroy(arlbm_server *s)
 {
     if (!s) return ARLBM_OK;
@@ -1501,13 +1745,48 @@ extern "C" int arlbm_server_destroy(arlbm_server *s)
     }
     s->dev.clear();
     s->pin.clear();
-    if (s->d_descs) (void)hipFree(s->d_descs);
-    if (s->d_items) (void)hipFree(s->d_items);
+    if (s->d_table) (void)hipFree(s->d_table);
+    if (s->d_flags) (void)hipFree(s->d_flags);
     for (int k = 0; k < 2; ++k) {
-        if (s->h_descs[k]) (void)hipHostFree(s->h_descs[k]);
-        if (s->h_items[k]) (void)hipHostFree(s->h_items[k]);
+        if (s->h_table[k]) (void)hipHostFree(s->h_table[k]);
         if (s->table_ev[k]) (void)hipEventDestroy(s->table_ev[k]);
+        if (s->gather[k].host) (void)hipHostFree(s->gather[k].host);
+        if (s->gather[k].ev) (void)hipEventDestroy(s->gather[k].ev);
     }
     delete s;
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_plan_schedule(const arlbm_config *cfgs, int32_t n, int32_t waves, int32_t *wave_start,
+                                   int32_t max_waves, int32_t *segs, int32_t max_segs, int32_t *nwaves,
+                                   int32_t *nsegs)
+{
+    if (!cfgs || n < 0 || waves < 1 || !nwaves || !nsegs) return sfail(nullptr, ARLBM_EINVAL, "bad argument");
+    std::vector<SchedLattice> lats;
+    for (int32_t i = 0; i < n; ++i) {
+        std::string e = check_config(&cfgs[i]);
+        if (!e.empty()) return sfail(nullptr, ARLBM_EINVAL, e);
+        if (cfgs[i].dim == 3) continue;
+        LatticeDesc d{};
+        d.variant = variant_of(cfgs[i].system, cfgs[i].dim);
+        d.cpl = columns_per_lane(&cfgs[i]);
+        d.ncols = (int32_t)((cfgs[i].nx + strip_out_w(d.cpl) - 1) / strip_out_w(d.cpl));
+        d.ny = (int32_t)cfgs[i].ny;
+        lats.push_back(sched_lattice(i, d));
+    }
+    std::vector<int32_t> start;
+    std::vector<Segment> sg;
+    const int64_t nw = lats.empty() ? 0 : build_schedule(lats, waves, start, sg);
+    *nwaves = (int32_t)nw;
+    *nsegs = (int32_t)sg.size();
+    if (nw > max_waves || (int64_t)sg.size() > max_segs || (nw > 0 && (!wave_start || !segs)))
+        return sfail(nullptr, ARLBM_EINVAL, "output arrays too small");
+    for (int64_t w = 0; w <= nw && nw > 0; ++w) wave_start[w] = start[w];
+    for (size_t k = 0; k < sg.size(); ++k) {
+        segs[4 * k + 0] = sg[k].lattice;
+        segs[4 * k + 1] = sg[k].col;
+        segs[4 * k + 2] = sg[k].y0;
+        segs[4 * k + 3] = sg[k].y1;
+    }
     return ARLBM_OK;
 }

@@ -319,11 +319,16 @@ __device__ __forceinline__ bool finite_val(T v) { return __builtin_isfinite(v); 
 
 // ------------------------------------------------------------------ 1D ----
 
+// A 1D segment: strips c0 .. c1-1 of 58 output cells each, one after the
+// other in one wave.  The step's coefficients are formed once, the next
+// strip's populations are requested before the current one is collided, and
+// the wave commits its bounds once for the whole segment.
 template <int SYS, typename T>
-__device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int col, bool first)
+__device__ __forceinline__ void seg1d(const LatticeDesc &L, int64_t iter, int c0, int c1)
 {
     constexpr int D = 1, M = SysInfo<SYS, 1>::M, Q = 3;
     const int64_t n = iter - L.iter0;
+    const bool first = c0 == 0;
     Coefs<T> cf;
     if (!step_coefs<D, T>(L, n, cf)) {
         if (first && (threadIdx.x & 63) == 0) flag_degenerate(L, n);
@@ -334,145 +339,161 @@ __device__ __forceinline__ void strip1d(const LatticeDesc &L, int64_t iter, int 
     const int nx = L.nx;
     const int64_t plane = L.pstride;
     if (stopped(L, n)) {
-        const int xs = col * kOutW - kHalo + lane;
-        null_copy<T>(L, n, Q * M, xs, lane >= kHalo && lane < kWave - kHalo && xs < nx, 0, 1, first);
+        for (int col = c0; col < c1; ++col) {
+            const int xs = col * kOutW - kHalo + lane;
+            null_copy<T>(L, n, Q * M, xs, lane >= kHalo && lane < kWave - kHalo && xs < nx, 0, 1,
+                         first && col == c0);
+        }
         return;
     }
     const T *fin = (const T *)L.f[n & 1];
     T *fout = (T *)L.f[(n + 1) & 1];
-    const int x = col * kOutW - kHalo + lane;
-    bool rx;
-    const int xm = bc_map(x, nx, L.bc[0], L.bc[1], rx);
-    const bool out = lane >= kHalo && lane < kWave - kHalo && x < nx;
-
-    // moments (with ghost map) and neighbours
-    T U[M], UL[M], UR[M];
-    const unsigned xo = (unsigned)xm;
-    T f[Q][M];
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-#pragma unroll
-        for (int c = 0; c < M; ++c) f[k][c] = ldo(fin + (size_t)(k * M + c) * plane, xo);
-#pragma unroll
-    for (int c = 0; c < M; ++c) U[c] = f[0][c] + f[1][c] + f[2][c];  // (2.3), velocity order
-    if constexpr (SYS != 0)
-        if (rx) U[1] = -U[1];
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-        UL[c] = from_left(U[c]);
-        UR[c] = from_right(U[c]);
-    }
-    Prim<T> q;
-    primitives<SYS, D, T>(U, P, q);
-    // indicator nu (2.9)-(2.10), 3-point sum (2.11), omega (2.12)
-    T nu = T(0);
-    add_theta<SYS, D, T>(0, q, U, UL, UR, P, nu);
-    const T nuL = from_left(nu), nuR = from_right(nu);
-    const T nt = nuL + nu + nuR;
-    const T w = L.omega_fixed_on ? cf.omega_fixed : omega_of<T>(nt);
-    if (L.omega_on && out) ((T *)L.omega)[x] = w;
-
-    // bed slope by central differences
-    T db = T(0);
     constexpr bool src = SYS == 2;
-    bool has_bed = false;
-    if constexpr (src) {
-        has_bed = L.bed != nullptr;
-        if (has_bed) {
-            const T b = ((const T *)L.bed)[xm];
-            db = ddiv<T>(from_right(b) - from_left(b), T(2) * P.dx);
-        }
-    }
-
-    // equilibrium (2.18) and collision at this source node
-    T F[M];
-    flux<SYS, D, T>(0, U, q, P, F);
-    T fs[Q][M];
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-        const T u = U[c];
-        const T feq0 = cf.a0 * u;
-        const T feq1 = cf.ap[0] * u + cf.bp * F[c];
-        const T feq2 = cf.ap[0] * u + cf.bm * F[c];
-        const T f0 = f[0][c], f1 = f[1][c], f2 = f[2][c];
-        fs[0][c] = f0 - w * (f0 - feq0);
-        fs[1][c] = f1 - w * (f1 - feq1);
-        fs[2][c] = f2 - w * (f2 - feq2);
-    }
-    if constexpr (src) {
-        if (has_bed) {
-            const T S1 = -P.g * U[0] * db;
-            fs[0][1] = fs[0][1] + cf.hdt * (cf.a0 * S1);
-            fs[1][1] = fs[1][1] + cf.hdt * (cf.ap[0] * S1);
-            fs[2][1] = fs[2][1] + cf.hdt * (cf.ap[0] * S1);
-        }
-    }
-    if constexpr (SYS == 3) {  // Arrhenius sink of rho Y, first half (2.6)
-        const T SY = -arrhenius_rate<T>(P, U[0], reactive_eint<D, T>(U), U[M - 1], nullptr);
-        fs[0][M - 1] = fs[0][M - 1] + cf.hdt * (cf.a0 * SY);
-        fs[1][M - 1] = fs[1][M - 1] + cf.hdt * (cf.ap[0] * SY);
-        fs[2][M - 1] = fs[2][M - 1] + cf.hdt * (cf.ap[0] * SY);
-    }
-    // pull streaming: F_+(x) = f*_+(x-1), F_-(x) = f*_-(x+1)
-    T Fp[M], Fm[M];
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-        Fp[c] = from_left(fs[1][c]);
-        Fm[c] = from_right(fs[2][c]);
-    }
-    if (x == 0 && L.bc[0] != 0) {
-#pragma unroll
-        for (int c = 0; c < M; ++c) Fp[c] = L.bc[0] == 1 ? fs[1][c] : (c == 1 ? -fs[2][c] : fs[2][c]);
-    }
-    if (x == nx - 1 && L.bc[1] != 0) {
-#pragma unroll
-        for (int c = 0; c < M; ++c) Fm[c] = L.bc[1] == 1 ? fs[2][c] : (c == 1 ? -fs[1][c] : fs[1][c]);
-    }
-    // moments (2.8) and second half source
-    T fn[Q][M], Un[M];
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-        fn[0][c] = fs[0][c];
-        fn[1][c] = Fp[c];
-        fn[2][c] = Fm[c];
-    }
-    if constexpr (src) {
-        if (has_bed) {
-            const T h = fs[0][0] + Fp[0] + Fm[0];
-            const T S1 = -P.g * h * db;
-            fn[0][1] = fn[0][1] + cf.hdt * (cf.a0 * S1);
-            fn[1][1] = fn[1][1] + cf.hdt * (cf.ap[0] * S1);
-            fn[2][1] = fn[2][1] + cf.hdt * (cf.ap[0] * S1);
-        }
-    }
-    if constexpr (SYS == 3) {  // (2.8) for rho Y, then the second half source
-        T sumF[M];
-#pragma unroll
-        for (int c = 0; c < M; ++c) sumF[c] = fs[0][c] + Fp[c] + Fm[c];
-        const T eint = reactive_eint<D, T>(sumF);
-        const T z = reactive_solve<T>(P, sumF[0], eint, sumF[M - 1], cf.hdt);
-        const T SY = -arrhenius_rate<T>(P, sumF[0], eint, z, nullptr);
-        fn[0][M - 1] = fn[0][M - 1] + cf.hdt * (cf.a0 * SY);
-        fn[1][M - 1] = fn[1][M - 1] + cf.hdt * (cf.ap[0] * SY);
-        fn[2][M - 1] = fn[2][M - 1] + cf.hdt * (cf.ap[0] * SY);
-    }
-#pragma unroll
-    for (int c = 0; c < M; ++c) Un[c] = fn[0][c] + fn[1][c] + fn[2][c];
-    T s0 = T(0);
-    unsigned flags = 0;
-    if (out) {
+    const bool has_bed = src && L.bed != nullptr;
+    // populations (with the ghost map) of strip col
+    auto load = [&](int col, T (&f)[Q][M], T &b) {
+        bool r;
+        const unsigned xo = (unsigned)bc_map(col * kOutW - kHalo + lane, nx, L.bc[0], L.bc[1], r);
 #pragma unroll
         for (int k = 0; k < Q; ++k)
 #pragma unroll
-            for (int c = 0; c < M; ++c) sto(fout + (size_t)(k * M + c) * plane, (unsigned)x, fn[k][c]);
+            for (int c = 0; c < M; ++c) f[k][c] = ldo(fin + (size_t)(k * M + c) * plane, xo);
+        if (has_bed) b = ((const T *)L.bed)[xo];
+    };
+    T s0 = T(0);
+    unsigned flags = 0;
+    T f[Q][M], b = T(0);
+    load(c0, f, b);
+    for (int col = c0; col < c1; ++col) {
+        T fnx[Q][M], bnx = T(0);
+        const bool more = col + 1 < c1;
+        if (more) load(col + 1, fnx, bnx);
+        const int x = col * kOutW - kHalo + lane;
+        bool rx;
+        (void)bc_map(x, nx, L.bc[0], L.bc[1], rx);
+        const bool out = lane >= kHalo && lane < kWave - kHalo && x < nx;
+
+        // moments (with ghost map) and neighbours
+        T U[M], UL[M], UR[M];
 #pragma unroll
-        for (int c = 0; c < M; ++c)
-            if (!finite_val<T>(Un[c])) flags |= 1u;
-        Prim<T> qn;
-        primitives<SYS, D, T>(Un, P, qn);
-        flags |= qn.flags;
-        const T sp = max_speed<SYS, T>(0, qn, P);
-        if (finite_val<T>(sp)) s0 = sp;
+        for (int c = 0; c < M; ++c) U[c] = f[0][c] + f[1][c] + f[2][c];  // (2.3), velocity order
+        if constexpr (SYS != 0)
+            if (rx) U[1] = -U[1];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            UL[c] = from_left(U[c]);
+            UR[c] = from_right(U[c]);
+        }
+        Prim<T> q;
+        primitives<SYS, D, T>(U, P, q);
+        // indicator nu (2.9)-(2.10), 3-point sum (2.11), omega (2.12)
+        T nu = T(0);
+        add_theta<SYS, D, T>(0, q, U, UL, UR, P, nu);
+        const T nuL = from_left(nu), nuR = from_right(nu);
+        const T nt = nuL + nu + nuR;
+        const T w = L.omega_fixed_on ? cf.omega_fixed : omega_of<T>(nt);
+        if (L.omega_on && out) ((T *)L.omega)[x] = w;
+
+        // bed slope by central differences
+        T db = T(0);
+        if constexpr (src)
+            if (has_bed) db = ddiv<T>(from_right(b) - from_left(b), T(2) * P.dx);
+
+        // equilibrium (2.18) and collision at this source node
+        T F[M];
+        flux<SYS, D, T>(0, U, q, P, F);
+        T fs[Q][M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const T u = U[c];
+            const T feq0 = cf.a0 * u;
+            const T feq1 = cf.ap[0] * u + cf.bp * F[c];
+            const T feq2 = cf.ap[0] * u + cf.bm * F[c];
+            const T f0 = f[0][c], f1 = f[1][c], f2 = f[2][c];
+            fs[0][c] = f0 - w * (f0 - feq0);
+            fs[1][c] = f1 - w * (f1 - feq1);
+            fs[2][c] = f2 - w * (f2 - feq2);
+        }
+        if constexpr (src) {
+            if (has_bed) {
+                const T S1 = -P.g * U[0] * db;
+                fs[0][1] = fs[0][1] + cf.hdt * (cf.a0 * S1);
+                fs[1][1] = fs[1][1] + cf.hdt * (cf.ap[0] * S1);
+                fs[2][1] = fs[2][1] + cf.hdt * (cf.ap[0] * S1);
+            }
+        }
+        if constexpr (SYS == 3) {  // Arrhenius sink of rho Y, first half (2.6)
+            const T SY = -arrhenius_rate<T>(P, U[0], reactive_eint<D, T>(U), U[M - 1], nullptr);
+            fs[0][M - 1] = fs[0][M - 1] + cf.hdt * (cf.a0 * SY);
+            fs[1][M - 1] = fs[1][M - 1] + cf.hdt * (cf.ap[0] * SY);
+            fs[2][M - 1] = fs[2][M - 1] + cf.hdt * (cf.ap[0] * SY);
+        }
+        // pull streaming: F_+(x) = f*_+(x-1), F_-(x) = f*_-(x+1)
+        T Fp[M], Fm[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            Fp[c] = from_left(fs[1][c]);
+            Fm[c] = from_right(fs[2][c]);
+        }
+        if (x == 0 && L.bc[0] != 0) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) Fp[c] = L.bc[0] == 1 ? fs[1][c] : (c == 1 ? -fs[2][c] : fs[2][c]);
+        }
+        if (x == nx - 1 && L.bc[1] != 0) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) Fm[c] = L.bc[1] == 1 ? fs[2][c] : (c == 1 ? -fs[1][c] : fs[1][c]);
+        }
+        // moments (2.8) and second half source
+        T fn[Q][M], Un[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            fn[0][c] = fs[0][c];
+            fn[1][c] = Fp[c];
+            fn[2][c] = Fm[c];
+        }
+        if constexpr (src) {
+            if (has_bed) {
+                const T h = fs[0][0] + Fp[0] + Fm[0];
+                const T S1 = -P.g * h * db;
+                fn[0][1] = fn[0][1] + cf.hdt * (cf.a0 * S1);
+                fn[1][1] = fn[1][1] + cf.hdt * (cf.ap[0] * S1);
+                fn[2][1] = fn[2][1] + cf.hdt * (cf.ap[0] * S1);
+            }
+        }
+        if constexpr (SYS == 3) {  // (2.8) for rho Y, then the second half source
+            T sumF[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) sumF[c] = fs[0][c] + Fp[c] + Fm[c];
+            const T eint = reactive_eint<D, T>(sumF);
+            const T z = reactive_solve<T>(P, sumF[0], eint, sumF[M - 1], cf.hdt);
+            const T SY = -arrhenius_rate<T>(P, sumF[0], eint, z, nullptr);
+            fn[0][M - 1] = fn[0][M - 1] + cf.hdt * (cf.a0 * SY);
+            fn[1][M - 1] = fn[1][M - 1] + cf.hdt * (cf.ap[0] * SY);
+            fn[2][M - 1] = fn[2][M - 1] + cf.hdt * (cf.ap[0] * SY);
+        }
+#pragma unroll
+        for (int c = 0; c < M; ++c) Un[c] = fn[0][c] + fn[1][c] + fn[2][c];
+        if (out) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k)
+#pragma unroll
+                for (int c = 0; c < M; ++c) sto(fout + (size_t)(k * M + c) * plane, (unsigned)x, fn[k][c]);
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+                if (!finite_val<T>(Un[c])) flags |= 1u;
+            Prim<T> qn;
+            primitives<SYS, D, T>(Un, P, qn);
+            flags |= qn.flags;
+            const T sp = max_speed<SYS, T>(0, qn, P);
+            if (finite_val<T>(sp) && sp > s0) s0 = sp;
+        }
+        if (more) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k)
+#pragma unroll
+                for (int c = 0; c < M; ++c) f[k][c] = fnx[k][c];
+            b = bnx;
+        }
     }
     if (first) scalar_update(L, n, cf.dt);
     commit<T>(L, n, s0, T(0), flags, 1);
@@ -580,8 +601,8 @@ struct PlaneIO<T, V, true> {
     }
 };
 
-// One wave marches a strip of strip_out_w(V) output columns up a band of
-// rows; lane l holds the V columns xa .. xa+V-1, xa = x0 - strip_halo(V) + V l.
+// One wave marches a strip of strip_out_w(V) output columns up the rows
+// ya .. yb-1; lane l holds the V columns xa .. xa+V-1, xa = x0 - strip_halo(V) + V l.
 // With V = 2 every row access of a wave is one 512-byte span at an 8-byte
 // aligned start instead of a 256-byte span at a 4-byte aligned one: fewer
 // cache lines per byte, and a halo of 4 columns in 128 instead of 3 in 64.
@@ -589,7 +610,7 @@ struct PlaneIO<T, V, true> {
 // two columns map to cells in descending order: the lane loads the ascending
 // pair and swaps it; the wave-uniform test keeps interior strips free of it.
 template <int SYS, bool BED, typename T, int V, bool BUF = false>
-__device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int col, int band, bool first,
+__device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int col, int ya, int yb, bool first,
                                         T *lds = nullptr)
 {
     constexpr int D = 2, M = SysInfo<SYS, 2>::M, Q = 5;
@@ -607,9 +628,8 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     // with V = 2, nx is even and xa is even, so xa < nx covers both columns
     const bool xout = lane * V >= HC && lane * V < kWave * V - HC && xa < nx;
     if (stopped(L, n)) {
-        const int y0 = band * L.band_h, y1 = y0 + L.band_h < ny ? y0 + L.band_h : ny;
 #pragma unroll
-        for (int v = 0; v < V; ++v) null_copy<T>(L, n, Q * M, xa + v, xout, y0, y1, first && v == 0);
+        for (int v = 0; v < V; ++v) null_copy<T>(L, n, Q * M, xa + v, xout, ya, yb, first && v == 0);
         return;
     }
     const PlaneIO<T, V, BUF> io(L, n);
@@ -628,8 +648,6 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
         swp = xm[0] > xm[1];
     }
     const bool anyswap = V > 1 && __ballot(swp) != 0ull;
-    const int ya = band * L.band_h;
-    const int yb = ya + L.band_h < ny ? ya + L.band_h : ny;
     const T two_dx = T(2) * P.dx;
 
     auto fix = [&](T (&a)[V]) {
@@ -797,11 +815,8 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     // row's step) at the price of a 4x body and more registers.  Measured on
     // MI355X (ms per step, rotating -> unrolled): advection 0.0540 -> 0.0512,
     // Euler 0.169 -> 0.179, shallow water 0.478 -> 0.492; so only advection
-    // unrolls (ARLBM_RING_UNROLL: 0 never, 1 always, 2 advection).
-#ifndef ARLBM_RING_UNROLL
-#define ARLBM_RING_UNROLL 2
-#endif
-    constexpr bool kUnroll = kRing && (ARLBM_RING_UNROLL == 1 || (ARLBM_RING_UNROLL == 2 && SYS == 0));
+    // unrolls.
+    constexpr bool kUnroll = kRing && SYS == 0;
     // Without the unrolled ring, shallow water (15 values per row) prefetches
     // two rows ahead.
     constexpr bool kPf2 = kRing && !kUnroll && SYS == 2;
@@ -1169,56 +1184,93 @@ __device__ __forceinline__ int logical_wave()
     return __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + (int)(threadIdx.x >> 6));
 }
 
-#ifndef ARLBM_LDS_RING_F64
-#define ARLBM_LDS_RING_F64 1
-#endif
-#ifndef ARLBM_STEP_MIN_WAVES
-#define ARLBM_STEP_MIN_WAVES 1
-#endif
+// FP64 2D steps keep two population rows per wave in LDS (measured per step
+// at 2048^2 and 4096^2: Euler 0.375 -> 0.318 ms, shallow water 1.086 ->
+// 0.909, reactive 0.517 -> 0.493, advection 0.117 -> 0.126, so advection,
+// whose rows are 5 values, reads them again; kernels whose slots would not
+// fit the CU's 160 KB of LDS do too).  Elements of one wave's two slots:
+template <int SYS, typename T, int V>
+__host__ __device__ constexpr int lds_ring_elems()
+{
+    return sizeof(T) == 8 && SYS != 0 &&
+                   kWavesPerBlock * 2 * 5 * SysInfo<SYS, 2>::M * kWave * V * sizeof(T) <= 160 * 1024
+               ? 2 * 5 * SysInfo<SYS, 2>::M * kWave * V
+               : 0;
+}
+
 template <int SYS, int D, bool BED, typename T, int V = 1, bool BUF = false>
-__global__ __launch_bounds__(kBlock, ARLBM_STEP_MIN_WAVES) void k_step_single(LatticeDesc L, int64_t iter, int32_t nwork)
+__global__ __launch_bounds__(kBlock) void k_step_single(LatticeDesc L, int64_t iter, int32_t nwork)
 {
     const int w = logical_wave();
     if (w >= nwork) return;
     if constexpr (D == 1) {
-        strip1d<SYS, T>(L, iter, w, w == 0);
-    } else if constexpr (sizeof(T) == 8 && SYS != 0 &&
-                         kWavesPerBlock * 2 * 5 * SysInfo<SYS, 2>::M * kWave * V * sizeof(T) <= 160 * 1024) {
-        // two LDS row slots per wave (FP64; measured per step at 2048^2 and
-        // 4096^2: Euler 0.375 -> 0.318 ms, shallow water 1.086 -> 0.909,
-        // reactive 0.517 -> 0.493, advection 0.117 -> 0.126, so advection,
-        // whose rows are 5 values, reads them again; kernels whose slots would
-        // not fit the CU's 160 KB of LDS do too)
-        constexpr int kSlot = 5 * SysInfo<SYS, 2>::M * kWave * V;
-        __shared__ T ring[kWavesPerBlock * 2 * kSlot];
-        strip2d<SYS, BED, T, V, BUF>(L, iter, w % L.ncols, w / L.ncols, w == 0,
-                                     ARLBM_LDS_RING_F64 ? ring + (threadIdx.x >> 6) * 2 * kSlot : nullptr);
+        seg1d<SYS, T>(L, iter, w, w + 1);
     } else {
-        strip2d<SYS, BED, T, V, BUF>(L, iter, w % L.ncols, w / L.ncols, w == 0);
+        const int col = w % L.ncols, ya = (w / L.ncols) * L.band_h;
+        const int yb = ya + L.band_h < L.ny ? ya + L.band_h : L.ny;
+        constexpr int kRing = lds_ring_elems<SYS, T, V>();
+        if constexpr (kRing > 0) {
+            __shared__ T ring[kWavesPerBlock * kRing];
+            strip2d<SYS, BED, T, V, BUF>(L, iter, col, ya, yb, w == 0, ring + (threadIdx.x >> 6) * kRing);
+        } else {
+            strip2d<SYS, BED, T, V, BUF>(L, iter, col, ya, yb, w == 0);
+        }
     }
 }
 
+// One 2D segment of the batched step with the lattice's own strip width and
+// buffer-resource addressing (served lattices whose population buffer spans
+// 4 GiB or more run a launch of their own).
+template <int SYS, bool BED, typename T, int V>
+__device__ __forceinline__ void seg2d(const LatticeDesc &L, int64_t iter, const Segment &g, T *lds)
+{
+    constexpr int kRing = lds_ring_elems<SYS, T, V>();
+    strip2d<SYS, BED, T, V, true>(L, iter, g.col, g.y0, g.y1, g.col == 0 && g.y0 == 0,
+                                  kRing > 0 ? lds : nullptr);
+}
+template <int SYS, bool BED, typename T>
+__device__ __forceinline__ void seg2d_cpl(const LatticeDesc &L, int64_t iter, const Segment &g, T *lds)
+{
+    // the widths the single-lattice path takes per system and precision
+    // (two columns per lane need an even nx)
+    constexpr bool kTwo = SYS == 2 || (SYS == 0 && sizeof(T) == 4);
+    if (kTwo && L.cpl == 2) seg2d<SYS, BED, T, kTwo ? 2 : 1>(L, iter, g, lds);
+    else seg2d<SYS, BED, T, 1>(L, iter, g, lds);
+}
+
+// Batched step: every wave runs its list of segments (a static schedule
+// balanced by the host), one segment after the other; a segment is a row
+// range of one 2D strip or a range of 1D strips of one lattice.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_step_batched(const LatticeDesc *descs, const WorkItem *items,
-                                                          int32_t nitems, int64_t iter)
+__global__ __launch_bounds__(kBlock) void k_step_batched(const LatticeDesc *__restrict__ descs,
+                                                          const int32_t *__restrict__ wave_start,
+                                                          const Segment *__restrict__ segs, int32_t nwaves,
+                                                          int64_t iter)
 {
     const int w = logical_wave();
-    if (w >= nitems) return;
-    const WorkItem it = items[w];
-    const LatticeDesc &L = descs[it.lattice];
-    switch (L.variant) {
-    case V_ADV1: strip1d<0, T>(L, iter, it.col, it.first); break;
-    case V_EUL1: strip1d<1, T>(L, iter, it.col, it.first); break;
-    case V_SWE1: strip1d<2, T>(L, iter, it.col, it.first); break;
-    case V_ADV2: strip2d<0, false, T, 1>(L, iter, it.col, it.band, it.first); break;
-    case V_EUL2: strip2d<1, false, T, 1>(L, iter, it.col, it.band, it.first); break;
-    case V_SWE2:
-        if (L.bed) strip2d<2, true, T, 1>(L, iter, it.col, it.band, it.first);
-        else strip2d<2, false, T, 1>(L, iter, it.col, it.band, it.first);
-        break;
-    case V_REU1: strip1d<3, T>(L, iter, it.col, it.first); break;
-    case V_REU2: strip2d<3, false, T, 1>(L, iter, it.col, it.band, it.first); break;
-    default: break;
+    if (w >= nwaves) return;
+    constexpr int kRing = lds_ring_elems<2, T, 2>() > lds_ring_elems<3, T, 1>() ? lds_ring_elems<2, T, 2>()
+                                                                                 : lds_ring_elems<3, T, 1>();
+    __shared__ T ring[kWavesPerBlock * (kRing > 0 ? kRing : 1)];
+    T *lds = ring + (threadIdx.x >> 6) * kRing;
+    const int s0 = wave_start[w], s1 = wave_start[w + 1];
+    for (int s = s0; s < s1; ++s) {
+        const Segment g = segs[s];
+        const LatticeDesc &L = descs[g.lattice];
+        switch (L.variant) {
+        case V_ADV1: seg1d<0, T>(L, iter, g.col, g.y1); break;
+        case V_EUL1: seg1d<1, T>(L, iter, g.col, g.y1); break;
+        case V_SWE1: seg1d<2, T>(L, iter, g.col, g.y1); break;
+        case V_REU1: seg1d<3, T>(L, iter, g.col, g.y1); break;
+        case V_ADV2: seg2d_cpl<0, false, T>(L, iter, g, lds); break;
+        case V_EUL2: seg2d_cpl<1, false, T>(L, iter, g, lds); break;
+        case V_SWE2:
+            if (L.bed) seg2d_cpl<2, true, T>(L, iter, g, lds);
+            else seg2d_cpl<2, false, T>(L, iter, g, lds);
+            break;
+        case V_REU2: seg2d_cpl<3, false, T>(L, iter, g, lds); break;
+        default: break;
+        }
     }
 }
 

@@ -43,7 +43,47 @@ def rel_l1(a, b):
     return float(np.sum(np.abs(a - b)) / np.sum(np.abs(b)))
 
 
-def oracle_run(p, steps, **kw):
-    L = ora_from(p, **kw)
+def rel_l1_per_comp(a, b):
+    """Relative L1 difference of each field (plane c of the leading axis)."""
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    return [float(np.sum(np.abs(a[c] - b[c])) / max(np.sum(np.abs(b[c])), 1e-300)) for c in range(b.shape[0])]
+
+
+def rel_max_per_comp(a, b):
+    """Largest pointwise difference of each field over the field's largest
+    magnitude: an elementwise bound that a local error (at a wall, a front)
+    cannot hide in."""
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    return [float(np.max(np.abs(a[c] - b[c])) / max(np.max(np.abs(b[c])), 1e-300)) for c in range(b.shape[0])]
+
+
+def fp64_parity_ok(U, Uo, system):
+    """FP64 GPU result against the oracle.  The GPU kernels keep the oracle's
+    operation order, so the results agree bit for bit; reactive Euler
+    evaluates its exponential and the root of (2.8) by methods of its own on
+    each side, so there the bound is 1e-12 pointwise, relative to each
+    field's largest magnitude."""
+    U = np.asarray(U).reshape(np.shape(Uo))
+    if system == A.REACTIVE:
+        return max(rel_max_per_comp(U, Uo)) <= 1e-12
+    return bool(np.array_equal(U, Uo))
+
+
+def block_bytes(n):
+    """Device bytes a server charges for a lattice whose buffers take n
+    bytes: the size class of its pool block, a quarter octave above 64 KiB
+    (at most 25% above n), as include/arlbm.h states."""
+    if n <= 1 << 16:
+        return 1 << 16
+    q = 1 << (n.bit_length() - 1 - 2)
+    return (n + q - 1) // q * q
+
+
+def oracle_run(p, steps, parallel=False, **kw):
+    """The oracle after `steps` steps; parallel=True takes its OpenMP build
+    (the same bits: a CPU test checks it) to keep long runs short."""
+    L = ora_from(p, parallel=parallel, **kw)
     L.run(steps)
     return L

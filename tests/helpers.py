@@ -15,8 +15,8 @@ def ora_cfg_from(p, omega_fixed=None, eps=None, cfl=None, bc=None):
                       nz=p.nz, z0=p.z0, z1=p.z1)
 
 
-def ora_from(p, **kw):
-    return O.Lattice(ora_cfg_from(p, **kw)).init(p.U0, p.bed)
+def ora_from(p, parallel=False, **kw):
+    return O.Lattice(ora_cfg_from(p, **kw), parallel=parallel).init(p.U0, p.bed)
 
 
 def run_until(L, T):

@@ -19,7 +19,8 @@ import pytest
 import oracle as O
 from paper_2609_18177_amd import arlbm as A
 from paper_2609_18177_amd import workloads as W
-from gpu_common import require_gpu, say, gpu_lattice, rel_l2_per_comp, rel_l1, oracle_run
+from gpu_common import (require_gpu, say, gpu_lattice, rel_l2_per_comp, rel_l1, oracle_run, rel_l1_per_comp,
+                        rel_max_per_comp, block_bytes)
 from helpers import ora_from, fsum
 
 pytestmark = pytest.mark.gpu
@@ -248,6 +249,8 @@ def _requests():
 
 
 def _serve(probs, budget, precision=A.F32, one_at_a_time=False, max_launches=1):
+    """Serve the problems; returns the completions in submission order and
+    the peak of the device bytes the pool held (blocks in use and free)."""
     srv = A.Server(budget, precision)
     ids, res, peak = [], {}, 0
     pending = list(probs)
@@ -256,12 +259,19 @@ def _serve(probs, budget, precision=A.F32, one_at_a_time=False, max_launches=1):
             p = pending.pop(0)
             ids.append(srv.submit(A.config_from(p, precision=precision), p.U0, p.bed, p.steps))
         srv.iterate(max_launches)
-        peak = max(peak, srv.memory())
+        assert srv.memory() <= srv.pool_bytes() <= budget
+        peak = max(peak, srv.pool_bytes())
         for c in srv.poll(16):
             res[c["id"]] = c
     assert srv.memory() == 0
     srv.close()
     return [res[i] for i in ids], peak
+
+
+def _tight_budget(probs):
+    """Room for the largest request's block and the smallest one's."""
+    sizes = [block_bytes(A.query_sizes(A.config_from(p, precision=A.F32)).total_bytes) for p in probs]
+    return max(sizes) + min(sizes), sizes
 
 
 def test_serving_alone_equals_mix_bitwise():
@@ -283,8 +293,7 @@ def test_serving_several_launches_per_iterate_bitwise():
     budget that makes requests wait for retirements."""
     require_gpu()
     probs = _requests()
-    sizes = [A.query_sizes(A.config_from(p, precision=A.F32)).total_bytes for p in probs]
-    budget = max(sizes) + min(sizes)
+    budget, _ = _tight_budget(probs)
     one, _ = _serve(probs, budget)
     many, peak = _serve(probs, budget, max_launches=7)
     assert peak <= budget
@@ -351,14 +360,129 @@ def test_serving_fp64_matches_oracle_and_fp32_is_close():
 def test_serving_budget_admission():
     require_gpu()
     probs = _requests()
-    sizes = [A.query_sizes(A.config_from(p, precision=A.F32)).total_bytes for p in probs]
-    budget = max(sizes) + min(sizes)
+    budget, sizes = _tight_budget(probs)
     res, peak = _serve(probs, budget)
     assert all(r["status"] == 0 for r in res)
     assert peak <= budget
+    say(f"[serving] tight budget {budget} bytes: pool peak {peak} bytes")
     srv = A.Server(min(sizes) - 1, A.F32)
     p = probs[0]
     with pytest.raises(A.ArlbmError) as e:
         srv.submit(A.config_from(p, precision=A.F32), p.U0, p.bed, p.steps)
     assert e.value.code == A.EBUDGET
     srv.close()
+
+
+def test_serving_rejects_zero_step_requests():
+    require_gpu()
+    p = W.euler_seeded_1d(0, n=300, steps=1)
+    srv = A.Server(1 << 28, A.F32)
+    with pytest.raises(A.ArlbmError) as e:
+        srv.submit(A.config_from(p, precision=A.F32), p.U0, p.bed, 0)
+    assert e.value.code == A.EINVAL
+    srv.close()
+
+
+STATE_HEADER_BYTES = 56  # magic, precision, variant, nx, ny, nz, pad, step, f_bytes, u_bytes
+
+
+def _saved(p, prec, steps):
+    G = gpu_lattice(p, prec)
+    G.step(steps)
+    blob = G.save_state()
+    G.close()
+    return blob
+
+
+@pytest.mark.parametrize("prec", [A.F32, A.F64])
+def test_serving_resumed_state_bitwise(prec):
+    """A lattice saved after k steps and resumed in the server for n more
+    steps, beside other requests, gives the bits, time and step count of the
+    single lattice stepped k + n times."""
+    require_gpu()
+    cases = [(W.euler_seeded_2d(2, n=120, steps=100), 37), (W.euler_seeded_1d(3, n=2000, steps=90), 20),
+             (W.reactive_seeded_2d(1, n=70, steps=40), 11)]
+    refs = []
+    for p, k in cases:
+        G = gpu_lattice(p, prec)
+        G.step(p.steps)
+        refs.append((G.moments(), G.sync()))
+        G.close()
+    srv = A.Server(1 << 30, prec)
+    ids = [srv.submit_state(A.config_from(p, precision=prec), _saved(p, prec, k), p.steps - k) for p, k in cases]
+    others = [srv.submit(A.config_from(q, precision=prec), q.U0, q.bed, q.steps) for q in _requests()[:3]]
+    res = {}
+    while len(res) < len(ids) + len(others):
+        srv.iterate(3)
+        for c in srv.poll(16):
+            res[c["id"]] = c
+    srv.close()
+    for (p, k), i, (U, st) in zip(cases, ids, refs):
+        r = res[i]
+        assert r["status"] == 0 and r["steps"] == p.steps - k, p.name
+        assert np.array_equal(r["U"].reshape(U.shape), U), p.name
+        assert r["t"] == st["t"], p.name
+    assert all(res[i]["status"] == 0 for i in others)
+    say(f"[serving] {len(cases)} resumed states served bitwise as single lattices (prec {prec})")
+
+
+def test_serving_poisoned_request_fails_alone_and_early():
+    """A request resumed from a checkpoint blob with a NaN written into one
+    population (host side) fails with ENONFINITE, reports the step the NaN
+    entered, and leaves the mix long before its step count; every other
+    request gives the bits it gives alone."""
+    require_gpu()
+    probs = _requests()
+    alone, _ = _serve(probs, 1 << 30, one_at_a_time=True)
+    p = W.euler_seeded_2d(4, n=130, steps=400)
+    blob = bytearray(_saved(p, A.F32, 5))
+    cell = 10 * p.nx + 10  # plane 0 (k = 0, rho) at x = y = 10
+    off = STATE_HEADER_BYTES + 4 * cell
+    blob[off:off + 4] = np.array([np.nan], dtype=np.float32).tobytes()
+    srv = A.Server(1 << 30, A.F32)
+    ids = []
+    bad = None
+    for i, q in enumerate(probs):
+        ids.append(srv.submit(A.config_from(q, precision=A.F32), q.U0, q.bed, q.steps))
+        if i == 1:
+            bad = srv.submit_state(A.config_from(p, precision=A.F32), bytes(blob), 2000)
+    res = {}
+    while len(res) < len(probs) + 1:
+        srv.iterate()
+        assert srv.memory() <= srv.pool_bytes() <= 1 << 30
+        for c in srv.poll(16):
+            res[c["id"]] = c
+    assert srv.memory() == 0
+    srv.close()
+    b = res[bad]
+    say(f"[serving poison] status {b['status']} flags {b['flags']} first bad step {b['first_bad_step']} "
+        f"retired after {b['steps']} of 2000 steps")
+    assert b["status"] == A.ENONFINITE and b["U"] is None
+    assert b["flags"] & A.FLAG_NONFINITE
+    assert b["first_bad_step"] == 5
+    assert b["steps"] < 100
+    for q, a, i in zip(probs, alone, ids):
+        r = res[i]
+        assert r["status"] == 0 and r["steps"] == q.steps, q.name
+        assert np.array_equal(a["U"], r["U"]), q.name
+        assert a["t"] == r["t"]
+
+
+def test_serving_resume_rejects_mismatched_blob():
+    require_gpu()
+    p = W.euler_seeded_2d(2, n=64, steps=10)
+    blob = _saved(p, A.F32, 3)
+    srv = A.Server(1 << 28, A.F32)
+    q = W.euler_seeded_2d(2, n=80, steps=10)
+    with pytest.raises(A.ArlbmError) as e:
+        srv.submit_state(A.config_from(q, precision=A.F32), blob, 5)
+    assert e.value.code == A.EINVAL
+    with pytest.raises(A.ArlbmError) as e:
+        srv.submit_state(A.config_from(p, precision=A.F32), blob[:100], 5)
+    assert e.value.code == A.EINVAL
+    srv64 = A.Server(1 << 28, A.F64)
+    with pytest.raises(A.ArlbmError) as e:
+        srv64.submit_state(A.config_from(p, precision=A.F64), blob, 5)
+    assert e.value.code == A.EINVAL
+    srv.close()
+    srv64.close()

@@ -1,20 +1,31 @@
 """GPU checks of reactive Euler (Section 5.4) against the FP64 oracle.
 
-* FP64: bit for bit with the oracle on seeded 1D and 2D reactive data, on
-  Example 5.12's circular data and on Example 5.11's detonation data (the
-  Arrhenius exponential and the Newton solve of (2.8) follow one written
-  algorithm on both sides);
+* FP64 against the oracle, pointwise relative to each field's largest
+  magnitude.  The two sides compute the Arrhenius factor and the root of
+  (2.8) independently (the oracle: the C library's exp and a regula falsi
+  bracket to adjacent doubles; the kernel: its own exp and a safeguarded
+  Newton iteration), so they agree to rounding, not bit for bit: within
+  1e-12 after the first 10 steps of every case, and within 1e-12 or the
+  run's own conditioning after the whole run, whichever is larger.  The
+  conditioning is measured on the oracle: how far its result moves when
+  every initial value is moved by one unit in the last place (random sign).
+  The 1D reacting fronts amplify such a perturbation to 2e-4 (seeded data,
+  200 steps) and 3e-3 (Example 5.11's detonation) while the 2D runs stay
+  near 1e-15, so 1e-12 holds in 2D and the 1D runs are held to their
+  conditioning;
 * FP32: relative L1 over all fields against the oracle, within the bound
   stated below;
 * a uniform reacting state (the trapezoidal-rule reduction pinned on the CPU);
 * time-targeted runs and the batched server with a reactive lattice in the mix.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
 from paper_2609_18177_amd import arlbm as A
 from paper_2609_18177_amd import workloads as W
-from gpu_common import require_gpu, say, gpu_lattice, rel_l2_per_comp, rel_l1
+from gpu_common import require_gpu, say, gpu_lattice, rel_l2_per_comp, rel_l1, rel_max_per_comp, fp64_parity_ok
 from helpers import ora_from, run_until
 
 pytestmark = pytest.mark.gpu
@@ -27,13 +38,36 @@ pytestmark = pytest.mark.gpu
 TOL_FP32 = 2e-3
 
 
+def _conditioning(p, steps, t_final, Uo):
+    """Pointwise spread of the oracle's result under a one-ulp random
+    perturbation of every initial value (per field, relative to the field's
+    largest magnitude)."""
+    rng = np.random.default_rng(12345)
+    q = dataclasses.replace(p, U0=p.U0 * (1.0 + rng.choice([-1.0, 1.0], size=p.U0.shape) * 2.0 ** -52))
+    Lq = ora_from(q)
+    if t_final is not None:
+        run_until(Lq, t_final)
+    else:
+        Lq.run(steps)
+    return rel_max_per_comp(Lq.moments(), Uo)
+
+
 def _parity(p, steps=None, t_final=None, tag=""):
+    # the first 10 steps, before any front has amplified rounding
+    L10 = ora_from(p)
+    L10.run(10)
+    G = gpu_lattice(p, A.F64)
+    G.step(10)
+    G.sync()
+    e10 = rel_max_per_comp(G.moments(), L10.moments())
+    G.close()
     Lo = ora_from(p)
     if t_final is not None:
         run_until(Lo, t_final)
     else:
         Lo.run(steps)
     Uo = Lo.moments()
+    cond = _conditioning(p, steps, t_final, Uo)
     out = {}
     for prec in (A.F64, A.F32):
         G = gpu_lattice(p, prec)
@@ -48,11 +82,15 @@ def _parity(p, steps=None, t_final=None, tag=""):
     U64, st64, k64 = out[A.F64]
     U32, st32, _ = out[A.F32]
     e32 = rel_l1(U32, Uo)
-    say(f"[reactive {tag}] steps {k64} bitwise={np.array_equal(U64, Uo)} fp64 rel L2 {rel_l2_per_comp(U64, Uo)} "
-        f"fp32 rel L1 {e32:.3e} flags {st64['flags']}/{st32['flags']}")
+    e64 = rel_max_per_comp(U64, Uo)
+    say(f"[reactive {tag}] steps {k64} fp64 pointwise rel after 10 steps {max(e10):.2e}, after the run {e64} "
+        f"(oracle conditioning {cond}) fp32 rel L1 {e32:.3e} flags {st64['flags']}/{st32['flags']}")
     assert k64 == Lo.steps
-    assert np.array_equal(U64, Uo)
-    assert st64["t"] == Lo.t
+    assert max(e10) <= 1e-12, e10
+    assert all(e <= max(1e-12, c) for e, c in zip(e64, cond)), (e64, cond)
+    # the time is a sum of steps set by the largest wave speed, which moves
+    # no more than the state does
+    assert abs(st64["t"] - Lo.t) <= max(1e-13, max(cond)) * Lo.t
     assert e32 < TOL_FP32, e32
     return U64, U32
 
@@ -131,5 +169,5 @@ def test_reactive_in_serving_mix():
             continue
         Lo = ora_from(p)
         Lo.run(p.steps)
-        assert np.array_equal(r["U"].reshape(Lo.moments().shape), Lo.moments()), p.name
-    say("[reactive serving] alone == mix (FP32), FP64 batched == oracle")
+        assert fp64_parity_ok(r["U"], Lo.moments(), p.system), p.name
+    say("[reactive serving] alone == mix (FP32), FP64 batched within 1e-12 of the oracle")
