@@ -296,20 +296,19 @@ int arlbm_server_destroy(arlbm_server *s);
 /* Diagnostics                                                               */
 /* ------------------------------------------------------------------------ */
 
-/* The batched launch's schedule for lattices of configurations cfgs[0..n-1]
+/* The batched launch's work list for lattices of configurations cfgs[0..n-1]
  * served together (3D lattices, which run launches of their own, take no
- * part), dealt to at most `waves` waves, computed on the host as the server
- * computes it (no GPU needed).  On return *nwaves waves and *nsegs segments;
- * wave w runs segments wave_start[w] .. wave_start[w+1]-1 (wave_start has
- * *nwaves + 1 entries), and segment k is segs[4k .. 4k+3] = (lattice index,
+ * part), for a launch of at most `waves` waves, computed on the host as the
+ * server computes it (no GPU needed).  On return the list has *nsegs items
+ * and the launch *nwaves waves; item k is segs[4k .. 4k+3] = (lattice index,
  * strip, first row, end row) for a 2D lattice, (lattice index, first strip,
- * 0, end strip) for a 1D one.  Strips are 58 output columns, or 120 where
- * the lattice runs two columns per lane.  EINVAL on a bad configuration or
- * when the output arrays (max_waves + 1 and 4 max_segs entries) are too
- * small (the counts are still set). */
-int arlbm_plan_schedule(const arlbm_config *cfgs, int32_t n, int32_t waves, int32_t *wave_start,
-                        int32_t max_waves, int32_t *segs, int32_t max_segs, int32_t *nwaves,
-                        int32_t *nsegs);
+ * 0, end strip) for a 1D one (strips are 58 output columns, or 120 where the
+ * lattice runs two columns per lane).  The list is cut into 8 queues, one per
+ * XCD: queue q holds items queue_start[q] .. queue_start[q+1]-1
+ * (queue_start has 9 entries).  EINVAL on a bad configuration or when segs
+ * (4 max_segs entries) is too small (the counts are still set). */
+int arlbm_plan_schedule(const arlbm_config *cfgs, int32_t n, int32_t waves, int32_t *queue_start,
+                        int32_t *segs, int32_t max_segs, int32_t *nsegs, int32_t *nwaves);
 
 /* Vector registers per lane of the fused step kernel for a precision, system
  * and dimension (from the code object; in 2D the kernel that a lattice of

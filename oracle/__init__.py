@@ -58,6 +58,8 @@ def lib(parallel: bool = False):
             getattr(L, name).argtypes = [vp, dp]
         L.ora_set_f.argtypes = [vp, dp]
         L.ora_alpha_bar.argtypes = [vp, dp]
+        L.ora_threads.argtypes = []
+        L.ora_threads.restype = C.c_int
         L.ora_time.argtypes = [vp]
         L.ora_time.restype = C.c_double
         L.ora_steps.argtypes = [vp]
@@ -249,3 +251,8 @@ def moment_update(cfg, sumF, half_dt, db=(0.0, 0.0)):
     lib().ora_moment_update(C.byref(cfg), np.ascontiguousarray(sumF, dtype=np.float64),
                             np.ascontiguousarray(db, dtype=np.float64), float(half_dt), out)
     return out
+
+
+def threads(parallel: bool = False) -> int:
+    """Threads the given build runs a step on."""
+    return lib(parallel).ora_threads()

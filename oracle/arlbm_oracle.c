@@ -49,6 +49,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define G2 2 /* ghost depth of the padded moment array */
 
@@ -838,6 +841,16 @@ void ora_set_f(ora_lattice *L, const double *f)
 void ora_last_omega(const ora_lattice *L, double *omega)
 {
     memcpy(omega, L->omega, sizeof(double) * (size_t)L->ncell);
+}
+
+/* Threads a parallel region of this build uses (1 without OpenMP). */
+int ora_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 double ora_time(const ora_lattice *L) { return L->t; }

@@ -78,6 +78,7 @@ void ora_get_f(const ora_lattice *L, double *f);         /* Q*m planes     */
 void ora_set_f(ora_lattice *L, const double *f);
 void ora_last_omega(const ora_lattice *L, double *omega);/* 1 plane        */
 double ora_time(const ora_lattice *L);
+int ora_threads(void); /* threads of a parallel region (1: single-threaded build) */
 int64_t ora_steps(const ora_lattice *L);
 void ora_last_scalars(const ora_lattice *L, double *abar3, double *dt);
 int32_t ora_flags(const ora_lattice *L);

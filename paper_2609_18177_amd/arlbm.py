@@ -113,7 +113,7 @@ def lib():
             "arlbm_server_pool_bytes": ([vp, C.POINTER(C.c_size_t)], C.c_int),
             "arlbm_server_destroy": ([vp], C.c_int),
             "arlbm_step_kernel_vgprs": ([C.c_int32, C.c_int32, C.c_int32], C.c_int),
-            "arlbm_plan_schedule": ([C.POINTER(Config), C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+            "arlbm_plan_schedule": ([C.POINTER(Config), C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_int32)], C.c_int),
         }
@@ -379,16 +379,17 @@ def step_kernel_vgprs(precision: int, system: int, dim: int) -> int:
 
 
 def plan_schedule(cfgs, waves: int):
-    """The batched launch's schedule for these configurations (host only):
-    (wave_start array of nwaves + 1 entries, segments as an (nsegs, 4) array
-    of (lattice, strip, first row, end row) or (lattice, first strip, 0, end
-    strip) for 1D)."""
+    """The batched launch's work list for these configurations (host only):
+    (queue_start, 9 entries: queue q holds items queue_start[q] ..
+    queue_start[q+1]-1; items as an (nsegs, 4) array of (lattice, strip,
+    first row, end row), or (lattice, first strip, 0, end strip) for 1D;
+    the number of waves the launch takes)."""
     arr = (Config * max(len(cfgs), 1))(*cfgs)
-    nw, ns = C.c_int32(), C.c_int32()
-    lib().arlbm_plan_schedule(arr, len(cfgs), int(waves), None, 0, None, 0, C.byref(nw), C.byref(ns))
-    ws = np.zeros(nw.value + 1, dtype=np.int32)
+    ns, nw = C.c_int32(), C.c_int32()
+    qs = np.zeros(9, dtype=np.int32)
+    ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))  # noqa: E731
+    lib().arlbm_plan_schedule(arr, len(cfgs), int(waves), ip(qs), None, 0, C.byref(ns), C.byref(nw))
     sg = np.zeros(4 * max(ns.value, 1), dtype=np.int32)
-    _check(lib().arlbm_plan_schedule(arr, len(cfgs), int(waves), ws.ctypes.data_as(C.POINTER(C.c_int32)),
-                                     nw.value, sg.ctypes.data_as(C.POINTER(C.c_int32)), ns.value,
-                                     C.byref(nw), C.byref(ns)))
-    return ws, sg[:4 * ns.value].reshape(-1, 4)
+    _check(lib().arlbm_plan_schedule(arr, len(cfgs), int(waves), ip(qs), ip(sg), ns.value, C.byref(ns),
+                                     C.byref(nw)))
+    return qs, sg[:4 * ns.value].reshape(-1, 4), nw.value

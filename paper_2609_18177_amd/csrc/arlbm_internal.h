@@ -85,15 +85,19 @@ struct LatticeDesc {
     void *nu3;                     // 3D: padded indicator (nx+2)(ny+2)(nz+2), then omega of the cells
 };
 
-// One segment of a wave's work in a batched launch.  2D: rows y0 .. y1-1 of
-// strip col.  1D: strips col .. y1-1 (y0 unused).  The segment that holds
-// the lattice's first cell (col 0, row 0) also updates its scalars.
+// One work item of a batched launch.  2D: rows y0 .. y1-1 of strip col.
+// 1D: strips col .. y1-1 (y0 unused).  The item that holds the lattice's
+// first cell (col 0, row 0) also updates its scalars.
 struct Segment {
     int32_t lattice;
     int32_t col;
     int32_t y0;
     int32_t y1;
 };
+
+// Work queues of a batched launch: one per XCD, counters 128 bytes apart.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 32;
 
 }  // namespace arlbm
 
@@ -106,8 +110,9 @@ struct Segment {
     hipError_t init(const LatticeDesc &h, const double *U0, const double *bed64, int slot_in,         \
                     hipStream_t s);                                                                    \
     hipError_t step_single(const LatticeDesc &h, int64_t iter, hipStream_t s);                        \
-    hipError_t step_batched(const LatticeDesc *d_descs, const int32_t *d_wave_start,                  \
-                            const Segment *d_segs, int32_t nwaves, int64_t iter, hipStream_t s);       \
+    hipError_t step_batched(const LatticeDesc *d_descs, const Segment *d_segs, const int32_t *d_qstart, \
+                            unsigned *d_counters, int32_t parity, int32_t nwaves, int64_t iter,        \
+                            hipStream_t s);                                                            \
     hipError_t conservation(const void *u, int64_t plane, int64_t pstride, int m, double *partial,    \
                             int nblocks, hipStream_t s);                                               \
     hipError_t moments(const void *f, void *u, int64_t plane, int64_t pstride, int m, int q,          \

@@ -137,11 +137,11 @@ hipError_t step_single(const LatticeDesc &h, int64_t iter, hipStream_t s)
 #undef C_
 }
 
-hipError_t step_batched(const LatticeDesc *d_descs, const int32_t *d_wave_start, const Segment *d_segs,
-                        int32_t nwaves, int64_t iter, hipStream_t s)
+hipError_t step_batched(const LatticeDesc *d_descs, const Segment *d_segs, const int32_t *d_qstart,
+                        unsigned *d_counters, int32_t parity, int32_t nwaves, int64_t iter, hipStream_t s)
 {
     hipLaunchKernelGGL((k_step_batched<real>), dim3(grid_for(nwaves, kWavesPerBlock)), dim3(kBlock), 0, s,
-                       d_descs, d_wave_start, d_segs, nwaves, iter);
+                       d_descs, d_segs, d_qstart, d_counters, parity, iter);
     return hipGetLastError();
 }
 

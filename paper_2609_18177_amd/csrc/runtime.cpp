@@ -994,8 +994,8 @@ struct arlbm_server {
     std::deque<Done> done;
     std::vector<Done> handed;  // results returned by the last poll
     BlockPool dev, pin;
-    // device work table: descriptors, then the schedule (the first segment
-    // of each wave, nwaves + 1 entries, then the segments); one allocation
+    // device work table: descriptors, the start of each XCD's part of the
+    // work list (kQueues + 1 entries), the work list; one allocation
     char *d_table = nullptr;
     size_t cap_table = 0;
     // pinned host copies of the work table, two used in turn; one is
@@ -1004,8 +1004,13 @@ struct arlbm_server {
     size_t hcap_table[2] = {0, 0};
     hipEvent_t table_ev[2] = {nullptr, nullptr};
     int table_set = 0;
-    int32_t nwaves = 0;
+    int32_t nwaves = 0;                  // waves of the batched launch
     size_t off_start = 0, off_segs = 0;  // byte offsets in the table
+    // queue counters of the batched launch: two sets (launch parity) of
+    // kQueues counters 128 bytes apart; a launch takes items with one set and
+    // zeroes the other for the next launch
+    unsigned *d_counters = nullptr;
+    int64_t batched_launches = 0;  // its parity picks the counter set
     // flag words of the residents gathered after each call's launches (two
     // in turn), read by a later call once their copy has completed: a
     // lattice that became non-finite or degenerate retires early
@@ -1073,31 +1078,43 @@ void push_failed(arlbm_server *s, uint64_t id, int rc, double submit_s)
 // (the batched kernel addresses planes through 32-bit buffer offsets).
 bool own_launch(const LatticeDesc &d) { return d.variant >= V_ADV3 || (d.variant >= V_ADV2 && !d.buf); }
 
-// Static schedule of the batched launch.  The work of every resident 1D and
-// 2D lattice is cut into items and dealt to at most batched_waves() waves
-// (one per SIMD) so that each wave's work is about equal.
+// Work list of the batched launch.  The work of every resident 1D and 2D
+// lattice is cut into items (row bands of 2D strips, runs of 1D strips),
+// and the launch's waves, one per SIMD, take items from a queue until it is
+// empty.  The items are taken in list order, so the items the waves hold at
+// any moment are neighbours in the list: the list holds each lattice's bands
+// in order, each band's strips left to right, so those waves march over the
+// same rows of neighbouring strips (their halo columns are in each other's
+// L2, and the concurrent reads cover whole plane rows).  The list is cut
+// into kQueues contiguous parts of about equal work, one per XCD; a wave
+// takes items from its XCD's part first (blocks are dealt to the XCDs round
+// robin, so block b runs on XCD b mod 8), its first one as a static deal
+// would give it, then from the others in turn.
 //
-// Cost model, in population values a wave moves: a 2D item of h rows of one
-// strip costs (h + 6) rows of 64 V lanes by Q m values (the march reads 3
-// rows of moments beyond each end and collides one row beyond each end); a
-// 1D strip costs 64 Q m values plus a latency share of one 1280-value row,
-// and a run of 1D strips two strips more.
+// Item height: the whole work is r rounds of the launch's waves, with r as
+// small as keeps bands of at most 256 rows, and every 2D lattice is cut into
+// bands of equal height, about h = (strip rows) / (r waves) rows (at least
+// 8); in a single round h is the lowest height whose items all fit the
+// waves.  A lattice alone thus gets the
+// single-lattice kernel's bands, one per wave (2048^2 Euler: 28 bands of 74
+// rows of its 36 strips); a large mix gets about r items per wave, which
+// the queue balances.  2D lattices come first, those with the tallest items
+// first, and 1D runs (of about one 2D item's work each) last, so the items
+// that end the launch are the smallest.  Cost model, in population values a
+// wave moves: a 2D item of h rows costs (h + 6) rows of 64 V lanes by Q m
+// values (the march reads 3 rows of moments beyond each end and collides one
+// row beyond each end); a 1D strip costs 64 Q m values plus a latency share
+// of one 1280-value row, and a run two strips more.
 //
-// Every lattice gets one band height, as tall as the common per-wave budget
-// B allows ((h + 6) unit <= B), and its items are its bands taken in order,
-// each band's strips left to right; the items are then dealt in that order,
-// as many consecutive items per wave as fit in B.  A large lattice thus gets
-// one band of one strip per wave, its waves laid out as the single-lattice
-// kernel lays them out: consecutive waves (which the step kernels deal to
-// one XCD) hold neighbouring strips of the same rows, so a wave's halo
-// columns are in its neighbours' L2 and the concurrent reads of one XCD
-// cover whole plane rows.  (Cutting each strip into row ranges instead put
-// the waves of one XCD at scattered rows of a few strips and ran the 2048^2
-// Euler lattice 51% slower than the single-lattice kernel.)  Small lattices
-// share waves.  B starts at the total cost over the waves and grows until
-// the deal needs no more waves than there are.
-constexpr int kWarmRows2d = 6, kWarmStrips1d = 2, kMinRows2d = 8;
-constexpr int64_t kStrip1dLatency = 1280;
+// Dealing the items statically instead (consecutive items per wave) gave
+// the same times for one item per wave, but two or more put a wave's items
+// one after the other on its own, so neighbouring waves no longer marched
+// over neighbouring strips: 4096^2 shallow water 0.46 -> 0.70 ms per step,
+// all 512 requests of the serving mix resident 21 -> 15 GLUPS; and cutting
+// strips into row ranges dealt down each strip put the waves of one XCD at
+// scattered rows (2048^2 Euler 51% slower than the single-lattice kernel).
+constexpr int kWarmRows2d = 6, kWarmStrips1d = 2, kMinRows2d = 8, kMaxRows2d = 256;
+constexpr int64_t kStrip1dLatency = 1280, kRowValues = 1280;
 
 int64_t batched_waves() { return 4 * (int64_t)num_cus(); }  // one wave per SIMD
 
@@ -1109,53 +1126,76 @@ struct SchedLattice {
     int64_t unit;   // cost per row (2D) or per strip (1D)
 };
 
-int64_t build_schedule(const std::vector<SchedLattice> &lats, int64_t W, std::vector<int32_t> &start,
-                       std::vector<Segment> &segs)
+// Items in queue order and the start of each XCD's part (kQueues + 1
+// entries); returns the number of waves to launch.
+int64_t build_schedule(const std::vector<SchedLattice> &lats, int64_t W, std::vector<Segment> &segs,
+                       std::vector<int32_t> &qstart)
 {
-    double total = 0.0;
+    segs.clear();
+    qstart.assign(kQueues + 1, 0);
+    int64_t S = 0;  // 2D strip rows
     for (const SchedLattice &l : lats)
-        total += l.one_d ? (double)(l.ncols + kWarmStrips1d) * (double)l.unit
-                         : (double)l.ncols * (double)(l.ny + kWarmRows2d) * (double)l.unit;
-    double B = total / (double)W;
-    for (int attempt = 0;; ++attempt) {
-        start.assign(1, 0);
-        segs.clear();
-        double rem = B;
-        auto put = [&](const Segment &g, double cost) {
-            // a new wave when this item does not fit the current one's budget
-            if ((int32_t)segs.size() > start.back() && cost > rem) {
-                start.push_back((int32_t)segs.size());
-                rem = B;
-            }
-            segs.push_back(g);
-            rem -= cost;
+        if (!l.one_d) S += (int64_t)l.ncols * l.ny;
+    std::vector<std::pair<int64_t, size_t>> order;  // (band height, lattice) of the 2D lattices
+    int64_t h = kMaxRows2d;
+    if (S > 0) {
+        int64_t r = std::max<int64_t>(1, (S + W * kMaxRows2d - 1) / (W * kMaxRows2d));
+        h = std::max<int64_t>(kMinRows2d, (S + W * r - 1) / (W * r));
+        auto items_at = [&](int64_t hh) {
+            int64_t n = 0;
+            for (const SchedLattice &l : lats)
+                if (!l.one_d) n += (int64_t)l.ncols * ((l.ny + std::min(hh, l.ny) - 1) / std::min(hh, l.ny));
+            return n;
         };
-        for (const SchedLattice &l : lats) {
-            if (l.one_d) {
-                // runs of strips of at most the budget
-                int64_t per = (int64_t)(B / (double)l.unit) - kWarmStrips1d;
-                per = std::max<int64_t>(1, per);
-                for (int64_t c = 0; c < l.ncols; c += per) {
-                    const int64_t e = std::min<int64_t>(l.ncols, c + per);
-                    put({l.lattice, (int32_t)c, 0, (int32_t)e}, (double)(e - c + kWarmStrips1d) * (double)l.unit);
-                }
-            } else {
-                int64_t h = (int64_t)(B / (double)l.unit) - kWarmRows2d;
-                h = std::min<int64_t>(l.ny, std::max<int64_t>(kMinRows2d, h));
-                const int64_t nb = (l.ny + h - 1) / h;
-                h = (l.ny + nb - 1) / nb;  // even bands
-                for (int64_t b = 0; b < nb; ++b) {
-                    const int64_t y0 = b * h, y1 = std::min<int64_t>(l.ny, y0 + h);
-                    for (int32_t c = 0; c < l.ncols; ++c)
-                        put({l.lattice, c, (int32_t)y0, (int32_t)y1}, (double)(y1 - y0 + kWarmRows2d) * (double)l.unit);
-                }
+        if (r == 1) {
+            // one round: the lowest height whose items all fit the waves (a
+            // second round for a few items would double the step time)
+            while (items_at(h) > W && h < kMaxRows2d) ++h;
+            if (items_at(h) > W) {
+                r = 2;
+                h = std::max<int64_t>(kMinRows2d, (S + W * r - 1) / (W * r));
             }
         }
-        if ((int32_t)segs.size() > start.back()) start.push_back((int32_t)segs.size());
-        const int64_t nw = (int64_t)start.size() - 1;
-        if (nw <= W || attempt >= 60) return nw;
-        B *= 1.02;
+        for (size_t i = 0; i < lats.size(); ++i) {
+            if (lats[i].one_d) continue;
+            const int64_t nb = (lats[i].ny + std::min(h, lats[i].ny) - 1) / std::min(h, lats[i].ny);
+            order.push_back({(lats[i].ny + nb - 1) / nb, i});
+        }
+        std::stable_sort(order.begin(), order.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
     }
+    std::vector<double> cost;
+    for (const auto &o : order) {
+        const SchedLattice &l = lats[o.second];
+        const int64_t hl = o.first;
+        for (int64_t y0 = 0; y0 < l.ny; y0 += hl) {
+            const int64_t y1 = std::min<int64_t>(l.ny, y0 + hl);
+            for (int32_t c = 0; c < l.ncols; ++c) {
+                segs.push_back({l.lattice, c, (int32_t)y0, (int32_t)y1});
+                cost.push_back((double)(y1 - y0 + kWarmRows2d) * (double)l.unit);
+            }
+        }
+    }
+    for (const SchedLattice &l : lats) {
+        if (!l.one_d) continue;
+        // runs of about one 2D item's work
+        const int64_t per = std::max<int64_t>(1, (h + kWarmRows2d) * kRowValues / l.unit - kWarmStrips1d);
+        for (int64_t c = 0; c < l.ncols; c += per) {
+            const int64_t e = std::min<int64_t>(l.ncols, c + per);
+            segs.push_back({l.lattice, (int32_t)c, 0, (int32_t)e});
+            cost.push_back((double)(e - c + kWarmStrips1d) * (double)l.unit);
+        }
+    }
+    // contiguous parts of about equal work
+    double total = 0.0;
+    for (double c : cost) total += c;
+    double acc = 0.0;
+    int q = 1;
+    for (size_t k = 0; k < cost.size() && q < kQueues; ++k) {
+        acc += cost[k];
+        while (q < kQueues && acc >= total * q / kQueues) qstart[q++] = (int32_t)(k + 1);
+    }
+    for (; q <= kQueues; ++q) qstart[q] = (int32_t)segs.size();
+    return std::min<int64_t>(W, (int64_t)segs.size());
 }
 
 // A schedule item of lattice i from its descriptor (1D and 2D lattices the
@@ -1177,11 +1217,11 @@ int rebuild_table(arlbm_server *s)
         descs.push_back(d);
         if (!own_launch(d)) lats.push_back(sched_lattice((int32_t)i, d));
     }
-    std::vector<int32_t> start;
     std::vector<Segment> segs;
-    const int64_t nw = lats.empty() ? 0 : build_schedule(lats, batched_waves(), start, segs);
+    std::vector<int32_t> qstart;
+    const int64_t nw = lats.empty() ? 0 : build_schedule(lats, batched_waves(), segs, qstart);
     s->off_start = align_up(sizeof(LatticeDesc) * descs.size());
-    s->off_segs = s->off_start + align_up(sizeof(int32_t) * start.size());
+    s->off_segs = s->off_start + align_up(sizeof(int32_t) * (kQueues + 1));
     const size_t bytes = s->off_segs + sizeof(Segment) * segs.size();
     hipError_t e;
     // the device table grows by reallocation, after the launches that still
@@ -1223,7 +1263,7 @@ int rebuild_table(arlbm_server *s)
         }
         char *h = s->h_table[k];
         std::memcpy(h, descs.data(), sizeof(LatticeDesc) * descs.size());
-        if (!start.empty()) std::memcpy(h + s->off_start, start.data(), sizeof(int32_t) * start.size());
+        if (!qstart.empty()) std::memcpy(h + s->off_start, qstart.data(), sizeof(int32_t) * qstart.size());
         if (!segs.empty()) std::memcpy(h + s->off_segs, segs.data(), sizeof(Segment) * segs.size());
         e = hipMemcpyAsync(s->d_table, h, bytes, hipMemcpyHostToDevice, s->stream);
         if (e == hipSuccess) e = hipEventRecord(s->table_ev[k], s->stream);
@@ -1561,6 +1601,16 @@ extern "C" int arlbm_server_create(size_t budget, int32_t precision, void *strea
     s->pin.stream = s->stream;
     s->pin.pinned = true;
     s->pin.cap = (size_t)1 << 30;
+    const size_t cbytes = sizeof(unsigned) * 2 * kQueues * kQueueStride;
+    hipError_t e = hipMalloc((void **)&s->d_counters, cbytes);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_counters, 0, cbytes, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        if (s->d_counters) (void)hipFree(s->d_counters);
+        delete s;
+        return sfail(nullptr, e == hipErrorOutOfMemory ? ARLBM_ENOMEM : ARLBM_EDEVICE,
+                     std::string("queue counters: ") + hipGetErrorString(e));
+    }
     *out = s;
     return ARLBM_OK;
 }
@@ -1669,10 +1719,13 @@ extern "C" int arlbm_server_iterate_n(arlbm_server *s, int32_t max_launches, int
         hipError_t e = hipSuccess;
         if (s->nwaves > 0) {
             const LatticeDesc *dd = (const LatticeDesc *)s->d_table;
-            const int32_t *ds = (const int32_t *)(s->d_table + s->off_start);
+            const int32_t *dq = (const int32_t *)(s->d_table + s->off_start);
             const Segment *dg = (const Segment *)(s->d_table + s->off_segs);
-            e = s->precision == ARLBM_F64 ? f64::step_batched(dd, ds, dg, s->nwaves, s->iter, s->stream)
-                                          : f32::step_batched(dd, ds, dg, s->nwaves, s->iter, s->stream);
+            const int32_t par = (int32_t)(s->batched_launches & 1);
+            e = s->precision == ARLBM_F64
+                    ? f64::step_batched(dd, dg, dq, s->d_counters, par, s->nwaves, s->iter, s->stream)
+                    : f32::step_batched(dd, dg, dq, s->d_counters, par, s->nwaves, s->iter, s->stream);
+            ++s->batched_launches;
         }
         if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("batched launch: ") + hipGetErrorString(e));
         // lattices outside the batched kernel (3D; 2D beyond 4 GiB of
@@ -1747,6 +1800,7 @@ extern "C" int arlbm_server_destroy(arlbm_server *s)
     s->pin.clear();
     if (s->d_table) (void)hipFree(s->d_table);
     if (s->d_flags) (void)hipFree(s->d_flags);
+    if (s->d_counters) (void)hipFree(s->d_counters);
     for (int k = 0; k < 2; ++k) {
         if (s->h_table[k]) (void)hipHostFree(s->h_table[k]);
         if (s->table_ev[k]) (void)hipEventDestroy(s->table_ev[k]);
@@ -1757,11 +1811,11 @@ extern "C" int arlbm_server_destroy(arlbm_server *s)
     return ARLBM_OK;
 }
 
-extern "C" int arlbm_plan_schedule(const arlbm_config *cfgs, int32_t n, int32_t waves, int32_t *wave_start,
-                                   int32_t max_waves, int32_t *segs, int32_t max_segs, int32_t *nwaves,
-                                   int32_t *nsegs)
+extern "C" int arlbm_plan_schedule(const arlbm_config *cfgs, int32_t n, int32_t waves, int32_t *queue_start,
+                                   int32_t *segs, int32_t max_segs, int32_t *nsegs, int32_t *nwaves)
 {
-    if (!cfgs || n < 0 || waves < 1 || !nwaves || !nsegs) return sfail(nullptr, ARLBM_EINVAL, "bad argument");
+    if (!cfgs || n < 0 || waves < 1 || !nsegs || !nwaves || !queue_start)
+        return sfail(nullptr, ARLBM_EINVAL, "bad argument");
     std::vector<SchedLattice> lats;
     for (int32_t i = 0; i < n; ++i) {
         std::string e = check_config(&cfgs[i]);
@@ -1774,14 +1828,14 @@ extern "C" int arlbm_plan_schedule(const arlbm_config *cfgs, int32_t n, int32_t 
         d.ny = (int32_t)cfgs[i].ny;
         lats.push_back(sched_lattice(i, d));
     }
-    std::vector<int32_t> start;
     std::vector<Segment> sg;
-    const int64_t nw = lats.empty() ? 0 : build_schedule(lats, waves, start, sg);
+    std::vector<int32_t> qs(kQueues + 1, 0);
+    const int64_t nw = lats.empty() ? 0 : build_schedule(lats, waves, sg, qs);
     *nwaves = (int32_t)nw;
     *nsegs = (int32_t)sg.size();
-    if (nw > max_waves || (int64_t)sg.size() > max_segs || (nw > 0 && (!wave_start || !segs)))
-        return sfail(nullptr, ARLBM_EINVAL, "output arrays too small");
-    for (int64_t w = 0; w <= nw && nw > 0; ++w) wave_start[w] = start[w];
+    for (int q = 0; q <= kQueues; ++q) queue_start[q] = qs[q];
+    if ((int64_t)sg.size() > max_segs || (!sg.empty() && !segs))
+        return sfail(nullptr, ARLBM_EINVAL, "output array too small");
     for (size_t k = 0; k < sg.size(); ++k) {
         segs[4 * k + 0] = sg[k].lattice;
         segs[4 * k + 1] = sg[k].col;

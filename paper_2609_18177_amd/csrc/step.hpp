@@ -1238,24 +1238,38 @@ __device__ __forceinline__ void seg2d_cpl(const LatticeDesc &L, int64_t iter, co
     else seg2d<SYS, BED, T, 1>(L, iter, g, lds);
 }
 
-// Batched step: every wave runs its list of segments (a static schedule
-// balanced by the host), one segment after the other; a segment is a row
-// range of one 2D strip or a range of 1D strips of one lattice.
+// Batched step: persistent waves take work items (a row band of one 2D strip
+// or a run of 1D strips of one lattice) from per-XCD queues until every queue
+// is empty.  Queue q holds items qstart[q] .. qstart[q+1]-1 of the work list.
+// Blocks are dealt to the 8 XCDs round robin, so block b runs on XCD b mod 8,
+// where its wave k has rank r = 4 (b / 8) + k among the XCD's w waves.  A
+// wave's first item is item r of its XCD's queue, as a static deal would give
+// it (a lattice alone thus runs in the single-lattice kernel's layout: one
+// band of one strip per wave, neighbouring strips on neighbouring waves of
+// one XCD); the items after the first w of each queue are taken through its
+// counter (item w + counter), first from the wave's own queue, then from the
+// queue with the most items left.  The counters of this launch are set
+// `parity` (kQueues counters kQueueStride words apart), the parity of the
+// number of batched launches made before it; the launch zeroes the other set,
+// which the previous batched launch used and the next one takes.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_step_batched(const LatticeDesc *__restrict__ descs,
-                                                          const int32_t *__restrict__ wave_start,
-                                                          const Segment *__restrict__ segs, int32_t nwaves,
+                                                          const Segment *__restrict__ segs,
+                                                          const int32_t *__restrict__ qstart,
+                                                          unsigned *__restrict__ counters, int32_t parity,
                                                           int64_t iter)
 {
-    const int w = logical_wave();
-    if (w >= nwaves) return;
     constexpr int kRing = lds_ring_elems<2, T, 2>() > lds_ring_elems<3, T, 1>() ? lds_ring_elems<2, T, 2>()
                                                                                  : lds_ring_elems<3, T, 1>();
     __shared__ T ring[kWavesPerBlock * (kRing > 0 ? kRing : 1)];
     T *lds = ring + (threadIdx.x >> 6) * kRing;
-    const int s0 = wave_start[w], s1 = wave_start[w + 1];
-    for (int s = s0; s < s1; ++s) {
-        const Segment g = segs[s];
+    const int lane = threadIdx.x & (kWave - 1);
+    unsigned *ctr = counters + (parity & 1) * (kQueues * kQueueStride);
+    if (blockIdx.x == 0 && threadIdx.x < kQueues)
+        counters[((parity + 1) & 1) * (kQueues * kQueueStride) + threadIdx.x * kQueueStride] = 0u;
+    const int wpx = (int)(gridDim.x / kQueues) * kWavesPerBlock;  // waves per XCD (gridDim.x: a multiple of 8)
+    auto run = [&](int item) {
+        const Segment g = segs[item];
         const LatticeDesc &L = descs[g.lattice];
         switch (L.variant) {
         case V_ADV1: seg1d<0, T>(L, iter, g.col, g.y1); break;
@@ -1271,6 +1285,53 @@ __global__ __launch_bounds__(kBlock) void k_step_batched(const LatticeDesc *__re
         case V_REU2: seg2d_cpl<3, false, T>(L, iter, g, lds); break;
         default: break;
         }
+    };
+    int c = (int)(blockIdx.x & (kQueues - 1));
+    const int rank = (int)__builtin_amdgcn_readfirstlane((blockIdx.x / kQueues) * kWavesPerBlock +
+                                                         (threadIdx.x >> 6));
+    // the wave's first item (static), else -1; later items from the counters
+    int item = rank < qstart[c + 1] - qstart[c] ? qstart[c] + rank : -1;
+    // every failed take means another wave took an item, so the loop ends;
+    // the bound on failed takes in a row makes the end certain
+    for (int failed = 0; failed < 4096;) {
+        if (item < 0) {
+            const int lo = qstart[c], n = qstart[c + 1] - lo;
+            int i = n;  // (the first wpx items went to the waves' first takes)
+            if (wpx < n) {
+                unsigned got = 0u;
+                if (lane == 0) got = atomicAdd(&ctr[c * kQueueStride], 1u);
+                i = wpx + (int)__builtin_amdgcn_readfirstlane(got);
+            }
+            if (i < n) {
+                item = lo + i;
+            } else {
+                ++failed;
+                // queue c is empty: read every counter at once (lane q reads
+                // queue q) and go on with the queue that has the most items
+                // left; stop when none has any
+                int left = -1;
+                if (lane < kQueues) {
+                    const unsigned taken =
+                        __hip_atomic_load(&ctr[lane * kQueueStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const int nq = qstart[lane + 1] - qstart[lane];
+                    const long long next = (long long)wpx + (long long)taken;
+                    left = next < nq ? nq - (int)next : 0;
+                }
+                int key = left < 0 ? -1 : left * kQueues + (kQueues - 1 - lane);
+#pragma unroll
+                for (int o = 4; o > 0; o >>= 1) {
+                    const int other = __shfl_xor(key, o, kWave);
+                    key = other > key ? other : key;
+                }
+                key = (int)__builtin_amdgcn_readfirstlane((unsigned)key);
+                if (key < kQueues) break;  // no queue has items left
+                c = kQueues - 1 - key % kQueues;
+                continue;
+            }
+        }
+        failed = 0;
+        run(item);
+        item = -1;
     }
 }
 

@@ -34,22 +34,31 @@ import bench  # noqa: E402  (kernel source hash; bench imports no GPU module at 
 # 2D kernels end in the columns per lane (2 for advection and shallow water
 # on lattices of even nx) and the buffer-resource addressing flag (populations
 # below 4 GiB)
-KERNELS = {"euler2d_f32": "k_step_single<1, 2, false, float, 1, true>",
+KERNELS = {"euler2d_batched_f32": "k_step_batched<float>",
+           "euler2d_f32": "k_step_single<1, 2, false, float, 1, true>",
            "euler2d_f64": "k_step_single<1, 2, false, double, 1, true>",
+           "swe2d_batched_f32": "k_step_batched<float>",
            "swe2d_f32": "k_step_single<2, 2, true, float, 2, true>",
-           "euler3d_f32": "k3_collide<1, float>"}
+           "euler3d_f32": "k3_collide<1, float>",
+           "serving_fixed_f32": "k_step_batched<float>"}
 # further kernels of a step (3D: the indicator and relaxation passes)
 EXTRA_KERNELS = {"euler3d_f32": ["k3_nu<1, float>", "k3_omega<float>"]}
-WORKLOAD_NAMES = {"euler2d_f32": "euler2d_2048_f32", "euler2d_f64": "euler2d_2048_f64",
-                  "swe2d_f32": "swe2d_4096_f32", "euler3d_f32": "euler3d_256_f32"}
+WORKLOAD_NAMES = {"euler2d_batched_f32": "euler2d_2048_batched_f32", "euler2d_f32": "euler2d_2048_f32",
+                  "euler2d_f64": "euler2d_2048_f64", "swe2d_batched_f32": "swe2d_4096_batched_f32",
+                  "swe2d_f32": "swe2d_4096_f32", "euler3d_f32": "euler3d_256_f32",
+                  "serving_fixed_f32": "serving_fixed_f32"}
+
+
+FROM_RAW = False  # --from-raw: summarise the CSVs an earlier run left in --raw
 
 
 def rocprof(args, raw, tag, prog, timeout):
     out = os.path.join(raw, tag)
     cmd = ["rocprofv3", *args, "--output-format", "csv", "-d", out, "-o", "run", "--", sys.executable, "-u", *prog]
-    print("+", " ".join(cmd), flush=True)
-    with open(os.path.join(raw, tag + ".log"), "w") as log:
-        subprocess.run(cmd, cwd=ROOT, stdout=log, stderr=subprocess.STDOUT, timeout=timeout, check=True)
+    if not FROM_RAW:
+        print("+", " ".join(cmd), flush=True)
+        with open(os.path.join(raw, tag + ".log"), "w") as log:
+            subprocess.run(cmd, cwd=ROOT, stdout=log, stderr=subprocess.STDOUT, timeout=timeout, check=True)
     rel = os.path.relpath(out, ROOT)
     return out, " ".join(["rocprofv3", *args, "--output-format csv -d", rel, "-o run --", "python3 -u", *prog])
 
@@ -120,11 +129,17 @@ def serving_profile(args, raw):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=sorted(KERNELS) + ["serving"], default="euler2d_f32")
+    ap.add_argument("--workload", choices=sorted(KERNELS) + ["serving"], default="euler2d_batched_f32")
+    ap.add_argument("--no-calibration", action="store_true",
+                    help="reuse the copy calibration of profiles/euler2d_2048_batched_f32_pmc.json")
     ap.add_argument("--raw", default="gpurun_out/prof")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--profiles-dir", default=os.path.join(ROOT, "profiles"))
+    ap.add_argument("--from-raw", action="store_true",
+                    help="write the summaries from the CSVs of an earlier run in --raw (no profiling)")
     args = ap.parse_args()
+    global FROM_RAW
+    FROM_RAW = args.from_raw
     raw = os.path.abspath(args.raw)
     os.makedirs(raw, exist_ok=True)
     if args.workload == "serving":
@@ -147,11 +162,17 @@ def main():
     write_kib, nw = per_dispatch(os.path.join(d, "run_counter_collection.csv"), "WRITE_SIZE", kname)
     extra_write = {k: per_dispatch(os.path.join(d, "run_counter_collection.csv"), "WRITE_SIZE", k)[0]
                    for k in extra_names}
-    cal_prog = ["bench.py", "--copy-calibration"]
-    d, cmd_cf = rocprof(["--pmc", "FETCH_SIZE"], raw, "copy_fetch", cal_prog, 120)
-    copy_fetch_kib, _ = per_dispatch(os.path.join(d, "run_counter_collection.csv"), "FETCH_SIZE", "copyBuffer")
-    d, cmd_cw = rocprof(["--pmc", "WRITE_SIZE"], raw, "copy_write", cal_prog, 120)
-    copy_write_kib, _ = per_dispatch(os.path.join(d, "run_counter_collection.csv"), "WRITE_SIZE", "copyBuffer")
+    if args.no_calibration:
+        with open(os.path.join(os.path.abspath(args.profiles_dir), "euler2d_2048_batched_f32_pmc.json")) as f:  # noqa: E501
+            cal = json.load(f)
+        copy_fetch_kib, copy_write_kib = cal["copy_fetch_kib_for_1GiB"], cal["copy_write_kib_for_1GiB"]
+        cmd_cf, cmd_cw = cal["commands"][3], cal["commands"][4]
+    else:
+        cal_prog = ["bench.py", "--copy-calibration"]
+        d, cmd_cf = rocprof(["--pmc", "FETCH_SIZE"], raw, "copy_fetch", cal_prog, 120)
+        copy_fetch_kib, _ = per_dispatch(os.path.join(d, "run_counter_collection.csv"), "FETCH_SIZE", "copyBuffer")
+        d, cmd_cw = rocprof(["--pmc", "WRITE_SIZE"], raw, "copy_write", cal_prog, 120)
+        copy_write_kib, _ = per_dispatch(os.path.join(d, "run_counter_collection.csv"), "WRITE_SIZE", "copyBuffer")
     gib = float(1 << 30)
     read_scale = gib / (copy_fetch_kib * 1024.0)
     write_scale = gib / (copy_write_kib * 1024.0)

@@ -8,9 +8,16 @@ Configurations (seeded synthetic inputs, see workloads.py):
      full size 2048^2 checked on its first steps
   4  2D shallow water over a Gaussian-bump bed, dry outside a disc,
      reflective walls; oracle at 256^2, full size 4096^2 on its first step
-Tolerances: FP64 1e-12 relative (per component, L2); FP32 relative L1 over
-all components as stated per test.
+FP64 is compared bit for bit (the kernels keep the oracle's operation
+order).  FP32 is compared per field, by relative L1 and by the largest
+pointwise difference over the field's largest magnitude, against bounds
+measured at each configuration's own step count; and against the problem's
+own conditioning at that precision: how far the FP64 result moves when the
+initial data is rounded to FP32.  Long runs with shocks and wet/dry fronts
+amplify rounding: configuration 4's 2000 steps at 256^2 move FP64 by 7e-3
+under that rounding, and FP32 lands at 0.9x that.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -25,44 +32,58 @@ from helpers import ora_from, fsum
 
 pytestmark = pytest.mark.gpu
 
-# FP32 against the FP64 oracle, relative L1 over all components.  Config 2
-# states 1e-4 (measured at most 2.5e-5 over seeds 0-9).  The 2D bounds are
-# derived from the arithmetic: FP32 rounding (6e-8 relative per operation,
-# a few ulp for the hardware reciprocal and square root) is amplified at
-# shocks by a factor measured at about 1e3-1e4 in FP64 (rounding-order
-# perturbations of 1e-16 grow to 1e-13-1e-12 over 2000 steps); measured
-# values are 1.1e-4 (2D Euler, 1000 steps) and 1e-5 (shallow water, 500
-# steps), and the bounds leave a margin of about 3x.
-TOL_FP32 = {"c1": 1e-5, "c2": 1e-4, "c3": 3e-4, "c4": 3e-5}
+# FP32 against the FP64 oracle, per field: (relative L1, pointwise) bounds,
+# and the configuration's stated bound on the relative L1 over all fields
+# (configuration 2: 1e-4).  Measured at the configurations' own step counts:
+# c2 (seeds 0-9, 2000 steps) at most 1.4e-4 / 1.3e-3 per field, 2.5e-5 over
+# all fields; c3 at 256^2 (seeds 0 and 1, 1000 steps) 6.5e-4 / 2.3e-3; c4 at
+# 256^2 (2000 steps) 6.7e-3 / 1.9e-2, its volume kept to 5e-8.  The bounds
+# keep a margin of about 3x.  FP32 rounding (6e-8 per operation, a few ulp
+# for the hardware reciprocal and root) is amplified at shocks and fronts:
+# on the 2D data the FP32 error is within 0.6-31x of the FP64 result's own
+# movement under FP32 rounding of the initial data (second check, bound
+# 100x).
+TOL_FP32 = {"c1": (1e-5, 1e-4), "c2": (5e-4, 5e-3), "c3": (2e-3, 7e-3), "c4": (2e-2, 6e-2)}
+TOL_FP32_ALL = {"c2": 1e-4}
 
 
-def _compare(p, steps, tag, fp32_tol):
-    Lo = oracle_run(p, steps)
+def _compare(p, steps, tag, tol):
+    Lo = oracle_run(p, steps, parallel=True)
     Uo = Lo.moments()
     G = gpu_lattice(p, A.F64)
     G.step(steps)
     st = G.sync()
     U64 = G.moments()
-    e64 = rel_l2_per_comp(U64, Uo)
     G.close()
     G = gpu_lattice(p, A.F32)
     G.step(steps)
     G.sync()
     U32 = G.moments()
-    e32 = rel_l1(U32, Uo)
     G.close()
-    say(f"[{tag}] steps={steps} fp64 rel L2 per field {e64} bitwise={np.array_equal(U64, Uo)} "
-        f"fp32 rel L1 {e32:.3e} t={st['t']:.6g} oracle t={Lo.t:.6g}")
-    assert max(e64) <= 1e-12, e64
-    assert e32 <= fp32_tol, e32
-    assert st["t"] == pytest.approx(Lo.t, rel=1e-14)
-    return U64, Uo
+    pr = dataclasses.replace(p, U0=p.U0.astype(np.float32).astype(np.float64),
+                             bed=None if p.bed is None else p.bed.astype(np.float32).astype(np.float64))
+    G = gpu_lattice(pr, A.F64)
+    G.step(steps)
+    cond = rel_l1_per_comp(G.moments(), U64)
+    G.close()
+    e1, em, eall = rel_l1_per_comp(U32, Uo), rel_max_per_comp(U32, Uo), rel_l1(U32, Uo)
+    say(f"[{tag}] steps={steps} fp64 bitwise={np.array_equal(U64, Uo)} t={st['t']:.6g} oracle t={Lo.t:.6g}; "
+        f"fp32 rel L1 per field {e1} pointwise {em} all fields {eall:.3e}; FP64 moved by FP32 input rounding {cond}")
+    assert np.array_equal(U64, Uo)
+    assert st["t"] == Lo.t
+    assert max(e1) <= tol[0], e1
+    assert max(em) <= tol[1], em
+    # (1D Riemann data is two constant states, which FP32 rounding moves by
+    # far less than the FP32 arithmetic does, so this check is for 2D data)
+    if p.dim == 2:
+        assert all(a <= max(100 * c, 1e-6) for a, c in zip(e1, cond)), (e1, cond)
+    return U64, Uo, U32
 
 
 def test_config1_advection_full():
     require_gpu()
     p = W.advection_sine(n=256, cfl=0.5, steps=512)
-    U64, Uo = _compare(p, 512, "c1", TOL_FP32["c1"])
+    U64, Uo, _ = _compare(p, 512, "c1", TOL_FP32["c1"])
     x = W.centres(256, 0.0, 1.0)
     ex = np.sin(2 * np.pi * (x - 1.0))
     err = math.sqrt(np.sum((U64[0] - ex) ** 2) / np.sum(ex ** 2))
@@ -74,20 +95,28 @@ def test_config1_advection_full():
 def test_config2_euler1d_full(seed):
     require_gpu()
     p = W.euler_seeded_1d(seed, n=4096, steps=2000)
-    _compare(p, 2000, f"c2 seed {seed}", TOL_FP32["c2"])
+    _, Uo, U32 = _compare(p, 2000, f"c2 seed {seed}", TOL_FP32["c2"])
+    assert rel_l1(U32, Uo) <= TOL_FP32_ALL["c2"]
 
 
 @pytest.mark.parametrize("seed", [0, 1])
 def test_config3_euler2d_256(seed):
+    """Configuration 3's data at 256^2 for its full 1000 steps."""
     require_gpu()
     p = W.euler_seeded_2d(seed, n=256, steps=1000)
-    _compare(p, 1000 if seed == 0 else 300, f"c3 256^2 seed {seed}", TOL_FP32["c3"])
+    _compare(p, 1000, f"c3 256^2 seed {seed}", TOL_FP32["c3"])
 
 
 def test_config4_swe_bed_256():
+    """Configuration 4's data at 256^2 for its full 2000 steps: wet/dry
+    fronts over the bed; the water volume is kept (reflective walls)."""
     require_gpu()
-    p = W.swe_bed_2d(0, n=256, steps=500)
-    _compare(p, 500, "c4 256^2", TOL_FP32["c4"])
+    p = W.swe_bed_2d(0, n=256, steps=2000)
+    _, _, U32 = _compare(p, 2000, "c4 256^2", TOL_FP32["c4"])
+    v0 = fsum(p.U0[0])
+    drift = (fsum(U32[0]) - v0) / v0
+    say(f"[c4 256^2] FP32 volume drift {drift:.2e}")
+    assert abs(drift) <= 1e-6
 
 
 def test_config3_full_size_first_steps():
@@ -349,12 +378,12 @@ def test_serving_fp64_matches_oracle_and_fp32_is_close():
     r64, _ = _serve(probs, 1 << 30, precision=A.F64)
     r32, _ = _serve(probs, 1 << 30, precision=A.F32)
     for p, a, b in zip(probs, r64, r32):
-        Uo = oracle_run(p, p.steps).moments().ravel()
-        e64 = max(rel_l2_per_comp(a["U"].reshape(1, -1), Uo.reshape(1, -1)))
-        e32 = rel_l1(b["U"], Uo)
-        say(f"[serving] {p.name}: batched FP64 vs oracle {e64:.2e}, batched FP32 vs oracle {e32:.2e}")
-        assert e64 <= 1e-12
-        assert e32 <= 1e-4
+        Uo = oracle_run(p, p.steps).moments()
+        e32 = rel_l1_per_comp(b["U"].reshape(Uo.shape), Uo)
+        say(f"[serving] {p.name}: batched FP64 bitwise with the oracle "
+            f"{np.array_equal(a['U'].reshape(Uo.shape), Uo)}, batched FP32 vs oracle per field {e32}")
+        assert np.array_equal(a["U"].reshape(Uo.shape), Uo)
+        assert max(e32) <= 1e-4
 
 
 def test_serving_budget_admission():
@@ -486,3 +515,54 @@ def test_serving_resume_rejects_mismatched_blob():
     assert e.value.code == A.EINVAL
     srv.close()
     srv64.close()
+
+
+# Served FP32 requests at the serving mix's own lengths (500-5000 steps)
+# against the FP64 plain path on the same inputs: per field (relative L1,
+# pointwise) bounds, measured values x3, and the FP64 result's own movement
+# under FP32 rounding of the initial data, which the FP32 error stays within
+# a small factor of wherever that movement is not negligible.  Shallow water
+# over a dry bed with reflective walls sloshes for thousands of steps with
+# wet/dry fronts: after 5000 steps FP64 itself moves by 7e-3 (relative L1)
+# under that rounding and FP32 lands at about 3x that (2.5e-2, pointwise
+# 0.19 at the fronts).
+SERVED_CASES = [
+    ("euler2d 256^2 2000 steps", lambda: W.euler_seeded_2d(3, n=256, steps=2000), (1e-3, 5e-3)),
+    ("swe 256^2 2000 steps", lambda: W.swe_bed_2d(4, n=256, steps=2000), (6e-3, 1.5e-2)),
+    ("swe 256^2 5000 steps", lambda: W.swe_bed_2d(5, n=256, steps=5000), (8e-2, 0.6)),
+    ("euler1d 65536 5000 steps", lambda: W.euler_seeded_1d(5, n=65536, steps=5000), (5e-5, 2e-2)),
+]
+
+
+def test_served_requests_at_full_length_against_fp64():
+    require_gpu()
+    probs = [(name, make(), tol) for name, make, tol in SERVED_CASES]
+    srv = A.Server(1 << 30, A.F32)
+    ids = [srv.submit(A.config_from(p, precision=A.F32), p.U0, p.bed, p.steps) for _, p, _ in probs]
+    res = {}
+    while len(res) < len(ids):
+        srv.iterate(16)
+        for c in srv.poll(16):
+            res[c["id"]] = c
+    srv.close()
+    for (name, p, tol), i in zip(probs, ids):
+        r = res[i]
+        assert r["status"] == 0 and r["steps"] == p.steps, name
+        G = gpu_lattice(p, A.F64)
+        G.step(p.steps)
+        U64 = G.moments()
+        G.close()
+        pr = dataclasses.replace(p, U0=p.U0.astype(np.float32).astype(np.float64),
+                                 bed=None if p.bed is None else p.bed.astype(np.float32).astype(np.float64))
+        G = gpu_lattice(pr, A.F64)
+        G.step(p.steps)
+        cond = rel_l1_per_comp(G.moments(), U64)
+        G.close()
+        U32 = r["U"].reshape(U64.shape)
+        e1, em = rel_l1_per_comp(U32, U64), rel_max_per_comp(U32, U64)
+        say(f"[served {name}] FP32 batched vs FP64 plain: rel L1 per field {e1}, pointwise {em}; "
+            f"FP64 moved by FP32 input rounding {cond}; flags {r['flags']}")
+        assert max(e1) <= tol[0], e1
+        assert max(em) <= tol[1], em
+        if p.dim == 2:
+            assert all(a <= 10 * c for a, c in zip(e1, cond)), (e1, cond)

@@ -1,8 +1,10 @@
 """GPU parity: the HIP library against the FP64 CPU oracle (MI355X only).
 
 FP64 path: the kernels are compiled without contraction and keep the
-oracle's operation order, so the bound is 1e-12 relative (the results are
-expected to agree to the last bit); FP32 path: per-configuration tolerances.
+oracle's operation order, so the results agree to the last bit and are
+compared bit for bit.  FP32 path: per field, relative L1 and the largest
+pointwise difference over the field's largest magnitude (a local error at a
+wall or a front cannot hide in the norm), bounds below.
 """
 import numpy as np
 import pytest
@@ -10,11 +12,17 @@ import pytest
 import oracle as O
 from paper_2609_18177_amd import arlbm as A
 from paper_2609_18177_amd import workloads as W
-from gpu_common import require_gpu, say, gpu_lattice, rel_l2_per_comp, rel_l1, oracle_run
+from gpu_common import (require_gpu, say, gpu_lattice, rel_l2_per_comp, oracle_run, rel_l1_per_comp,
+                        rel_max_per_comp)
 
 pytestmark = pytest.mark.gpu
 
 T, R, P = W.TRANSMISSIVE, W.REFLECTIVE, W.PERIODIC
+
+# FP32 against the oracle after 60 steps of these cases, per field: measured
+# at most 1.1e-5 relative L1 and 6.1e-5 pointwise (the shallow-water cases
+# with a wet/dry edge); the bounds keep a margin of about 8x.
+TOL_FP32_L1, TOL_FP32_MAX = 1e-4, 5e-4
 
 
 def small_problem(kind, bcs, n=(131, 45)):
@@ -77,13 +85,13 @@ def test_first_step_fields_fp64(kind, bcs):
     Ug, Uo = G.moments(), Lo.moments()
     err = rel_l2_per_comp(Ug, Uo)
     say("  U1 rel err", err, "bitwise", bool(np.array_equal(Ug, Uo)))
-    assert max(err) <= 1e-14
+    assert np.array_equal(Ug, Uo)
     wg, wo = G.omega(), Lo.last_omega()
     say("  omega max abs diff", float(np.abs(wg - wo).max()))
-    assert np.abs(wg - wo).max() <= 1e-14
-    assert st["t"] == pytest.approx(Lo.t, rel=1e-15)
+    assert np.array_equal(wg, wo)
+    assert st["t"] == Lo.t
     ab = Lo.alpha_bar()
-    np.testing.assert_allclose(st["abar"], ab, rtol=1e-15)
+    assert list(st["abar"]) == list(ab)
     G.close()
 
 
@@ -99,8 +107,8 @@ def test_multi_step_parity_fp64(kind, bcs):
     Ug, Uo = G.moments(), Lo.moments()
     err = rel_l2_per_comp(Ug, Uo)
     say("  U60 rel err", err, "bitwise", bool(np.array_equal(Ug, Uo)), "t", st["t"], Lo.t)
-    assert max(err) <= 1e-12
-    assert st["t"] == pytest.approx(Lo.t, rel=1e-14)
+    assert np.array_equal(Ug, Uo)
+    assert st["t"] == Lo.t
     G.close()
 
 
@@ -114,7 +122,8 @@ def test_multi_step_parity_fp32(kind, bcs):
     G.step(60)
     G.sync()
     Ug, Uo = G.moments(), Lo.moments()
-    e = rel_l1(Ug, Uo)
-    say("  fp32 rel L1", e)
-    assert e <= 1e-4
+    e1, em = rel_l1_per_comp(Ug, Uo), rel_max_per_comp(Ug, Uo)
+    say("  fp32 rel L1 per field", e1, "pointwise", em)
+    assert max(e1) <= TOL_FP32_L1, e1
+    assert max(em) <= TOL_FP32_MAX, em
     G.close()

@@ -54,7 +54,8 @@ def test_profiles_match_kernel_sources():
     sys.path.insert(0, ROOT)
     import bench
     h = bench.kernel_source_hash()
-    for name in ("euler2d_2048_f32", "euler2d_2048_f64", "swe2d_4096_f32", "euler3d_256_f32"):
+    for name in ("euler2d_2048_batched_f32", "euler2d_2048_f32", "euler2d_2048_f64", "swe2d_4096_batched_f32",
+                 "swe2d_4096_f32", "euler3d_256_f32", "serving_fixed_f32"):
         with open(os.path.join(ROOT, "profiles", f"{name}_pmc.json")) as f:
             rec = json.load(f)
         assert rec["kernel_source_sha256_16"] == h, name

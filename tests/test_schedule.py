@@ -1,8 +1,10 @@
-"""The batched launch's static schedule (host logic, no GPU): every cell of
-every served 1D and 2D lattice is stepped by exactly one segment, the
-schedule fits the waves it is given, a lattice alone gets the single-lattice
-kernel's decomposition (one band of one strip per wave, bands of equal
-height), and the work per wave is balanced."""
+"""The batched launch's work list (host logic, no GPU): every cell of every
+served 1D and 2D lattice is stepped by exactly one item; a lattice alone
+gets the single-lattice kernel's bands (one band of one strip per wave);
+the list fits one round of the launch's waves where the work allows; it holds each
+lattice's bands in order with each band's strips left to right; its eight
+per-XCD queues carry about equal work; the items that end it are the
+smallest."""
 import numpy as np
 import pytest
 
@@ -21,17 +23,18 @@ def _strips(cfg):
 
 
 def _cost(cfg, seg):
-    """The cost model the header describes: rows + 6 (2D) or strips + 2 (1D),
-    times the values a wave moves per row or strip."""
+    """The cost model the runtime describes: rows + 6 (2D) or strips + 2
+    (1D), times the values a wave moves per row or strip."""
     ncols, cpl = _strips(cfg)
+    seg = [int(v) for v in seg]
     m = {A.ADVECTION: 1, A.EULER: cfg.dim + 2, A.SWE: cfg.dim + 1, A.REACTIVE: cfg.dim + 3}[cfg.system]
     if cfg.dim == 2:
         return (seg[3] - seg[2] + 6) * 64 * cpl * 5 * m
     return (seg[3] - seg[1] + 2) * (64 * 3 * m + 1280)
 
 
-def _check_cover(cfgs, ws, segs):
-    assert ws[0] == 0 and np.all(np.diff(ws) >= 1) and ws[-1] == len(segs)
+def _check_cover(cfgs, qs, segs):
+    assert qs[0] == 0 and qs[-1] == len(segs) and np.all(np.diff(qs) >= 0)
     for i, cfg in enumerate(cfgs):
         if cfg.dim == 3:
             assert not np.any(segs[:, 0] == i)
@@ -43,6 +46,11 @@ def _check_cover(cfgs, ws, segs):
             for _, c, y0, y1 in mine:
                 assert 0 <= c < ncols and 0 <= y0 < y1 <= cfg.ny
                 hits[c, y0:y1] += 1
+            # bands in order, each band's strips left to right, one height
+            keys = [(y0, c) for _, c, y0, _ in mine]
+            assert keys == sorted(keys)
+            h = mine[0, 3] - mine[0, 2]
+            assert np.all(mine[:, 3] - mine[:, 2] <= h)
         else:
             hits = np.zeros(ncols, dtype=np.int32)
             for _, c0, _, c1 in mine:
@@ -54,45 +62,63 @@ def _check_cover(cfgs, ws, segs):
 def test_lattice_alone_gets_the_single_kernel_bands():
     p = W.euler_seeded_2d(0, n=2048, steps=1)
     cfg = A.config_from(p, precision=A.F32)
-    ws, segs = A.plan_schedule([cfg], WAVES)
-    _check_cover([cfg], ws, segs)
+    qs, segs, nw = A.plan_schedule([cfg], WAVES)
+    _check_cover([cfg], qs, segs)
     # 36 strips of 58 columns; 28 bands of 74 rows (the last one 50): one
-    # segment per wave, consecutive waves on neighbouring strips of a band
-    assert len(ws) - 1 == 28 * 36 and len(segs) == 28 * 36
+    # item per wave
+    assert len(segs) == 28 * 36 and nw == len(segs)
     assert np.all(segs[:36, 2] == 0) and np.array_equal(segs[:36, 1], np.arange(36))
     heights = segs[:, 3] - segs[:, 2]
     assert heights.max() == 74 and set(heights.tolist()) <= {74, 2048 - 27 * 74}
 
 
-@pytest.mark.parametrize("precision", [A.F32, A.F64])
-def test_serving_mix_is_covered_and_balanced(precision):
-    reqs = W.serving_requests(60, rate_hz=200.0, seed=3)
+def test_shallow_water_alone_gets_tall_bands():
+    """4096^2 shallow water with two columns per lane: 35 strips of 120
+    columns, 29 bands of 142 rows, one round."""
+    p = W.swe_bed_2d(0, n=4096, steps=1)
+    cfg = A.config_from(p, precision=A.F32)
+    qs, segs, nw = A.plan_schedule([cfg], WAVES)
+    _check_cover([cfg], qs, segs)
+    assert len(segs) == 35 * 29 <= WAVES
+    assert (segs[:, 3] - segs[:, 2]).max() == 142
+
+
+def _queues_balanced(cfgs, qs, segs, tol):
+    work = [sum(_cost(cfgs[s[0]], s) for s in segs[qs[q]:qs[q + 1]]) for q in range(8)]
+    mean = sum(work) / 8
+    assert max(work) <= (1 + tol) * mean and min(work) >= (1 - tol) * mean, [w / mean for w in work]
+
+
+@pytest.mark.parametrize("n,precision", [(60, A.F32), (60, A.F64), (512, A.F32)])
+def test_serving_mix_rounds_and_queues(n, precision):
+    reqs = W.serving_requests(n, rate_hz=200.0, seed=0)
     cfgs = [A.config_from(r.problem(), precision=precision) for r in reqs]
-    ws, segs = A.plan_schedule(cfgs, WAVES)
-    nw = len(ws) - 1
-    assert nw <= WAVES
-    _check_cover(cfgs, ws, segs)
-    cost = np.array([sum(_cost(cfgs[s[0]], s) for s in segs[ws[w]:ws[w + 1]]) for w in range(nw)])
-    total = sum(_cost(c, s) for c, s in ((cfgs[s[0]], s) for s in segs))
-    # a wave's work stays near the mean over all the waves the GPU has: the
-    # launch takes about as long as its longest wave
-    assert cost.max() <= 1.5 * total / WAVES, (cost.max(), total / WAVES)
+    qs, segs, nw = A.plan_schedule(cfgs, WAVES)
+    assert nw == min(WAVES, len(segs))
+    _check_cover(cfgs, qs, segs)
+    two_d = segs[np.array([cfgs[i].dim == 2 for i in segs[:, 0]])]
+    rows = two_d[:, 3] - two_d[:, 2]
+    # the 2D items: at most 256 rows, one round of the waves where the work
+    # allows it, tallest first; 1D runs after them
+    assert rows.max() <= 256
+    strip_rows = sum(_strips(c)[0] * c.ny for c in cfgs if c.dim == 2)
+    rounds = -(-strip_rows // (WAVES * 256))
+    if rounds == 1:
+        assert len(two_d) <= WAVES or rows.max() >= strip_rows // (2 * WAVES)
+    first_1d = np.argmax([cfgs[i].dim == 1 for i in segs[:, 0]])
+    assert all(cfgs[i].dim == 1 for i in segs[first_1d:, 0])
+    heights = [max(s[3] - s[2] for s in two_d[two_d[:, 0] == i]) for i in dict.fromkeys(two_d[:, 0])]
+    assert heights == sorted(heights, reverse=True)
+    _queues_balanced(cfgs, qs, segs, 0.05)
 
 
-def test_small_mix_spreads_and_3d_is_left_out():
-    """Far less work than the GPU holds: every 1D strip gets a wave of its
-    own and 2D bands are cut down to 8 rows, as the single-lattice kernel
-    spreads a small lattice, so the step takes as little time as it can."""
+def test_small_mix_and_3d_left_out():
     cfgs = [A.config_from(W.euler_seeded_1d(0, n=3000), precision=A.F32),
             A.config_from(W.swe_bed_2d(1, n=40), precision=A.F32),
             A.config_from(W.euler_octants_3d(seed=0, n=12), precision=A.F32)]
-    ws, segs = A.plan_schedule(cfgs, WAVES)
-    _check_cover(cfgs, ws, segs)
-    one_d = segs[segs[:, 0] == 0]
-    assert np.all(one_d[:, 3] - one_d[:, 1] == 1) and len(one_d) == (3000 + 57) // 58
-    two_d = segs[segs[:, 0] == 1]
-    assert np.all(two_d[:, 3] - two_d[:, 2] == 8)
-    assert len(ws) - 1 == len(segs)
+    qs, segs, nw = A.plan_schedule(cfgs, WAVES)
+    _check_cover(cfgs, qs, segs)
+    assert nw == len(segs)
 
 
 def test_plan_rejects_bad_input():
