@@ -53,7 +53,7 @@ ONLY = ["euler2d_batched_f32", "euler2d_f32", "euler2d_f64", "swe2d_batched_f32"
 # FP32-vs-FP64 bounds per served system (relative L1 over all fields of a
 # request's result): see the serving section of the design doc for the measured
 # values and the conditioning they rest on
-SERVED_FP32_TOL = {"euler1d": 1e-3, "euler2d": 3e-3, "swe2d": 1e-1}
+SERVED_FP32_TOL = {"euler1d": 5e-3, "euler2d": 2e-3, "swe2d": 1.5e-1}
 
 
 def alg_bytes_per_lup(p, size):

@@ -110,32 +110,26 @@ std::string check_config(const arlbm_config *c)
 //        Euler 0.1758 -> 0.1777, reactive Euler 0.290 -> 0.298;
 //   FP64 shallow water 1.177 -> 1.140, Euler 0.388 -> 0.430.
 // The faster width is taken per system and precision.
-#ifndef ARLBM_CPL_OVERRIDE
-#define ARLBM_CPL_OVERRIDE 0
-#endif
 int columns_per_lane(const arlbm_config *c)
 {
     if (c->dim != 2 || c->nx % 2 != 0) return 1;
-    if (ARLBM_CPL_OVERRIDE) return ARLBM_CPL_OVERRIDE;
     static const int f32[4] = {2, 1, 2, 1}, f64[4] = {1, 1, 2, 1};  // advection, Euler, shallow water, reactive
     return (c->precision == ARLBM_F64 ? f64 : f32)[c->system];
 }
 
 // Planes are stored at a stride of nx*ny rounded up to a multiple of 64
-// elements (every plane starts 256-byte aligned) plus ARLBM_PLANE_PAD
+// elements (every plane starts 256-byte aligned) plus kPlanePad
 // elements, so that the planes of a power-of-two lattice do not all start at
 // the same offset of the memory interleave: the step reads and writes row j
 // of all Q m planes together.  Measured (ms per step, pad 0 / 64 / 256 /
 // 1088 elements): 2048^2 Euler FP32 0.173 / 0.166 / 0.184 / 0.167, 4096^2
 // shallow water FP32 0.486 / 0.465 / 0.463 / 0.460, FP64 0.903 / 0.903 /
 // 0.894 / 0.883, 256^3 Euler FP32 1.72 / 1.70 / 1.76 / 1.70.
-#ifndef ARLBM_PLANE_PAD
-#define ARLBM_PLANE_PAD 1088
-#endif
+constexpr int64_t kPlanePad = 1088;
 int64_t plane_stride(const arlbm_config *c)
 {
     const int64_t plane = c->nx * c->ny * c->nz;
-    return (plane + 63) / 64 * 64 + ARLBM_PLANE_PAD;
+    return (plane + 63) / 64 * 64 + kPlanePad;
 }
 
 void fill_sizes(const arlbm_config *c, arlbm_sizes *o)
@@ -166,18 +160,10 @@ void fill_sizes(const arlbm_config *c, arlbm_sizes *o)
 // with twice the rows beats two waves per SIMD by 15-25% for both FP32 and
 // FP64 (fewer concurrent streams into HBM, half the warm-up rows), and never
 // more than the waves the GPU can hold at once.
-#ifndef ARLBM_BAND_WAVE_SCALE
-#define ARLBM_BAND_WAVE_SCALE 1.0
-#endif
-#ifndef ARLBM_WAVES_PER_SIMD
-#define ARLBM_WAVES_PER_SIMD 1
-#endif
 int choose_band(int64_t ny, int ncols, int64_t resident_waves, int64_t simds)
 {
     if (resident_waves <= 0) resident_waves = 4096;
-    resident_waves = (int64_t)(resident_waves * ARLBM_BAND_WAVE_SCALE);
-    if (ARLBM_WAVES_PER_SIMD > 0 && simds * ARLBM_WAVES_PER_SIMD < resident_waves)
-        resident_waves = simds * ARLBM_WAVES_PER_SIMD;
+    if (simds < resident_waves) resident_waves = simds;  // one wave per SIMD
     int64_t nb = resident_waves / ncols;
     if (nb < 1) nb = 1;
     int64_t h = (ny + nb - 1) / nb;
@@ -438,10 +424,7 @@ extern "C" int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, 
     d.cpl = columns_per_lane(cfg);
     // buffer-resource addressing: every plane offset and cell offset of the
     // population buffer in 32 bits
-#ifndef ARLBM_BUF_MAX_BYTES
-#define ARLBM_BUF_MAX_BYTES 0xffffffffull
-#endif
-    d.buf = cfg->dim == 2 && h->sz.f_bytes <= ARLBM_BUF_MAX_BYTES ? 1 : 0;
+    d.buf = cfg->dim == 2 && h->sz.f_bytes <= 0xffffffffull ? 1 : 0;
     d.ncols = (int32_t)((cfg->nx + strip_out_w(d.cpl) - 1) / strip_out_w(d.cpl));
     // copies of each wave-speed slot: a 1D step launches one wave per strip,
     // and about 8 waves per copy keep its atomics from queueing while its
@@ -1099,8 +1082,10 @@ bool own_launch(const LatticeDesc &d) { return d.variant >= V_ADV3 || (d.variant
 // single-lattice kernel's bands, one per wave (2048^2 Euler: 28 bands of 74
 // rows of its 36 strips); a large mix gets about r items per wave, which
 // the queue balances.  2D lattices come first, those with the tallest items
-// first, and 1D runs (of about one 2D item's work each) last, so the items
-// that end the launch are the smallest.  Cost model, in population values a
+// first, and 1D runs last, so the items that end the launch are the
+// smallest; a run is as short as spreads the 1D strips over the waves the 2D
+// items leave free (a 1D lattice alone: about one strip per wave, as in the
+// single-lattice kernel) and at most about one 2D item's work.  Cost model, in population values a
 // wave moves: a 2D item of h rows costs (h + 6) rows of 64 V lanes by Q m
 // values (the march reads 3 rows of moments beyond each end and collides one
 // row beyond each end); a 1D strip costs 64 Q m values plus a latency share
@@ -1175,10 +1160,18 @@ int64_t build_schedule(const std::vector<SchedLattice> &lats, int64_t W, std::ve
             }
         }
     }
+    // 1D runs: spread over the waves the 2D items leave in the first round
+    // (at least an eighth of them), but no longer than about one 2D item's
+    // work
+    int64_t strips1d = 0;
+    for (const SchedLattice &l : lats)
+        if (l.one_d) strips1d += l.ncols;
+    const int64_t free_waves = std::max<int64_t>(W - (int64_t)segs.size(), std::max<int64_t>(1, W / 8));
+    const int64_t spread = (strips1d + free_waves - 1) / free_waves;
     for (const SchedLattice &l : lats) {
         if (!l.one_d) continue;
-        // runs of about one 2D item's work
-        const int64_t per = std::max<int64_t>(1, (h + kWarmRows2d) * kRowValues / l.unit - kWarmStrips1d);
+        const int64_t cap = std::max<int64_t>(1, (h + kWarmRows2d) * kRowValues / l.unit - kWarmStrips1d);
+        const int64_t per = std::max<int64_t>(1, std::min(spread, cap));
         for (int64_t c = 0; c < l.ncols; c += per) {
             const int64_t e = std::min<int64_t>(l.ncols, c + per);
             segs.push_back({l.lattice, (int32_t)c, 0, (int32_t)e});

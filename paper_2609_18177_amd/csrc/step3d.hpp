@@ -77,15 +77,7 @@ __device__ __forceinline__ Slab slab_of(int64_t total)
 // collide and relaxation passes at 256 x 4, the indicator at 128 x 8 / 64 x
 // 16: 1.645 / 1.638 (FP64 3.264 / 3.236); the relaxation no better at 128 or
 // 64 wide.
-#ifndef ARLBM_3D_TX
-#define ARLBM_3D_TX 256
-#endif
-#ifndef ARLBM_3D_NU_TX
-#define ARLBM_3D_NU_TX 64
-#endif
-#ifndef ARLBM_3D_OM_TX
-#define ARLBM_3D_OM_TX ARLBM_3D_TX
-#endif
+constexpr int kTileW = 256, kTileWNu = 64, kTileWOmega = 256;  // tile widths: collide, indicator, relaxation
 constexpr int kTileShift = 10;
 template <int TX>
 struct Tiling {
@@ -148,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k3_nu(LatticeDesc L, int64_t iter)
     T *nu_out = (T *)L.nu3;
     const int px = L.nx + 2, py = L.ny + 2;
     const int64_t npad = (int64_t)px * py * (L.nz + 2);
-    const auto tl = tiling_of<ARLBM_3D_NU_TX>(px, py, L.nz + 2);
+    const auto tl = tiling_of<kTileWNu>(px, py, L.nz + 2);
     const Slab sl = slab_of(tl.total);
     for (int64_t g = sl.first; g < sl.end; g += sl.step) {
         int i, j, l;
@@ -201,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void k3_omega(LatticeDesc L, int64_t iter)
     const int64_t npad = (int64_t)(L.nx + 2) * (L.ny + 2) * (L.nz + 2);
     T *w_out = (T *)L.nu3 + npad;
     const T wfix = T(L.omega_fixed);
-    const auto tl = tiling_of<ARLBM_3D_OM_TX>(L.nx, L.ny, L.nz);
+    const auto tl = tiling_of<kTileWOmega>(L.nx, L.ny, L.nz);
     const Slab sl = slab_of(tl.total);
     for (int64_t g = sl.first; g < sl.end; g += sl.step) {
         int i, j, l;
@@ -258,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k3_collide(LatticeDesc L, int64_t iter
     unsigned flags = 0;
     // every lane of a wave runs the same number of iterations (the reduction
     // below needs the whole wave)
-    const auto tl = tiling_of<ARLBM_3D_TX>(L.nx, L.ny, L.nz);
+    const auto tl = tiling_of<kTileW>(L.nx, L.ny, L.nz);
     const Slab sl = slab_of(tl.total);
     for (int64_t g = sl.first; g < sl.lim; g += sl.step) {
         int i = 0, j = 0, l = 0;

@@ -113,12 +113,27 @@ def test_serving_mix_rounds_and_queues(n, precision):
 
 
 def test_small_mix_and_3d_left_out():
+    """Far less work than the waves: every 1D strip an item of its own, 2D
+    bands of 8 rows, as the single-lattice kernel spreads a small lattice."""
     cfgs = [A.config_from(W.euler_seeded_1d(0, n=3000), precision=A.F32),
             A.config_from(W.swe_bed_2d(1, n=40), precision=A.F32),
             A.config_from(W.euler_octants_3d(seed=0, n=12), precision=A.F32)]
     qs, segs, nw = A.plan_schedule(cfgs, WAVES)
     _check_cover(cfgs, qs, segs)
     assert nw == len(segs)
+    one_d = segs[segs[:, 0] == 0]
+    assert np.all(one_d[:, 3] - one_d[:, 1] == 1)
+    assert np.all(segs[segs[:, 0] == 1][:, 3] - segs[segs[:, 0] == 1][:, 2] == 8)
+
+
+def test_1d_lattices_alone_spread_over_the_waves():
+    """Only 1D lattices (no 2D work to size items from): runs short enough
+    that the strips fill the waves in one round."""
+    cfgs = [A.config_from(W.euler_seeded_1d(s, n=65536), precision=A.F32) for s in range(3)]
+    qs, segs, nw = A.plan_schedule(cfgs, WAVES)
+    _check_cover(cfgs, qs, segs)
+    strips = 3 * ((65536 + 57) // 58)
+    assert len(segs) <= WAVES and np.max(segs[:, 3] - segs[:, 1]) <= -(-strips // WAVES)
 
 
 def test_plan_rejects_bad_input():
