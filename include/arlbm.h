@@ -197,6 +197,19 @@ int arlbm_read_omega(arlbm_lattice *h, double *omega_out);
  * (Neumaier) summation in a fixed order, so repeated calls agree bitwise. */
 int arlbm_conservation(arlbm_lattice *h, double *sums_out);
 
+/* arlbm_conservation without any device allocation, for callers that
+ * cannot allocate (a serving loop or harness that forbids hipMalloc, work
+ * recorded while no allocation may happen): the per-block partial sums live
+ * in a device array of the library, 256 blocks x 6 fields of doubles
+ * (12 KiB), one copy per GPU, held until the process ends, instead of a
+ * buffer the lattice allocates on its first request.  Same sums, bit for
+ * bit.  The array is shared by every call on a GPU and keeps the last
+ * call's contents (every call overwrites what it reads): calls that overlap
+ * on one GPU (several streams or threads at once) race.  EINVAL for a
+ * lattice of more than 6 fields (none of the systems has more); EDEVICE if
+ * the array's address cannot be had. */
+int arlbm_conservation_noalloc(arlbm_lattice *h, double *sums_out);
+
 /* Checkpoint: the state is the f planes, the moment planes, the device
  * scalars and the step count.  state_bytes gives the size of the blob. */
 int arlbm_state_bytes(arlbm_lattice *h, size_t *bytes);

@@ -96,6 +96,7 @@ def lib():
             "arlbm_set_omega_export": ([vp, C.c_int], C.c_int),
             "arlbm_read_omega": ([vp, dp], C.c_int),
             "arlbm_conservation": ([vp, dp], C.c_int),
+            "arlbm_conservation_noalloc": ([vp, dp], C.c_int),
             "arlbm_state_bytes": ([vp, C.POINTER(C.c_size_t)], C.c_int),
             "arlbm_save_state": ([vp, vp, C.c_size_t], C.c_int),
             "arlbm_load_state": ([vp, vp, C.c_size_t], C.c_int),
@@ -270,6 +271,12 @@ class Lattice:
     def conservation(self) -> np.ndarray:
         out = np.empty(self.m)
         _check(lib().arlbm_conservation(self._h, _dptr(out)), self._h)
+        return out
+
+    def conservation_noalloc(self) -> np.ndarray:
+        """arlbm_conservation with the library's device scratch array."""
+        out = np.empty(self.m)
+        _check(lib().arlbm_conservation_noalloc(self._h, _dptr(out)), self._h)
         return out
 
     def save_state(self) -> bytes:

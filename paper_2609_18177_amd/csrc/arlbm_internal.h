@@ -95,6 +95,11 @@ struct Segment {
     int32_t y1;
 };
 
+// Conservation sums: per-block compensated partial sums of each field, over
+// kConsBlocks blocks, for at most kConsMaxFields fields (3D reactive Euler).
+constexpr int kConsBlocks = 256;
+constexpr int kConsMaxFields = 6;
+
 // Work queues of a batched launch: one per XCD, counters 128 bytes apart.
 constexpr int kQueues = 8;
 constexpr int kQueueStride = 32;
@@ -130,4 +135,8 @@ ARLBM_DECLARE_LAUNCHERS(f64)
 namespace arlbm {
 // out[i] = descs[i].sc->flags for i < n (either precision: the scalars are FP64).
 hipError_t gather_flags_launch(const LatticeDesc *descs, int32_t n, unsigned *out, hipStream_t s);
+// Device address of this GPU's copy of the conservation scratch (a
+// file-scope device array of kConsBlocks * kConsMaxFields doubles), looked up
+// once per device with that device current.
+hipError_t conservation_scratch(double **out);
 }  // namespace arlbm

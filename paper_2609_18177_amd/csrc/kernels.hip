@@ -6,6 +6,8 @@
 #include "step.hpp"
 #include "step3d.hpp"
 
+#include <mutex>
+
 namespace arlbm {
 static int cell_grid_flags(int64_t n)
 {
@@ -224,6 +226,32 @@ hipError_t gather_flags_launch(const LatticeDesc *descs, int32_t n, unsigned *ou
 {
     hipLaunchKernelGGL(k_gather_flags, dim3(cell_grid_flags(n)), dim3(kBlock), 0, s, descs, n, out);
     return hipGetLastError();
+}
+
+// Partial sums of the allocation-free conservation sums: one copy per GPU,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in, not the device array: only the address hipGetSymbolAddress
+// returns (per device) reaches a kernel.
+static __device__ __align__(256) double scratch[kConsBlocks * kConsMaxFields];
+
+hipError_t conservation_scratch(double **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = (double *)p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 #endif
 }  // namespace arlbm

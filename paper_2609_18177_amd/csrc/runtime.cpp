@@ -31,7 +31,6 @@ namespace {
 thread_local std::string g_thread_err;
 
 constexpr size_t kAlign = 256;
-constexpr int kConsBlocks = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -659,29 +658,24 @@ extern "C" int arlbm_read_omega(arlbm_lattice *h, double *omega)
     return read_planes(h, h->desc.omega, 1, omega);
 }
 
-extern "C" int arlbm_conservation(arlbm_lattice *h, double *sums)
+// Sums of each field from the per-block partials (compensated, in a fixed
+// order), then the partials' reduction on the host in a fixed order.
+static int conservation_impl(arlbm_lattice *h, double *partial, double *sums)
 {
-    if (!h || !sums) return fail(h, ARLBM_EINVAL, "NULL argument");
     const int m = h->sz.m;
-    int rc = form_moments(h);
-    if (rc) return rc;
     const void *u = h->desc.u[h->step & 1];
-    // per-block partials of up to 6 fields (3D reactive Euler), allocated on
-    // the first request, so that a lattice that never asks allocates nothing
-    if (!h->d_partial) HIPCHK(h, hipMalloc((void **)&h->d_partial, sizeof(double) * kConsBlocks * 6));
-    hipError_t e = is_f64(h) ? f64::conservation(u, h->desc.plane, h->desc.pstride, m, h->d_partial, kConsBlocks,
+    hipError_t e = is_f64(h) ? f64::conservation(u, h->desc.plane, h->desc.pstride, m, partial, kConsBlocks,
                                                  h->stream)
-                             : f32::conservation(u, h->desc.plane, h->desc.pstride, m, h->d_partial, kConsBlocks,
+                             : f32::conservation(u, h->desc.plane, h->desc.pstride, m, partial, kConsBlocks,
                                                  h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "conservation launch");
-    std::vector<double> part((size_t)m * kConsBlocks);
-    HIPCHK(h, hipMemcpyAsync(part.data(), h->d_partial, sizeof(double) * part.size(), hipMemcpyDeviceToHost,
-                             h->stream));
+    double part[kConsMaxFields * kConsBlocks];
+    HIPCHK(h, hipMemcpyAsync(part, partial, sizeof(double) * m * kConsBlocks, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     for (int c = 0; c < m; ++c) {
         double s = 0.0, comp = 0.0;
         for (int b = 0; b < kConsBlocks; ++b) {
-            const double v = part[(size_t)c * kConsBlocks + b];
+            const double v = part[c * kConsBlocks + b];
             const double t = s + v;
             comp += std::fabs(s) >= std::fabs(v) ? (s - t) + v : (v - t) + s;
             s = t;
@@ -689,6 +683,30 @@ extern "C" int arlbm_conservation(arlbm_lattice *h, double *sums)
         sums[c] = s + comp;
     }
     return ARLBM_OK;
+}
+
+extern "C" int arlbm_conservation(arlbm_lattice *h, double *sums)
+{
+    if (!h || !sums) return fail(h, ARLBM_EINVAL, "NULL argument");
+    int rc = form_moments(h);
+    if (rc) return rc;
+    // per-block partials of up to kConsMaxFields fields, allocated on the
+    // first request, so that a lattice that never asks allocates nothing
+    if (!h->d_partial)
+        HIPCHK(h, hipMalloc((void **)&h->d_partial, sizeof(double) * kConsBlocks * kConsMaxFields));
+    return conservation_impl(h, h->d_partial, sums);
+}
+
+extern "C" int arlbm_conservation_noalloc(arlbm_lattice *h, double *sums)
+{
+    if (!h || !sums) return fail(h, ARLBM_EINVAL, "NULL argument");
+    if (h->sz.m > kConsMaxFields)
+        return fail(h, ARLBM_EINVAL, "the conservation scratch holds partial sums of at most 6 fields");
+    double *partial = nullptr;
+    HIPCHK(h, conservation_scratch(&partial));
+    int rc = form_moments(h);
+    if (rc) return rc;
+    return conservation_impl(h, partial, sums);
 }
 
 namespace {
