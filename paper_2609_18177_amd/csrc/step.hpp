@@ -752,6 +752,14 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
     T s0 = T(0), s1 = T(0);
     unsigned flags = 0;
 
+    // primitives of the U1 row that the last nu_row() formed: the next row()
+    // collides that row (as U0) and takes them instead of forming them again.
+    // Only with one column per lane: the two-column strips are at the
+    // register limit, and carrying them cost the batched kernel's
+    // two-column shallow-water strips 19% (more spills), against 1% gained
+    // by 2D Euler.
+    constexpr bool kCarry = V == 1;
+    Prim<T> Qn[V];
     auto nu_row = [&]() {  // nu at the row of U1 (eqs. 2.13-2.14)
         T UL[V][M], UR[V][M];
 #pragma unroll
@@ -767,11 +775,10 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
         T nu[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            Prim<T> qc;
-            primitives<SYS, D, T>(U1[v], P, qc);
+            primitives<SYS, D, T>(U1[v], P, Qn[v]);
             nu[v] = T(0);
-            add_theta<SYS, D, T>(0, qc, U1[v], UL[v], UR[v], P, nu[v]);
-            add_theta<SYS, D, T>(1, qc, U1[v], U0[v], U2[v], P, nu[v]);
+            add_theta<SYS, D, T>(0, Qn[v], U1[v], UL[v], UR[v], P, nu[v]);
+            add_theta<SYS, D, T>(1, Qn[v], U1[v], U0[v], U2[v], P, nu[v]);
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -929,6 +936,11 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
             fix(B2);
             loadB(r + 2, Bnx);
         }
+        Prim<T> Qc[V];  // primitives of the row collided here (formed by the last nu_row)
+        if constexpr (kCarry) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) Qc[v] = Qn[v];
+        }
         nu_row();
         // 3x3 box sum (2.15) in row-major order, relaxation parameter (2.16)
         T w[V];
@@ -955,8 +967,8 @@ __device__ __forceinline__ void strip2d(const LatticeDesc &L, int64_t iter, int 
         T fs[V][Q][M];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            Prim<T> q;
-            primitives<SYS, D, T>(U0[v], P, q);
+            if constexpr (!kCarry) primitives<SYS, D, T>(U0[v], P, Qc[v]);
+            const Prim<T> &q = Qc[v];
             T Fx[M], Fy[M];
             flux<SYS, D, T>(0, U0[v], q, P, Fx);
             flux<SYS, D, T>(1, U0[v], q, P, Fy);
