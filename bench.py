@@ -291,7 +291,7 @@ def run_latency_small(args):
 
 def run_euler3d(torch, args, steps=None):
     """3D Euler (D3Q7), seeded octant data on 256^3 cells, FP32: the
-    three-pass step; FP32 against FP64 after the timed steps."""
+    fused one-pass step; FP32 against FP64 after the timed steps."""
     p = W.euler_octants_3d(seed=0, n=256, steps=100)
     steps = steps or args.steps3d
     log(f"[euler3d] 256^3 FP32: warmup {args.warmup}, timed {steps}")

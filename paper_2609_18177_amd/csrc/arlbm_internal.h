@@ -82,7 +82,6 @@ struct LatticeDesc {
     int32_t abar_n;       // copies of each wave-speed slot in use: a power of two <= kAbarCopies, fixed per lattice
     double dx, cfl, eps, gamma, g, adv[3], h_dry, rho_floor, p_floor, omega_fixed;
     double q_heat, k_rate, t_act;  // reactive Euler: heat release, rate constant, activation temperature
-    void *nu3;                     // 3D: padded indicator (nx+2)(ny+2)(nz+2), then omega of the cells
 };
 
 // One work item of a batched launch.  2D: rows y0 .. y1-1 of strip col.

@@ -34,12 +34,19 @@ static int grid_for(int64_t items, int per_block)
     return (int)(b < 8 ? 8 : b);
 }
 
-// Grid of a 3D pass: a multiple of 8 blocks (one slab per XCD), at most 4096.
-static int slab_grid(int64_t cells)
+// Compute units of the current device (cached per device).
+static int num_cus()
 {
-    int64_t b = (cells + kBlock - 1) / kBlock;
-    b = (b + 7) / 8 * 8;
-    return (int)(b > 4096 ? 4096 : (b < 8 ? 8 : b));
+    constexpr int kMaxDevices = 64;
+    static int cus[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 256;
+    if (cus[dev] <= 0) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+        cus[dev] = c;
+    }
+    return cus[dev];
 }
 
 static int cell_grid(int64_t cells)
@@ -68,13 +75,11 @@ template <int SYS, int D>
 static hipError_t step_impl(const LatticeDesc &h, int64_t iter, hipStream_t s)
 {
     if constexpr (D == 3) {
-        // indicator on the padded lattice (from the moments the previous
-        // step or the initialisation left in u[n&1]), relaxation parameter,
-        // collide and pull (which also writes the moments of the new state)
-        const int64_t npad = (int64_t)(h.nx + 2) * (h.ny + 2) * (h.nz + 2);
-        hipLaunchKernelGGL((k3_nu<SYS, real>), dim3(slab_grid(npad)), dim3(kBlock), 0, s, h, iter);
-        hipLaunchKernelGGL((k3_omega<real>), dim3(slab_grid(h.plane)), dim3(kBlock), 0, s, h, iter);
-        hipLaunchKernelGGL((k3_collide<SYS, real>), dim3(slab_grid(h.plane)), dim3(kBlock), 0, s, h, iter);
+        // one fused pass: tiles x plane chunks filling the chip once
+        using G = Tile3<real>;
+        const int nt = k3_tiles(h.nx, h.ny, G::TX, G::TY);
+        const int nb = nt * k3_chunks(nt, h.nz, num_cus());
+        hipLaunchKernelGGL((k3_step<SYS, real>), dim3(nb), dim3(G::kThreads), 0, s, h, iter);
     } else {
         const int64_t nbands = D == 2 ? (h.ny + h.band_h - 1) / h.band_h : 1;
         const int64_t nwork = (int64_t)h.ncols * nbands;
@@ -188,9 +193,9 @@ static const void *step_fn(int variant, int cpl)
     case V_EUL2: return step_fn2<1, false>(cpl);
     case V_SWE2: return step_fn2<2, true>(cpl);
     case V_REU2: return step_fn2<3, false>(cpl);
-    case V_ADV3: return (const void *)&k3_collide<0, real>;
-    case V_EUL3: return (const void *)&k3_collide<1, real>;
-    case V_REU3: return (const void *)&k3_collide<3, real>;
+    case V_ADV3: return (const void *)&k3_step<0, real>;
+    case V_EUL3: return (const void *)&k3_step<1, real>;
+    case V_REU3: return (const void *)&k3_step<3, real>;
     default: return nullptr;
     }
 }

@@ -73,8 +73,9 @@ struct Prim {
 // or below a floor raises the positivity flag).  Shallow water: a cell with
 // h <= h_dry (FP64 compare) has zero velocity and momentum flux and the
 // acoustic speed in L uses max(h, h_dry); depths within h_dry of zero are dry,
-// so only h < -h_dry raises the positivity flag.
-template <int SYS, int D, typename T>
+// so only h < -h_dry raises the positivity flag.  kSpeed = false leaves out
+// the sound speeds and the flags (what the flux alone needs is the same).
+template <int SYS, int D, typename T, bool kSpeed = true>
 __device__ __forceinline__ void primitives(const T *U, const Phys<T> &P, Prim<T> &q)
 {
     q.flags = 0;
@@ -106,12 +107,16 @@ __device__ __forceinline__ void primitives(const T *U, const Phys<T> &P, Prim<T>
             q.Y = ddiv<T>(q.Z, q.rho);
             q.p = P.gm1 * ((q.E - T(0.5) * q.rho * q2) - P.qh * q.Z);
         }
-        const bool pok = double(q.p) > P.p_floor, rok = double(q.rho) > P.rho_floor;
-        const T pf = pok ? q.p : P.p_floor_t;
-        const T rf = rok ? q.rho : P.rho_floor_t;
-        if (!(pok && rok)) q.flags |= 2u;
-        q.c = dsqrt<T>(ddiv<T>(P.gamma * pf, rf));
-        q.cL = q.c;
+        if constexpr (kSpeed) {
+            const bool pok = double(q.p) > P.p_floor, rok = double(q.rho) > P.rho_floor;
+            const T pf = pok ? q.p : P.p_floor_t;
+            const T rf = rok ? q.rho : P.rho_floor_t;
+            if (!(pok && rok)) q.flags |= 2u;
+            q.c = dsqrt<T>(ddiv<T>(P.gamma * pf, rf));
+            q.cL = q.c;
+        } else {
+            q.c = q.cL = T(0);
+        }
     } else if constexpr (SYS == 2) {
         const T h = U[0];
         q.rho = h;
@@ -122,9 +127,13 @@ __device__ __forceinline__ void primitives(const T *U, const Phys<T> &P, Prim<T>
             q.mom[1] = wet ? U[2] : T(0);
             q.vel[1] = wet ? ddiv<T>(U[2], h) : T(0);
         }
-        if (double(h) < -P.h_dry) q.flags |= 2u;
-        q.c = dsqrt<T>(P.g * (h > T(0) ? h : T(0)));
-        q.cL = dsqrt<T>(P.g * (wet ? h : P.h_dry_t));
+        if constexpr (kSpeed) {
+            if (double(h) < -P.h_dry) q.flags |= 2u;
+            q.c = dsqrt<T>(P.g * (h > T(0) ? h : T(0)));
+            q.cL = dsqrt<T>(P.g * (wet ? h : P.h_dry_t));
+        } else {
+            q.c = q.cL = T(0);
+        }
         q.E = q.p = T(0);
     } else {
         q.rho = U[0];

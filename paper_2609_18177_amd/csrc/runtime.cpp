@@ -139,12 +139,8 @@ void fill_sizes(const arlbm_config *c, arlbm_sizes *o)
     o->m = m;
     o->q = q;
     o->f_bytes = align_up((size_t)q * m * ps * s);
-    // in 3D the moment buffers are a ping-pong kept current by the step, and
-    // behind U the second one holds the padded indicator and omega of the
-    // cells between the passes of a step
-    size_t u_elems = (size_t)m * ps;
-    if (c->dim == 3) u_elems += (size_t)(c->nx + 2) * (c->ny + 2) * (c->nz + 2) + (size_t)ps;
-    o->u_bytes = align_up(u_elems * s);
+    // in 3D the moment buffers are a ping-pong kept current by the step
+    o->u_bytes = align_up((size_t)m * ps * s);
     o->bed_bytes = c->has_bed ? align_up(ps * s) : 0;
     o->scalar_bytes = align_up(sizeof(DevScalars));
     o->omega_bytes = align_up(ps * s);
@@ -490,8 +486,6 @@ extern "C" int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, 
                         std::string("device allocation failed: ") + hipGetErrorString(err));
         }
     }
-    if (cfg->dim == 3)
-        d.nu3 = (char *)d.u[1] + (size_t)h->sz.m * d.pstride * (cfg->precision == ARLBM_F64 ? 8 : 4);
     // without an omega plane the kernels store no omega (omega_on = 0)
     d.omega_on = d.omega ? 1 : 0;
     *out = h;

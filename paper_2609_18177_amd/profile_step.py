@@ -39,10 +39,10 @@ KERNELS = {"euler2d_batched_f32": "k_step_batched<float>",
            "euler2d_f64": "k_step_single<1, 2, false, double, 1, true>",
            "swe2d_batched_f32": "k_step_batched<float>",
            "swe2d_f32": "k_step_single<2, 2, true, float, 2, true>",
-           "euler3d_f32": "k3_collide<1, float>",
+           "euler3d_f32": "k3_step<1, float>",
            "serving_fixed_f32": "k_step_batched<float>"}
 # further kernels of a step (3D: the indicator and relaxation passes)
-EXTRA_KERNELS = {"euler3d_f32": ["k3_nu<1, float>", "k3_omega<float>"]}
+EXTRA_KERNELS = {}
 WORKLOAD_NAMES = {"euler2d_batched_f32": "euler2d_2048_batched_f32", "euler2d_f32": "euler2d_2048_f32",
                   "euler2d_f64": "euler2d_2048_f64", "swe2d_batched_f32": "swe2d_4096_batched_f32",
                   "swe2d_f32": "swe2d_4096_f32", "euler3d_f32": "euler3d_256_f32",

@@ -88,6 +88,28 @@ def test_euler3d_ragged_noncubic():
     _cmp(p, 15, "ragged 17x13x11")
 
 
+@pytest.mark.parametrize("bc", [
+    (A.PERIODIC,) * 6,
+    (A.REFLECTIVE, A.TRANSMISSIVE, A.PERIODIC, A.PERIODIC, A.TRANSMISSIVE, A.REFLECTIVE),
+    (A.PERIODIC, A.PERIODIC, A.TRANSMISSIVE, A.REFLECTIVE, A.REFLECTIVE, A.REFLECTIVE),
+])
+def test_euler3d_several_tiles_and_chunks(bc):
+    """70 x 37 x 33 cells: three tiles across x and five along y (each of
+    them ragged at the far side) and plane chunks, with every kind of face."""
+    require_gpu()
+    h = 1.0 / 32
+    base = W.euler_octants_3d(seed=5, n=16)
+    nx, ny, nz = 70, 37, 33
+    Z, Y, X = np.meshgrid(*(W.centres(m, 0.0, m * h) for m in (nz, ny, nx)), indexing="ij")
+    st = W.octant_states(5)
+    idx = (X >= 1.1).astype(int) + 2 * (Y >= 0.5).astype(int) + 4 * (Z >= 0.6).astype(int)
+    arr = np.array(st)[idx]
+    U0 = W.euler3_conserved(arr[..., 0], arr[..., 1], arr[..., 2], arr[..., 3], arr[..., 4])
+    p = W.Problem("tiles3d", W.EULER, 3, nx, ny, 0.0, nx * h, 0.0, ny * h, bc[:4], 0.5, 12, U0,
+                  nz=nz, z0=0.0, z1=nz * h, bc_z=bc[4:])
+    _cmp(p, 12, f"tiles {nx}x{ny}x{nz} bc {bc}", omega_export=True)
+
+
 def test_advection3d_periodic():
     require_gpu()
     _cmp(W.advection_sine_3d(n=20, steps=20), 20, "advection", tol32=1e-5)
