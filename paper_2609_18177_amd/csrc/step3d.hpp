@@ -114,6 +114,15 @@ __device__ __forceinline__ int mirror3(int k) { return k <= 3 ? k + 3 : k - 3; }
 // the compiler then forms each field's address there (a few scalar ops)
 // instead of holding one 64-bit address per field across the plane loop,
 // which exceeds the scalar registers.
+// Store of the new state, marked non-temporal: nothing reads it again in this
+// step, and it stays out of the way of the moments the tiles' halos read
+// from L2 (256^3 Euler FP32: 1.200 -> 1.156 ms per step).
+template <typename T>
+__device__ __forceinline__ void sto_nt(T *base, unsigned off, T v)
+{
+    __builtin_nontemporal_store(v, base + off);
+}
+
 template <typename P>
 __device__ __forceinline__ void opaque(P *&base, int64_t &stride)
 {
@@ -367,15 +376,15 @@ __global__ __launch_bounds__(Tile3<T>::kThreads) void k3_step(LatticeDesc L, int
             for (int k = 1; k < Q; ++k) sn = sn + last[k];
             Un[M - 1] = sn;
 #pragma unroll
-            for (int k = 0; k < Q; ++k) sto(fo + (int64_t)(k * M + M - 1) * ps, cell, last[k]);
+            for (int k = 0; k < Q; ++k) sto_nt(fo + (int64_t)(k * M + M - 1) * ps, cell, last[k]);
 #pragma unroll
-            for (int c = 0; c < M - 1; ++c) sto(fo + (int64_t)(6 * M + c) * ps, cell, F6[c]);
+            for (int c = 0; c < M - 1; ++c) sto_nt(fo + (int64_t)(6 * M + c) * ps, cell, F6[c]);
         } else {
 #pragma unroll
-            for (int c = 0; c < M; ++c) sto(fo + (int64_t)(6 * M + c) * ps, cell, F6[c]);
+            for (int c = 0; c < M; ++c) sto_nt(fo + (int64_t)(6 * M + c) * ps, cell, F6[c]);
         }
 #pragma unroll
-        for (int c = 0; c < M; ++c) sto(uo + (int64_t)c * pu, cell, Un[c]);
+        for (int c = 0; c < M; ++c) sto_nt(uo + (int64_t)c * pu, cell, Un[c]);
         Prim<T> qn;
         primitives<SYS, D, T>(Un, P, qn);
         bool ok = true;
@@ -462,7 +471,7 @@ __global__ __launch_bounds__(Tile3<T>::kThreads) void k3_step(LatticeDesc L, int
 #pragma unroll
         for (int c = 0; c < M; ++c) S[c] = F[c];
 #pragma unroll
-        for (int c = 0; c < CW; ++c) sto(fo + (int64_t)(0 * M + c) * ps, cell, F[c]);
+        for (int c = 0; c < CW; ++c) sto_nt(fo + (int64_t)(0 * M + c) * ps, cell, F[c]);
         Lk[0] = F[M - 1];
 #pragma unroll
         for (int k = 1; k < 6; ++k) {
@@ -493,7 +502,7 @@ __global__ __launch_bounds__(Tile3<T>::kThreads) void k3_step(LatticeDesc L, int
 #pragma unroll
             for (int c = 0; c < M; ++c) S[c] = S[c] + F[c];
 #pragma unroll
-            for (int c = 0; c < CW; ++c) sto(fo + (int64_t)(k * M + c) * ps, cell, F[c]);
+            for (int c = 0; c < CW; ++c) sto_nt(fo + (int64_t)(k * M + c) * ps, cell, F[c]);
             Lk[k] = F[M - 1];
         }
         if (s == nz - 1 && zhi_wall) {
