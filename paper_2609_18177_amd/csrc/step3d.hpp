@@ -114,13 +114,20 @@ __device__ __forceinline__ int mirror3(int k) { return k <= 3 ? k + 3 : k - 3; }
 // the compiler then forms each field's address there (a few scalar ops)
 // instead of holding one 64-bit address per field across the plane loop,
 // which exceeds the scalar registers.
-// Store of the new state, marked non-temporal: nothing reads it again in this
-// step, and it stays out of the way of the moments the tiles' halos read
-// from L2 (256^3 Euler FP32: 1.200 -> 1.156 ms per step).
+// Populations of the old state read and the new state stored non-temporal:
+// nothing reads them again in this step, and they stay out of the way of the
+// moments the tiles' halos read from L2 (256^3 Euler FP32, ms per step:
+// stores 1.200 -> 1.156, then loads 1.163 -> 1.135; in the 2D kernels
+// either made the step 2-30% slower).
 template <typename T>
 __device__ __forceinline__ void sto_nt(T *base, unsigned off, T v)
 {
     __builtin_nontemporal_store(v, base + off);
+}
+template <typename T>
+__device__ __forceinline__ T ldo_nt(const T *base, unsigned off)
+{
+    return __builtin_nontemporal_load(base + off);
 }
 
 template <typename P>
@@ -413,9 +420,9 @@ __global__ __launch_bounds__(Tile3<T>::kThreads) void k3_step(LatticeDesc L, int
         opaque(fi, ps);
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            fown[0][c] = mid ? ldo(fi + (int64_t)(0 * M + c) * ps, pb + doff) : T(0);
-            fown[1][c] = need3 ? ldo(fi + (int64_t)(3 * M + c) * ps, pb + doff) : T(0);
-            fown[2][c] = need6 ? ldo(fi + (int64_t)(6 * M + c) * ps, pb + doff) : T(0);
+            fown[0][c] = mid ? ldo_nt(fi + (int64_t)(0 * M + c) * ps, pb + doff) : T(0);
+            fown[1][c] = need3 ? ldo_nt(fi + (int64_t)(3 * M + c) * ps, pb + doff) : T(0);
+            fown[2][c] = need6 ? ldo_nt(fi + (int64_t)(6 * M + c) * ps, pb + doff) : T(0);
         }
         if (!mid) return;
         if (!refl_xy) {
@@ -423,7 +430,7 @@ __global__ __launch_bounds__(Tile3<T>::kThreads) void k3_step(LatticeDesc L, int
             for (int j = 0; j < 4; ++j) {
                 const int k = j < 2 ? j + 1 : j + 2;
 #pragma unroll
-                for (int c = 0; c < M; ++c) fpull[j][c] = ldo(fi + (int64_t)(k * M + c) * ps, pb + poff[j]);
+                for (int c = 0; c < M; ++c) fpull[j][c] = ldo_nt(fi + (int64_t)(k * M + c) * ps, pb + poff[j]);
             }
         } else {
 #pragma unroll
@@ -431,7 +438,7 @@ __global__ __launch_bounds__(Tile3<T>::kThreads) void k3_step(LatticeDesc L, int
                 const int k = j < 2 ? j + 1 : j + 2;
                 const int ks = (refl_m >> j) & 1u ? mirror3(k) : k;
 #pragma unroll
-                for (int c = 0; c < M; ++c) fpull[j][c] = fi[(int64_t)(ks * M + c) * ps + pb + poff[j]];
+                for (int c = 0; c < M; ++c) fpull[j][c] = __builtin_nontemporal_load(fi + ((int64_t)(ks * M + c) * ps + pb + poff[j]));
             }
         }
     };
