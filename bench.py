@@ -317,6 +317,7 @@ def run_euler3d(torch, args, steps=None):
     ms_step = tm.ms / steps
     b = alg_bytes_per_lup(p, 4)
     out.update({"glups": p.cells / (ms_step * 1e-3) / 1e9, "ms_per_step": ms_step, "cells": p.cells,
+                "alg_bytes_per_lup": b,
                 "alg_gbs": b * p.cells / (ms_step * 1e-3) / 1e9,
                 "alg_frac": b * p.cells / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, "flags": st["flags"]})
     return out
@@ -674,6 +675,9 @@ def main():
     extra["roofline_batched_c4"] = roofline("k_step_batched<float>", "swe2d_4096_batched_f32",
                                             alg_bytes_per_lup(c4, 4), c4.cells,
                                             extra["c4_swe2d_4096"]["fp32_batched"]["ms_per_step"])
+    e3 = extra["euler3d_256_f32"]
+    extra["roofline_euler3d_256"] = roofline("k3_step<EULER,float>", "euler3d_256_f32", e3["alg_bytes_per_lup"],
+                                             e3["cells"], e3["ms_per_step"])
     fx = extra["serving_fixed_mix"]
     prof = read_profile("serving_fixed_f32")
     extra["roofline_batched_serving_fixed_mix"] = {

@@ -16,7 +16,8 @@ import pytest
 
 from paper_2609_18177_amd import arlbm as A
 from paper_2609_18177_amd import workloads as W
-from gpu_common import require_gpu, say, gpu_lattice, rel_l2_per_comp, rel_l1, fp64_parity_ok
+from gpu_common import (require_gpu, say, gpu_lattice, rel_l2_per_comp, rel_l1, rel_l1_per_comp, fp64_parity_ok,
+                        oracle_run)
 from helpers import ora_from, run_until, fsum
 
 pytestmark = pytest.mark.gpu
@@ -108,6 +109,29 @@ def test_euler3d_several_tiles_and_chunks(bc):
     p = W.Problem("tiles3d", W.EULER, 3, nx, ny, 0.0, nx * h, 0.0, ny * h, bc[:4], 0.5, 12, U0,
                   nz=nz, z0=0.0, z1=nz * h, bc_z=bc[4:])
     _cmp(p, 12, f"tiles {nx}x{ny}x{nz} bc {bc}", omega_export=True)
+
+
+def test_euler3d_full_size_first_steps():
+    """256^3, the lattice and launch the benchmark times (128 tiles in two
+    plane chunks): two steps against the oracle, FP64 bit for bit, FP32
+    within the 3D bound per field."""
+    require_gpu()
+    p = W.euler_octants_3d(seed=0, n=256, steps=2)
+    Lo = oracle_run(p, 2, parallel=True)
+    Uo = Lo.moments()
+    for prec in (A.F64, A.F32):
+        G = gpu_lattice(p, prec)
+        G.step(2)
+        st = G.sync()
+        U = G.moments()
+        G.close()
+        e = rel_l1_per_comp(U, Uo)
+        say(f"[3d 256^3] prec={prec} 2 steps bitwise={np.array_equal(U, Uo)} rel L1 per field {e}")
+        if prec == A.F64:
+            assert np.array_equal(U, Uo) and st["t"] == Lo.t
+        else:
+            assert max(e) <= TOL_FP32, e
+        del U
 
 
 def test_advection3d_periodic():
