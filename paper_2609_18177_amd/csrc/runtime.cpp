@@ -1081,37 +1081,50 @@ bool own_launch(const LatticeDesc &d) { return d.variant >= V_ADV3 || (d.variant
 // in order, each band's strips left to right, so those waves march over the
 // same rows of neighbouring strips (their halo columns are in each other's
 // L2, and the concurrent reads cover whole plane rows).  The list is cut
-// into kQueues contiguous parts of about equal work, one per XCD; a wave
-// takes items from its XCD's part first (blocks are dealt to the XCDs round
-// robin, so block b runs on XCD b mod 8), its first one as a static deal
-// would give it, then from the others in turn.
+// into kQueues parts, one per XCD; a wave takes items from its XCD's part
+// first (blocks are dealt to the XCDs round robin, so block b runs on XCD
+// b mod 8), its first one as a static deal would give it, then from the
+// part with the most items left.
 //
 // Item height: the whole work is r rounds of the launch's waves, with r as
 // small as keeps bands of at most 256 rows, and every 2D lattice is cut into
 // bands of equal height, about h = (strip rows) / (r waves) rows (at least
 // 8); in a single round h is the lowest height whose items all fit the
-// waves.  A lattice alone thus gets the
-// single-lattice kernel's bands, one per wave (2048^2 Euler: 28 bands of 74
-// rows of its 36 strips); a large mix gets about r items per wave, which
-// the queue balances.  2D lattices come first, those with the tallest items
-// first, and 1D runs last, so the items that end the launch are the
-// smallest; a run is as short as spreads the 1D strips over the waves the 2D
-// items leave free (a 1D lattice alone: about one strip per wave, as in the
-// single-lattice kernel) and at most about one 2D item's work.  Cost model, in population values a
-// wave moves: a 2D item of h rows costs (h + 6) rows of 64 V lanes by Q m
-// values (the march reads 3 rows of moments beyond each end and collides one
-// row beyond each end); a 1D strip costs 64 Q m values plus a latency share
-// of one 1280-value row, and a run two strips more.
+// waves.  A lattice alone thus gets the single-lattice kernel's bands, one
+// per wave (2048^2 Euler: 28 bands of 74 rows of its 36 strips); a large mix
+// gets about r items per wave, which the queues balance.  Lattices with the
+// tallest bands come first.  Each part holds a contiguous range of the bands
+// (equal counts in one round, so that every band is a wave's first item;
+// about equal work over several rounds), then every kQueues-th 1D run, the
+// largest first: the runs fill the waves whose bands end early.  A run
+// spreads the 1D strips over the waves the bands leave free (a 1D lattice
+// alone: about one strip per wave, as in the single-lattice kernel), or,
+// when the bands leave fewer than an eighth of the waves free, over all of
+// them in runs of at least 8 strips; it is never longer than about one 2D
+// item's work.  Cost model, in population values a wave moves: a 2D item
+// of h rows costs (h + 6) rows of 64 V lanes by Q m values (the march reads
+// 3 rows of moments beyond each end and collides one row beyond each end);
+// a 1D strip costs 64 Q m values plus a latency share of one 1280-value row,
+// and a run two strips more.
 //
-// Dealing the items statically instead (consecutive items per wave) gave
-// the same times for one item per wave, but two or more put a wave's items
-// one after the other on its own, so neighbouring waves no longer marched
-// over neighbouring strips: 4096^2 shallow water 0.46 -> 0.70 ms per step,
-// all 512 requests of the serving mix resident 21 -> 15 GLUPS; and cutting
-// strips into row ranges dealt down each strip put the waves of one XCD at
-// scattered rows (2048^2 Euler 51% slower than the single-lattice kernel).
+// Measured on the 65 lattices of the fixed serving mix (ms per launch):
+// parts of equal work in one round and the 1D runs at the end of the list
+// put a few bands of one part behind its XCD's waves, and the other XCDs'
+// waves first took the small 1D runs the list ended with (the mix's 2D
+// Euler lattices with its 1D ones 0.552, with one 1D lattice 0.469 against
+// 0.387 alone; now 0.395); the whole mix 0.826 -> 0.809.  Bands of exactly h
+// rows with the rows left over as short items (0.83), the last eighth of
+// the 2D work in bands a quarter as tall (0.88), and one round of bands up
+// to 384 rows (0.90) measured slower.  Dealing the items statically
+// instead (consecutive items per wave) gave the same times for one item per
+// wave, but two or more put a wave's items one after the other on its own,
+// so neighbouring waves no longer marched over neighbouring strips: 4096^2
+// shallow water 0.46 -> 0.70 ms per step, all 512 requests of the serving
+// mix resident 21 -> 15 GLUPS; and cutting strips into row ranges dealt
+// down each strip put the waves of one XCD at scattered rows (2048^2 Euler
+// 51% slower than the single-lattice kernel).
 constexpr int kWarmRows2d = 6, kWarmStrips1d = 2, kMinRows2d = 8, kMaxRows2d = 256;
-constexpr int64_t kStrip1dLatency = 1280, kRowValues = 1280;
+constexpr int64_t kStrip1dLatency = 1280, kRowValues = 1280, kRun1dMix = 8;
 
 int64_t batched_waves() { return 4 * (int64_t)num_cus(); }  // one wave per SIMD
 
@@ -1133,10 +1146,9 @@ int64_t build_schedule(const std::vector<SchedLattice> &lats, int64_t W, std::ve
     int64_t S = 0;  // 2D strip rows
     for (const SchedLattice &l : lats)
         if (!l.one_d) S += (int64_t)l.ncols * l.ny;
-    std::vector<std::pair<int64_t, size_t>> order;  // (band height, lattice) of the 2D lattices
-    int64_t h = kMaxRows2d;
+    int64_t h = kMaxRows2d, r = 1;
     if (S > 0) {
-        int64_t r = std::max<int64_t>(1, (S + W * kMaxRows2d - 1) / (W * kMaxRows2d));
+        r = std::max<int64_t>(1, (S + W * kMaxRows2d - 1) / (W * kMaxRows2d));
         h = std::max<int64_t>(kMinRows2d, (S + W * r - 1) / (W * r));
         auto items_at = [&](int64_t hh) {
             int64_t n = 0;
@@ -1153,53 +1165,78 @@ int64_t build_schedule(const std::vector<SchedLattice> &lats, int64_t W, std::ve
                 h = std::max<int64_t>(kMinRows2d, (S + W * r - 1) / (W * r));
             }
         }
-        for (size_t i = 0; i < lats.size(); ++i) {
-            if (lats[i].one_d) continue;
-            const int64_t nb = (lats[i].ny + std::min(h, lats[i].ny) - 1) / std::min(h, lats[i].ny);
-            order.push_back({(lats[i].ny + nb - 1) / nb, i});
-        }
-        std::stable_sort(order.begin(), order.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
     }
-    std::vector<double> cost;
+    // each lattice in bands of equal height, at most h; lattices with the
+    // tallest bands first
+    struct Item {
+        Segment seg;
+        double cost;
+    };
+    std::vector<Item> big, small;
+    std::vector<std::pair<int64_t, const SchedLattice *>> order;  // (band height, lattice)
+    for (const SchedLattice &l : lats) {
+        if (l.one_d) continue;
+        const int64_t hl = std::min(h, l.ny);
+        const int64_t nb = (l.ny + hl - 1) / hl;
+        order.push_back({(l.ny + nb - 1) / nb, &l});
+    }
+    std::stable_sort(order.begin(), order.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
     for (const auto &o : order) {
-        const SchedLattice &l = lats[o.second];
-        const int64_t hl = o.first;
-        for (int64_t y0 = 0; y0 < l.ny; y0 += hl) {
-            const int64_t y1 = std::min<int64_t>(l.ny, y0 + hl);
-            for (int32_t c = 0; c < l.ncols; ++c) {
-                segs.push_back({l.lattice, c, (int32_t)y0, (int32_t)y1});
-                cost.push_back((double)(y1 - y0 + kWarmRows2d) * (double)l.unit);
-            }
+        const SchedLattice &l = *o.second;
+        for (int64_t y0 = 0; y0 < l.ny; y0 += o.first) {
+            const int64_t y1 = std::min<int64_t>(l.ny, y0 + o.first);
+            for (int32_t c = 0; c < l.ncols; ++c)
+                big.push_back({{l.lattice, c, (int32_t)y0, (int32_t)y1}, (double)(y1 - y0 + kWarmRows2d) * (double)l.unit});
         }
     }
-    // 1D runs: spread over the waves the 2D items leave in the first round
-    // (at least an eighth of them), but no longer than about one 2D item's
-    // work
+    // 1D runs, no longer than about one 2D item's work.  Where the 2D items
+    // leave at least an eighth of the waves free, the 1D strips are spread
+    // over those (a 1D lattice alone: about one strip per wave); otherwise
+    // over all the waves in runs of at least kRun1dMix strips, which the
+    // waves take as their 2D items end.
     int64_t strips1d = 0;
     for (const SchedLattice &l : lats)
         if (l.one_d) strips1d += l.ncols;
-    const int64_t free_waves = std::max<int64_t>(W - (int64_t)segs.size(), std::max<int64_t>(1, W / 8));
-    const int64_t spread = (strips1d + free_waves - 1) / free_waves;
+    const int64_t free_waves = W - (int64_t)big.size();
+    const int64_t spread = free_waves >= W / 8 ? (strips1d + free_waves - 1) / free_waves
+                                               : std::max<int64_t>((strips1d + W - 1) / W, kRun1dMix);
     for (const SchedLattice &l : lats) {
         if (!l.one_d) continue;
         const int64_t cap = std::max<int64_t>(1, (h + kWarmRows2d) * kRowValues / l.unit - kWarmStrips1d);
         const int64_t per = std::max<int64_t>(1, std::min(spread, cap));
         for (int64_t c = 0; c < l.ncols; c += per) {
             const int64_t e = std::min<int64_t>(l.ncols, c + per);
-            segs.push_back({l.lattice, (int32_t)c, 0, (int32_t)e});
-            cost.push_back((double)(e - c + kWarmStrips1d) * (double)l.unit);
+            small.push_back({{l.lattice, (int32_t)c, 0, (int32_t)e}, (double)(e - c + kWarmStrips1d) * (double)l.unit});
         }
     }
-    // contiguous parts of about equal work
-    double total = 0.0;
-    for (double c : cost) total += c;
-    double acc = 0.0;
-    int q = 1;
-    for (size_t k = 0; k < cost.size() && q < kQueues; ++k) {
-        acc += cost[k];
-        while (q < kQueues && acc >= total * q / kQueues) qstart[q++] = (int32_t)(k + 1);
+    std::stable_sort(small.begin(), small.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
+    // each queue: a contiguous part of the bands, then every kQueues-th of
+    // the smaller items (largest first), which fill the waves that finish
+    // early.  In one round the parts have equal counts, so that every band is
+    // a first item (a queue with more bands than its XCD's waves would leave
+    // the extra ones to waves that first take the other queues' small items);
+    // over several rounds they carry about equal work.
+    std::vector<size_t> bstart(kQueues + 1, big.size());
+    bstart[0] = 0;
+    if (r == 1) {
+        const size_t per = (big.size() + kQueues - 1) / kQueues;
+        for (int q = 1; q < kQueues; ++q) bstart[q] = std::min(big.size(), per * q);
+    } else {
+        double total = 0.0;
+        for (const Item &it : big) total += it.cost;
+        double acc = 0.0;
+        int q = 1;
+        for (size_t k = 0; k < big.size() && q < kQueues; ++k) {
+            acc += big[k].cost;
+            while (q < kQueues && acc >= total * q / kQueues) bstart[q++] = k + 1;
+        }
     }
-    for (; q <= kQueues; ++q) qstart[q] = (int32_t)segs.size();
+    for (int q = 0; q < kQueues; ++q) {
+        qstart[q] = (int32_t)segs.size();
+        for (size_t k = bstart[q]; k < bstart[q + 1]; ++k) segs.push_back(big[k].seg);
+        for (size_t k = q; k < small.size(); k += kQueues) segs.push_back(small[k].seg);
+    }
+    qstart[kQueues] = (int32_t)segs.size();
     return std::min<int64_t>(W, (int64_t)segs.size());
 }
 

@@ -2,9 +2,9 @@
 served 1D and 2D lattice is stepped by exactly one item; a lattice alone
 gets the single-lattice kernel's bands (one band of one strip per wave);
 the list fits one round of the launch's waves where the work allows; it holds each
-lattice's bands in order with each band's strips left to right; its eight
-per-XCD queues carry about equal work; the items that end it are the
-smallest."""
+lattice's bands in order with each band's strips left to right; each of its
+eight per-XCD queues holds bands, then 1D runs; in one round every band is a
+wave's first item, over several rounds the queues carry about equal work."""
 import numpy as np
 import pytest
 
@@ -89,6 +89,23 @@ def _queues_balanced(cfgs, qs, segs, tol):
     assert max(work) <= (1 + tol) * mean and min(work) >= (1 - tol) * mean, [w / mean for w in work]
 
 
+def _queue_parts(cfgs, qs, segs):
+    """Each queue: its 2D bands, then its 1D runs (the runs dealt round
+    robin over the queues, largest first)."""
+    runs = []
+    for q in range(8):
+        part = segs[qs[q]:qs[q + 1]]
+        dims = np.array([cfgs[i].dim for i in part[:, 0]], dtype=int)
+        if len(dims) and np.any(dims == 1):
+            first = int(np.argmax(dims == 1))
+            assert np.all(dims[first:] == 1), q
+        runs.append(part[dims == 1] if len(dims) else part[:0])
+    counts = [len(r) for r in runs]
+    assert max(counts) - min(counts) <= 1, counts
+    return [segs[qs[q]:qs[q + 1]][np.array([cfgs[i].dim == 2 for i in segs[qs[q]:qs[q + 1], 0]], dtype=bool)]
+            for q in range(8)]
+
+
 @pytest.mark.parametrize("n,precision", [(60, A.F32), (60, A.F64), (512, A.F32)])
 def test_serving_mix_rounds_and_queues(n, precision):
     reqs = W.serving_requests(n, rate_hz=200.0, seed=0)
@@ -99,17 +116,22 @@ def test_serving_mix_rounds_and_queues(n, precision):
     two_d = segs[np.array([cfgs[i].dim == 2 for i in segs[:, 0]])]
     rows = two_d[:, 3] - two_d[:, 2]
     # the 2D items: at most 256 rows, one round of the waves where the work
-    # allows it, tallest first; 1D runs after them
+    # allows it, lattices with the tallest bands first
     assert rows.max() <= 256
     strip_rows = sum(_strips(c)[0] * c.ny for c in cfgs if c.dim == 2)
     rounds = -(-strip_rows // (WAVES * 256))
-    if rounds == 1:
-        assert len(two_d) <= WAVES or rows.max() >= strip_rows // (2 * WAVES)
-    first_1d = np.argmax([cfgs[i].dim == 1 for i in segs[:, 0]])
-    assert all(cfgs[i].dim == 1 for i in segs[first_1d:, 0])
-    heights = [max(s[3] - s[2] for s in two_d[two_d[:, 0] == i]) for i in dict.fromkeys(two_d[:, 0])]
+    parts = _queue_parts(cfgs, qs, segs)
+    bands = np.concatenate(parts)
+    heights = [max(s[3] - s[2] for s in bands[bands[:, 0] == i]) for i in dict.fromkeys(bands[:, 0])]
     assert heights == sorted(heights, reverse=True)
-    _queues_balanced(cfgs, qs, segs, 0.05)
+    if len(two_d) <= WAVES:
+        # one round: every band is the first item of a wave of its XCD
+        assert max(len(p) for p in parts) <= WAVES // 8
+    else:
+        assert rounds > 1 or rows.max() >= strip_rows // (2 * WAVES)
+        work = [sum(_cost(cfgs[s[0]], s) for s in p) for p in parts]
+        mean = sum(work) / 8
+        assert max(work) <= 1.05 * mean and min(work) >= 0.95 * mean, [w / mean for w in work]
 
 
 def test_small_mix_and_3d_left_out():
@@ -141,3 +163,22 @@ def test_plan_rejects_bad_input():
     cfg.cfl = 2.0
     with pytest.raises(A.ArlbmError):
         A.plan_schedule([cfg], WAVES)
+
+
+def test_heavy_round_with_1d_runs():
+    """2D bands filling one round of the waves beside 1D lattices: every band
+    is a wave's first item and the 1D strips go in runs of at least 8, dealt
+    round robin to the ends of the queues."""
+    cfgs = [A.config_from(W.euler_seeded_2d(s, n=n), precision=A.F32)
+            for s, n in enumerate((1000, 984, 900, 882, 861, 742, 692, 602, 525, 507, 469, 431))]
+    cfgs += [A.config_from(W.euler_seeded_1d(s, n=n), precision=A.F32) for s, n in enumerate((60603, 33971, 8438))]
+    qs, segs, nw = A.plan_schedule(cfgs, WAVES)
+    _check_cover(cfgs, qs, segs)
+    parts = _queue_parts(cfgs, qs, segs)
+    assert sum(len(p) for p in parts) <= WAVES
+    assert max(len(p) for p in parts) <= WAVES // 8
+    one_d = segs[np.array([cfgs[i].dim == 1 for i in segs[:, 0]])]
+    lengths = one_d[:, 3] - one_d[:, 1]
+    ends = {i: _strips(cfgs[i])[0] for i in set(one_d[:, 0])}
+    inner = np.array([s[3] < ends[s[0]] for s in one_d])
+    assert np.all(lengths[inner] >= 8)
