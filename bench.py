@@ -153,21 +153,32 @@ def _drain(srv, want):
     return res
 
 
-def time_batched(torch, problems, precision, steps, warmup):
+def time_batched(torch, problems, precision, steps, warmup, repeats=None):
     """Steps of the batched kernel over the given lattices, all resident:
     the server admits them and runs the warm-up launches in one call, then
     one call makes the K timed launches (each a batched step of every
-    lattice), timed with events on the server's stream."""
+    lattice), timed with events on the server's stream.  repeats=(r, k):
+    afterwards r more timed calls of k launches each, whose times per launch
+    are appended to the list `repeats_ms` returned as a third value."""
     need = sum(A.query_sizes(A.config_from(p, precision=precision)).total_bytes for p in problems)
     srv = A.Server(int(need * 1.3) + (64 << 20), precision)
     warmup = max(warmup, 1)
-    ids = [srv.submit(A.config_from(p, precision=precision), p.U0, p.bed, warmup + steps + 1) for p in problems]
+    extra = repeats[0] * repeats[1] if repeats else 0
+    ids = [srv.submit(A.config_from(p, precision=precision), p.U0, p.bed, warmup + steps + extra + 1)
+           for p in problems]
     srv.iterate(warmup)
     with Timer(torch) as tm:
         srv.iterate(steps)
+    reps = []
+    for _ in range(repeats[0] if repeats else 0):
+        with Timer(torch) as tr:
+            srv.iterate(repeats[1])
+        reps.append(tr.ms / repeats[1])
     res = _drain(srv, ids)
     srv.close()
     bad = [res[i]["status"] for i in ids if res[i]["status"] != 0]
+    if repeats:
+        return tm.ms, bad, reps
     return tm.ms, bad
 
 
@@ -175,10 +186,16 @@ def run_throughput(torch, args, p, tag):
     """FP32 batched (the metric's path), FP32 single-lattice and FP64 plain
     on the same lattice, K timed steps each."""
     log(f"[{tag}] {p.name}: FP32 batched, warmup {args.warmup}, timed {args.steps}")
-    ms_b, bad = time_batched(torch, [p], A.F32, args.steps, args.warmup)
-    out = {"fp32_batched": {"ms_per_step": ms_b / args.steps, "failed": bad}}
     if args.only:
-        return out
+        ms_b, bad = time_batched(torch, [p], A.F32, args.steps, args.warmup)
+        return {"fp32_batched": {"ms_per_step": ms_b / args.steps, "failed": bad}}
+    # then 5 repeats of 200 launches each: their median and spread beside
+    # the K-launch figure
+    ms_b, bad, reps = time_batched(torch, [p], A.F32, args.steps, args.warmup, repeats=(5, 200))
+    out = {"fp32_batched": {"ms_per_step": ms_b / args.steps, "failed": bad,
+                            "repeats_ms_per_step": {"n": len(reps), "launches_each": 200,
+                                                    "median": float(np.median(reps)), "min": float(min(reps)),
+                                                    "max": float(max(reps))}}}
     log(f"[{tag}] FP32 single-lattice kernel")
     ms_s, st = time_plain(torch, p, A.F32, args.steps, args.warmup)
     out["fp32_single"] = {"ms_per_step": ms_s / args.steps, "flags": st["flags"]}
