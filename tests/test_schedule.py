@@ -83,12 +83,6 @@ def test_shallow_water_alone_gets_tall_bands():
     assert (segs[:, 3] - segs[:, 2]).max() == 142
 
 
-def _queues_balanced(cfgs, qs, segs, tol):
-    work = [sum(_cost(cfgs[s[0]], s) for s in segs[qs[q]:qs[q + 1]]) for q in range(8)]
-    mean = sum(work) / 8
-    assert max(work) <= (1 + tol) * mean and min(work) >= (1 - tol) * mean, [w / mean for w in work]
-
-
 def _queue_parts(cfgs, qs, segs):
     """Each queue: its 2D bands, then its 1D runs (the runs dealt round
     robin over the queues, largest first)."""
