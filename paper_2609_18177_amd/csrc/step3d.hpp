@@ -79,7 +79,8 @@ __device__ __forceinline__ void load_U3(const LatticeDesc &L, const T *u, int i,
 // its own 1.34; tiles of 16 rows 1.23-1.27; the same with populations
 // requested two planes ahead (8 waves of 256 registers) 1.29; requesting
 // each group of the next plane as soon as its registers are free 1.68; the
-// collision before the indicator 1.195.
+// collision before the indicator 1.195; with the non-temporal accesses below
+// 1.135-1.17 (0.50-0.52 of the HBM peak at 280 B per update).
 template <typename T>
 struct Tile3 {
     static constexpr int TX = sizeof(T) == 4 ? 32 : 16, TY = 16;
@@ -110,10 +111,6 @@ __host__ __device__ inline int k3_chunks(int ntiles, int nz, int num_cus)
 // A 3D velocity mirrored through its axis (1 <-> 4, 2 <-> 5, 3 <-> 6).
 __device__ __forceinline__ int mirror3(int k) { return k <= 3 ? k + 3 : k - 3; }
 
-// A uniform base pointer and plane stride made opaque where they are used:
-// the compiler then forms each field's address there (a few scalar ops)
-// instead of holding one 64-bit address per field across the plane loop,
-// which exceeds the scalar registers.
 // Populations of the old state read and the new state stored non-temporal:
 // nothing reads them again in this step, and they stay out of the way of the
 // moments the tiles' halos read from L2 (256^3 Euler FP32, ms per step:
@@ -130,6 +127,10 @@ __device__ __forceinline__ T ldo_nt(const T *base, unsigned off)
     return __builtin_nontemporal_load(base + off);
 }
 
+// A uniform base pointer and plane stride made opaque where they are used:
+// the compiler then forms each field's address there (a few scalar ops)
+// instead of holding one 64-bit address per field across the plane loop,
+// which exceeds the scalar registers.
 template <typename P>
 __device__ __forceinline__ void opaque(P *&base, int64_t &stride)
 {
