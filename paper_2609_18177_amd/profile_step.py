@@ -151,6 +151,12 @@ def main():
     stats = kernel_stats(os.path.join(d, "run_kernel_stats.csv"), kname)
     if stats is None:
         raise SystemExit(f"kernel {kname} not found in the trace")
+    # the benchmark's own event-timed figure of the traced run
+    event_ms = None
+    with open(os.path.join(raw, "trace.log")) as f:
+        for ln in f:
+            if ln.startswith(f"[only] {args.workload} ms/step "):
+                event_ms = float(ln.split()[-1])
     extra_names = EXTRA_KERNELS.get(args.workload, [])
     extra_stats = {k: kernel_stats(os.path.join(d, "run_kernel_stats.csv"), k) for k in extra_names}
     pmc_prog = ["bench.py", "--only", args.workload, "--steps", "10", "--warmup", "2"]
@@ -181,6 +187,7 @@ def main():
     wl = WORKLOAD_NAMES[args.workload]
     rec = {"workload": wl, "kernel": kname, "kernel_source_sha256_16": bench.kernel_source_hash(),
            "avg_kernel_ns": stats["avg_ns"] if stats else None, "kernel_calls": stats["calls"] if stats else None,
+           "event_ms_per_step_same_run": event_ms,
            "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,
            "copy_fetch_kib_for_1GiB": copy_fetch_kib, "copy_write_kib_for_1GiB": copy_write_kib,
            "read_scale": read_scale, "write_scale": write_scale,
@@ -208,6 +215,8 @@ def main():
             f.write(f"| kernel calls (trace run) | {stats['calls']} |\n")
             f.write(f"| average kernel duration | {stats['avg_ns'] / 1e3:.2f} us |\n")
             f.write(f"| min / max duration | {stats['min_ns'] / 1e3:.2f} / {stats['max_ns'] / 1e3:.2f} us |\n")
+        if event_ms is not None:
+            f.write(f"| bench.py's event-timed time per step, same traced run | {event_ms * 1e3:.2f} us |\n")
         f.write(f"| FETCH_SIZE per dispatch | {fetch_kib:.4g} KiB ({nf} dispatches) |\n")
         f.write(f"| WRITE_SIZE per dispatch | {write_kib:.4g} KiB ({nw} dispatches) |\n")
         f.write(f"| 1 GiB copy: FETCH_SIZE / WRITE_SIZE | {copy_fetch_kib:.4g} / {copy_write_kib:.4g} KiB |\n")
