@@ -568,7 +568,9 @@ def roofline(kernel, workload, alg_bytes, lups, ms):
             "traffic": prof["hbm_bytes_per_launch"] if prof else None,
             "kernel": kernel, "alg_bytes_per_lup": alg_bytes, "lups_per_launch": lups,
             "alg_bytes_per_launch": alg_bytes * lups, "avg_kernel_ms": ms,
-            "avg_kernel_ms_rocprof": prof["avg_kernel_ns"] / 1e6 if prof else None}
+            "avg_kernel_ms_rocprof": prof["avg_kernel_ns"] / 1e6 if prof else None,
+            # counter traffic over the profiled kernel time: the DRAM rate
+            "traffic_gbs": prof["hbm_bytes_per_launch"] / prof["avg_kernel_ns"] if prof else None}
 
 
 def main():
@@ -700,7 +702,8 @@ def main():
     extra["roofline_batched_serving_fixed_mix"] = {
         "bound": "hbm", "achieved": fx["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fx["alg_frac"],
         "traffic": prof["hbm_bytes_per_launch"] if prof else None, "alg_bytes_per_launch": fx["alg_bytes_per_launch"],
-        "avg_kernel_ms": fx["ms_per_launch"], "avg_kernel_ms_rocprof": prof["avg_kernel_ns"] / 1e6 if prof else None}
+        "avg_kernel_ms": fx["ms_per_launch"], "avg_kernel_ms_rocprof": prof["avg_kernel_ns"] / 1e6 if prof else None,
+        "traffic_gbs": prof["hbm_bytes_per_launch"] / prof["avg_kernel_ns"] if prof else None}
     print(json.dumps(line), flush=True)
 
 
