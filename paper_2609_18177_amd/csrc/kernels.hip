@@ -76,7 +76,7 @@ static hipError_t step_impl(const LatticeDesc &h, int64_t iter, hipStream_t s)
 {
     if constexpr (D == 3) {
         // one fused pass: tiles x plane chunks filling the chip once
-        using G = Tile3<real>;
+        using G = Tile3<SYS, real>;
         const int nt = k3_tiles(h.nx, h.ny, G::TX, G::TY);
         const int nb = nt * k3_chunks(nt, h.nz, num_cus());
         hipLaunchKernelGGL((k3_step<SYS, real>), dim3(nb), dim3(G::kThreads), 0, s, h, iter);

@@ -81,9 +81,14 @@ __device__ __forceinline__ void load_U3(const LatticeDesc &L, const T *u, int i,
 // each group of the next plane as soon as its registers are free 1.68; the
 // collision before the indicator 1.195; with the non-temporal accesses below
 // 1.135-1.17 (0.50-0.52 of the HBM peak at 280 B per update).
-template <typename T>
+template <int SYS, typename T>
 struct Tile3 {
-    static constexpr int TX = sizeof(T) == 4 ? 32 : 16, TY = 16;
+    // FP32 reactive Euler (six fields, the Arrhenius rate at every pulled
+    // source) in tiles of 8 rows: 448 threads of 249 registers instead of 768
+    // spilling 384 bytes each (256^3: 2.73 -> 2.45 ms per step; advection in
+    // tiles of 24 rows, 1024 threads: 0.33 -> 0.44, not kept)
+    static constexpr int TX = sizeof(T) == 4 ? 32 : 16;
+    static constexpr int TY = SYS == 3 && sizeof(T) == 4 ? 8 : 16;
     static constexpr int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;  // moments: tile + 3
     static constexpr int W2 = TX + 4, H2 = TY + 4, N2 = W2 * H2;  // indicator: tile + 2
     static constexpr int W1 = TX + 2, H1 = TY + 2, N1 = W1 * H1;  // omega: tile + 1
@@ -138,9 +143,9 @@ __device__ __forceinline__ void opaque(P *&base, int64_t &stride)
 }
 
 template <int SYS, typename T>
-__global__ __launch_bounds__(Tile3<T>::kThreads) void k3_step(LatticeDesc L, int64_t iter)
+__global__ __launch_bounds__((Tile3<SYS, T>::kThreads)) void k3_step(LatticeDesc L, int64_t iter)
 {
-    using G = Tile3<T>;
+    using G = Tile3<SYS, T>;
     constexpr int D = 3, M = SysInfo<SYS, 3>::M, Q = 7;
     constexpr int TX = G::TX, TY = G::TY, W3 = G::W3, W2 = G::W2, W1 = G::W1;
     __shared__ T lu[4][M][G::N3];
