@@ -71,30 +71,45 @@ __device__ __forceinline__ void load_U3(const LatticeDesc &L, const T *u, int i,
 // FP32).  Sums keep the order of the cell-parallel formulation (k = 0 .. 6
 // in 2.8, the box sum as above), so FP64 results are the oracle's bits.
 //
-// Tiles of 16 rows, 32 columns in FP32 (rows start on 128-byte lines; 768
-// threads, 168 registers) and 16 in FP64 (448 threads; the destination
-// threads need all 256 registers).  A 256^3 lattice is 128 FP32 tiles in two
-// plane chunks, 256 FP64 tiles in one: one block per CU.  Measured at 256^3
-// Euler FP32 (ms per step): tiles of 8 rows with the indicator in waves of
-// its own 1.34; tiles of 16 rows 1.23-1.27; the same with populations
-// requested two planes ahead (8 waves of 256 registers) 1.29; requesting
-// each group of the next plane as soon as its registers are free 1.68; the
-// collision before the indicator 1.195; with the non-temporal accesses below
-// 1.135-1.17 (0.50-0.52 of the HBM peak at 280 B per update).
+// Tiles of 32 x 16 columns.  Euler (FP32 and FP64) and FP64 advection: 512
+// threads, all of them destination threads (two waves per SIMD, up to 256
+// registers), each evaluating one or two indicator cells.  FP32 advection:
+// 768 threads, the first 512 the destination threads.  A 256^3 lattice is
+// 128 tiles in two plane chunks: one block per CU.  Measured at 256^3 Euler
+// FP32 (ms per step): tiles of 8 rows with the indicator in waves of its own
+// 1.34; tiles of 16 rows in 768 threads of 168 registers 1.23-1.27; the same
+// with populations requested two planes ahead (8 waves of 256 registers)
+// 1.29; requesting each group of the next plane as soon as its registers are
+// free 1.68; the collision before the indicator 1.195; with the
+// non-temporal accesses below 1.135-1.17; with the late moment loads (below)
+// 1.16-1.18, and in 512 threads 1.136-1.14 (768 threads spilled 20 bytes per
+// lane; 512 threads of 32 x 24 tiles: 2.03; 32 x 8 tiles: 1.53; advection in
+// 512 threads: 0.33 -> 0.37).  Euler FP64: 16 x 16 tiles of 448 threads (one
+// destination wave per SIMD) 4.09; 16 x 32 and 32 x 16 of 512 threads 3.18
+// and 3.07 (the three-pass version before the fusion: 3.2).
 template <int SYS, typename T>
 struct Tile3 {
     // FP32 reactive Euler (six fields, the Arrhenius rate at every pulled
     // source) in tiles of 8 rows: 448 threads of 249 registers instead of 768
     // spilling 384 bytes each (256^3: 2.73 -> 2.45 ms per step; advection in
-    // tiles of 24 rows, 1024 threads: 0.33 -> 0.44, not kept)
-    static constexpr int TX = sizeof(T) == 4 ? 32 : 16;
+    // tiles of 24 rows, 1024 threads: 0.33 -> 0.44, not kept).  FP64 reactive
+    // Euler keeps 16 x 16 tiles (six fields of a 32 x 16 tile and its halo
+    // exceed the LDS), of 256 threads that all collide: one wave per SIMD,
+    // with room for 512 registers, against 448 threads of which 256 collide
+    // and spill 464 bytes each (256^3: 10.3 -> 5.3 ms per step; in FP32 the
+    // same made reactive Euler slower, 2.41 -> 2.76).
+    static constexpr bool kWide64 = sizeof(T) == 8 && SYS != 3;
+    static constexpr int TX = sizeof(T) == 4 || kWide64 ? 32 : 16;
     static constexpr int TY = SYS == 3 && sizeof(T) == 4 ? 8 : 16;
     static constexpr int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;  // moments: tile + 3
     static constexpr int W2 = TX + 4, H2 = TY + 4, N2 = W2 * H2;  // indicator: tile + 2
     static constexpr int W1 = TX + 2, H1 = TY + 2, N1 = W1 * H1;  // omega: tile + 1
     static constexpr int NT = TX * TY;
     static constexpr int kDest = (NT + kWave - 1) / kWave * kWave;  // destination threads
-    static constexpr int kThreads = ((N2 > NT ? N2 : NT) + kWave - 1) / kWave * kWave;
+    // every thread collides and evaluates one or two indicator cells, or (FP32
+    // advection and reactive Euler) one indicator cell each
+    static constexpr bool kAllDest = sizeof(T) == 8 || SYS == 1;
+    static constexpr int kThreads = kAllDest ? kDest : ((N2 > NT ? N2 : NT) + kWave - 1) / kWave * kWave;
     static constexpr int kUPer = (N3 + kThreads - 1) / kThreads;  // cells per thread: moments,
     static constexpr int kNPer = (N2 + kThreads - 1) / kThreads;  // indicator,
     static constexpr int kWPer = (N1 + kThreads - 1) / kThreads;  // omega
@@ -546,12 +561,19 @@ __global__ __launch_bounds__((Tile3<SYS, T>::kThreads)) void k3_step(LatticeDesc
     T fown[3][M], fpull[4][M];
     if (is_dest) dest_load(za - 1, fown, fpull);
     __syncthreads();
+    // FP32 Euler and reactive Euler request the moments of plane s + 4 after
+    // the indicator, so that they hold no registers during the collision, and
+    // put them into LDS after the next omega (256^3 Euler FP32: 1.19 -> 1.16
+    // ms per step; with it advection took 0.33 -> 0.38, Euler FP64 in 16 x 32
+    // tiles 3.18 -> 3.33)
+    constexpr bool kLate = sizeof(T) == 4 && SYS != 0;
     for (int s = za - 1; s <= zb; ++s) {
-        if (s + 3 <= zb + 2) {
+        if (!kLate && s + 3 <= zb + 2) {
             u_store(s + 3, Unext);
             if (s + 4 <= zb + 2) u_load(s + 4, Unext);
         }
         w_stage(s);
+        if (kLate && s + 3 <= zb + 2) u_store(s + 3, Unext);
         __syncthreads();
         // the collision first: the next plane's populations are requested
         // before the indicator is evaluated, so they arrive during it and the
@@ -562,6 +584,7 @@ __global__ __launch_bounds__((Tile3<SYS, T>::kThreads)) void k3_step(LatticeDesc
             if (s < zb) dest_load(s + 1, fown, fpull);
         }
         if (s + 2 <= zb + 1) nu_stage(s + 2);
+        if (kLate && s + 4 <= zb + 2) u_load(s + 4, Unext);
         __syncthreads();
     }
     if (blockIdx.x == 0 && tid < kWave) scalar_update(L, n, cf.dt);
