@@ -131,11 +131,11 @@ __host__ __device__ inline int k3_chunks(int ntiles, int nz, int num_cus)
 // A 3D velocity mirrored through its axis (1 <-> 4, 2 <-> 5, 3 <-> 6).
 __device__ __forceinline__ int mirror3(int k) { return k <= 3 ? k + 3 : k - 3; }
 
-// Populations of the old state read and the new state stored non-temporal:
-// nothing reads them again in this step, and they stay out of the way of the
-// moments the tiles' halos read from L2 (256^3 Euler FP32, ms per step:
-// stores 1.200 -> 1.156, then loads 1.163 -> 1.135; in the 2D kernels
-// either made the step 2-30% slower).
+// Populations of the old state read (except the +-x pulls, below) and the
+// new state stored non-temporal: nothing reads them again in this step, and
+// they stay out of the way of the moments the tiles' halos read from L2
+// (256^3 Euler FP32, ms per step: stores 1.200 -> 1.156, then loads 1.163 ->
+// 1.135; in the 2D kernels either made the step 2-30% slower).
 template <typename T>
 __device__ __forceinline__ void sto_nt(T *base, unsigned off, T v)
 {
@@ -446,12 +446,19 @@ __global__ __launch_bounds__((Tile3<SYS, T>::kThreads)) void k3_step(LatticeDesc
             fown[2][c] = need6 ? ldo_nt(fi + (int64_t)(6 * M + c) * ps, pb + doff) : T(0);
         }
         if (!mid) return;
+        // the +-x pulls read one cell of the line the neighbouring tile
+        // reads the rest of at about the same time: they are kept in L2
+        // (non-temporal, the line was often gone by the second read: 256^3
+        // Euler FP32 read 2.81 GB per step instead of 2.73, at equal time)
         if (!refl_xy) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int k = j < 2 ? j + 1 : j + 2;
 #pragma unroll
-                for (int c = 0; c < M; ++c) fpull[j][c] = ldo_nt(fi + (int64_t)(k * M + c) * ps, pb + poff[j]);
+                for (int c = 0; c < M; ++c) {
+                    const T *src = fi + (int64_t)(k * M + c) * ps;
+                    fpull[j][c] = k == 1 || k == 4 ? ldo(src, pb + poff[j]) : ldo_nt(src, pb + poff[j]);
+                }
             }
         } else {
 #pragma unroll
@@ -459,7 +466,10 @@ __global__ __launch_bounds__((Tile3<SYS, T>::kThreads)) void k3_step(LatticeDesc
                 const int k = j < 2 ? j + 1 : j + 2;
                 const int ks = (refl_m >> j) & 1u ? mirror3(k) : k;
 #pragma unroll
-                for (int c = 0; c < M; ++c) fpull[j][c] = __builtin_nontemporal_load(fi + ((int64_t)(ks * M + c) * ps + pb + poff[j]));
+                for (int c = 0; c < M; ++c) {
+                    const T *src = fi + (int64_t)(ks * M + c) * ps;
+                    fpull[j][c] = k == 1 || k == 4 ? ldo(src, pb + poff[j]) : ldo_nt(src, pb + poff[j]);
+                }
             }
         }
     };
