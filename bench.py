@@ -51,8 +51,10 @@ KERNEL_SOURCES = ["paper_2609_18177_amd/csrc/step.hpp", "paper_2609_18177_amd/cs
 ONLY = ["euler2d_batched_f32", "euler2d_f32", "euler2d_f64", "swe2d_batched_f32", "swe2d_f32", "euler3d_f32",
         "serving", "serving_fixed_f32"]
 # FP32-vs-FP64 bounds per served system (relative L1 over all fields of a
-# request's result): see the serving section of the design doc for the measured
-# values and the conditioning they rest on
+# request's result), set above the largest error measured over the served
+# requests; shallow water's is loose because a wet/dry front moves with a
+# single cell's rounding, so the FP64 result itself changes by about as much
+# when its initial data are rounded to FP32
 SERVED_FP32_TOL = {"euler1d": 5e-3, "euler2d": 2e-3, "swe2d": 1.5e-1}
 
 

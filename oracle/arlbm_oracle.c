@@ -14,7 +14,7 @@
  *   source node and pull streaming (the implementation form after (2.7)) ->
  *   implicit moment update (2.8) -> second half source.
  *
- * Readings where the paper is silent (each is listed in the design doc):
+ * Readings where the paper is silent:
  *   - left eigenvectors: L = R^{-1}, R with first component 1 in every
  *     acoustic/entropy column, shear columns (0,..,1,..) (Toro's form);
  *   - boundaries: ghost cells by a mirror index map U(-1-i) <- U(i) (depth 2

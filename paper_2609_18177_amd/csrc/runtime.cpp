@@ -1198,7 +1198,7 @@ int64_t build_schedule(const std::vector<SchedLattice> &lats, int64_t W, std::ve
     for (const SchedLattice &l : lats)
         if (l.one_d) strips1d += l.ncols;
     const int64_t free_waves = W - (int64_t)big.size();
-    const int64_t spread = free_waves >= W / 8 ? (strips1d + free_waves - 1) / free_waves
+    const int64_t spread = free_waves > 0 && free_waves >= W / 8 ? (strips1d + free_waves - 1) / free_waves
                                                : std::max<int64_t>((strips1d + W - 1) / W, kRun1dMix);
     for (const SchedLattice &l : lats) {
         if (!l.one_d) continue;

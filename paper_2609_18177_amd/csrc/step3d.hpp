@@ -62,7 +62,8 @@ __device__ __forceinline__ void load_U3(const LatticeDesc &L, const T *u, int i,
 //      bounds (2.19).  The thread then requests the next plane's populations,
 //      which arrive during the rest of the iteration.  Then (all threads) the
 //      indicator (2.13-2.14) of plane s+2 over the tile and a two-cell halo,
-//      from the LDS moments of planes s+1 .. s+3.
+//      from the LDS moments of planes s+1 .. s+3, and (FP32 Euler and
+//      reactive Euler) the request of plane s+4's moments.
 //
 // Every population of the old state is read from HBM once and every
 // population and moment of the new state written once; the old moments are

@@ -176,3 +176,15 @@ def test_heavy_round_with_1d_runs():
     ends = {i: _strips(cfgs[i])[0] for i in set(one_d[:, 0])}
     inner = np.array([s[3] < ends[s[0]] for s in one_d])
     assert np.all(lengths[inner] >= 8)
+
+
+@pytest.mark.parametrize("waves", [1, 2, 3, 4, 5, 7, 8, 9])
+def test_few_waves(waves):
+    """A launch of fewer waves than XCDs (a host plan asked for any count):
+    with the 2D bands taking every wave, the 1D strips still go in runs and
+    every cell is covered once."""
+    cfgs = [A.config_from(W.euler_seeded_2d(0, n=200), precision=A.F32),
+            A.config_from(W.euler_seeded_1d(1, n=5000), precision=A.F32)]
+    qs, segs, nw = A.plan_schedule(cfgs, waves)
+    _check_cover(cfgs, qs, segs)
+    assert 1 <= nw <= waves
