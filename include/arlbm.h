@@ -323,6 +323,18 @@ int arlbm_server_destroy(arlbm_server *s);
 int arlbm_plan_schedule(const arlbm_config *cfgs, int32_t n, int32_t waves, int32_t *queue_start,
                         int32_t *segs, int32_t max_segs, int32_t *nsegs, int32_t *nwaves);
 
+/* How the server splits lattices of configurations cfgs[0..n-1] served
+ * together into batched launches of at most `waves` waves, computed on the
+ * host (no GPU needed).  When their 2D work needs more than one round of
+ * the waves, the lattices are split into groups that each fit one round, and
+ * each group is one launch of the step, the groups one after the other;
+ * otherwise there is one group.  On return group_of[i] (n entries, caller
+ * owned) is lattice i's group in 0 .. *ngroups-1, or -1 for a 3D lattice
+ * (its step is a launch of its own).  arlbm_plan_schedule on the
+ * configurations of one group gives that launch's work list.  EINVAL on a
+ * bad configuration or argument. */
+int arlbm_plan_groups(const arlbm_config *cfgs, int32_t n, int32_t waves, int32_t *group_of, int32_t *ngroups);
+
 /* Vector registers per lane of the fused step kernel for a precision, system
  * and dimension (from the code object; in 2D the kernel that a lattice of
  * even nx runs), or -1. */

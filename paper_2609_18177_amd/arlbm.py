@@ -117,6 +117,8 @@ def lib():
             "arlbm_plan_schedule": ([C.POINTER(Config), C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_int32)], C.c_int),
+            "arlbm_plan_groups": ([C.POINTER(Config), C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32)], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -400,3 +402,14 @@ def plan_schedule(cfgs, waves: int):
     _check(lib().arlbm_plan_schedule(arr, len(cfgs), int(waves), ip(qs), ip(sg), ns.value, C.byref(ns),
                                      C.byref(nw)))
     return qs, sg[:4 * ns.value].reshape(-1, 4), nw.value
+
+
+def plan_groups(cfgs, waves: int):
+    """How the server splits these configurations into batched launches
+    (host only): (group of each lattice, -1 for 3D; number of groups)."""
+    arr = (Config * max(len(cfgs), 1))(*cfgs)
+    grp = np.zeros(max(len(cfgs), 1), dtype=np.int32)
+    ng = C.c_int32()
+    _check(lib().arlbm_plan_groups(arr, len(cfgs), int(waves), grp.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   C.byref(ng)))
+    return grp[:len(cfgs)], ng.value

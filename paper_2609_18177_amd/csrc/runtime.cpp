@@ -999,8 +999,13 @@ struct arlbm_server {
     size_t hcap_table[2] = {0, 0};
     hipEvent_t table_ev[2] = {nullptr, nullptr};
     int table_set = 0;
-    int32_t nwaves = 0;                  // waves of the batched launch
-    size_t off_start = 0, off_segs = 0;  // byte offsets in the table
+    // the batched launches of a step (launch_groups): waves and the byte
+    // offsets of the queue starts and items in the table
+    struct Launch {
+        int32_t nwaves;
+        size_t off_start, off_segs;
+    };
+    std::vector<Launch> launches;
     // queue counters of the batched launch: two sets (launch parity) of
     // kQueues counters 128 bytes apart; a launch takes items with one set and
     // zeroes the other for the next launch
@@ -1136,17 +1141,16 @@ struct SchedLattice {
     int64_t unit;   // cost per row (2D) or per strip (1D)
 };
 
-// Items in queue order and the start of each XCD's part (kQueues + 1
-// entries); returns the number of waves to launch.
-int64_t build_schedule(const std::vector<SchedLattice> &lats, int64_t W, std::vector<Segment> &segs,
-                       std::vector<int32_t> &qstart)
+// The band height h of a one-launch schedule for these lattices and its
+// rounds r (items per wave): the lowest height at most kMaxRows2d that puts
+// at most one item on every wave, else two or more rounds.
+void band_height(const std::vector<SchedLattice> &lats, int64_t W, int64_t &h, int64_t &r)
 {
-    segs.clear();
-    qstart.assign(kQueues + 1, 0);
     int64_t S = 0;  // 2D strip rows
     for (const SchedLattice &l : lats)
         if (!l.one_d) S += (int64_t)l.ncols * l.ny;
-    int64_t h = kMaxRows2d, r = 1;
+    h = kMaxRows2d;
+    r = 1;
     if (S > 0) {
         r = std::max<int64_t>(1, (S + W * kMaxRows2d - 1) / (W * kMaxRows2d));
         h = std::max<int64_t>(kMinRows2d, (S + W * r - 1) / (W * r));
@@ -1166,6 +1170,17 @@ int64_t build_schedule(const std::vector<SchedLattice> &lats, int64_t W, std::ve
             }
         }
     }
+}
+
+// Items in queue order and the start of each XCD's part (kQueues + 1
+// entries); returns the number of waves to launch.
+int64_t build_schedule(const std::vector<SchedLattice> &lats, int64_t W, std::vector<Segment> &segs,
+                       std::vector<int32_t> &qstart)
+{
+    segs.clear();
+    qstart.assign(kQueues + 1, 0);
+    int64_t h, r;
+    band_height(lats, W, h, r);
     // each lattice in bands of equal height, at most h; lattices with the
     // tallest bands first
     struct Item {
@@ -1240,6 +1255,117 @@ int64_t build_schedule(const std::vector<SchedLattice> &lats, int64_t W, std::ve
     return std::min<int64_t>(W, (int64_t)segs.size());
 }
 
+// Launch groups of the batched step.  When the resident 2D work needs more
+// than one round of the waves, one launch would deal several bands to each
+// wave, and its items differ in cost per row (a shallow-water strip of two
+// columns per lane moves 1.5 times an Euler strip's bytes per row, one of one
+// column 0.75 times): the waves end far apart.  The lattices are instead
+// split into groups of one cost per strip row, each group one launch of one
+// round sized to fill the waves, the launches one after the other on the
+// stream (every lattice in exactly one group, so it is stepped once per
+// iteration with the same bits).  A class with fewer than kMinGroupRows
+// rows per wave joins the class nearest in cost; a class still needing more
+// than one round is split, largest lattices first into the group with the
+// least work, into the fewest groups that each fit one round (a single
+// lattice that does not cannot be shortened by any split); the 1D lattices
+// join the lightest group; past kMaxGroups groups, one launch.  The fixed
+// serving mix (20 Euler, 15 + 8 shallow-water and 22 1D lattices) took
+// 0.812 ms per step in one launch, 0.722 in two (Euler; shallow water and
+// 1D), 0.848 in two of mixed classes balanced by work, and 0.902 in one
+// launch of one round with bands of equal cost (158-487 rows).
+// Returns the group of each lattice (0 .. groups-1).
+constexpr int64_t kMaxGroups = 8, kMinGroupRows = 24;
+std::vector<int32_t> launch_groups(const std::vector<SchedLattice> &lats, int64_t W, int64_t &ngroups)
+{
+    std::vector<int32_t> grp(lats.size(), 0);
+    ngroups = 1;
+    int64_t h, r;
+    band_height(lats, W, h, r);
+    if (r == 1) return grp;
+    auto rows = [&](size_t i) { return lats[i].one_d ? (int64_t)0 : (int64_t)lats[i].ncols * lats[i].ny; };
+    // classes of one cost per strip row
+    struct Class {
+        int64_t unit, rows;
+        std::vector<size_t> members;
+    };
+    std::vector<Class> cls;
+    for (size_t i = 0; i < lats.size(); ++i) {
+        if (lats[i].one_d) continue;
+        auto it = std::find_if(cls.begin(), cls.end(), [&](const Class &c) { return c.unit == lats[i].unit; });
+        if (it == cls.end()) {
+            cls.push_back({lats[i].unit, 0, {}});
+            it = cls.end() - 1;
+        }
+        it->rows += rows(i);
+        it->members.push_back(i);
+    }
+    auto ratio = [](int64_t a, int64_t b) { return a > b ? (double)a / (double)b : (double)b / (double)a; };
+    auto merge_into_nearest = [&](size_t k) {
+        size_t best = k;
+        for (size_t j = 0; j < cls.size(); ++j)
+            if (j != k && (best == k || ratio(cls[j].unit, cls[k].unit) < ratio(cls[best].unit, cls[k].unit)))
+                best = j;
+        cls[best].rows += cls[k].rows;
+        cls[best].members.insert(cls[best].members.end(), cls[k].members.begin(), cls[k].members.end());
+        cls.erase(cls.begin() + (long)k);
+    };
+    for (bool again = true; again && cls.size() > 1;) {
+        again = false;
+        size_t k = 0;
+        for (size_t j = 1; j < cls.size(); ++j)
+            if (cls[j].rows < cls[k].rows) k = j;
+        if (cls[k].rows < W * kMinGroupRows) {
+            merge_into_nearest(k);
+            again = true;
+        }
+    }
+    while ((int64_t)cls.size() > kMaxGroups) {
+        size_t k = 0;
+        for (size_t j = 1; j < cls.size(); ++j)
+            if (cls[j].rows < cls[k].rows) k = j;
+        merge_into_nearest(k);
+    }
+    // each class in the fewest groups that fit one round
+    std::vector<std::vector<size_t>> groups;
+    for (Class &c : cls) {
+        std::stable_sort(c.members.begin(), c.members.end(), [&](size_t a, size_t b) { return rows(a) > rows(b); });
+        const int64_t nmax = std::min<int64_t>(kMaxGroups, (int64_t)c.members.size());
+        std::vector<std::vector<size_t>> best;
+        for (int64_t g = 1; g <= nmax && best.empty(); ++g) {
+            std::vector<std::vector<size_t>> part(g);
+            std::vector<int64_t> load(g, 0);
+            for (size_t i : c.members) {
+                const int64_t k = std::min_element(load.begin(), load.end()) - load.begin();
+                part[k].push_back(i);
+                load[k] += rows(i);
+            }
+            bool ok = true;
+            for (const auto &pg : part) {
+                std::vector<SchedLattice> sub;
+                for (size_t i : pg) sub.push_back(lats[i]);
+                int64_t hk, rk;
+                band_height(sub, W, hk, rk);
+                ok = ok && (rk == 1 || pg.size() == 1);
+            }
+            if (ok) best = part;
+        }
+        if (best.empty()) best.push_back(c.members);
+        for (auto &pg : best) groups.push_back(pg);
+    }
+    if (groups.size() < 2 || (int64_t)groups.size() > kMaxGroups) return grp;
+    std::vector<double> cost(groups.size(), 0.0);
+    for (size_t k = 0; k < groups.size(); ++k)
+        for (size_t i : groups[k]) {
+            grp[i] = (int32_t)k;
+            cost[k] += (double)rows(i) * (double)lats[i].unit;
+        }
+    const int32_t light = (int32_t)(std::min_element(cost.begin(), cost.end()) - cost.begin());
+    for (size_t i = 0; i < lats.size(); ++i)
+        if (lats[i].one_d) grp[i] = light;
+    ngroups = (int64_t)groups.size();
+    return grp;
+}
+
 // A schedule item of lattice i from its descriptor (1D and 2D lattices the
 // batched kernel steps).
 SchedLattice sched_lattice(int32_t i, const LatticeDesc &d)
@@ -1259,12 +1385,22 @@ int rebuild_table(arlbm_server *s)
         descs.push_back(d);
         if (!own_launch(d)) lats.push_back(sched_lattice((int32_t)i, d));
     }
-    std::vector<Segment> segs;
-    std::vector<int32_t> qstart;
-    const int64_t nw = lats.empty() ? 0 : build_schedule(lats, batched_waves(), segs, qstart);
-    s->off_start = align_up(sizeof(LatticeDesc) * descs.size());
-    s->off_segs = s->off_start + align_up(sizeof(int32_t) * (kQueues + 1));
-    const size_t bytes = s->off_segs + sizeof(Segment) * segs.size();
+    // one schedule per launch group, laid out after the descriptors
+    int64_t ng = 0;
+    const std::vector<int32_t> grp = lats.empty() ? std::vector<int32_t>() : launch_groups(lats, batched_waves(), ng);
+    std::vector<std::vector<Segment>> segs(ng);
+    std::vector<std::vector<int32_t>> qstart(ng);
+    std::vector<arlbm_server::Launch> launches(ng);
+    size_t bytes = align_up(sizeof(LatticeDesc) * descs.size());
+    for (int64_t k = 0; k < ng; ++k) {
+        std::vector<SchedLattice> sub;
+        for (size_t i = 0; i < lats.size(); ++i)
+            if (grp[i] == k) sub.push_back(lats[i]);
+        launches[k].nwaves = (int32_t)build_schedule(sub, batched_waves(), segs[k], qstart[k]);
+        launches[k].off_start = bytes;
+        launches[k].off_segs = bytes + align_up(sizeof(int32_t) * (kQueues + 1));
+        bytes = launches[k].off_segs + align_up(sizeof(Segment) * segs[k].size());
+    }
     hipError_t e;
     // the device table grows by reallocation, after the launches that still
     // read the old one
@@ -1305,13 +1441,16 @@ int rebuild_table(arlbm_server *s)
         }
         char *h = s->h_table[k];
         std::memcpy(h, descs.data(), sizeof(LatticeDesc) * descs.size());
-        if (!qstart.empty()) std::memcpy(h + s->off_start, qstart.data(), sizeof(int32_t) * qstart.size());
-        if (!segs.empty()) std::memcpy(h + s->off_segs, segs.data(), sizeof(Segment) * segs.size());
+        for (int64_t g = 0; g < ng; ++g) {
+            std::memcpy(h + launches[g].off_start, qstart[g].data(), sizeof(int32_t) * qstart[g].size());
+            if (!segs[g].empty())
+                std::memcpy(h + launches[g].off_segs, segs[g].data(), sizeof(Segment) * segs[g].size());
+        }
         e = hipMemcpyAsync(s->d_table, h, bytes, hipMemcpyHostToDevice, s->stream);
         if (e == hipSuccess) e = hipEventRecord(s->table_ev[k], s->stream);
         if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("table upload: ") + hipGetErrorString(e));
     }
-    s->nwaves = (int32_t)nw;
+    s->launches = launches;
     s->dirty = false;
     return ARLBM_OK;
 }
@@ -1759,15 +1898,17 @@ extern "C" int arlbm_server_iterate_n(arlbm_server *s, int32_t max_launches, int
     for (const Resident &r : s->resident) nl = std::min<int64_t>(nl, r.end_it - s->iter);
     for (int64_t l = 0; l < nl; ++l) {
         hipError_t e = hipSuccess;
-        if (s->nwaves > 0) {
+        for (const arlbm_server::Launch &g : s->launches) {
+            if (g.nwaves <= 0) continue;
             const LatticeDesc *dd = (const LatticeDesc *)s->d_table;
-            const int32_t *dq = (const int32_t *)(s->d_table + s->off_start);
-            const Segment *dg = (const Segment *)(s->d_table + s->off_segs);
+            const int32_t *dq = (const int32_t *)(s->d_table + g.off_start);
+            const Segment *dg = (const Segment *)(s->d_table + g.off_segs);
             const int32_t par = (int32_t)(s->batched_launches & 1);
             e = s->precision == ARLBM_F64
-                    ? f64::step_batched(dd, dg, dq, s->d_counters, par, s->nwaves, s->iter, s->stream)
-                    : f32::step_batched(dd, dg, dq, s->d_counters, par, s->nwaves, s->iter, s->stream);
+                    ? f64::step_batched(dd, dg, dq, s->d_counters, par, g.nwaves, s->iter, s->stream)
+                    : f32::step_batched(dd, dg, dq, s->d_counters, par, g.nwaves, s->iter, s->stream);
             ++s->batched_launches;
+            if (e != hipSuccess) break;
         }
         if (e != hipSuccess) return sfail(s, ARLBM_EDEVICE, std::string("batched launch: ") + hipGetErrorString(e));
         // lattices outside the batched kernel (3D; 2D beyond 4 GiB of
@@ -1853,15 +1994,14 @@ extern "C" int arlbm_server_destroy(arlbm_server *s)
     return ARLBM_OK;
 }
 
-extern "C" int arlbm_plan_schedule(const arlbm_config *cfgs, int32_t n, int32_t waves, int32_t *queue_start,
-                                   int32_t *segs, int32_t max_segs, int32_t *nsegs, int32_t *nwaves)
+// Schedule entries of the 1D and 2D lattices among configurations
+// cfgs[0..n-1] (lattice index = configuration index); "" or the first
+// configuration error.
+std::string plan_lattices(const arlbm_config *cfgs, int32_t n, std::vector<SchedLattice> &lats)
 {
-    if (!cfgs || n < 0 || waves < 1 || !nsegs || !nwaves || !queue_start)
-        return sfail(nullptr, ARLBM_EINVAL, "bad argument");
-    std::vector<SchedLattice> lats;
     for (int32_t i = 0; i < n; ++i) {
         std::string e = check_config(&cfgs[i]);
-        if (!e.empty()) return sfail(nullptr, ARLBM_EINVAL, e);
+        if (!e.empty()) return e;
         if (cfgs[i].dim == 3) continue;
         LatticeDesc d{};
         d.variant = variant_of(cfgs[i].system, cfgs[i].dim);
@@ -1870,6 +2010,33 @@ extern "C" int arlbm_plan_schedule(const arlbm_config *cfgs, int32_t n, int32_t 
         d.ny = (int32_t)cfgs[i].ny;
         lats.push_back(sched_lattice(i, d));
     }
+    return "";
+}
+
+extern "C" int arlbm_plan_groups(const arlbm_config *cfgs, int32_t n, int32_t waves, int32_t *group_of,
+                                 int32_t *ngroups)
+{
+    if (!cfgs || n < 0 || waves < 1 || !ngroups || (n > 0 && !group_of))
+        return sfail(nullptr, ARLBM_EINVAL, "bad argument");
+    std::vector<SchedLattice> lats;
+    std::string e = plan_lattices(cfgs, n, lats);
+    if (!e.empty()) return sfail(nullptr, ARLBM_EINVAL, e);
+    int64_t ng = 1;
+    const std::vector<int32_t> grp = lats.empty() ? std::vector<int32_t>() : launch_groups(lats, waves, ng);
+    for (int32_t i = 0; i < n; ++i) group_of[i] = -1;
+    for (size_t k = 0; k < lats.size(); ++k) group_of[lats[k].lattice] = grp[k];
+    *ngroups = lats.empty() ? 0 : (int32_t)ng;
+    return ARLBM_OK;
+}
+
+extern "C" int arlbm_plan_schedule(const arlbm_config *cfgs, int32_t n, int32_t waves, int32_t *queue_start,
+                                   int32_t *segs, int32_t max_segs, int32_t *nsegs, int32_t *nwaves)
+{
+    if (!cfgs || n < 0 || waves < 1 || !nsegs || !nwaves || !queue_start)
+        return sfail(nullptr, ARLBM_EINVAL, "bad argument");
+    std::vector<SchedLattice> lats;
+    std::string e = plan_lattices(cfgs, n, lats);
+    if (!e.empty()) return sfail(nullptr, ARLBM_EINVAL, e);
     std::vector<Segment> sg;
     std::vector<int32_t> qs(kQueues + 1, 0);
     const int64_t nw = lats.empty() ? 0 : build_schedule(lats, waves, sg, qs);

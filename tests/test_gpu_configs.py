@@ -349,6 +349,33 @@ def test_serving_several_launches_per_iterate_bitwise():
     say(f"[serving] {len(probs)} requests, 7 launches per iterate == 1, bitwise")
 
 
+@pytest.mark.parametrize("prec", [A.F32, A.F64])
+def test_serving_launch_groups_bitwise(prec):
+    """A mix whose 2D work needs more than one round of the waves is stepped
+    in several launches, one per cost class (Euler; shallow water of two
+    columns per lane; of one, with the 1D lattice): every result equals the
+    same lattice stepped alone on the single-lattice kernel, bit for bit."""
+    require_gpu()
+    import torch
+    probs = [dataclasses.replace(W.euler_seeded_2d(s, n=2048), steps=4) for s in range(3)]
+    probs += [dataclasses.replace(W.swe_bed_2d(s, n=n), steps=4) for s, n in ((0, 2048), (1, 2048), (2, 2047))]
+    probs.append(W.euler_seeded_1d(3, n=20000, steps=4))
+    cfgs = [A.config_from(p, precision=prec) for p in probs]
+    waves = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    grp, ng = A.plan_groups(cfgs, waves)
+    say(f"[groups] prec={prec} waves={waves} groups={ng} of {grp.tolist()}")
+    assert ng >= 2
+    need = sum(A.query_sizes(c).total_bytes for c in cfgs)
+    mix, _ = _serve(probs, int(need * 1.3) + (64 << 20), precision=prec)
+    for p, b in zip(probs, mix):
+        L = gpu_lattice(p, prec)
+        L.step(p.steps)
+        a = L.moments()
+        L.close()
+        assert b["status"] == 0 and b["steps"] == p.steps
+        assert np.array_equal(a, b["U"].reshape(a.shape)), p.name
+
+
 def test_serving_failed_admissions_leave_the_mix_intact():
     """Requests that fail the checks set_state makes after the initialisation
     (an all-dry shallow-water state: zero wave-speed bounds; an eps above the

@@ -188,3 +188,80 @@ def test_few_waves(waves):
     qs, segs, nw = A.plan_schedule(cfgs, waves)
     _check_cover(cfgs, qs, segs)
     assert 1 <= nw <= waves
+
+
+def _fixed_mix_cfgs(budget=4 * 2 ** 30):
+    """The default serving mix's requests in arrival order, as many as a
+    budget holds at once (FP32)."""
+    cfgs, used = [], 0
+    for r in W.serving_requests(512, rate_hz=200.0, seed=0):
+        c = A.config_from(r.problem(), precision=A.F32)
+        b = A.query_sizes(c).total_bytes * 1.25
+        if used + b > budget:
+            break
+        cfgs.append(c)
+        used += b
+    return cfgs
+
+
+def _two_d_items(cfgs, segs):
+    return int(np.sum([cfgs[i].dim == 2 for i in segs[:, 0]])) if len(segs) else 0
+
+
+def test_launch_groups_of_the_fixed_mix():
+    """2D work beyond one round of the waves is split into launches that each
+    fit one round: every lattice in exactly one group, and in each group's
+    work list every band a wave's first item."""
+    cfgs = _fixed_mix_cfgs()
+    grp, ng = A.plan_groups(cfgs, WAVES)
+    qs, segs, nw = A.plan_schedule(cfgs, WAVES)
+    assert _two_d_items(cfgs, segs) > WAVES  # one launch would take two rounds
+    assert ng >= 2 and set(grp.tolist()) == set(range(ng))
+    for g in range(ng):
+        sub = [c for c, k in zip(cfgs, grp) if k == g]
+        # one cost class per launch here: Euler; shallow water of two
+        # columns per lane; of one column, beside the 1D lattices
+        assert len(set(_strips(c)[1] * 10 + c.system for c in sub if c.dim == 2)) == 1
+        qs, segs, nw = A.plan_schedule(sub, WAVES)
+        _check_cover(sub, qs, segs)
+        assert _two_d_items(sub, segs) <= WAVES
+        parts = _queue_parts(sub, qs, segs)
+        assert max(len(p) for p in parts) <= WAVES // 8
+
+
+def test_launch_groups_one_round_and_3d():
+    """Work that fits one round stays one launch; 3D lattices are in none."""
+    cfgs = [A.config_from(W.euler_seeded_2d(s, n=n), precision=A.F32) for s, n in enumerate((600, 300, 130))]
+    cfgs.append(A.config_from(W.euler_octants_3d(seed=0, n=16), precision=A.F32))
+    cfgs.append(A.config_from(W.euler_seeded_1d(0, n=9000), precision=A.F32))
+    grp, ng = A.plan_groups(cfgs, WAVES)
+    assert ng == 1 and grp.tolist() == [0, 0, 0, -1, 0]
+    grp, ng = A.plan_groups([cfgs[3]], WAVES)
+    assert ng == 0 and grp.tolist() == [-1]
+
+
+def test_launch_groups_with_a_lattice_beyond_one_round():
+    """A 2D lattice that alone needs more than one round keeps a group of its
+    own (no split shortens it); the others fit one round beside it."""
+    big = A.config_from(W.euler_seeded_2d(0, n=8192), precision=A.F32)
+    cfgs = [big] + [A.config_from(W.euler_seeded_2d(s, n=n), precision=A.F32) for s, n in enumerate((1000, 700, 500))]
+    grp, ng = A.plan_groups(cfgs, WAVES)
+    assert ng >= 2
+    assert all(grp[i] != grp[0] for i in range(1, len(cfgs)))
+    for g in range(ng):
+        sub = [c for c, k in zip(cfgs, grp) if k == g]
+        qs, segs, nw = A.plan_schedule(sub, WAVES)
+        _check_cover(sub, qs, segs)
+        if all(c is not big for c in sub):
+            assert _two_d_items(sub, segs) <= WAVES
+
+
+@pytest.mark.parametrize("waves", [1, 3, 8, 64])
+def test_launch_groups_few_waves(waves):
+    cfgs = _fixed_mix_cfgs(512 << 20)
+    grp, ng = A.plan_groups(cfgs, waves)
+    assert ng >= 1 and np.all((grp >= 0) & (grp < ng))
+    for g in range(ng):
+        sub = [c for c, k in zip(cfgs, grp) if k == g]
+        qs, segs, nw = A.plan_schedule(sub, waves)
+        _check_cover(sub, qs, segs)
