@@ -505,8 +505,10 @@ def run_serving_fixed(torch, args, steps=None):
     cells = sum(p.cells for p in probs)
     alg = sum(p.cells * alg_bytes_per_lup(p, 4) for p in probs)
     ms_step = ms / steps
-    return {"lattices": len(probs), "cells_per_launch": cells, "alg_bytes_per_launch": alg,
-            "ms_per_launch": ms_step, "glups": cells / (ms_step * 1e-3) / 1e9,
+    waves = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    _, groups = A.plan_groups([A.config_from(p, precision=A.F32) for p in probs], waves)
+    return {"lattices": len(probs), "cells_per_step": cells, "alg_bytes_per_step": alg,
+            "launches_per_step": groups, "ms_per_step": ms_step, "glups": cells / (ms_step * 1e-3) / 1e9,
             "alg_gbs": alg / (ms_step * 1e-3) / 1e9, "alg_frac": alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "failed": bad,
             "systems": {s: sum(1 for p in probs if system_of(p) == s) for s in ("euler1d", "euler2d", "swe2d")}}
@@ -633,7 +635,7 @@ def main():
         elif args.only == "serving_fixed_f32":
             r = run_serving_fixed(torch, args)
             log(f"[only] serving_fixed_f32 {r}")
-            ms = r["ms_per_launch"] * args.steps
+            ms = r["ms_per_step"] * args.steps
         else:
             r, _ = run_serving(torch, args, args.requests, args.rate)
             log(f"[only] serving {r}")
@@ -701,11 +703,14 @@ def main():
                                              e3["cells"], e3["ms_per_step"])
     fx = extra["serving_fixed_mix"]
     prof = read_profile("serving_fixed_f32")
+    # the mix is stepped in one batched launch per group of lattices: its
+    # figures are per step (all the step's launches)
     extra["roofline_batched_serving_fixed_mix"] = {
         "bound": "hbm", "achieved": fx["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fx["alg_frac"],
-        "traffic": prof["hbm_bytes_per_launch"] if prof else None, "alg_bytes_per_launch": fx["alg_bytes_per_launch"],
-        "avg_kernel_ms": fx["ms_per_launch"], "avg_kernel_ms_rocprof": prof["avg_kernel_ns"] / 1e6 if prof else None,
-        "traffic_gbs": prof["hbm_bytes_per_launch"] / prof["avg_kernel_ns"] if prof else None}
+        "traffic": prof["hbm_bytes_per_step"] if prof else None, "alg_bytes_per_step": fx["alg_bytes_per_step"],
+        "launches_per_step": fx["launches_per_step"], "ms_per_step": fx["ms_per_step"],
+        "kernel_ms_per_step_rocprof": prof["kernel_ns_per_step"] / 1e6 if prof else None,
+        "traffic_gbs": prof["hbm_bytes_per_step"] / prof["kernel_ns_per_step"] if prof else None}
     print(json.dumps(line), flush=True)
 
 

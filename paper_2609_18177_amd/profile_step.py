@@ -185,8 +185,13 @@ def main():
     read_b = fetch_kib * 1024.0 * read_scale
     write_b = write_kib * 1024.0 * write_scale
     wl = WORKLOAD_NAMES[args.workload]
+    # launches of the kernel per step: the trace run's calls over its steps
+    # (the served mix is stepped in one launch per group of lattices)
+    dps = max(1, round(stats["calls"] / (args.steps + 10)))
     rec = {"workload": wl, "kernel": kname, "kernel_source_sha256_16": bench.kernel_source_hash(),
            "avg_kernel_ns": stats["avg_ns"] if stats else None, "kernel_calls": stats["calls"] if stats else None,
+           "launches_per_step": dps, "kernel_ns_per_step": stats["avg_ns"] * dps,
+           "hbm_bytes_per_step": (read_b + write_b) * dps,
            "event_ms_per_step_same_run": event_ms,
            "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,
            "copy_fetch_kib_for_1GiB": copy_fetch_kib, "copy_write_kib_for_1GiB": copy_write_kib,
@@ -223,6 +228,10 @@ def main():
         f.write(f"| calibration (bytes moved / counter bytes) read, write | {read_scale:.3f}, {write_scale:.3f} |\n")
         f.write(f"| HBM read / write per launch (calibrated) | {read_b / 1e6:.1f} / {write_b / 1e6:.1f} MB |\n")
         f.write(f"| HBM bytes per launch | {(read_b + write_b) / 1e6:.1f} MB |\n")
+        if dps > 1:
+            f.write(f"| launches per step (trace calls / steps) | {dps} |\n")
+            f.write(f"| kernel time per step (launches x average) | {stats['avg_ns'] * dps / 1e3:.2f} us |\n")
+            f.write(f"| HBM bytes per step | {(read_b + write_b) * dps / 1e6:.1f} MB |\n")
         for k, v in rec.get("other_kernels_of_the_step", {}).items():
             ns = v["avg_kernel_ns"]
             rb, wb = v["hbm_read_bytes"], v["hbm_write_bytes"]
