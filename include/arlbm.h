@@ -224,8 +224,10 @@ int arlbm_destroy(arlbm_lattice *h);
 const char *arlbm_last_error(const arlbm_lattice *h);
 
 /* ------------------------------------------------------------------------ */
-/* Serving: many FP32 lattices resident at once, one batched launch per      */
-/* iteration advances every resident lattice by one step.                    */
+/* Serving: many FP32 lattices resident at once; each iteration advances    */
+/* every resident lattice by one step in one batched launch (one per group   */
+/* of lattices of one cost per row when their 2D work exceeds one round of   */
+/* the waves) and a launch per 3D lattice.                                   */
 /* ------------------------------------------------------------------------ */
 
 typedef struct arlbm_server arlbm_server;
@@ -284,9 +286,10 @@ int arlbm_server_submit_state(arlbm_server *s, const arlbm_config *cfg, const vo
  * after the iteration (either may be NULL). */
 int arlbm_server_iterate(arlbm_server *s, int32_t *resident, int32_t *queued);
 
-/* As arlbm_server_iterate, with up to max_launches (>= 1) batched launches
- * after the admissions, fewer where a resident lattice would otherwise pass
- * its step count: retirements and results are those of one launch per call,
+/* As arlbm_server_iterate, with up to max_launches (>= 1) steps (each the
+ * step's launches) after the admissions, fewer where a resident lattice
+ * would otherwise pass its step count: retirements and results are those of
+ * one step per call,
  * while the host keeps more work queued on the GPU (requests submitted
  * meanwhile wait for the next call).  *launched (may be NULL) receives the
  * launches made.  EINVAL if max_launches < 1. */
