@@ -292,7 +292,7 @@ int arlbm_server_iterate(arlbm_server *s, int32_t *resident, int32_t *queued);
  * one step per call,
  * while the host keeps more work queued on the GPU (requests submitted
  * meanwhile wait for the next call).  *launched (may be NULL) receives the
- * launches made.  EINVAL if max_launches < 1. */
+ * steps made.  EINVAL if max_launches < 1. */
 int arlbm_server_iterate_n(arlbm_server *s, int32_t max_launches, int32_t *resident,
                            int32_t *queued, int32_t *launched);
 
