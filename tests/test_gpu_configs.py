@@ -135,17 +135,21 @@ def test_config4_swe_bed_256():
 
 
 def test_config3_full_size_first_steps():
-    """2048^2 in the launch configuration the benchmark times: two steps
-    against the oracle, FP64 bit for bit, FP32 within 1e-5 relative L2."""
+    """2048^2 on the single-lattice kernel and through the batched kernel of
+    the serving runtime (the launch the benchmark times): two steps against
+    the oracle, FP64 bit for bit on both paths, FP32 within 1e-5 relative L2
+    and the batched FP32 result bit for bit the single-lattice one."""
     require_gpu()
     p = W.euler_seeded_2d(0, n=2048, steps=2)
     Lo = oracle_run(p, 2)
     Uo = Lo.moments()
+    single = {}
     for prec, tol in ((A.F64, 0.0), (A.F32, 1e-5)):
         G = gpu_lattice(p, prec)
         G.step(2)
         st = G.sync()
         U = G.moments()
+        single[prec] = U
         e = rel_l2_per_comp(U, Uo)
         say(f"[c3 2048^2] prec={prec} 2 steps rel L2 {e} bitwise={np.array_equal(U, Uo)} abar {st['abar']} "
             f"oracle {list(Lo.alpha_bar())}")
@@ -153,9 +157,22 @@ def test_config3_full_size_first_steps():
             assert np.array_equal(U, Uo) and st["t"] == Lo.t
         assert max(e) <= tol
         G.close()
+    for prec in (A.F64, A.F32):
+        need = A.query_sizes(A.config_from(p, precision=prec)).total_bytes
+        (b,), _ = _serve([p], int(need * 1.3) + (64 << 20), precision=prec)
+        assert b["status"] == 0 and b["steps"] == 2
+        U = b["U"].reshape(Uo.shape)
+        say(f"[c3 2048^2 batched] prec={prec} bitwise vs oracle {np.array_equal(U, Uo)}, "
+            f"vs single-lattice {np.array_equal(U, single[prec])}")
+        assert np.array_equal(U, single[prec])
+        if prec == A.F64:
+            assert np.array_equal(U, Uo) and b["t"] == Lo.t
 
 
 def test_config4_full_size_first_step():
+    """4096^2 shallow water with the bed: one FP64 step bit for bit against
+    the oracle on the single-lattice kernel and through the batched kernel
+    of the serving runtime (the launch the benchmark times)."""
     require_gpu()
     p = W.swe_bed_2d(0, n=4096, steps=1)
     Lo = oracle_run(p, 1)
@@ -168,6 +185,11 @@ def test_config4_full_size_first_step():
     say(f"[c4 4096^2] FP64 1 step rel L2 {e} bitwise={np.array_equal(U, Uo)}")
     assert np.array_equal(U, Uo)
     G.close()
+    need = A.query_sizes(A.config_from(p, precision=A.F64)).total_bytes
+    (b,), _ = _serve([p], int(need * 1.3) + (64 << 20), precision=A.F64)
+    assert b["status"] == 0 and b["steps"] == 1
+    say(f"[c4 4096^2 batched] FP64 bitwise vs oracle {np.array_equal(b['U'].reshape(Uo.shape), Uo)}")
+    assert np.array_equal(b["U"].reshape(Uo.shape), Uo)
 
 
 @pytest.mark.parametrize("prec,tol", [(A.F64, 1e-13), (A.F32, 1e-6)])
