@@ -379,16 +379,18 @@ def test_serving_launch_groups_bitwise(prec):
     same lattice stepped alone on the single-lattice kernel, bit for bit."""
     require_gpu()
     import torch
-    probs = [dataclasses.replace(W.euler_seeded_2d(s, n=2048), steps=4) for s in range(3)]
-    probs += [dataclasses.replace(W.swe_bed_2d(s, n=n), steps=4) for s, n in ((0, 2048), (1, 2048), (2, 2047))]
-    probs.append(W.euler_seeded_1d(3, n=20000, steps=4))
+    # different step counts and several launches per call: lattices retire
+    # at different iterations, so the groups are rebuilt during the run
+    probs = [dataclasses.replace(W.euler_seeded_2d(s, n=2048), steps=3 + s) for s in range(3)]
+    probs += [dataclasses.replace(W.swe_bed_2d(s, n=n), steps=k) for s, n, k in ((0, 2048, 6), (1, 2048, 2), (2, 2047, 5))]
+    probs.append(W.euler_seeded_1d(3, n=20000, steps=7))
     cfgs = [A.config_from(p, precision=prec) for p in probs]
     waves = 4 * torch.cuda.get_device_properties(0).multi_processor_count
     grp, ng = A.plan_groups(cfgs, waves)
     say(f"[groups] prec={prec} waves={waves} groups={ng} of {grp.tolist()}")
     assert ng >= 2
     need = sum(A.query_sizes(c).total_bytes for c in cfgs)
-    mix, _ = _serve(probs, int(need * 1.3) + (64 << 20), precision=prec)
+    mix, _ = _serve(probs, int(need * 1.3) + (64 << 20), precision=prec, max_launches=3)
     for p, b in zip(probs, mix):
         L = gpu_lattice(p, prec)
         L.step(p.steps)
