@@ -400,6 +400,35 @@ def test_serving_launch_groups_bitwise(prec):
         assert np.array_equal(a, b["U"].reshape(a.shape)), p.name
 
 
+@pytest.mark.parametrize("prec", [A.F32, A.F64])
+def test_serving_multi_round_launch_bitwise(prec):
+    """One lattice whose bands take more than one round of the waves (8192 x
+    2048 Euler: 2130 bands of 130-137 rows for 1024 waves), so the waves of
+    the batched launch take further bands from the queue counters and steal
+    from other queues: the result equals the single-lattice kernel's, bit for
+    bit."""
+    require_gpu()
+    import torch
+    nx, ny = 8192, 2048
+    X, Y = np.meshgrid(W.centres(nx, 0.0, 4.0), W.centres(ny, 0.0, 1.0), indexing="xy")
+    st = np.array(W.quadrant_states(0))
+    pr = st[np.where(X > 2.0, np.where(Y > 0.5, 0, 3), np.where(Y > 0.5, 1, 2))]
+    p = dataclasses.replace(W.euler_seeded_2d(0, n=64), nx=nx, ny=ny, x0=0.0, x1=4.0, y0=0.0, y1=1.0,
+                            U0=W.euler_conserved(pr[..., 0], pr[..., 1], pr[..., 2], pr[..., 3]), steps=3)
+    cfg = A.config_from(p, precision=prec)
+    waves = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    qs, segs, nw = A.plan_schedule([cfg], waves)
+    say(f"[multi-round] prec={prec} {len(segs)} bands for {nw} waves")
+    assert len(segs) > nw
+    (b,), _ = _serve([p], int(A.query_sizes(cfg).total_bytes * 1.3) + (64 << 20), precision=prec)
+    L = gpu_lattice(p, prec)
+    L.step(p.steps)
+    a = L.moments()
+    L.close()
+    assert b["status"] == 0 and b["steps"] == p.steps
+    assert np.array_equal(a, b["U"].reshape(a.shape))
+
+
 def test_serving_failed_admissions_leave_the_mix_intact():
     """Requests that fail the checks set_state makes after the initialisation
     (an all-dry shallow-water state: zero wave-speed bounds; an eps above the
