@@ -60,3 +60,15 @@ def test_profiles_match_kernel_sources():
             rec = json.load(f)
         assert rec["kernel_source_sha256_16"] == h, name
         assert rec["hbm_bytes_per_launch"] > 0 and rec["avg_kernel_ns"] > 0, name
+
+
+def test_profiled_kernel_time_within_the_event_timed_step():
+    """In each profile, the kernel time per step that rocprofv3 traced over
+    the benchmark's timed launches is at most the step time the benchmark's
+    own events measured in the same run (the events also hold the gaps
+    between launches)."""
+    for name in ("euler2d_2048_batched_f32", "euler2d_2048_f32", "euler2d_2048_f64", "swe2d_4096_batched_f32",
+                 "swe2d_4096_f32", "euler3d_256_f32", "serving_fixed_f32"):
+        with open(os.path.join(ROOT, "profiles", f"{name}_pmc.json")) as f:
+            rec = json.load(f)
+        assert rec["kernel_ns_per_step"] <= rec["event_ms_per_step_same_run"] * 1e6, name
