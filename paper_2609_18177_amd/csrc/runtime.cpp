@@ -1268,11 +1268,14 @@ int64_t build_schedule(const std::vector<SchedLattice> &lats, int64_t W, std::ve
 // than one round is split, largest lattices first into the group with the
 // least work, into the fewest groups that each fit one round (a single
 // lattice that does not cannot be shortened by any split); the 1D lattices
-// join the lightest group; past kMaxGroups groups, one launch.  The fixed
-// serving mix (20 Euler, 15 + 8 shallow-water and 22 1D lattices) took
-// 0.812 ms per step in one launch, 0.722 in two (Euler; shallow water and
-// 1D), 0.848 in two of mixed classes balanced by work, and 0.902 in one
-// launch of one round with bands of equal cost (158-487 rows).
+// join the heaviest group, whose waves take their runs as bands end; past
+// kMaxGroups groups, one launch.  The fixed serving mix (20 Euler, 15 + 8
+// shallow-water and 22 1D lattices) took 0.812 ms per step in one launch,
+// 0.722 in two (Euler; shallow water and 1D), 0.848 in two of mixed classes
+// balanced by work, 0.902 in one launch of one round with bands of equal
+// cost (158-487 rows); in the three classes 0.708 with the 1D lattices in
+// the lightest group, 0.712 in a launch of their own, 0.690 in the
+// heaviest.
 // Returns the group of each lattice (0 .. groups-1).
 constexpr int64_t kMaxGroups = 8, kMinGroupRows = 24;
 std::vector<int32_t> launch_groups(const std::vector<SchedLattice> &lats, int64_t W, int64_t &ngroups)
@@ -1359,9 +1362,9 @@ std::vector<int32_t> launch_groups(const std::vector<SchedLattice> &lats, int64_
             grp[i] = (int32_t)k;
             cost[k] += (double)rows(i) * (double)lats[i].unit;
         }
-    const int32_t light = (int32_t)(std::min_element(cost.begin(), cost.end()) - cost.begin());
+    const int32_t heavy = (int32_t)(std::max_element(cost.begin(), cost.end()) - cost.begin());
     for (size_t i = 0; i < lats.size(); ++i)
-        if (lats[i].one_d) grp[i] = light;
+        if (lats[i].one_d) grp[i] = heavy;
     ngroups = (int64_t)groups.size();
     return grp;
 }

@@ -374,8 +374,8 @@ def test_serving_several_launches_per_iterate_bitwise():
 @pytest.mark.parametrize("prec", [A.F32, A.F64])
 def test_serving_launch_groups_bitwise(prec):
     """A mix whose 2D work needs more than one round of the waves is stepped
-    in several launches, one per cost class (Euler; shallow water of two
-    columns per lane; of one, with the 1D lattice): every result equals the
+    in several launches, one per cost class (Euler, with the 1D lattice;
+    shallow water of two columns per lane; of one): every result equals the
     same lattice stepped alone on the single-lattice kernel, bit for bit."""
     require_gpu()
     import torch

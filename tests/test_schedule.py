@@ -219,8 +219,8 @@ def test_launch_groups_of_the_fixed_mix():
     assert ng >= 2 and set(grp.tolist()) == set(range(ng))
     for g in range(ng):
         sub = [c for c, k in zip(cfgs, grp) if k == g]
-        # one cost class per launch here: Euler; shallow water of two
-        # columns per lane; of one column, beside the 1D lattices
+        # one cost class per launch here: Euler, with the 1D lattices;
+        # shallow water of two columns per lane; of one column
         assert len(set(_strips(c)[1] * 10 + c.system for c in sub if c.dim == 2)) == 1
         qs, segs, nw = A.plan_schedule(sub, WAVES)
         _check_cover(sub, qs, segs)
