@@ -338,6 +338,13 @@ int arlbm_plan_schedule(const arlbm_config *cfgs, int32_t n, int32_t waves, int3
  * bad configuration or argument. */
 int arlbm_plan_groups(const arlbm_config *cfgs, int32_t n, int32_t waves, int32_t *group_of, int32_t *ngroups);
 
+/* The Arrhenius factor's exponential exactly as the kernels evaluate it,
+ * callable on the host (no GPU needed): arlbm_kernel_exp is the FP64 kernels'
+ * (Cody-Waite reduction, degree-13 series), arlbm_kernel_expf the FP32
+ * kernels' (degree 7).  Section 5.4: R = K rho Y exp(-T_i / T). */
+double arlbm_kernel_exp(double x);
+float arlbm_kernel_expf(float x);
+
 /* Vector registers per lane of the fused step kernel for a precision, system
  * and dimension (from the code object; in 2D the kernel that a lattice of
  * even nx runs), or -1. */

@@ -119,6 +119,8 @@ def lib():
                                      C.POINTER(C.c_int32)], C.c_int),
             "arlbm_plan_groups": ([C.POINTER(Config), C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32)], C.c_int),
+            "arlbm_kernel_exp": ([C.c_double], C.c_double),
+            "arlbm_kernel_expf": ([C.c_float], C.c_float),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -413,3 +415,9 @@ def plan_groups(cfgs, waves: int):
     _check(lib().arlbm_plan_groups(arr, len(cfgs), int(waves), grp.ctypes.data_as(C.POINTER(C.c_int32)),
                                    C.byref(ng)))
     return grp[:len(cfgs)], ng.value
+
+
+def kernel_exp(x: float, precision: int = F64) -> float:
+    """The Arrhenius factor's exponential as the FP64 (or FP32) kernels
+    evaluate it, on the host."""
+    return lib().arlbm_kernel_exp(float(x)) if precision == F64 else lib().arlbm_kernel_expf(float(x))

