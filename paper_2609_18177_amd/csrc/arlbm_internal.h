@@ -114,6 +114,7 @@ constexpr int kQueueStride = 32;
     hipError_t init(const LatticeDesc &h, const double *U0, const double *bed64, int slot_in,         \
                     hipStream_t s);                                                                    \
     hipError_t step_single(const LatticeDesc &h, int64_t iter, hipStream_t s);                        \
+    hipError_t steps1d(const LatticeDesc &h, int64_t iter0, int32_t nsteps, hipStream_t s);           \
     hipError_t step_batched(const LatticeDesc *d_descs, const Segment *d_segs, const int32_t *d_qstart, \
                             unsigned *d_counters, int32_t parity, int32_t nwaves, int64_t iter,        \
                             hipStream_t s);                                                            \

@@ -144,6 +144,20 @@ hipError_t step_single(const LatticeDesc &h, int64_t iter, hipStream_t s)
 #undef C_
 }
 
+hipError_t steps1d(const LatticeDesc &h, int64_t iter0, int32_t nsteps, hipStream_t s)
+{
+    const int nw = h.ncols < 16 ? h.ncols : 16;  // one wave per strip up to 16
+    const dim3 g(1), b(64 * nw);
+    switch (h.variant) {
+    case V_ADV1: hipLaunchKernelGGL((k_steps1d<0, real>), g, b, 0, s, h, iter0, nsteps); break;
+    case V_EUL1: hipLaunchKernelGGL((k_steps1d<1, real>), g, b, 0, s, h, iter0, nsteps); break;
+    case V_SWE1: hipLaunchKernelGGL((k_steps1d<2, real>), g, b, 0, s, h, iter0, nsteps); break;
+    case V_REU1: hipLaunchKernelGGL((k_steps1d<3, real>), g, b, 0, s, h, iter0, nsteps); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t step_batched(const LatticeDesc *d_descs, const Segment *d_segs, const int32_t *d_qstart,
                         unsigned *d_counters, int32_t parity, int32_t nwaves, int64_t iter, hipStream_t s)
 {

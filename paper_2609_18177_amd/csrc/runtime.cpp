@@ -504,11 +504,26 @@ extern "C" int arlbm_set_state_device(arlbm_lattice *h, const double *U0, const 
     return set_state_impl(h, U0, bed, true, t0);
 }
 
+constexpr int32_t kSteps1dMaxStrips = 16, kSteps1dRun = 1024;
+
 extern "C" int arlbm_step(arlbm_lattice *h, int64_t n)
 {
     if (!h) return fail(nullptr, ARLBM_EINVAL, "handle is NULL");
     if (h->busy) return fail(h, ARLBM_EBUSY, "lattice is owned by a server");
     if (n < 0) return fail(h, ARLBM_EINVAL, "n must be >= 0");
+    // a small 1D lattice takes its steps in launches of up to kSteps1dRun
+    // steps of one workgroup (k_steps1d), the same bits as one launch per step
+    if (h->cfg.dim == 1 && h->desc.ncols <= kSteps1dMaxStrips && n >= 2) {
+        while (n > 0) {
+            const int32_t k = (int32_t)std::min<int64_t>(n, kSteps1dRun);
+            hipError_t e = is_f64(h) ? f64::steps1d(h->desc, h->step, k, h->stream)
+                                     : f32::steps1d(h->desc, h->step, k, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "step launch");
+            h->step += k;
+            n -= k;
+        }
+        return ARLBM_OK;
+    }
     for (int64_t i = 0; i < n; ++i) {
         hipError_t e = L_step(h, h->step);
         if (e != hipSuccess) return hip_fail(h, e, "step launch");

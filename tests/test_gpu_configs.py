@@ -429,6 +429,30 @@ def test_serving_multi_round_launch_bitwise(prec):
     assert np.array_equal(a, b["U"].reshape(a.shape))
 
 
+@pytest.mark.parametrize("prec", [A.F32, A.F64])
+def test_small_1d_steps_in_one_launch_bitwise(prec):
+    """1D lattices of at most 16 strips take their steps in launches of up to
+    1024 steps of one workgroup (a barrier between steps): the same bits,
+    time, step count and flags as one launch per step, for every system,
+    across a launch boundary (1500 steps)."""
+    require_gpu()
+    cases = [(W.advection_sine(n=256), 512), (W.euler_seeded_1d(2, n=900, steps=1500), 1500),
+             (W.swe_bed_1d(n=500, steps=200), 200), (W.reactive_seeded_1d(0, n=600, steps=150), 150)]
+    for p, steps in cases:
+        runs = []
+        for per_call in (steps, 1):
+            L = gpu_lattice(p, prec)
+            for _ in range(steps // per_call):
+                L.step(per_call)
+            st = L.sync(check=False)
+            runs.append((L.moments(), st))
+            L.close()
+        (a, sa), (b, sb) = runs
+        say(f"[1d steps] {p.name} prec={prec} {steps} steps bitwise={np.array_equal(a, b)}")
+        assert np.array_equal(a, b), p.name
+        assert sa["t"] == sb["t"] and sa["step"] == sb["step"] and sa["flags"] == sb["flags"]
+
+
 def test_serving_failed_admissions_leave_the_mix_intact():
     """Requests that fail the checks set_state makes after the initialisation
     (an all-dry shallow-water state: zero wave-speed bounds; an eps above the
