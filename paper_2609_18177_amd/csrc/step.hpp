@@ -500,13 +500,16 @@ __device__ __forceinline__ void seg1d(const LatticeDesc &L, int64_t iter, int c0
 }
 
 // Several steps of a small 1D lattice in one launch: one workgroup, one wave
-// per strip (at most 16 strips), a barrier between steps; the acquire at
-// device scope after it drops the CU's L1 lines, so the next step reads the
-// populations, times and wave-speed slots the step wrote, from L2.  A step
-// then costs no launch: a 256-cell advection solve of 512 steps took 1.32 ms
-// against 2.23 ms in one launch per step.  With several strips per wave the
-// strips follow one another: 4096 cells (71 strips on 16 waves) took 25 ms
-// against 9.8 ms, so larger lattices keep one launch per step.
+// per strip (at most 16 strips), a barrier between steps.  Before it every
+// wave waits for its stores and wave-speed atomics to complete; after it the
+// acquire at device scope drops the CU's L1 lines, so the next step reads
+// the populations, times and slots the step wrote, from L2.  A step then
+// costs no launch: a 256-cell advection solve of 512 steps took 1.55 ms
+// against 2.23 ms in one launch per step (1.44 ms without the wait before
+// the barrier, which leaves the order to the CU's path to L2).  With several
+// strips per wave the strips follow one another: 4096 cells (71 strips on
+// 16 waves) took 25 ms against 9.8 ms, so larger lattices keep one launch
+// per step.
 template <int SYS, typename T>
 __global__ __launch_bounds__(1024) void k_steps1d(LatticeDesc L, int64_t iter0, int32_t nsteps)
 {
@@ -514,6 +517,7 @@ __global__ __launch_bounds__(1024) void k_steps1d(LatticeDesc L, int64_t iter0, 
     const int c0 = (int)((int64_t)w * L.ncols / nw), c1 = (int)((int64_t)(w + 1) * L.ncols / nw);
     for (int s = 0; s < nsteps; ++s) {
         if (c0 < c1) seg1d<SYS, T>(L, iter0 + s, c0, c1);
+        __builtin_amdgcn_s_waitcnt(0);  // vmcnt, expcnt and lgkmcnt all zero
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
