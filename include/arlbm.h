@@ -245,8 +245,9 @@ typedef struct arlbm_completion {
     double submit_s;      /* host clock (seconds) at submit                     */
     double admit_s;       /* host clock when its lattice became resident        */
     double done_s;        /* host clock when its result was read back           */
-    double *U;            /* m planes FP64, owned by the server until the next
-                             poll; NULL if status != 0                         */
+    double *U;            /* m planes FP64: the caller's array given to
+                             arlbm_server_result_into, else owned by the server
+                             until the next poll; NULL if status != 0          */
     int64_t u_count;      /* number of doubles in U                             */
 } arlbm_completion;
 
@@ -295,6 +296,17 @@ int arlbm_server_iterate(arlbm_server *s, int32_t *resident, int32_t *queued);
  * steps made.  EINVAL if max_launches < 1. */
 int arlbm_server_iterate_n(arlbm_server *s, int32_t max_launches, int32_t *resident,
                            int32_t *queued, int32_t *launched);
+
+/* Give a queued request (submitted, not yet admitted by an iteration) a
+ * destination for its result: dst holds count = m * nx * ny * nz doubles (m
+ * planes FP64, the layout of arlbm_read_moments), is owned by the caller and
+ * must stay valid until the request's completion has been polled or the
+ * server destroyed.  At retirement the moments are copied from the pinned
+ * read-back block straight into dst (several host threads), and the
+ * completion's U points at dst: the caller needs no copy of its own.  dst is
+ * written only if the request completes with status 0.  EINVAL if no queued
+ * request has this id, or count is not the result's size. */
+int arlbm_server_result_into(arlbm_server *s, uint64_t id, double *dst, int64_t count);
 
 /* Pop up to max finished requests into out; *n receives the count. */
 int arlbm_server_poll(arlbm_server *s, arlbm_completion *out, int32_t max, int32_t *n);

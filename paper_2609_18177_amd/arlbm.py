@@ -109,6 +109,7 @@ def lib():
             "arlbm_server_iterate": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
             "arlbm_server_iterate_n": ([vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                         C.POINTER(C.c_int32)], C.c_int),
+            "arlbm_server_result_into": ([vp, C.c_uint64, dp, C.c_int64], C.c_int),
             "arlbm_server_poll": ([vp, C.POINTER(Completion), C.c_int32, C.POINTER(C.c_int32)], C.c_int),
             "arlbm_server_memory": ([vp, C.POINTER(C.c_size_t)], C.c_int),
             "arlbm_server_pool_bytes": ([vp, C.POINTER(C.c_size_t)], C.c_int),
@@ -321,19 +322,32 @@ class Server:
         h = C.c_void_p()
         _check(lib().arlbm_server_create(int(hbm_budget), precision, C.c_void_p(stream.cuda_stream), C.byref(h)))
         self._h = h
+        self._dst = {}  # request id -> the array its result is written into
 
-    def submit(self, cfg: Config, U0: np.ndarray, bed: Optional[np.ndarray], nsteps: int) -> int:
+    def _result_into(self, rid: int, count: int):
+        dst = np.empty(count)
+        _check(lib().arlbm_server_result_into(self._h, rid, _dptr(dst), count))
+        self._dst[rid] = dst
+
+    def submit(self, cfg: Config, U0: np.ndarray, bed: Optional[np.ndarray], nsteps: int,
+               result_into: bool = True) -> int:
+        """Queue a request; with result_into the server writes its result
+        into an array of this object's, which poll hands back uncopied."""
         U0 = np.ascontiguousarray(U0, dtype=np.float64)
         bed = None if bed is None else np.ascontiguousarray(bed, dtype=np.float64)
         rid = C.c_uint64()
         _check(lib().arlbm_server_submit(self._h, C.byref(cfg), _dptr(U0), _dptr(bed), int(nsteps), C.byref(rid)))
+        if result_into:
+            self._result_into(rid.value, U0.size)
         return rid.value
 
-    def submit_state(self, cfg: Config, blob: bytes, nsteps: int) -> int:
+    def submit_state(self, cfg: Config, blob: bytes, nsteps: int, result_into: bool = True) -> int:
         """Queue a request that resumes a state saved by Lattice.save_state."""
         buf = C.create_string_buffer(blob, len(blob))
         rid = C.c_uint64()
         _check(lib().arlbm_server_submit_state(self._h, C.byref(cfg), buf, len(blob), int(nsteps), C.byref(rid)))
+        if result_into:
+            self._result_into(rid.value, query_sizes(cfg).m * cfg.nx * cfg.ny * cfg.nz)
         return rid.value
 
     def iterate(self, max_launches: int = 1):
@@ -353,7 +367,13 @@ class Server:
         out = []
         for i in range(n.value):
             c = arr[i]
-            U = np.ctypeslib.as_array(c.U, shape=(c.u_count,)).copy() if c.status == OK and c.u_count else None
+            dst = self._dst.pop(c.id, None)
+            U = None
+            if c.status == OK and c.u_count:
+                if dst is not None and C.cast(c.U, C.c_void_p).value == dst.ctypes.data:
+                    U = dst
+                else:
+                    U = np.ctypeslib.as_array(c.U, shape=(c.u_count,)).copy()
             out.append({"id": c.id, "status": c.status, "flags": c.flags, "steps": c.steps,
                         "first_bad_step": c.first_bad_step, "t": c.t,
                         "submit_s": c.submit_s,
@@ -377,6 +397,7 @@ class Server:
         if h:
             lib().arlbm_server_destroy(h)
             self._h = None
+        self._dst = {}
 
     def __del__(self):
         try:

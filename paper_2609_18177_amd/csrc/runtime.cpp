@@ -7,6 +7,8 @@
 // keeps many lattices resident and advances all of them with one batched
 // launch per iteration.
 #include <hip/hip_runtime.h>
+#include <stdlib.h>
+#include <sys/mman.h>
 
 #include <algorithm>
 #include <chrono>
@@ -16,6 +18,7 @@
 #include <cstring>
 #include <deque>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -254,35 +257,220 @@ void free_owned(arlbm_lattice *h)
 }
 
 // Host-side admissibility of an initial state (finite, rho > 0, p > 0, h >= 0).
+// memcpy of large host arrays over several threads: a fresh destination
+// faults its pages in on first touch, and those faults proceed in parallel
+// (measured on 32 MB: 21 ms on one thread, 4 ms on eight).
+void par_copy(void *dst, const void *src, size_t bytes)
+{
+    constexpr size_t kPerThread = (size_t)4 << 20;
+    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>({(size_t)8, hw, bytes / kPerThread});
+    if (bytes == 0) return;
+    if (nt < 2) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    const size_t chunk = (bytes / nt + 4095) / 4096 * 4096;  // nt * chunk >= bytes
+    std::vector<std::thread> th;
+    size_t started = 0;  // chunks 1 .. started run on threads of their own
+    try {
+        th.reserve(nt - 1);
+        for (size_t t = 1; t < nt && t * chunk < bytes; ++t) {
+            const size_t a = t * chunk, len = std::min(chunk, bytes - a);
+            th.emplace_back([=] { std::memcpy((char *)dst + a, (const char *)src + a, len); });
+            started = t;
+        }
+    } catch (...) {
+        // no thread for the remaining chunks: copied below
+    }
+    std::memcpy(dst, src, std::min(chunk, bytes));
+    const size_t rest = (started + 1) * chunk;
+    if (rest < bytes) std::memcpy((char *)dst + rest, (const char *)src + rest, bytes - rest);
+    for (auto &x : th) x.join();
+}
+
+// Host <-> device copies of large pageable arrays (the plain path's state
+// upload and read-back): the data moves through two pinned chunks used in
+// turn, the host copy of one chunk (several threads) overlapping the DMA of
+// the other.  The chunk pairs are kept for the process in a free list, one
+// pair per transfer in progress.  Arrays below kBounceMin go directly.
+constexpr size_t kBounceChunk = (size_t)16 << 20, kBounceMin = (size_t)8 << 20;
+std::mutex g_bounce_mu;
+std::vector<char *> g_bounce_free;
+
+char *bounce_take()
+{
+    {
+        std::lock_guard<std::mutex> g(g_bounce_mu);
+        if (!g_bounce_free.empty()) {
+            char *b = g_bounce_free.back();
+            g_bounce_free.pop_back();
+            return b;
+        }
+    }
+    void *p = nullptr;
+    return hipHostMalloc(&p, 2 * kBounceChunk, hipHostMallocDefault) == hipSuccess ? (char *)p : nullptr;
+}
+
+void bounce_give(char *b)
+{
+    std::lock_guard<std::mutex> g(g_bounce_mu);
+    g_bounce_free.push_back(b);
+}
+
+// dst (device) <- src (host), ordered on the stream; returns once the
+// source has been read (the last DMA done).
+hipError_t copy_h2d(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    char *buf = bytes >= kBounceMin ? bounce_take() : nullptr;
+    if (!buf) {
+        hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+        return e == hipSuccess ? hipStreamSynchronize(st) : e;
+    }
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreateWithFlags(&ev[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
+    bool used[2] = {false, false};
+    for (size_t off = 0, k = 0; e == hipSuccess && off < bytes; off += kBounceChunk, ++k) {
+        const int b = (int)(k & 1);
+        const size_t len = std::min(kBounceChunk, bytes - off);
+        if (used[b]) e = hipEventSynchronize(ev[b]);  // the chunk's previous DMA has read it
+        if (e != hipSuccess) break;
+        par_copy(buf + b * kBounceChunk, (const char *)src + off, len);
+        e = hipMemcpyAsync((char *)dst + off, buf + b * kBounceChunk, len, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipEventRecord(ev[b], st);
+        used[b] = true;
+    }
+    // both chunks idle before the pair goes back to the free list
+    const hipError_t es = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = es;
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (es == hipSuccess) bounce_give(buf);
+    return e;
+}
+
+// dst (host) <- src (device) after the work ordered before it on the stream;
+// returns with dst written.
+hipError_t copy_d2h(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    char *buf = bytes >= kBounceMin ? bounce_take() : nullptr;
+    if (!buf) {
+        hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st);
+        return e == hipSuccess ? hipStreamSynchronize(st) : e;
+    }
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreateWithFlags(&ev[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
+    const size_t nchunks = (bytes + kBounceChunk - 1) / kBounceChunk;
+    auto enqueue = [&](size_t k) {
+        const int b = (int)(k & 1);
+        const size_t off = k * kBounceChunk, len = std::min(kBounceChunk, bytes - off);
+        hipError_t r = hipMemcpyAsync(buf + b * kBounceChunk, (const char *)src + off, len, hipMemcpyDeviceToHost, st);
+        return r == hipSuccess ? hipEventRecord(ev[b], st) : r;
+    };
+    for (size_t k = 0; k < 2 && k < nchunks && e == hipSuccess; ++k) e = enqueue(k);
+    for (size_t k = 0; k < nchunks && e == hipSuccess; ++k) {
+        const int b = (int)(k & 1);
+        const size_t off = k * kBounceChunk, len = std::min(kBounceChunk, bytes - off);
+        e = hipEventSynchronize(ev[b]);
+        if (e != hipSuccess) break;
+        par_copy((char *)dst + off, buf + b * kBounceChunk, len);
+        if (k + 2 < nchunks) e = enqueue(k + 2);  // into the chunk just emptied
+    }
+    const hipError_t es = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = es;
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (es == hipSuccess) bounce_give(buf);
+    return e;
+}
+
+// Host checks of an initial state, over several threads for large lattices.
+// The result is the sequential one: a non-finite value anywhere first, then
+// a non-finite bed, then the first cell (lowest index) that breaks
+// positivity.
 int check_state(arlbm_lattice *h, const double *U0, const double *bed)
 {
     const arlbm_config &c = h->cfg;
     const int64_t plane = h->desc.plane;
     const int m = h->sz.m;
-    for (int64_t i = 0; i < (int64_t)m * plane; ++i)
-        if (!std::isfinite(U0[i])) return fail(h, ARLBM_EPOSITIVITY, "initial state is not finite");
-    if (bed)
-        for (int64_t i = 0; i < plane; ++i)
-            if (!std::isfinite(bed[i])) return fail(h, ARLBM_EPOSITIVITY, "bed is not finite");
-    if (c.system == ARLBM_EULER || c.system == ARLBM_REACTIVE) {
-        const int e = c.dim + 1;
-        for (int64_t i = 0; i < plane; ++i) {
-            const double rho = U0[i];
-            double ke = 0.0;
-            for (int d = 0; d < c.dim; ++d) {
-                const double mom = U0[(1 + d) * plane + i];
-                ke += 0.5 * mom * mom / rho;
+    enum { kOk = 0, kRho, kP, kDepth };
+    struct Part {
+        bool nonfinite = false, bed_nonfinite = false;
+        int64_t bad = -1;  // first cell breaking positivity
+        int kind = kOk;
+    };
+    auto check = [&](int64_t i0, int64_t i1, Part &r) {
+        for (int f = 0; f < m && !r.nonfinite; ++f)
+            for (int64_t i = i0; i < i1; ++i)
+                if (!std::isfinite(U0[(int64_t)f * plane + i])) {
+                    r.nonfinite = true;
+                    break;
+                }
+        if (bed)
+            for (int64_t i = i0; i < i1; ++i)
+                if (!std::isfinite(bed[i])) {
+                    r.bed_nonfinite = true;
+                    break;
+                }
+        if (c.system == ARLBM_EULER || c.system == ARLBM_REACTIVE) {
+            const int e = c.dim + 1;
+            for (int64_t i = i0; i < i1; ++i) {
+                const double rho = U0[i];
+                double ke = 0.0;
+                for (int d = 0; d < c.dim; ++d) {
+                    const double mom = U0[(1 + d) * plane + i];
+                    ke += 0.5 * mom * mom / rho;
+                }
+                double chem = 0.0;
+                if (c.system == ARLBM_REACTIVE) chem = c.q_heat * U0[(int64_t)(e + 1) * plane + i];
+                const double p = (c.gamma - 1.0) * (U0[(int64_t)e * plane + i] - ke - chem);
+                if (!(rho > 0.0) || !(p > 0.0)) {
+                    r.bad = i;
+                    r.kind = !(rho > 0.0) ? kRho : kP;
+                    break;
+                }
             }
-            double chem = 0.0;
-            if (c.system == ARLBM_REACTIVE) chem = c.q_heat * U0[(int64_t)(e + 1) * plane + i];
-            const double p = (c.gamma - 1.0) * (U0[(int64_t)e * plane + i] - ke - chem);
-            if (!(rho > 0.0)) return fail(h, ARLBM_EPOSITIVITY, "initial density must be > 0");
-            if (!(p > 0.0)) return fail(h, ARLBM_EPOSITIVITY, "initial pressure must be > 0");
+        } else if (c.system == ARLBM_SWE) {
+            for (int64_t i = i0; i < i1; ++i)
+                if (!(U0[i] >= 0.0)) {
+                    r.bad = i;
+                    r.kind = kDepth;
+                    break;
+                }
         }
-    } else if (c.system == ARLBM_SWE) {
-        for (int64_t i = 0; i < plane; ++i)
-            if (!(U0[i] >= 0.0)) return fail(h, ARLBM_EPOSITIVITY, "initial depth must be >= 0");
+    };
+    const int64_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const int64_t nt = std::max<int64_t>(1, std::min<int64_t>({8, hw, plane / (1 << 18)}));
+    std::vector<Part> parts((size_t)nt);
+    std::vector<std::thread> th;
+    const int64_t per = (plane + nt - 1) / nt;
+    try {
+        for (int64_t t = 1; t < nt; ++t)
+            th.emplace_back(check, std::min(plane, t * per), std::min(plane, (t + 1) * per), std::ref(parts[t]));
+    } catch (...) {
+        for (auto &x : th) x.join();
+        th.clear();
+        parts.assign(1, Part{});
+        check(0, plane, parts[0]);
     }
+    if (parts.size() == (size_t)nt) check(0, std::min(plane, per), parts[0]);
+    for (auto &x : th) x.join();
+    Part all;
+    for (const Part &r : parts) {
+        all.nonfinite |= r.nonfinite;
+        all.bed_nonfinite |= r.bed_nonfinite;
+        if (r.bad >= 0 && all.bad < 0) {  // parts in index order: the first one found is the lowest
+            all.bad = r.bad;
+            all.kind = r.kind;
+        }
+    }
+    if (all.nonfinite) return fail(h, ARLBM_EPOSITIVITY, "initial state is not finite");
+    if (all.bed_nonfinite) return fail(h, ARLBM_EPOSITIVITY, "bed is not finite");
+    if (all.kind == kRho) return fail(h, ARLBM_EPOSITIVITY, "initial density must be > 0");
+    if (all.kind == kP) return fail(h, ARLBM_EPOSITIVITY, "initial pressure must be > 0");
+    if (all.kind == kDepth) return fail(h, ARLBM_EPOSITIVITY, "initial depth must be >= 0");
     return ARLBM_OK;
 }
 
@@ -323,9 +511,8 @@ int set_state_impl(arlbm_lattice *h, const double *U0, const double *bed, bool o
     } else {
         int rc = check_state(h, U0, need_bed ? bed : nullptr);
         if (rc) return rc;
-        HIPCHK(h, hipMemcpyAsync(U0d, U0, sizeof(double) * m * plane, hipMemcpyHostToDevice, h->stream));
-        if (need_bed)
-            HIPCHK(h, hipMemcpyAsync(bedd, bed, sizeof(double) * plane, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, copy_h2d(U0d, U0, sizeof(double) * m * plane, h->stream));
+        if (need_bed) HIPCHK(h, copy_h2d(bedd, bed, sizeof(double) * plane, h->stream));
     }
     DevScalars sc{};
     sc.t[0] = t0;
@@ -613,11 +800,26 @@ static int read_planes_async(arlbm_lattice *h, const void *src, int m, double *o
     return ARLBM_OK;
 }
 
+// The same into pageable host memory, returning with out written: large
+// reads are packed as FP64 into the population buffer the step does not read
+// next and moved through the pinned chunks of copy_d2h.
 static int read_planes(arlbm_lattice *h, const void *src, int m, double *out)
 {
-    int rc = read_planes_async(h, src, m, out);
-    if (rc) return rc;
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+    const int64_t plane = h->desc.plane, ps = h->desc.pstride;
+    const size_t bytes = sizeof(double) * (size_t)plane * m;
+    if (bytes < kBounceMin) {
+        int rc = read_planes_async(h, src, m, out);
+        if (rc) return rc;
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        return ARLBM_OK;
+    }
+    double *stage = (double *)h->desc.f[(h->step + 1) & 1];
+    if (is_f64(h))
+        HIPCHK(h, hipMemcpy2DAsync(stage, sizeof(double) * plane, src, sizeof(double) * ps, sizeof(double) * plane, m,
+                                   hipMemcpyDeviceToDevice, h->stream));
+    else
+        HIPCHK(h, f32::to_double(src, stage, plane, ps, m, h->stream));
+    HIPCHK(h, copy_d2h(out, stage, bytes, h->stream));
     return ARLBM_OK;
 }
 
@@ -827,12 +1029,23 @@ extern "C" int arlbm_step_kernel_vgprs(int32_t precision, int32_t system, int32_
 namespace {
 // Host arrays the server keeps (queued initial states, results): left
 // uninitialised when allocated, since a parallel copy fills them at once.
+// Host arrays of queued states and results.  Large ones are 2 MiB aligned
+// and advised for transparent huge pages, so that their first touch (the
+// copy into them) takes one fault per 2 MiB instead of per 4 KiB.
 struct HostArray {
-    std::unique_ptr<double[]> p;
+    struct Free {
+        void operator()(double *q) const { free(q); }
+    };
+    std::unique_ptr<double, Free> p;
     size_t n = 0;
     bool alloc(size_t count)  // false when the memory is not there
     {
-        p.reset(count ? new (std::nothrow) double[count] : nullptr);
+        constexpr size_t kHuge = (size_t)2 << 20;
+        const size_t bytes = sizeof(double) * count;
+        void *q = nullptr;
+        if (count && posix_memalign(&q, bytes >= 2 * kHuge ? kHuge : 64, bytes) != 0) q = nullptr;
+        if (q && bytes >= 2 * kHuge) (void)madvise(q, bytes / kHuge * kHuge, MADV_HUGEPAGE);
+        p.reset((double *)q);
         n = p ? count : 0;
         return p || count == 0;
     }
@@ -840,38 +1053,6 @@ struct HostArray {
     const double *data() const { return p.get(); }
     size_t size() const { return n; }
 };
-
-// memcpy of large host arrays over several threads: a fresh destination
-// faults its pages in on first touch, and those faults proceed in parallel
-// (measured on 32 MB: 21 ms on one thread, 4 ms on eight).
-void par_copy(void *dst, const void *src, size_t bytes)
-{
-    constexpr size_t kPerThread = (size_t)4 << 20;
-    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
-    const size_t nt = std::min<size_t>({(size_t)8, hw, bytes / kPerThread});
-    if (bytes == 0) return;
-    if (nt < 2) {
-        std::memcpy(dst, src, bytes);
-        return;
-    }
-    const size_t chunk = (bytes / nt + 4095) / 4096 * 4096;  // nt * chunk >= bytes
-    std::vector<std::thread> th;
-    size_t started = 0;  // chunks 1 .. started run on threads of their own
-    try {
-        th.reserve(nt - 1);
-        for (size_t t = 1; t < nt && t * chunk < bytes; ++t) {
-            const size_t a = t * chunk, len = std::min(chunk, bytes - a);
-            th.emplace_back([=] { std::memcpy((char *)dst + a, (const char *)src + a, len); });
-            started = t;
-        }
-    } catch (...) {
-        // no thread for the remaining chunks: copied below
-    }
-    std::memcpy(dst, src, std::min(chunk, bytes));
-    const size_t rest = (started + 1) * chunk;
-    if (rest < bytes) std::memcpy((char *)dst + rest, (const char *)src + rest, bytes - rest);
-    for (auto &x : th) x.join();
-}
 
 struct Pending {
     uint64_t id;
@@ -883,6 +1064,7 @@ struct Pending {
     int64_t nsteps;
     double submit_s;
     size_t bytes;  // device memory charged: the size class of the lattice's block
+    double *dst = nullptr;  // caller memory for the result (arlbm_server_result_into), or none
 };
 struct Resident {
     uint64_t id;
@@ -894,6 +1076,7 @@ struct Resident {
     size_t bytes;
     void *dev;       // the lattice's device block (pool)
     size_t dev_cls;  // its size class
+    double *dst;     // caller memory for the result, or nullptr
 };
 struct Done {
     arlbm_completion c;
@@ -910,6 +1093,7 @@ struct Staged {
     void *host;  // pinned block: scalars [, scalars out], planes
     size_t host_cls;
     hipEvent_t ev;
+    double *dst = nullptr;  // retirement: caller memory for the result, or nullptr
 };
 
 // Size classes a quarter octave apart (a block is at most 25% larger than
@@ -1087,10 +1271,11 @@ void push_failed(arlbm_server *s, uint64_t id, int rc, double submit_s)
     s->done.push_back(std::move(d));
 }
 
-// Served lattices that the batched kernel does not step: 3D lattices (three
-// passes over the whole lattice, the indicator needing every neighbour's
-// moments first) and 2D lattices whose population buffer spans 4 GiB or more
-// (the batched kernel addresses planes through 32-bit buffer offsets).
+// Served lattices that the batched kernel does not step: 3D lattices (their
+// fused z-marching step keeps tiles of moments and indicators in LDS, a
+// launch shape of its own) and 2D lattices whose population buffer spans
+// 4 GiB or more (the batched kernel addresses planes through 32-bit buffer
+// offsets).
 bool own_launch(const LatticeDesc &d) { return d.variant >= V_ADV3 || (d.variant >= V_ADV2 && !d.buf); }
 
 // Work list of the batched launch.  The work of every resident 1D and 2D
@@ -1591,7 +1776,7 @@ void admit_enqueue(arlbm_server *s, Pending &p)
     lat->busy = true;
     const double t_admit = now_s();
     s->resident.push_back({p.id, lat, s->iter - p.step0, s->iter, s->iter + p.nsteps, p.submit_s, t_admit, p.bytes,
-                           blk, dcls});
+                           blk, dcls, p.dst});
     s->staged.push_back({resume ? Staged::ADMIT_STATE : Staged::ADMIT, p.id, lat, 0, p.submit_s, t_admit, host,
                          hcls, ev});
     s->in_use += p.bytes;
@@ -1633,7 +1818,7 @@ int retire_enqueue(arlbm_server *s, const Resident &r)
         push_failed(s, r.id, rc, r.submit_s);
         return rc;
     }
-    s->staged.push_back({Staged::RETIRE, r.id, h, steps, r.submit_s, r.admit_s, host, hcls, ev});
+    s->staged.push_back({Staged::RETIRE, r.id, h, steps, r.submit_s, r.admit_s, host, hcls, ev, r.dst});
     s->dev.release(r.dev, r.dev_cls);
     s->in_use -= r.bytes;
     return ARLBM_OK;
@@ -1671,8 +1856,17 @@ int finish_staged(arlbm_server *s)
             // the positivity flag is advisory: the moments are still the result
             if (rc == ARLBM_OK) {
                 const double *U = (const double *)((const char *)g.host + align_up(sizeof(DevScalars)));
-                if (d.U.alloc((size_t)h->sz.m * h->desc.plane)) par_copy(d.U.data(), U, sizeof(double) * d.U.size());
-                else rc = ARLBM_ENOMEM;
+                const size_t nU = (size_t)h->sz.m * h->desc.plane;
+                if (g.dst) {
+                    // straight into the caller's array: no copy at poll
+                    par_copy(g.dst, U, sizeof(double) * nU);
+                    d.c.U = g.dst;
+                    d.c.u_count = (int64_t)nU;
+                } else if (d.U.alloc(nU)) {
+                    par_copy(d.U.data(), U, sizeof(double) * nU);
+                } else {
+                    rc = ARLBM_ENOMEM;
+                }
             }
             d.c.status = rc;
             d.c.done_s = now_s();
@@ -1872,6 +2066,19 @@ extern "C" int arlbm_server_submit_state(arlbm_server *s, const arlbm_config *cf
     return queue_request(s, std::move(p), id);
 }
 
+extern "C" int arlbm_server_result_into(arlbm_server *s, uint64_t id, double *dst, int64_t count)
+{
+    if (!s || !dst) return sfail(s, ARLBM_EINVAL, "bad argument");
+    for (Pending &p : s->queue) {
+        if (p.id != id) continue;
+        const int64_t need = (int64_t)num_fields(p.cfg.system, p.cfg.dim) * p.cfg.nx * p.cfg.ny * p.cfg.nz;
+        if (count != need) return sfail(s, ARLBM_EINVAL, "count is not the size of the request's result");
+        p.dst = dst;
+        return ARLBM_OK;
+    }
+    return sfail(s, ARLBM_EINVAL, "no queued request has this id");
+}
+
 extern "C" int arlbm_server_iterate(arlbm_server *s, int32_t *n_res, int32_t *n_queued)
 {
     return arlbm_server_iterate_n(s, 1, n_res, n_queued, nullptr);
@@ -1967,8 +2174,13 @@ extern "C" int arlbm_server_poll(arlbm_server *s, arlbm_completion *out, int32_t
     for (int32_t i = 0; i < k; ++i) {
         Done &d = s->handed[i];
         out[i] = d.c;
-        out[i].U = d.c.status == ARLBM_OK ? d.U.data() : nullptr;
-        out[i].u_count = d.c.status == ARLBM_OK ? (int64_t)d.U.size() : 0;
+        if (d.c.status != ARLBM_OK) {
+            out[i].U = nullptr;
+            out[i].u_count = 0;
+        } else if (!d.c.U) {  // a result in the server's own memory
+            out[i].U = d.U.data();
+            out[i].u_count = (int64_t)d.U.size();
+        }
     }
     *n = k;
     return ARLBM_OK;

@@ -685,3 +685,62 @@ def test_served_requests_at_full_length_against_fp64():
         assert max(em) <= tol[1], em
         if p.dim == 2:
             assert all(a <= 10 * c for a, c in zip(e1, cond)), (e1, cond)
+
+
+@pytest.mark.parametrize("n", [700, 1100])
+def test_large_transfers_through_pinned_chunks(n):
+    """States of 8 MB and more go to and from the device through two pinned
+    chunks of 16 MB used in turn: 700^2 Euler (15.7 MB, one chunk) and
+    1100^2 (38.7 MB, a ragged third chunk; its omega plane 9.7 MB, one
+    chunk).  One FP64 step bit for bit against the oracle, the omega plane
+    too; FP32 read back through the same chunks against the FP64 result."""
+    require_gpu()
+    p = W.euler_seeded_2d(1, n=n, steps=1)
+    Lo = oracle_run(p, 1, parallel=True)
+    Uo = Lo.moments()
+    G = gpu_lattice(p, A.F64, omega_export=True)
+    G.step(1)
+    st = G.sync()
+    U = G.moments()
+    w = G.omega()
+    G.close()
+    say(f"[pinned chunks {n}^2] FP64 bitwise {np.array_equal(U, Uo)} omega {np.array_equal(w, Lo.last_omega())}")
+    assert np.array_equal(U, Uo) and st["t"] == Lo.t
+    assert np.array_equal(w, Lo.last_omega())
+    G = gpu_lattice(p, A.F32)
+    G.step(1)
+    G.sync()
+    U32 = G.moments()
+    G.close()
+    assert max(rel_l2_per_comp(U32, Uo)) <= 1e-5
+
+
+def test_serving_result_into_caller_array():
+    """A request whose result the server writes into the caller's array
+    (arlbm_server_result_into) gives the bits of one read back into the
+    server's own memory, and poll hands back that very array; the call
+    rejects an id that is not queued and a wrong count."""
+    require_gpu()
+    probs = [W.euler_seeded_2d(0, n=1100, steps=3), W.euler_seeded_1d(2, n=4096, steps=5)]
+    srv = A.Server(1 << 30, A.F32)
+    ids = []
+    for p in probs:
+        for into in (True, False):
+            ids.append(srv.submit(A.config_from(p, precision=A.F32), p.U0, p.bed, p.steps, result_into=into))
+    with pytest.raises(A.ArlbmError):
+        srv._result_into(ids[1], probs[0].U0.size + 1)  # queued, wrong count
+    dst = {i: srv._dst[i] for i in ids[0::2]}
+    res = {}
+    while len(res) < len(ids):
+        srv.iterate(8)
+        for c in srv.poll(16):
+            res[c["id"]] = c
+    with pytest.raises(A.ArlbmError):
+        srv._result_into(ids[1], probs[0].U0.size)  # completed: no longer queued
+    srv.close()
+    for k, p in enumerate(probs):
+        a, b = res[ids[2 * k]], res[ids[2 * k + 1]]
+        assert a["status"] == 0 and b["status"] == 0 and a["steps"] == b["steps"] == p.steps
+        assert a["U"] is dst[ids[2 * k]]
+        assert not np.shares_memory(b["U"], dst[ids[2 * k]])
+        assert np.array_equal(a["U"], b["U"]) and a["t"] == b["t"]
