@@ -1988,12 +1988,16 @@ extern "C" int arlbm_server_create(size_t budget, int32_t precision, void *strea
     s->precision = precision;
     s->stream = (hipStream_t)stream;
     // device blocks held for lattices (in use or free): at most the budget;
-    // free pinned staging blocks: at most 1 GiB
+    // pinned staging blocks (in use or free): at most 4 GiB, room to keep the
+    // admission and read-back blocks of large lattices for reuse (a 4096^2
+    // shallow-water state takes 671 and 470 MB; with a 1 GiB cap each solve
+    // gave one back and pinned the other again: 4096^2 solve 1035 ms, of
+    // which 920 ms of steps)
     s->dev.cap = budget;
     s->dev.stream = s->stream;
     s->pin.stream = s->stream;
     s->pin.pinned = true;
-    s->pin.cap = (size_t)1 << 30;
+    s->pin.cap = (size_t)4 << 30;
     const size_t cbytes = sizeof(unsigned) * 2 * kQueues * kQueueStride;
     hipError_t e = hipMalloc((void **)&s->d_counters, cbytes);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_counters, 0, cbytes, s->stream);
