@@ -252,6 +252,45 @@ def test_checkpoint_resume_bitwise(prec):
     assert np.array_equal(ref, straight) and np.array_equal(ref, resumed)
 
 
+def test_set_state_checks_large_states_in_order():
+    """The host checks of a large state run over several threads and still
+    report what a sequential pass would: a non-finite value anywhere first,
+    then the first cell (lowest index) whose density or pressure (depth) is
+    not positive.  1024^2: four parts of 256 rows each."""
+    require_gpu()
+    p = W.euler_seeded_2d(0, n=1024, steps=1)
+    L = A.Lattice(A.config_from(p, precision=A.F32))
+
+    def fails_with(U, text, bed=None):
+        with pytest.raises(A.ArlbmError) as e:
+            L.set_state(U, bed)
+        assert e.value.code == A.EPOSITIVITY and text in str(e.value), str(e.value)
+
+    bad = p.U0.copy()
+    bad[3, 10, 5] = 0.0      # part 0: energy 0, so the pressure is negative
+    bad[0, 900, 7] = -1.0    # part 3: negative density, a later cell
+    fails_with(bad, "pressure")
+    bad = p.U0.copy()
+    bad[0, 300, 1] = -1.0    # part 1: negative density
+    bad[3, 1000, 2] = np.inf  # part 3: not finite, reported first
+    fails_with(bad, "not finite")
+    bad = p.U0.copy()
+    bad[0, 700, 9] = -2.0    # part 2 only
+    bad[0, 700, 8] = 0.0     # the cell before it: zero density, same message
+    fails_with(bad, "density")
+    L.set_state(p.U0)        # the lattice still takes a good state
+    L.close()
+    q = W.swe_bed_2d(0, n=1024, steps=1)
+    L = A.Lattice(A.config_from(q, precision=A.F32))
+    bad = q.U0.copy()
+    bad[0, 600, 3] = -1e-3
+    fails_with(bad, "depth", q.bed)
+    bed = q.bed.copy()
+    bed[800, 800] = np.nan
+    fails_with(bad, "bed is not finite", bed)  # a non-finite bed before any depth
+    L.close()
+
+
 def test_set_state_rejects_bad_states():
     require_gpu()
     p = W.euler_seeded_2d(0, n=32, steps=1)
