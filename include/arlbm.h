@@ -154,8 +154,11 @@ int arlbm_create(const arlbm_config *cfg, const arlbm_buffers *bufs, void *strea
  * bed (one plane); t0 is the starting time.  Rejects non-finite values,
  * rho <= 0 or p <= 0 (Euler), h < 0 (shallow water) with EPOSITIVITY, a zero
  * wave-speed bound with EDEGENERATE and an eps above the Theorem 4.3 bound
- * with EINVAL.  Initialises f = f^eq(U0) with the step-0 coefficients and
- * synchronises the stream. */
+ * with EINVAL (the first problem a sequential pass over the cells would
+ * meet; the checks of large states run on several host threads).
+ * Initialises f = f^eq(U0) with the step-0 coefficients and synchronises the
+ * stream.  Arrays of 8 MB and more move through two pinned 16 MB chunks of
+ * the library's, used in turn. */
 int arlbm_set_state(arlbm_lattice *h, const double *U0, const double *bed, double t0);
 
 /* Same, with U0 (and bed) already on the device as FP64 planes. */
@@ -183,7 +186,9 @@ int arlbm_step_until(arlbm_lattice *h, double t_final, int64_t max_steps, int64_
  * the state is no longer usable. */
 int arlbm_sync(arlbm_lattice *h, arlbm_status *st);
 
-/* Copy the current moments U = sum_k f_k to host FP64 planes (synchronises). */
+/* Copy the current moments U = sum_k f_k to host FP64 planes (synchronises;
+ * large reads are packed into the population buffer the next step writes and
+ * move through the pinned chunks that arlbm_set_state uses). */
 int arlbm_read_moments(arlbm_lattice *h, double *U_out);
 
 /* Enable (1) or disable (0) writing the relaxation parameter of each step to
