@@ -501,15 +501,17 @@ __device__ __forceinline__ void seg1d(const LatticeDesc &L, int64_t iter, int c0
 
 // Several steps of a small 1D lattice in one launch: one workgroup, one wave
 // per strip (at most 16 strips), a barrier between steps.  Before it every
-// wave waits for its stores and wave-speed atomics to complete; after it the
-// acquire at device scope drops the CU's L1 lines, so the next step reads
-// the populations, times and slots the step wrote, from L2.  A step then
-// costs no launch: a 256-cell advection solve of 512 steps took 1.55 ms
-// against 2.23 ms in one launch per step (1.44 ms without the wait before
-// the barrier, which leaves the order to the CU's path to L2).  With several
-// strips per wave the strips follow one another: 4096 cells (71 strips on
-// 16 waves) took 25 ms against 9.8 ms, so larger lattices keep one launch
-// per step.
+// wave waits for its stores and wave-speed atomics to complete.  The
+// barrier's workgroup-scope fences then make them visible to the other waves:
+// the waves of one workgroup run on one CU and share its L1, which the CU
+// keeps coherent with its own stores and atomics, so the next step reads the
+// populations, times and slots the step wrote without dropping any cache
+// lines.  A step then costs no launch: a 256-cell advection solve of 512
+// steps took 2.23 ms in one launch per step, 1.52 ms here with an acquire at
+// device scope after the barrier (which invalidates the L1), 1.33 ms without;
+// 900 cells of Euler over 1500 steps 9.07 -> 6.73 ms.  With several strips
+// per wave the strips follow one another: 4096 cells (71 strips on 16 waves)
+// took 25 ms against 9.8 ms, so larger lattices keep one launch per step.
 template <int SYS, typename T>
 __global__ __launch_bounds__(1024) void k_steps1d(LatticeDesc L, int64_t iter0, int32_t nsteps)
 {
@@ -519,7 +521,6 @@ __global__ __launch_bounds__(1024) void k_steps1d(LatticeDesc L, int64_t iter0, 
         if (c0 < c1) seg1d<SYS, T>(L, iter0 + s, c0, c1);
         __builtin_amdgcn_s_waitcnt(0);  // vmcnt, expcnt and lgkmcnt all zero
         __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
 }
 
